@@ -1,0 +1,303 @@
+"""ctypes binding of the FP64 CPU oracle (``oracle/hl_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by
+``__graft_entry__.smoke()`` and by the CPU-baseline leg of ``bench.py``.
+The HIP library never imports or links anything from here.
+
+All arrays follow the layout of the C-ABI of the library: node vectors
+``[n_nodes, dim]``, cell vectors ``[n_cells, dim]``, B as ``[n_cells, nB]``
+with components (11, 22, 33, 12, 13, 23) in 3D and (11, 22, 12) in 2D.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hl_oracle.c")
+LIB = os.path.join(HERE, "libhl_oracle.so")
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
+          "-Wall", "-Wno-unused-function"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C, no FMA contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Params(C.Structure):
+    _fields_ = [("c_cfl", C.c_double), ("c_v", C.c_double), ("c_i", C.c_double),
+                ("delta0", C.c_double), ("delta1", C.c_double), ("eps_tol", C.c_double),
+                ("detect", C.c_int), ("pad", C.c_int)]
+
+
+class Info(C.Structure):
+    _fields_ = [("dt_next", C.c_double), ("dt_acoustic", C.c_double),
+                ("dt_volume", C.c_double), ("mass", C.c_double), ("mom", C.c_double * 3),
+                ("energy", C.c_double), ("kinetic", C.c_double), ("elastic", C.c_double),
+                ("n_p0", C.c_int64), ("n_flag_first", C.c_int64), ("mood_iters", C.c_int32),
+                ("status", C.c_int32)]
+
+    def as_dict(self):
+        return dict(dt_next=self.dt_next, dt_acoustic=self.dt_acoustic,
+                    dt_volume=self.dt_volume, mass=self.mass, mom=list(self.mom),
+                    energy=self.energy, kinetic=self.kinetic, elastic=self.elastic,
+                    n_p0=self.n_p0, n_flag_first=self.n_flag_first,
+                    mood_iters=self.mood_iters, status=self.status)
+
+
+def default_params(c_cfl=0.25, detect=True):
+    """Paper values: C_v = 0.2, C_i = 0.1, delta0 = 1e-4, delta1 = 1e-3
+    (Sections 3.5 and 3.6)."""
+    return Params(c_cfl, 0.2, 0.1, 1e-4, 1e-3, 1e-12, 1 if detect else 0, 0)
+
+
+_lib = None
+_P = C.POINTER(C.c_double)
+_I32 = C.POINTER(C.c_int32)
+_U8 = C.POINTER(C.c_uint8)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        L.orc_mesh_new.restype = C.c_void_p
+        L.orc_mesh_new.argtypes = [C.c_int, C.c_int64, C.c_int64, _I32, _U8, _P]
+        L.orc_mesh_free.argtypes = [C.c_void_p]
+        L.orc_init_state.restype = C.c_int
+        L.orc_init_state.argtypes = [C.c_void_p] + [_P] * 6 + [_P] * 7
+        L.orc_step.restype = C.c_int
+        L.orc_step.argtypes = ([C.c_void_p] + [_P] * 4 + [_P] * 6 + [C.c_double, C.POINTER(Params),
+                               _U8, C.c_int] + [_P] * 7 + [C.POINTER(Info)])
+        L.orc_initial_dt.restype = C.c_double
+        L.orc_initial_dt.argtypes = [C.c_void_p] + [_P] * 6 + [C.POINTER(Params)]
+        L.orc_cell_geometry.argtypes = [C.c_int, _P, _P, _P, _P, _P, _P]
+        L.orc_corner_shape.argtypes = [C.c_int, _P, C.c_int, _P]
+        L.orc_point_stress.argtypes = [C.c_double] * 4 + [_P, _P, _P, _P, _P]
+        L.orc_point_stress_direction.argtypes = [C.c_double] * 4 + [_P, C.c_double, _P, _P]
+        L.orc_point_cn.restype = C.c_int
+        L.orc_point_cn.argtypes = [C.c_int, _P, _P, _P, C.c_double, _P]
+        L.orc_lsq.argtypes = [C.c_void_p] + [_P] * 5
+        L.orc_predict.argtypes = ([C.c_void_p] + [_P] * 7 + [C.c_double, _U8] + [_P] * 5)
+        L.orc_diagnostics.argtypes = [C.c_void_p] + [_P] * 8 + [C.POINTER(Info)]
+        L.orc_info_size.restype = C.c_int
+        L.orc_params_size.restype = C.c_int
+        assert L.orc_info_size() == C.sizeof(Info)
+        assert L.orc_params_size() == C.sizeof(Params)
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_P)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_P)
+
+
+# -------------------------------------------------------------- point-wise
+
+def cell_geometry(X):
+    """X: [(d+1), d] vertex coordinates -> dict(V, xc, C, A, Lc)."""
+    X = _f64(X)
+    d = X.shape[1]
+    V = np.zeros(1)
+    Lc = np.zeros(1)
+    xc = np.zeros(3)
+    Cc = np.zeros((d + 1, 3))
+    A = np.zeros((d + 1, 3))
+    lib().orc_cell_geometry(d, _ptr(X), _ptr(V), _ptr(xc), _ptr(Cc), _ptr(A), _ptr(Lc))
+    return dict(V=V[0], xc=xc[:d], C=Cc[:, :d], A=A[:, :d], Lc=Lc[0])
+
+
+def corner_shape(X, p):
+    X = _f64(X)
+    N = np.zeros((3, 3))
+    lib().orc_corner_shape(X.shape[1], _ptr(X), int(p), _ptr(N))
+    return N
+
+
+def point_stress(rho0, mu, K, tau, B):
+    """Full 3x3 B -> (T 3x3, p, a, Psi)."""
+    B = _f64(B)
+    T = np.zeros((3, 3))
+    p = np.zeros(1)
+    a = np.zeros(1)
+    psi = np.zeros(1)
+    lib().orc_point_stress(rho0, mu, K, tau, _ptr(B), _ptr(T), _ptr(p), _ptr(a), _ptr(psi))
+    return T, p[0], a[0], psi[0]
+
+
+def point_stress_direction(rho0, mu, K, tau, B, dtau, dB):
+    B = _f64(B)
+    dB = _f64(dB)
+    dT = np.zeros((3, 3))
+    lib().orc_point_stress_direction(rho0, mu, K, tau, _ptr(B), dtau, _ptr(dB), _ptr(dT))
+    return dT
+
+
+def point_cn(d, Bn, Ln, L1, dt):
+    Bn, Ln, L1 = _f64(Bn), _f64(Ln), _f64(L1)
+    out = np.zeros((3, 3))
+    st = lib().orc_point_cn(d, _ptr(Bn), _ptr(Ln), _ptr(L1), dt, _ptr(out))
+    assert st == 0
+    return out
+
+
+# -------------------------------------------------------------- mesh level
+
+@dataclass
+class State:
+    x: np.ndarray
+    vhat: np.ndarray
+    tau: np.ndarray
+    v: np.ndarray
+    e: np.ndarray
+    B: np.ndarray
+
+    def copy(self):
+        return State(*(np.array(a, copy=True) for a in
+                       (self.x, self.vhat, self.tau, self.v, self.e, self.B)))
+
+
+class Mesh:
+    """Oracle mesh: connectivity, node->corner lists and wall bases."""
+
+    def __init__(self, dim, x, cells, nwall=None, normals=None):
+        self.dim = int(dim)
+        self.cells = np.ascontiguousarray(cells, dtype=np.int32)
+        self.nn = int(np.asarray(x).shape[0])
+        self.nc = int(self.cells.shape[0])
+        self.nB = 6 if dim == 3 else 3
+        if nwall is None:
+            nwall = np.zeros(self.nn, np.uint8)
+        if normals is None:
+            normals = np.zeros((self.nn, dim, dim))
+        self._nwall = np.ascontiguousarray(nwall, dtype=np.uint8)
+        self._normals = _f64(normals)
+        h = lib().orc_mesh_new(self.dim, self.nn, self.nc, self.cells.ctypes.data_as(_I32),
+                               self._nwall.ctypes.data_as(_U8), _ptr(self._normals))
+        if not h:
+            raise ValueError("invalid mesh")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.orc_mesh_free(h)
+            self.h = None
+
+
+class Problem:
+    """Mesh + material + state, advanced by the oracle."""
+
+    def __init__(self, w, params=None):
+        self.w = w
+        self.dim = w.dim
+        self.mesh = Mesh(w.dim, w.x, w.cells, w.nwall, w.normals)
+        nc, nn, d = w.n_cells, w.n_nodes, w.dim
+        self.rho0 = _f64(w.rho0)
+        self.mu = _f64(w.mu)
+        lam = _f64(w.lam)
+        self.m = np.zeros(nc)
+        self.K = np.zeros(nc)
+        st = State(_f64(w.x).copy(), np.zeros((nn, d)), np.zeros(nc), np.zeros((nc, d)),
+                   np.zeros(nc), np.zeros((nc, self.mesh.nB)))
+        vc, vn = _f64(w.v_cell), _f64(w.v_node)
+        rc = lib().orc_init_state(self.mesh.h, _ptr(st.x), _ptr(self.rho0), _ptr(self.mu),
+                                  _ptr(lam), _ptr(vc), _ptr(vn), _ptr(self.m), _ptr(self.K),
+                                  _ptr(st.tau), _ptr(st.v), _ptr(st.e), _ptr(st.B),
+                                  _ptr(st.vhat))
+        if rc != 0:
+            raise ValueError("degenerate cell in the initial mesh")
+        self.state = st
+        self.params = params if params is not None else default_params(w.c_cfl)
+        self.dt_prev = 0.0
+        self.t = 0.0
+
+    def initial_dt(self):
+        s = self.state
+        return lib().orc_initial_dt(self.mesh.h, _ptr(self.rho0), _ptr(self.mu), _ptr(self.K),
+                                    _ptr(s.x), _ptr(s.tau), _ptr(self.m),
+                                    C.byref(self.params))
+
+    def step(self, dt, mask=None, replay=False, state=None):
+        """Advance ``state`` (default: the held state) by ``dt``.  Returns
+        (new_state, vstar, mask, info); the held state is replaced only when
+        ``state`` is None."""
+        s = self.state if state is None else state
+        nc, nn, d = self.mesh.nc, self.mesh.nn, self.dim
+        mk = np.zeros(nc, np.uint8) if mask is None else np.array(mask, dtype=np.uint8, copy=True)
+        out = State(np.zeros((nn, d)), np.zeros((nn, d)), np.zeros(nc), np.zeros((nc, d)),
+                    np.zeros(nc), np.zeros((nc, self.mesh.nB)))
+        vstar = np.zeros((nn, d))
+        info = Info()
+        ins = [_f64(a) for a in (s.x, s.vhat, s.tau, s.v, s.e, s.B)]
+        lib().orc_step(self.mesh.h, _ptr(self.rho0), _ptr(self.mu), _ptr(self.K), _ptr(self.m),
+                       *[_ptr(a) for a in ins], float(dt), C.byref(self.params),
+                       mk.ctypes.data_as(_U8), 1 if replay else 0,
+                       _ptr(out.x), _ptr(out.vhat), _ptr(out.tau), _ptr(out.v), _ptr(out.e),
+                       _ptr(out.B), _ptr(vstar), C.byref(info))
+        if state is None:
+            self.state = out
+            self.t += dt
+            self.dt_prev = dt
+        return out, vstar, mk, info
+
+    def run(self, steps, dt=None, callback=None):
+        """Advance ``steps`` steps with CFL control (or a fixed ``dt``)."""
+        dt_next = self.initial_dt() if dt is None else dt
+        infos = []
+        for _ in range(steps):
+            cur = dt_next
+            _, _, mk, info = self.step(cur)
+            infos.append(info.as_dict())
+            if callback:
+                callback(self, mk, info)
+            dt_next = info.dt_next if dt is None else dt
+        return infos
+
+    def lsq(self, state=None):
+        s = self.state if state is None else state
+        g = np.zeros((self.mesh.nc, 1 + self.dim + self.mesh.nB, 3))
+        ins = [_f64(a) for a in (s.x, s.tau, s.v, s.B)]
+        lib().orc_lsq(self.mesh.h, *[_ptr(a) for a in ins], _ptr(g))
+        return g[:, :, :self.dim]
+
+    def predict(self, dt, mask=None, state=None):
+        s = self.state if state is None else state
+        nq = self.mesh.nc * (self.dim + 1)
+        mk = np.zeros(self.mesh.nc, np.uint8) if mask is None else np.asarray(mask, np.uint8)
+        tau_s, v_s = np.zeros(nq), np.zeros((nq, 3))
+        B_s, T_s, z_s = np.zeros((nq, 3, 3)), np.zeros((nq, 3, 3)), np.zeros(nq)
+        ins = [_f64(a) for a in (s.x, s.tau, s.v, s.B)]
+        lib().orc_predict(self.mesh.h, _ptr(self.rho0), _ptr(self.mu), _ptr(self.K),
+                          *[_ptr(a) for a in ins], float(dt), mk.ctypes.data_as(_U8),
+                          _ptr(tau_s), _ptr(v_s), _ptr(B_s), _ptr(T_s), _ptr(z_s))
+        return dict(tau=tau_s, v=v_s, B=B_s, T=T_s, z=z_s)
+
+    def diagnostics(self, state=None):
+        s = self.state if state is None else state
+        info = Info()
+        ins = [_f64(a) for a in (s.tau, s.v, s.e, s.B)]
+        lib().orc_diagnostics(self.mesh.h, _ptr(self.rho0), _ptr(self.mu), _ptr(self.K),
+                              _ptr(self.m), *[_ptr(a) for a in ins], C.byref(info))
+        return info.as_dict()
