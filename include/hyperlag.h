@@ -1,0 +1,179 @@
+/*
+ * hyperlag.h -- C-ABI of libhyperlag.so: one second-order cell-centred
+ * Lagrangian ADER-MOOD time step for neo-Hookean solids on 2D triangle and
+ * 3D tetrahedral meshes, computed by HIP kernels on one AMD Instinct GPU
+ * (gfx950), in FP64 throughout.
+ *
+ * Method: Boscheri, Loubere & Maire, "A cell-centered Lagrangian ADER-MOOD
+ * finite volume scheme on unstructured meshes for a class of
+ * hyper-elasticity models" (arXiv 2104.02139):
+ *   - conservation laws and B evolution: Section 2.2 (eqs. cl, trcb);
+ *   - neo-Hookean law: Section 2.2.4 (eqs. EOS_neoHook, cstnh);
+ *   - geometry and corner vectors: Section 3.1 (eq. def_lcpncp);
+ *   - subcell force and nodal solver: Section 3.3 (eqs. subforce,
+ *     nodal_solver, Mcp);
+ *   - ADER midpoint update and Crank-Nicolson B update: Section 3.4
+ *     (eqs. tau_c^n .. subforce^n, firstB, CN_B);
+ *   - MOOD detection and cascade: Section 3.5 (eqs. PAD, RDMP), Section
+ *     3.7 (Figure sketch);
+ *   - time step: Section 3.6 (eqs. CFL, CFL2);
+ *   - boundary conditions: Section 3.8 and Appendix B (eq. sBC1).
+ *
+ * Conventions
+ *   - Every call returns hl_status: 0 = HL_OK, < 0 error, > 0 warning.  No
+ *     exception crosses the ABI.  hl_status_str() gives the text.
+ *   - A failed call leaves the held state unchanged.
+ *   - Input arrays are BORROWED for the duration of the call only; the
+ *     library copies what it keeps.  "on_device" != 0 means the pointer is
+ *     HIP device memory (for instance a torch tensor's data_ptr()),
+ *     otherwise host memory.
+ *   - All arrays are row-major in the caller's numbering: node vectors
+ *     [n_nodes][dim], cell vectors [n_cells][dim], B as [n_cells][nB] with
+ *     nB = 6 components (11,22,33,12,13,23) in 3D and nB = 3 components
+ *     (11,22,12) in 2D (plane strain, B33 == 1).
+ *   - The context owns every device buffer it allocates (hipMalloc) and
+ *     frees them in hl_destroy.  All work is enqueued on the stream given
+ *     to hl_create (borrowed, may be NULL for the default stream); calls
+ *     that return host data synchronise that stream.
+ *   - Calls on one context are not thread-safe; distinct contexts are
+ *     independent.
+ */
+#ifndef HYPERLAG_H
+#define HYPERLAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hl_ctx hl_ctx;
+
+typedef enum {
+    HL_OK = 0,
+    HL_WARN_PARACHUTE_INADMISSIBLE = 1, /* a first-order cell is not admissible */
+    HL_E_INVALID = -1,                  /* bad argument                          */
+    HL_E_DEGENERATE_CELL = -2,          /* a cell with V <= 0 at upload           */
+    HL_E_OOM = -4,                      /* device allocation failed              */
+    HL_E_HIP = -5,                      /* a HIP runtime call failed             */
+    HL_E_STATE = -6                     /* call order (no mesh / no state yet)   */
+} hl_status;
+
+/* Scheme parameters (Sections 3.5 and 3.6).  Paper values: c_v = 0.2,
+ * c_i = 0.1, delta0 = 1e-4, delta1 = 1e-3, c_cfl = 0.4 (2D) / 0.25 (3D). */
+typedef struct {
+    double c_cfl;   /* acoustic CFL number                                  */
+    double c_v;     /* bound on the relative volume change per step        */
+    double c_i;     /* bound on the growth of dt per step                  */
+    double delta0;  /* absolute relaxed-DMP tolerance on rho               */
+    double delta1;  /* relative relaxed-DMP tolerance on rho               */
+    double eps_tol; /* eps = e - |v|^2/2 is troubled below -eps_tol (|e| + |v|^2/2) */
+    int32_t detect; /* 0: accept the unlimited second-order candidate      */
+    int32_t reserved;
+} hl_params;
+
+/* Per-step report.  Filled by hl_step / hl_step_replay when non-NULL. */
+typedef struct {
+    double dt_used;      /* dt of the step just taken (mesh 0)              */
+    double dt_next;      /* CFL-controlled dt for the next step (mesh 0)    */
+    double dt_acoustic;  /* C_CFL min L_c / a_c at t^{n+1}                  */
+    double dt_volume;    /* C_v dt min V^{n+1} / |V^{n+1} - V^n|            */
+    double mass, mom[3], energy, kinetic, elastic; /* sums over all cells   */
+    int64_t n_p0;        /* cells advanced at first order                  */
+    int64_t n_flag_first;/* cells flagged on the first candidate            */
+    int32_t mood_iters;  /* candidate evaluations (1 = nothing flagged)     */
+    int32_t status;      /* 1: some first-order cell is not admissible      */
+} hl_step_info;
+
+/* Fields for hl_query / hl_upload_field. */
+enum {
+    HL_X = 0,     /* node positions          [n_nodes][dim]   double       */
+    HL_VHAT = 1,  /* carried node velocity   [n_nodes][dim]   double       */
+    HL_TAU = 2,   /* specific volume         [n_cells]        double       */
+    HL_V = 3,     /* cell velocity           [n_cells][dim]   double       */
+    HL_E = 4,     /* specific total energy   [n_cells]        double       */
+    HL_B = 5,     /* left Cauchy-Green       [n_cells][nB]    double       */
+    HL_VSTAR = 6, /* node velocity of the last step [n_nodes][dim] (query) */
+    HL_ORDER = 7, /* 1 = cell advanced at first order in the last step,
+                     [n_cells] uint8 (query)                               */
+    HL_MASS = 8,  /* cell mass               [n_cells]        double (query) */
+    HL_T = 9      /* Cauchy stress [n_cells][6] (11,22,33,12,13,23) in 3D,
+                     [n_cells][4] (11,22,12,33) in 2D (query)              */
+};
+
+/* Create a context on HIP device `device`; work goes to `hip_stream`
+ * (a hipStream_t, borrowed; NULL = default stream). */
+hl_status hl_create(hl_ctx **out, int device, void *hip_stream);
+
+/* Free every device buffer and the context.  NULL is accepted. */
+hl_status hl_destroy(hl_ctx *ctx);
+
+/* Upload a simplicial mesh (Section 3.1, "Mesh and notation").
+ *   dim           2 (triangles) or 3 (tetrahedra)
+ *   x0            [n_nodes][dim] initial node positions
+ *   cells         [n_cells][dim+1] node indices, every cell positively
+ *                 oriented (V > 0), else HL_E_DEGENERATE_CELL
+ *   nwall         [n_nodes] number of slip-wall constraints at the node
+ *                 (0 = free, dim = node held fixed), or NULL for none
+ *   normals       [n_nodes][dim][dim]: the first nwall[p] rows are the unit
+ *                 wall normals of node p (Appendix B symmetry/wall BC), or
+ *                 NULL when nwall is NULL
+ * Builds the node->corner lists (cells ascending, then local node order).
+ * Replaces any previous mesh and discards the state.  n_cells may be 0. */
+hl_status hl_mesh_upload(hl_ctx *ctx, int dim, int64_t n_nodes, const double *x0,
+                         int64_t n_cells, const int32_t *cells, const uint8_t *nwall,
+                         const double *normals, int on_device);
+
+/* Initial state (Section 4 preamble): tau = 1/rho0, B = I, v_c = v_cell,
+ * e = |v_c|^2 / 2, m_c = rho0 V_c, carried node velocity = v_node projected
+ * on the directions its walls allow.  Material per cell: rho0, shear
+ * modulus mu and Lame lambda (the volumetric energy uses the bulk modulus
+ * K = lambda + 2 mu / 3).  p may be NULL for the paper defaults with the
+ * 2D/3D CFL number. */
+hl_status hl_state_init(hl_ctx *ctx, const double *rho0, const double *mu, const double *lam,
+                        const double *v_cell, const double *v_node, const hl_params *p,
+                        int on_device);
+
+/* Replace the parameters used by the following steps. */
+hl_status hl_set_params(hl_ctx *ctx, const hl_params *p);
+
+/* Acoustic time step C_CFL min_c L_c / a_c of the current state (eq. CFL2
+ * at the first step).  It also becomes the dt used by hl_step(ctx, 0). */
+hl_status hl_compute_dt(hl_ctx *ctx, double *dt_out);
+
+/* One ADER-MOOD step (Section 3.7): unlimited second-order candidate,
+ * detection, first-order recompute of troubled cells until no new cell is
+ * flagged, then the CFL reduction for the next dt.  dt > 0 is used as is;
+ * dt <= 0 uses the dt computed on the device by the previous step (or by
+ * hl_compute_dt), with no host round trip.  Returns
+ * HL_WARN_PARACHUTE_INADMISSIBLE (with the step applied) if a first-order
+ * cell is not physically admissible. */
+hl_status hl_step(hl_ctx *ctx, double dt, hl_step_info *info_or_null);
+
+/* One step with a frozen cascade choice: mask[c] = 1 advances cell c at
+ * first order, 0 at second order; no detection.  mask: [n_cells] uint8. */
+hl_status hl_step_replay(hl_ctx *ctx, double dt, const uint8_t *mask, int on_device,
+                         hl_step_info *info_or_null);
+
+/* Copy a field of the current state to `out` (count = number of elements
+ * of the field's type, checked). */
+hl_status hl_query(hl_ctx *ctx, int field, void *out, int64_t count, int on_device);
+
+/* Overwrite a state field (HL_X, HL_VHAT, HL_TAU, HL_V, HL_E, HL_B). */
+hl_status hl_upload_field(hl_ctx *ctx, int field, const void *in, int64_t count, int on_device);
+
+/* Average duration in milliseconds of the kernel named `name` over the
+ * steps taken since the last hl_profile_reset (timed with HIP events on the
+ * context's stream when profiling is on).  Names: "node_agg", "predict",
+ * "node_solve", "update", "reduce".  *launches receives the launch count. */
+hl_status hl_profile_enable(hl_ctx *ctx, int on);
+hl_status hl_profile_reset(hl_ctx *ctx);
+hl_status hl_profile_get(hl_ctx *ctx, const char *name, double *avg_ms, int64_t *launches);
+
+const char *hl_status_str(hl_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYPERLAG_H */

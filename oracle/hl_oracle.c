@@ -475,8 +475,8 @@ static void cell_W(const orc_mesh *M, const double *tau, const double *v, const 
 
 /* grad[c][w][j] = d W_w / d x_j from an unweighted least-squares fit over
  * all cells sharing a node with c, each visited once per shared node.  A
- * stencil whose normal matrix is singular (det A <= 1e-12 (tr A / d)^d)
- * gives a zero gradient. */
+ * stencil with fewer than d visits, or whose normal matrix is singular
+ * (det A <= 1e-12 (tr A / d)^d), gives a zero gradient. */
 static void lsq_gradients(const orc_mesh *M, const double *xc, const double *tau, const double *v,
                           const double *B, double *grad) {
     int d = M->dim, nW = M->nW, nv = M->nv;
@@ -484,12 +484,14 @@ static void lsq_gradients(const orc_mesh *M, const double *xc, const double *tau
         double A[3][3] = {{0}};
         double b[10][3] = {{0}};
         double Wc[10], Wk[10];
+        int visits = 0;
         cell_W(M, tau, v, B, c, Wc);
         for (int k = 0; k < nv; ++k) {
             int64_t p = M->c2n[c * nv + k];
             for (int64_t q = M->n2c_off[p]; q < M->n2c_off[p + 1]; ++q) {
                 int64_t j = M->n2c[q] / nv;
                 if (j == c) continue;
+                ++visits;
                 double dx[3] = {0, 0, 0};
                 for (int i = 0; i < d; ++i) dx[i] = xc[j * 3 + i] - xc[c * 3 + i];
                 cell_W(M, tau, v, B, j, Wk);
@@ -508,7 +510,7 @@ static void lsq_gradients(const orc_mesh *M, const double *xc, const double *tau
         double scale = pow(trA / d, d);
         double *g = grad + c * nW * 3;
         memset(g, 0, sizeof(double) * nW * 3);
-        if (!(trA > 0.0) || !(detA > 1e-12 * scale)) continue;
+        if (visits < d || !(trA > 0.0) || !(detA > 1e-12 * scale)) continue;
         for (int w = 0; w < nW; ++w) {
             double Am[9], rhs[3];
             for (int a = 0; a < d; ++a) {

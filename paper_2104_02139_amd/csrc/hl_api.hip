@@ -1,0 +1,801 @@
+// hl_api.hip -- host side of libhyperlag: the C-ABI declared in
+// include/hyperlag.h (context, mesh upload, state init, step, MOOD loop,
+// queries, kernel timing).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hl_device.h"
+#include "hl_kernels.h"
+#include "hyperlag.h"
+
+namespace {
+
+enum { PK_CENTROIDS = 0, PK_NODE_AGG, PK_PREDICT, PK_NODE_SOLVE, PK_UPDATE, PK_REDUCE, PK_COUNT };
+const char *kProfNames[PK_COUNT] = {"centroids", "node_agg", "predict", "node_solve", "update", "reduce"};
+
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<int> pending_kind;  // kernel kind of pending pair i
+    size_t used = 0;                // pairs in use
+    double total_ms[PK_COUNT] = {};
+    int64_t count[PK_COUNT] = {};
+};
+
+}  // namespace
+
+struct hl_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int dim = 0;
+    int64_t nn = 0, nc = 0;
+    int n_mesh = 1;
+    // mesh
+    int32_t *c2n = nullptr, *n2c_off = nullptr, *n2c = nullptr;
+    uint8_t *nallow = nullptr;
+    double *allow = nullptr;
+    std::vector<double> x0_host;
+    std::vector<int32_t> c2n_host;
+    // material
+    double *mass = nullptr, *rho0 = nullptr, *mu = nullptr, *K = nullptr;
+    // state, double buffered
+    double *x[2] = {}, *vhat[2] = {}, *tau[2] = {}, *v[2] = {}, *e[2] = {}, *B[2] = {};
+    int cur = 0;
+    // work
+    double *vstar = nullptr, *xc = nullptr, *agg = nullptr, *corner = nullptr, *dtc = nullptr;
+    uint8_t *mask = nullptr, *flag = nullptr;
+    unsigned *counters = nullptr;
+    unsigned *counters_host = nullptr;
+    double *dt_cur = nullptr, *dt_next = nullptr, *dt_red = nullptr, *dt_parts = nullptr;
+    double *diag_part = nullptr, *diag_out = nullptr;
+    double *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    bool have_mesh = false, have_state = false;
+    hl_params prm{};
+    std::vector<void *> allocs;
+    Prof prof;
+};
+
+namespace {
+
+#define HIPCHK(call)                                  \
+    do {                                              \
+        hipError_t _e = (call);                       \
+        if (_e != hipSuccess) return HL_E_HIP;        \
+    } while (0)
+
+hl_params default_params(int dim) {
+    hl_params p;
+    p.c_cfl = dim == 2 ? 0.4 : 0.25;
+    p.c_v = 0.2;
+    p.c_i = 0.1;
+    p.delta0 = 1e-4;
+    p.delta1 = 1e-3;
+    p.eps_tol = 1e-12;
+    p.detect = 1;
+    p.reserved = 0;
+    return p;
+}
+
+bool params_valid(const hl_params &p) {
+    return p.c_cfl > 0 && p.c_v > 0 && p.c_i >= 0 && p.delta0 >= 0 && p.delta1 >= 0 && p.eps_tol >= 0;
+}
+
+void free_all(hl_ctx *c) {
+    for (void *p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    if (c->counters_host) (void)hipHostFree(c->counters_host);
+    c->counters_host = nullptr;
+    c->c2n = c->n2c_off = c->n2c = nullptr;
+    c->nallow = nullptr;
+    c->allow = c->mass = c->rho0 = c->mu = c->K = nullptr;
+    for (int b = 0; b < 2; ++b) c->x[b] = c->vhat[b] = c->tau[b] = c->v[b] = c->e[b] = c->B[b] = nullptr;
+    c->vstar = c->xc = c->agg = c->corner = c->dtc = nullptr;
+    c->mask = c->flag = nullptr;
+    c->counters = nullptr;
+    c->dt_cur = c->dt_next = c->dt_red = c->dt_parts = c->diag_part = c->diag_out = c->scratch = nullptr;
+    c->have_mesh = c->have_state = false;
+}
+
+template <class T>
+hl_status dalloc(hl_ctx *c, T **p, size_t n) {
+    void *q = nullptr;
+    size_t bytes = std::max<size_t>(n * sizeof(T), 256);
+    if (hipMalloc(&q, bytes) != hipSuccess) return HL_E_OOM;
+    c->allocs.push_back(q);
+    *p = reinterpret_cast<T *>(q);
+    return HL_OK;
+}
+
+// bring a borrowed input array to the host
+template <class T>
+hl_status to_host(const T *src, size_t n, int on_device, std::vector<T> &dst) {
+    dst.resize(n);
+    if (n == 0) return HL_OK;
+    if (!src) return HL_E_INVALID;
+    if (on_device) {
+        if (hipMemcpy(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost) != hipSuccess) return HL_E_HIP;
+    } else {
+        std::memcpy(dst.data(), src, n * sizeof(T));
+    }
+    return HL_OK;
+}
+
+// signed simplex measure with the same edge formulas as the device code
+double host_volume(int d, const double *X /* (d+1) x d */) {
+    if (d == 3) {
+        double e1[3], e2[3], e3[3];
+        for (int i = 0; i < 3; ++i) {
+            e1[i] = X[3 + i] - X[i];
+            e2[i] = X[6 + i] - X[i];
+            e3[i] = X[9 + i] - X[i];
+        }
+        const double s = 1.0 / 6.0;
+        double c0 = s * (e2[1] * e3[2] - e2[2] * e3[1]);
+        double c1 = s * (e2[2] * e3[0] - e2[0] * e3[2]);
+        double c2 = s * (e2[0] * e3[1] - e2[1] * e3[0]);
+        return e1[0] * c0 + e1[1] * c1 + e1[2] * c2;
+    }
+    double e1x = X[2] - X[0], e1y = X[3] - X[1];
+    double e2x = X[4] - X[0], e2y = X[5] - X[1];
+    return e1x * (0.5 * e2y) + e1y * (-0.5 * e2x);
+}
+
+// Orthonormal basis of the directions a node with `nw` unit wall normals
+// may move in (slip walls, Appendix B).  Returns the number of columns;
+// P[i*d + t] is component i of column t.
+int wall_basis(int d, int nw, const double *nrm, double *P) {
+    for (int i = 0; i < d * d; ++i) P[i] = 0.0;
+    // orthonormalise the normals
+    double Q[3][3];
+    int nq = 0;
+    for (int r = 0; r < nw && r < d; ++r) {
+        double w[3] = {0, 0, 0};
+        for (int i = 0; i < d; ++i) w[i] = nrm[r * d + i];
+        for (int q = 0; q < nq; ++q) {
+            double s = 0;
+            for (int i = 0; i < 3; ++i) s += w[i] * Q[q][i];
+            for (int i = 0; i < 3; ++i) w[i] -= s * Q[q][i];
+        }
+        double n = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        if (n < 1e-8) continue;
+        for (int i = 0; i < 3; ++i) Q[nq][i] = w[i] / n;
+        ++nq;
+    }
+    if (nq == 0) {
+        for (int i = 0; i < d; ++i) P[i * d + i] = 1.0;
+        return d;
+    }
+    if (nq >= d) return 0;
+    if (d == 2) {  // tangent of the one wall
+        P[0 * 2 + 0] = -Q[0][1];
+        P[1 * 2 + 0] = Q[0][0];
+        return 1;
+    }
+    if (nq == 2) {  // 3D: line along n1 x n2
+        double t[3] = {Q[0][1] * Q[1][2] - Q[0][2] * Q[1][1], Q[0][2] * Q[1][0] - Q[0][0] * Q[1][2],
+                       Q[0][0] * Q[1][1] - Q[0][1] * Q[1][0]};
+        double n = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+        for (int i = 0; i < 3; ++i) P[i * 3 + 0] = t[i] / n;
+        return 1;
+    }
+    // 3D, one wall: t1 = n x a (a = axis least aligned with n), t2 = n x t1
+    const double *n = Q[0];
+    int ax = 0;
+    for (int i = 1; i < 3; ++i)
+        if (std::fabs(n[i]) < std::fabs(n[ax])) ax = i;
+    double a[3] = {0, 0, 0};
+    a[ax] = 1.0;
+    double t1[3] = {n[1] * a[2] - n[2] * a[1], n[2] * a[0] - n[0] * a[2], n[0] * a[1] - n[1] * a[0]};
+    double l = std::sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+    for (int i = 0; i < 3; ++i) t1[i] /= l;
+    double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+    for (int i = 0; i < 3; ++i) {
+        P[i * 3 + 0] = t1[i];
+        P[i * 3 + 1] = t2[i];
+    }
+    return 2;
+}
+
+hl::StepArgs make_args(hl_ctx *c, int src) {
+    hl::StepArgs a{};
+    int dst = 1 - src;
+    a.nc = c->nc;
+    a.nn = c->nn;
+    a.c2n = c->c2n;
+    a.n2c_off = c->n2c_off;
+    a.n2c = c->n2c;
+    a.nallow = c->nallow;
+    a.allow = c->allow;
+    a.mass = c->mass;
+    a.rho0 = c->rho0;
+    a.mu = c->mu;
+    a.K = c->K;
+    a.cell_mesh = nullptr;
+    a.node_mesh = nullptr;
+    a.dt = c->dt_cur;
+    a.x = c->x[src];
+    a.vhat = c->vhat[src];
+    a.tau = c->tau[src];
+    a.v = c->v[src];
+    a.e = c->e[src];
+    a.B = c->B[src];
+    a.x1 = c->x[dst];
+    a.vhat1 = c->vhat[dst];
+    a.tau1 = c->tau[dst];
+    a.v1 = c->v[dst];
+    a.e1 = c->e[dst];
+    a.B1 = c->B[dst];
+    a.vstar = c->vstar;
+    a.xc = c->xc;
+    a.agg = c->agg;
+    a.corner = c->corner;
+    a.dtc = c->dtc;
+    a.mask = c->mask;
+    a.flag = c->flag;
+    a.counters = c->counters;
+    a.delta0 = c->prm.delta0;
+    a.delta1 = c->prm.delta1;
+    a.eps_tol = c->prm.eps_tol;
+    a.detect = c->prm.detect;
+    return a;
+}
+
+// ------------------------------------------------------------ profiling
+void prof_begin(hl_ctx *c, int kind, size_t *slot) {
+    if (!c->prof.on) return;
+    Prof &P = c->prof;
+    if (2 * (P.used + 1) > P.pool.size()) {
+        size_t grow = std::max<size_t>(256, P.pool.size());
+        for (size_t i = 0; i < grow; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            P.pool.push_back(e);
+        }
+    }
+    *slot = P.used++;
+    P.pending_kind.resize(P.used);
+    P.pending_kind[*slot] = kind;
+    (void)hipEventRecord(P.pool[2 * *slot], c->stream);
+}
+
+void prof_end(hl_ctx *c, size_t slot) {
+    if (!c->prof.on) return;
+    (void)hipEventRecord(c->prof.pool[2 * slot + 1], c->stream);
+}
+
+void prof_collect(hl_ctx *c) {
+    Prof &P = c->prof;
+    if (P.used == 0) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (size_t i = 0; i < P.used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, P.pool[2 * i], P.pool[2 * i + 1]) == hipSuccess) {
+            P.total_ms[P.pending_kind[i]] += ms;
+            P.count[P.pending_kind[i]] += 1;
+        }
+    }
+    P.used = 0;
+}
+
+#define PROF(c, kind, stmt)          \
+    do {                             \
+        size_t _slot = 0;            \
+        prof_begin((c), (kind), &_slot); \
+        stmt;                        \
+        prof_end((c), _slot);        \
+    } while (0)
+
+template <int D>
+hl_status run_step(hl_ctx *c, const uint8_t *replay_mask, int mask_on_device, hl_step_info *info) {
+    hipStream_t s = c->stream;
+    const int src = c->cur;
+    hl::StepArgs a = make_args(c, src);
+    // start from a clean mask (or the frozen one)
+    if (replay_mask) {
+        if (c->nc) {
+            HIPCHK(hipMemcpyAsync(c->mask, replay_mask, (size_t)c->nc,
+                                  mask_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        }
+        a.detect = 0;
+    } else if (c->nc) {
+        HIPCHK(hipMemsetAsync(c->mask, 0, (size_t)c->nc, s));
+    }
+    if (c->nc == 0) {
+        // nothing moves: copy the node state through
+        for (int i = 0; i < 1; ++i) {
+            HIPCHK(hipMemcpyAsync(c->x[1 - src], c->x[src], sizeof(double) * c->nn * D, hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync(c->vhat[1 - src], c->vhat[src], sizeof(double) * c->nn * D, hipMemcpyDeviceToDevice, s));
+        }
+        if (c->nn) HIPCHK(hipMemsetAsync(c->vstar, 0, sizeof(double) * c->nn * D, s));
+        HIPCHK(hipStreamSynchronize(s));
+        c->cur = 1 - src;
+        if (info) std::memset(info, 0, sizeof(*info));
+        return HL_OK;
+    }
+    PROF(c, PK_CENTROIDS, hl::launch_centroids<D>(a, s));
+    PROF(c, PK_NODE_AGG, hl::launch_node_agg<D>(a, s));
+    int iters = 0;
+    int64_t first = -1;
+    unsigned inadm = 0;
+    for (;;) {
+        HIPCHK(hipMemsetAsync(c->counters, 0, 2 * sizeof(unsigned), s));
+        PROF(c, PK_PREDICT, hl::launch_predict<D>(a, s));
+        PROF(c, PK_NODE_SOLVE, hl::launch_node_solve<D>(a, s));
+        PROF(c, PK_UPDATE, hl::launch_update<D>(a, s));
+        ++iters;
+        if (!a.detect) {
+            HIPCHK(hipMemcpyAsync(c->counters_host, c->counters, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            inadm = c->counters_host[1];
+            break;
+        }
+        HIPCHK(hipMemcpyAsync(c->counters_host, c->counters, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        unsigned nflag = c->counters_host[0];
+        inadm = c->counters_host[1];
+        if (first < 0) first = nflag;
+        if (nflag == 0) break;
+        hl::launch_apply_flags(c->nc, c->mask, c->flag, s);
+    }
+    PROF(c, PK_REDUCE, {
+        hl::launch_dt_reduce(c->nc, c->dtc, nullptr, c->dt_red, c->n_mesh, s);
+        hl::launch_dt_finalize(c->n_mesh, c->dt_red, c->dt_cur, c->prm, 0, c->dt_next, c->dt_parts, s);
+    });
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        const int dst = 1 - src;
+        hl::launch_diag<D>(a, c->tau[dst], c->v[dst], c->e[dst], c->B[dst], c->diag_part, c->diag_out, s);
+        double d[8], dts[4];
+        HIPCHK(hipMemcpyAsync(d, c->diag_out, sizeof d, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&dts[0], c->dt_cur, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&dts[1], c->dt_next, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&dts[2], c->dt_parts, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        info->dt_used = dts[0];
+        info->dt_next = dts[1];
+        info->dt_acoustic = dts[2];
+        info->dt_volume = dts[3];
+        info->mass = d[0];
+        info->mom[0] = d[1];
+        info->mom[1] = d[2];
+        info->mom[2] = d[3];
+        info->energy = d[4];
+        info->kinetic = d[5];
+        info->elastic = d[6];
+        info->n_p0 = (int64_t)llround(d[7]);
+        info->n_flag_first = first < 0 ? 0 : first;
+        info->mood_iters = iters;
+        info->status = inadm ? 1 : 0;
+    }
+    c->cur = 1 - src;
+    return inadm ? HL_WARN_PARACHUTE_INADMISSIBLE : HL_OK;
+}
+
+int field_width(const hl_ctx *c, int field, bool *node, bool *is_u8) {
+    *node = false;
+    *is_u8 = false;
+    const int d = c->dim;
+    switch (field) {
+        case HL_X:
+        case HL_VHAT:
+        case HL_VSTAR:
+            *node = true;
+            return d;
+        case HL_TAU:
+        case HL_E:
+        case HL_MASS:
+            return 1;
+        case HL_V:
+            return d;
+        case HL_B:
+            return d == 3 ? 6 : 3;
+        case HL_ORDER:
+            *is_u8 = true;
+            return 1;
+        case HL_T:
+            return d == 3 ? 6 : 4;
+        default:
+            return -1;
+    }
+}
+
+double *field_ptr(hl_ctx *c, int field) {
+    const int b = c->cur;
+    switch (field) {
+        case HL_X: return c->x[b];
+        case HL_VHAT: return c->vhat[b];
+        case HL_VSTAR: return c->vstar;
+        case HL_TAU: return c->tau[b];
+        case HL_E: return c->e[b];
+        case HL_MASS: return c->mass;
+        case HL_V: return c->v[b];
+        case HL_B: return c->B[b];
+        default: return nullptr;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hl_status_str(hl_status s) {
+    switch (s) {
+        case HL_OK: return "ok";
+        case HL_WARN_PARACHUTE_INADMISSIBLE: return "a first-order (parachute) cell is not admissible";
+        case HL_E_INVALID: return "invalid argument";
+        case HL_E_DEGENERATE_CELL: return "cell with non-positive volume";
+        case HL_E_OOM: return "device allocation failed";
+        case HL_E_HIP: return "HIP runtime error";
+        case HL_E_STATE: return "call out of order (mesh or state missing)";
+        default: return "unknown status";
+    }
+}
+
+hl_status hl_create(hl_ctx **out, int device, void *hip_stream) {
+    if (!out) return HL_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return HL_E_HIP;
+    if (device < 0 || device >= n) return HL_E_INVALID;
+    if (hipSetDevice(device) != hipSuccess) return HL_E_HIP;
+    hl_ctx *c = new hl_ctx();
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return HL_OK;
+}
+
+hl_status hl_destroy(hl_ctx *c) {
+    if (!c) return HL_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+    free_all(c);
+    delete c;
+    return HL_OK;
+}
+
+hl_status hl_mesh_upload(hl_ctx *c, int dim, int64_t n_nodes, const double *x0, int64_t n_cells,
+                         const int32_t *cells, const uint8_t *nwall, const double *normals, int on_device) {
+    if (!c || (dim != 2 && dim != 3) || n_nodes < 0 || n_cells < 0) return HL_E_INVALID;
+    if (n_cells * (dim + 1) >= (int64_t)INT32_MAX) return HL_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    const int nv = dim + 1;
+    std::vector<double> xh, nrm;
+    std::vector<int32_t> ch;
+    std::vector<uint8_t> nw;
+    hl_status st;
+    if ((st = to_host(x0, (size_t)(n_nodes * dim), on_device, xh)) != HL_OK) return st;
+    if ((st = to_host(cells, (size_t)(n_cells * nv), on_device, ch)) != HL_OK) return st;
+    if (nwall) {
+        if ((st = to_host(nwall, (size_t)n_nodes, on_device, nw)) != HL_OK) return st;
+        if (!normals) return HL_E_INVALID;
+        if ((st = to_host(normals, (size_t)(n_nodes * dim * dim), on_device, nrm)) != HL_OK) return st;
+    } else {
+        nw.assign((size_t)n_nodes, 0);
+        nrm.assign((size_t)(n_nodes * dim * dim), 0.0);
+    }
+    for (int64_t q = 0; q < n_cells * nv; ++q)
+        if (ch[q] < 0 || ch[q] >= n_nodes) return HL_E_INVALID;
+    for (int64_t p = 0; p < n_nodes; ++p)
+        if (nw[p] > dim) return HL_E_INVALID;
+    for (double v : xh)
+        if (!std::isfinite(v)) return HL_E_INVALID;
+    // positive orientation of every cell
+    for (int64_t cc = 0; cc < n_cells; ++cc) {
+        double X[12];
+        for (int k = 0; k < nv; ++k)
+            for (int i = 0; i < dim; ++i) X[k * dim + i] = xh[(size_t)ch[cc * nv + k] * dim + i];
+        if (!(host_volume(dim, X) > 0.0)) return HL_E_DEGENERATE_CELL;
+    }
+    // node -> corner lists in (cell, local node) order
+    std::vector<int32_t> off((size_t)n_nodes + 1, 0), lst((size_t)(n_cells * nv));
+    for (int64_t q = 0; q < n_cells * nv; ++q) off[(size_t)ch[q] + 1]++;
+    for (int64_t p = 0; p < n_nodes; ++p) off[p + 1] += off[p];
+    {
+        std::vector<int32_t> fill(off.begin(), off.end() - 1);
+        for (int64_t q = 0; q < n_cells * nv; ++q) lst[fill[ch[q]]++] = (int32_t)q;
+    }
+    std::vector<uint8_t> nal((size_t)n_nodes);
+    std::vector<double> alw((size_t)(n_nodes * dim * dim));
+    for (int64_t p = 0; p < n_nodes; ++p)
+        nal[p] = (uint8_t)wall_basis(dim, nw[p], nrm.data() + p * dim * dim, alw.data() + p * dim * dim);
+
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    c->dim = dim;
+    c->nn = n_nodes;
+    c->nc = n_cells;
+    c->n_mesh = 1;
+    const size_t nn = (size_t)n_nodes, ncl = (size_t)n_cells, ncor = ncl * nv;
+    const int NA = dim == 3 ? hl::Dims<3>::NA : hl::Dims<2>::NA;
+    const int CW = dim == 3 ? hl::Dims<3>::CW : hl::Dims<2>::CW;
+    const int nB = dim == 3 ? 6 : 3;
+#define A_(p, n)                                  \
+    do {                                          \
+        if ((st = dalloc(c, &(p), (n))) != HL_OK) { \
+            free_all(c);                          \
+            return st;                            \
+        }                                         \
+    } while (0)
+    A_(c->c2n, ncor);
+    A_(c->n2c_off, nn + 1);
+    A_(c->n2c, ncor);
+    A_(c->nallow, nn);
+    A_(c->allow, nn * dim * dim);
+    A_(c->mass, ncl);
+    A_(c->rho0, ncl);
+    A_(c->mu, ncl);
+    A_(c->K, ncl);
+    for (int b = 0; b < 2; ++b) {
+        A_(c->x[b], nn * dim);
+        A_(c->vhat[b], nn * dim);
+        A_(c->tau[b], ncl);
+        A_(c->v[b], ncl * dim);
+        A_(c->e[b], ncl);
+        A_(c->B[b], ncl * nB);
+    }
+    A_(c->vstar, nn * dim);
+    A_(c->xc, ncl * dim);
+    A_(c->agg, nn * NA);
+    A_(c->corner, ncor * CW);
+    A_(c->dtc, 2 * ncl);
+    A_(c->mask, ncl);
+    A_(c->flag, ncl);
+    A_(c->counters, 4);
+    A_(c->dt_cur, 16);
+    A_(c->dt_next, 16);
+    A_(c->dt_red, 32);
+    A_(c->dt_parts, 32);
+    A_(c->diag_part, 8 * (ncl / 256 + 2));
+    A_(c->diag_out, 16);
+    c->scratch_bytes = std::max<size_t>(sizeof(double) * std::max(nn * dim, ncl * 6), 256);
+    A_(c->scratch, c->scratch_bytes / sizeof(double));
+#undef A_
+    if (hipHostMalloc((void **)&c->counters_host, 4 * sizeof(unsigned), hipHostMallocDefault) != hipSuccess) {
+        free_all(c);
+        return HL_E_OOM;
+    }
+    hipStream_t s = c->stream;
+    HIPCHK(hipMemcpyAsync(c->c2n, ch.data(), sizeof(int32_t) * ncor, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->n2c_off, off.data(), sizeof(int32_t) * (nn + 1), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->n2c, lst.data(), sizeof(int32_t) * ncor, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->nallow, nal.data(), nn, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->allow, alw.data(), sizeof(double) * nn * dim * dim, hipMemcpyHostToDevice, s));
+    // positions AoS -> SoA on the host
+    std::vector<double> xs(nn * dim);
+    for (size_t p = 0; p < nn; ++p)
+        for (int i = 0; i < dim; ++i) xs[i * nn + p] = xh[p * dim + i];
+    HIPCHK(hipMemcpyAsync(c->x[0], xs.data(), sizeof(double) * nn * dim, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->x0_host.swap(xh);
+    c->c2n_host.swap(ch);
+    c->cur = 0;
+    c->prm = default_params(dim);
+    c->have_mesh = true;
+    c->have_state = false;
+    return HL_OK;
+}
+
+hl_status hl_set_params(hl_ctx *c, const hl_params *p) {
+    if (!c || !p || !params_valid(*p)) return HL_E_INVALID;
+    c->prm = *p;
+    return HL_OK;
+}
+
+hl_status hl_state_init(hl_ctx *c, const double *rho0, const double *mu, const double *lam, const double *v_cell,
+                        const double *v_node, const hl_params *p, int on_device) {
+    if (!c) return HL_E_INVALID;
+    if (!c->have_mesh) return HL_E_STATE;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    const int d = c->dim, nv = d + 1, nB = d == 3 ? 6 : 3;
+    const size_t nc = (size_t)c->nc, nn = (size_t)c->nn;
+    std::vector<double> r, m_, l, vc, vn;
+    hl_status st;
+    if ((st = to_host(rho0, nc, on_device, r)) != HL_OK) return st;
+    if ((st = to_host(mu, nc, on_device, m_)) != HL_OK) return st;
+    if ((st = to_host(lam, nc, on_device, l)) != HL_OK) return st;
+    if ((st = to_host(v_cell, nc * d, on_device, vc)) != HL_OK) return st;
+    if ((st = to_host(v_node, nn * d, on_device, vn)) != HL_OK) return st;
+    for (size_t i = 0; i < nc; ++i)
+        if (!(r[i] > 0) || !(m_[i] >= 0) || !std::isfinite(l[i])) return HL_E_INVALID;
+    hl_params prm = p ? *p : default_params(d);
+    if (!params_valid(prm)) return HL_E_INVALID;
+
+    std::vector<double> mass(nc), K(nc), tau(nc), e(nc), vs(nc * d), Bs(nc * nB, 0.0), vh(nn * d);
+    for (size_t cc = 0; cc < nc; ++cc) {
+        double X[12];
+        for (int k = 0; k < nv; ++k)
+            for (int i = 0; i < d; ++i) X[k * d + i] = c->x0_host[(size_t)c->c2n_host[cc * nv + k] * d + i];
+        mass[cc] = r[cc] * host_volume(d, X);
+        K[cc] = l[cc] + 2.0 * m_[cc] / 3.0;
+        tau[cc] = 1.0 / r[cc];
+        double k2 = 0.0;
+        for (int i = 0; i < d; ++i) {
+            vs[i * nc + cc] = vc[cc * d + i];
+            k2 += vc[cc * d + i] * vc[cc * d + i];
+        }
+        e[cc] = 0.5 * k2;
+        for (int s = 0; s < d; ++s) Bs[s * nc + cc] = 1.0;  // diagonal comps first
+    }
+    // carried node velocity projected on the allowed directions
+    std::vector<uint8_t> nal(nn);
+    std::vector<double> alw(nn * d * d);
+    if (nn) {
+        HIPCHK(hipMemcpy(nal.data(), c->nallow, nn, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(alw.data(), c->allow, sizeof(double) * nn * d * d, hipMemcpyDeviceToHost));
+    }
+    for (size_t pp = 0; pp < nn; ++pp) {
+        const double *P = alw.data() + pp * d * d;
+        double o[3] = {0, 0, 0};
+        for (int t = 0; t < nal[pp]; ++t) {
+            double s = 0;
+            for (int i = 0; i < d; ++i) s += P[i * d + t] * vn[pp * d + i];
+            for (int i = 0; i < d; ++i) o[i] += s * P[i * d + t];
+        }
+        for (int i = 0; i < d; ++i) vh[i * nn + pp] = o[i];
+    }
+    hipStream_t s = c->stream;
+    // restore positions to the uploaded mesh
+    std::vector<double> xs(nn * d);
+    for (size_t pp = 0; pp < nn; ++pp)
+        for (int i = 0; i < d; ++i) xs[i * nn + pp] = c->x0_host[pp * d + i];
+    c->cur = 0;
+    HIPCHK(hipMemcpyAsync(c->x[0], xs.data(), sizeof(double) * nn * d, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->mass, mass.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->rho0, r.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->mu, m_.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->K, K.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->tau[0], tau.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->e[0], e.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->v[0], vs.data(), sizeof(double) * nc * d, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->B[0], Bs.data(), sizeof(double) * nc * nB, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->vhat[0], vh.data(), sizeof(double) * nn * d, hipMemcpyHostToDevice, s));
+    if (nc) HIPCHK(hipMemsetAsync(c->mask, 0, nc, s));
+    if (nn) HIPCHK(hipMemsetAsync(c->vstar, 0, sizeof(double) * nn * d, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->prm = prm;
+    c->have_state = true;
+    double dt0;
+    return hl_compute_dt(c, &dt0);
+}
+
+hl_status hl_compute_dt(hl_ctx *c, double *dt_out) {
+    if (!c) return HL_E_INVALID;
+    if (!c->have_state) return HL_E_STATE;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    hipStream_t s = c->stream;
+    hl::StepArgs a = make_args(c, c->cur);
+    a.tau = c->tau[c->cur];
+    if (c->dim == 3)
+        hl::launch_acoustic<3>(a, s);
+    else
+        hl::launch_acoustic<2>(a, s);
+    hl::launch_dt_reduce(c->nc, c->dtc, nullptr, c->dt_red, c->n_mesh, s);
+    hl::launch_dt_finalize(c->n_mesh, c->dt_red, c->dt_cur, c->prm, 1, c->dt_next, c->dt_parts, s);
+    double dt = 0.0;
+    HIPCHK(hipMemcpyAsync(&dt, c->dt_next, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (dt_out) *dt_out = dt;
+    return HL_OK;
+}
+
+static hl_status step_common(hl_ctx *c, double dt, const uint8_t *mask, int on_device, hl_step_info *info) {
+    if (!c) return HL_E_INVALID;
+    if (!c->have_state) return HL_E_STATE;
+    if (!std::isfinite(dt)) return HL_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    hipStream_t s = c->stream;
+    if (dt > 0.0)
+        hl::launch_fill(c->dt_cur, c->n_mesh, dt, s);
+    else
+        HIPCHK(hipMemcpyAsync(c->dt_cur, c->dt_next, sizeof(double) * c->n_mesh, hipMemcpyDeviceToDevice, s));
+    hl_status st = c->dim == 3 ? run_step<3>(c, mask, on_device, info) : run_step<2>(c, mask, on_device, info);
+    if (c->prof.on) prof_collect(c);
+    if (hipGetLastError() != hipSuccess) return HL_E_HIP;
+    return st;
+}
+
+hl_status hl_step(hl_ctx *c, double dt, hl_step_info *info) { return step_common(c, dt, nullptr, 0, info); }
+
+hl_status hl_step_replay(hl_ctx *c, double dt, const uint8_t *mask, int on_device, hl_step_info *info) {
+    if (!mask && c && c->nc) return HL_E_INVALID;
+    return step_common(c, dt, mask, on_device, info);
+}
+
+hl_status hl_query(hl_ctx *c, int field, void *out, int64_t count, int on_device) {
+    if (!c || !out) return HL_E_INVALID;
+    if (!c->have_state) return HL_E_STATE;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    bool node, u8;
+    int w = field_width(c, field, &node, &u8);
+    if (w < 0) return HL_E_INVALID;
+    const int64_t n = node ? c->nn : c->nc;
+    if (count != n * w) return HL_E_INVALID;
+    hipStream_t s = c->stream;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (n == 0) return HL_OK;
+    if (u8) {
+        HIPCHK(hipMemcpyAsync(out, c->mask, (size_t)n, k, s));
+    } else if (field == HL_T) {
+        hl::StepArgs a = make_args(c, c->cur);
+        if (c->dim == 3)
+            hl::launch_stress_query<3>(a, c->scratch, s);
+        else
+            hl::launch_stress_query<2>(a, c->scratch, s);
+        HIPCHK(hipMemcpyAsync(out, c->scratch, sizeof(double) * n * w, k, s));
+    } else {
+        double *src = field_ptr(c, field);
+        if (w == 1) {
+            HIPCHK(hipMemcpyAsync(out, src, sizeof(double) * n, k, s));
+        } else {
+            hl::launch_soa_to_aos(n, w, src, c->scratch, s);
+            HIPCHK(hipMemcpyAsync(out, c->scratch, sizeof(double) * n * w, k, s));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return HL_OK;
+}
+
+hl_status hl_upload_field(hl_ctx *c, int field, const void *in, int64_t count, int on_device) {
+    if (!c || !in) return HL_E_INVALID;
+    if (!c->have_state) return HL_E_STATE;
+    if (field != HL_X && field != HL_VHAT && field != HL_TAU && field != HL_V && field != HL_E && field != HL_B)
+        return HL_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    bool node, u8;
+    int w = field_width(c, field, &node, &u8);
+    const int64_t n = node ? c->nn : c->nc;
+    if (count != n * w) return HL_E_INVALID;
+    if (n == 0) return HL_OK;
+    hipStream_t s = c->stream;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    double *dst = field_ptr(c, field);
+    if (w == 1) {
+        HIPCHK(hipMemcpyAsync(dst, in, sizeof(double) * n, k, s));
+    } else {
+        HIPCHK(hipMemcpyAsync(c->scratch, in, sizeof(double) * n * w, k, s));
+        hl::launch_aos_to_soa(n, w, c->scratch, dst, s);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return HL_OK;
+}
+
+hl_status hl_profile_enable(hl_ctx *c, int on) {
+    if (!c) return HL_E_INVALID;
+    if (!on && c->prof.on) prof_collect(c);
+    c->prof.on = on != 0;
+    return HL_OK;
+}
+
+hl_status hl_profile_reset(hl_ctx *c) {
+    if (!c) return HL_E_INVALID;
+    prof_collect(c);
+    for (int k = 0; k < PK_COUNT; ++k) {
+        c->prof.total_ms[k] = 0.0;
+        c->prof.count[k] = 0;
+    }
+    return HL_OK;
+}
+
+hl_status hl_profile_get(hl_ctx *c, const char *name, double *avg_ms, int64_t *launches) {
+    if (!c || !name) return HL_E_INVALID;
+    prof_collect(c);
+    for (int k = 0; k < PK_COUNT; ++k) {
+        if (std::strcmp(name, kProfNames[k]) == 0) {
+            if (launches) *launches = c->prof.count[k];
+            if (avg_ms) *avg_ms = c->prof.count[k] ? c->prof.total_ms[k] / (double)c->prof.count[k] : 0.0;
+            return HL_OK;
+        }
+    }
+    return HL_E_INVALID;
+}
+
+}  // extern "C"

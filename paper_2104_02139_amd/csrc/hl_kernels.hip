@@ -1,0 +1,887 @@
+// hl_kernels.hip -- HIP kernels of one cell-centred Lagrangian ADER-MOOD
+// step (Boscheri, Loubere & Maire, arXiv 2104.02139) for gfx950, FP64.
+//
+// Data layout in HBM (structure of arrays unless noted):
+//   x, vhat, vstar : [D][n_nodes]            node vectors
+//   tau, e         : [n_cells]               cell scalars
+//   v              : [D][n_cells]            cell velocity
+//   B              : [NB][n_cells]           left Cauchy-Green, stored comps
+//   c2n            : [n_cells][D+1] int32    cell -> node
+//   n2c_off, n2c   : CSR node -> corner id (corner = c*(D+1) + k), corners of
+//                    a node in ascending cell order
+//   agg            : [n_nodes][NA]           per-node least-squares sums
+//   corner         : [n_cells*(D+1)][CW]     per-corner M_cp (sym DxD) and
+//                    r_cp = M_cp v*_cp - T*_cp C_cp
+// Every sum over a node's corners runs in CSR order and every sum over a
+// cell's nodes in local order, so results do not depend on the launch
+// shape and there are no floating-point atomics (only an integer-coded
+// minimum, which is order independent).
+#include "hl_device.h"
+#include "hl_kernels.h"
+
+namespace hl {
+
+__device__ __forceinline__ int64_t gtid() {
+    return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+}
+
+__device__ __forceinline__ double mesh_dt(const double *dtm, const int32_t *mesh_id, int64_t i) {
+    return dtm[mesh_id ? mesh_id[i] : 0];
+}
+
+// ----------------------------------------------------------- centroids
+template <int D>
+__global__ __launch_bounds__(256) void k_centroids(int64_t nc, int64_t nn, const int32_t *__restrict__ c2n,
+                                                   const double *__restrict__ x, double *__restrict__ xc) {
+    int64_t c = gtid();
+    if (c >= nc) return;
+    double s[D] = {};
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        int64_t p = c2n[c * (D + 1) + k];
+#pragma unroll
+        for (int i = 0; i < D; ++i) s[i] += x[i * nn + p];
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) xc[i * nc + c] = s[i] * (1.0 / (D + 1));
+}
+
+// ------------------------------------------------ node aggregates (R8)
+// For node p and every cell j around it, with y = x_j - x_p (centroid
+// relative to the node): n, sum y, sum y y^T, sum W_j, sum y W_j^T, and the
+// min / max of rho_j = 1 / tau_j.  A cell c then assembles its
+// least-squares normal equations over all cells sharing a node with it
+// (one visit per shared node) from the aggregates of its own nodes.
+template <int D>
+__global__ __launch_bounds__(256) void k_node_agg(int64_t nn, int64_t nc, const int32_t *__restrict__ off,
+                                                  const int32_t *__restrict__ n2c, const double *__restrict__ x,
+                                                  const double *__restrict__ xc, const double *__restrict__ tau,
+                                                  const double *__restrict__ v, const double *__restrict__ B,
+                                                  double *__restrict__ agg) {
+    using Dm = Dims<D>;
+    int64_t p = gtid();
+    if (p >= nn) return;
+    double xp[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) xp[i] = x[i * nn + p];
+    double n = 0.0, Sy[D] = {}, Syy[Dm::NMS] = {}, SW[Dm::NW] = {}, SyW[Dm::NW][D] = {};
+    double rmin = __builtin_huge_val(), rmax = -__builtin_huge_val();
+    const int32_t q0 = off[p], q1 = off[p + 1];
+    for (int32_t q = q0; q < q1; ++q) {
+        const int64_t j = n2c[q] / (D + 1);
+        double y[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) y[i] = xc[i * nc + j] - xp[i];
+        double W[Dm::NW];
+        W[0] = tau[j];
+#pragma unroll
+        for (int i = 0; i < D; ++i) W[1 + i] = v[i * nc + j];
+#pragma unroll
+        for (int s = 0; s < Dm::NB; ++s) W[1 + D + s] = B[s * nc + j];
+        n += 1.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            Sy[i] += y[i];
+#pragma unroll
+            for (int k = i; k < D; ++k) Syy[midx<D>(i, k)] += y[i] * y[k];
+        }
+#pragma unroll
+        for (int w = 0; w < Dm::NW; ++w) {
+            SW[w] += W[w];
+#pragma unroll
+            for (int i = 0; i < D; ++i) SyW[w][i] += y[i] * W[w];
+        }
+        double r = 1.0 / W[0];
+        rmin = fmin(rmin, r);
+        rmax = fmax(rmax, r);
+    }
+    double *o = agg + p * Dm::NA;
+    o[0] = n;
+#pragma unroll
+    for (int i = 0; i < D; ++i) o[Dm::O_SY + i] = Sy[i];
+#pragma unroll
+    for (int s = 0; s < Dm::NMS; ++s) o[Dm::O_SYY + s] = Syy[s];
+#pragma unroll
+    for (int w = 0; w < Dm::NW; ++w) {
+        o[Dm::O_SW + w] = SW[w];
+#pragma unroll
+        for (int i = 0; i < D; ++i) o[Dm::O_SYW + w * D + i] = SyW[w][i];
+    }
+    o[Dm::O_RMM] = rmin;
+    o[Dm::O_RMM + 1] = rmax;
+}
+
+// ---------------------------------------------------------- helpers
+template <int D>
+__device__ __forceinline__ void load_B6(const double *__restrict__ B, int64_t nc, int64_t c, double b[6]) {
+    if (D == 3) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) b[s] = B[s * nc + c];
+    } else {
+        b[0] = B[c];
+        b[1] = B[nc + c];
+        b[2] = 1.0;
+        b[3] = B[2 * nc + c];
+        b[4] = 0.0;
+        b[5] = 0.0;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void store_B6(double *__restrict__ B, int64_t nc, int64_t c, const double b[6]) {
+    if (D == 3) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) B[s * nc + c] = b[s];
+    } else {
+        B[c] = b[0];
+        B[nc + c] = b[1];
+        B[2 * nc + c] = b[3];
+    }
+}
+
+// 6-vector slot of stored B component s (W index 1 + D + s)
+template <int D>
+__device__ __forceinline__ constexpr int bslot(int s) {
+    return D == 3 ? s : (s == 2 ? 3 : s);
+}
+
+// ------------------------------------------ predictor + corner records
+// Reconstruction (R8), ADER midpoint predictor (Section 3.4, reading R7),
+// corner stress and impedance (R5), corner matrix M_cp (eq. Mcp, R4) and
+// r_cp = M_cp v*_cp - T*_cp C_cp (eq. nodal_solver^n).
+template <int D>
+__global__ __launch_bounds__(256) void k_predict(StepArgs a) {
+    using Dm = Dims<D>;
+    constexpr int NV = D + 1;
+    const int64_t c = gtid();
+    if (c >= a.nc) return;
+    const int64_t nc = a.nc, nn = a.nn;
+    int32_t nid[NV];
+    double X[NV][D];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        nid[k] = a.c2n[c * NV + k];
+#pragma unroll
+        for (int i = 0; i < D; ++i) X[k][i] = a.x[i * nn + nid[k]];
+    }
+    Geo<D> g;
+    geom<D>(X, g);
+    double xc[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s += X[k][i];
+        xc[i] = s * (1.0 / NV);
+    }
+    const double tau = a.tau[c];
+    double vc[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) vc[i] = a.v[i * nc + c];
+    double b[6];
+    load_B6<D>(a.B, nc, c, b);
+    const double rho0 = a.rho0[c], mu = a.mu[c], K = a.K[c];
+    const double dt = mesh_dt(a.dt, a.cell_mesh, c);
+    const bool p1 = a.mask[c] == 0;
+
+    // S = sum_j C_j C_j^T / |C_j|; corner shape N_k = S - C_k C_k^T / |C_k|
+    double S[Dm::NMS] = {};
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double r = 1.0 / g.cn[j];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int k = i; k < D; ++k) S[midx<D>(i, k)] += g.C[j][i] * g.C[j][k] * r;
+    }
+
+    double ts[NV], vs[NV][D], bs[NV][6];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        ts[k] = tau;
+#pragma unroll
+        for (int i = 0; i < D; ++i) vs[k][i] = vc[i];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) bs[k][s] = b[s];
+    }
+
+    if (p1) {
+        // ---- least-squares normal equations from the node aggregates
+        double A[Dm::NMS] = {};
+        double rhs[Dm::NW][D] = {};
+        double visits = 0.0;  // neighbour visits: sum over nodes of (n - 1)
+        double Wc[Dm::NW];
+        Wc[0] = tau;
+#pragma unroll
+        for (int i = 0; i < D; ++i) Wc[1 + i] = vc[i];
+#pragma unroll
+        for (int s = 0; s < Dm::NB; ++s) Wc[1 + D + s] = b[bslot<D>(s)];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const double *ag = a.agg + (int64_t)nid[k] * Dm::NA;
+            double u[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) u[i] = xc[i] - X[k][i];
+            const double n = ag[0];
+            visits += n - 1.0;
+            double Sy[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) Sy[i] = ag[Dm::O_SY + i];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = i; j < D; ++j)
+                    A[midx<D>(i, j)] += ag[Dm::O_SYY + midx<D>(i, j)] - u[i] * Sy[j] - Sy[i] * u[j] + n * u[i] * u[j];
+#pragma unroll
+            for (int w = 0; w < Dm::NW; ++w) {
+                const double sw = ag[Dm::O_SW + w];
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    rhs[w][j] += ag[Dm::O_SYW + w * D + j] - u[j] * sw - Sy[j] * Wc[w] + n * u[j] * Wc[w];
+            }
+        }
+        double inv[Dm::NMS];
+        double det, tr = 0.0;
+        if (D == 3)
+            det = sym_inv3(A, inv);
+        else
+            det = sym_inv2(A, inv);
+#pragma unroll
+        for (int i = 0; i < D; ++i) tr += A[midx<D>(i, i)];
+        double scl = tr / D;
+        double scale = D == 3 ? scl * scl * scl : scl * scl;
+        const bool ok = (visits >= D) && (tr > 0.0) && (det > 1e-12 * scale);
+        double grad[Dm::NW][D];
+#pragma unroll
+        for (int w = 0; w < Dm::NW; ++w)
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) s += inv[midx<D>(i, j)] * rhs[w][j];
+                grad[w][i] = ok ? s : 0.0;
+            }
+
+        // ---- time derivatives at the cell centre (reading R7)
+        double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) G[i][j] = grad[1 + i][j];
+        double gB[6][D];  // d b_s / d x_j in 6-vector order
+#pragma unroll
+        for (int s = 0; s < 6; ++s)
+#pragma unroll
+            for (int j = 0; j < D; ++j) gB[s][j] = 0.0;
+#pragma unroll
+        for (int s = 0; s < Dm::NB; ++s)
+#pragma unroll
+            for (int j = 0; j < D; ++j) gB[bslot<D>(s)][j] = grad[1 + D + s][j];
+
+        double trG = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) trG += G[i][i];
+        const double dtau = tau * trG;
+        double B3[3][3] = {{b[0], b[3], b[4]}, {b[3], b[1], b[5]}, {b[4], b[5], b[2]}};
+        double dB[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            const int i = s < 3 ? s : (s == 5 ? 1 : 0);
+            const int j = s < 3 ? s : (s == 3 ? 1 : 2);
+            double y = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) y += G[i][k] * B3[k][j] + B3[i][k] * G[j][k];
+            dB[s] = y;
+        }
+        // div T by the chain rule through T(tau, B)
+        const double J = rho0 * tau;
+        const double lj = log(J);
+        const double cJ = cbrt(J);
+        const double J53 = 1.0 / (J * cJ * cJ);   // J^{-5/3}
+        const double J83 = J53 / J;               // J^{-8/3}
+        const double mdpdJ = 0.5 * K * (1.0 + (1.0 - lj) / (J * J));  // -dp/dJ
+        const double trB3 = (b[0] + b[1] + b[2]) * (1.0 / 3.0);
+        double divT[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const double devB = B3[i][j] - (i == j ? trB3 : 0.0);
+                s1 += devB * grad[0][j];
+                s2 += gB[sidx(i, j)][j];
+            }
+            const double dtr = gB[0][i] + gB[1][i] + gB[2][i];
+            divT[i] = rho0 * (mdpdJ * grad[0][i] - (5.0 / 3.0) * mu * J83 * s1) + mu * J53 * (s2 - dtr * (1.0 / 3.0));
+        }
+        const double h = 0.5 * dt;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double dl[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) dl[i] = X[k][i] - xc[i];
+            double st = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) st += grad[0][j] * dl[j];
+            ts[k] = tau + st + h * dtau;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double sv = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) sv += G[i][j] * dl[j];
+                vs[k][i] = vc[i] + sv + h * tau * divT[i];
+            }
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                if (D == 2 && (s == 2 || s == 4 || s == 5)) continue;
+                double sb = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) sb += gB[s][j] * dl[j];
+                bs[k][s] = b[s] + sb + h * dB[s];
+            }
+        }
+    }
+
+    // ---- corner records
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double T[6];
+        stress6(rho0, mu, K, ts[k], bs[k], T);
+        const double z = sound(rho0, mu, K, ts[k]) / ts[k];
+        const double rk = 1.0 / g.cn[k];
+        double M[Dm::NMS];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = i; j < D; ++j)
+                M[midx<D>(i, j)] = z * (S[midx<D>(i, j)] - g.C[k][i] * g.C[k][j] * rk);
+        double r[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) s += M[midx<D>(i, j)] * vs[k][j] - T[sidx(i, j)] * g.C[k][j];
+            r[i] = s;
+        }
+        double *o = a.corner + (c * NV + k) * Dm::CW;
+#pragma unroll
+        for (int s = 0; s < Dm::NMS; ++s) o[s] = M[s];
+#pragma unroll
+        for (int i = 0; i < D; ++i) o[Dm::NMS + i] = r[i];
+    }
+}
+
+// ---------------------------------------------------------- node solve
+// M_p v*_p = sum_c (M_cp v*_cp - T*_cp C_cp) (eq. nodal_solver^n, readings
+// R14, R15); slip walls by Galerkin projection onto the allowed directions
+// (Appendix B eq. sBC1, reading R22).  Then x^{n+1} = x^n + dt v*_p and
+// vhat^{n+1} = 2 v*_p - vhat^n (Section 3.4, reading R9).
+template <int D>
+__global__ __launch_bounds__(256) void k_node_solve(StepArgs a) {
+    using Dm = Dims<D>;
+    const int64_t p = gtid();
+    if (p >= a.nn) return;
+    const int64_t nn = a.nn;
+    double M[Dm::NMS] = {}, r[D] = {};
+    const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
+    for (int32_t q = q0; q < q1; ++q) {
+        const double *rec = a.corner + (int64_t)a.n2c[q] * Dm::CW;
+#pragma unroll
+        for (int s = 0; s < Dm::NMS; ++s) M[s] += rec[s];
+#pragma unroll
+        for (int i = 0; i < D; ++i) r[i] += rec[Dm::NMS + i];
+    }
+    double vs[D] = {};
+    const int na = a.nallow[p];
+    if (q1 > q0 && na == D) {
+        double inv[Dm::NMS];
+        if (D == 3)
+            sym_inv3(M, inv);
+        else
+            sym_inv2(M, inv);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) s += inv[midx<D>(i, j)] * r[j];
+            vs[i] = s;
+        }
+    } else if (q1 > q0 && na > 0) {
+        // P: D x na orthonormal columns, P[i][t] = allow[p*D*D + i*D + t]
+        const double *P = a.allow + p * D * D;
+        double Mf[D][D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) Mf[i][j] = M[midx<D>(i, j)];
+        double Ar[D][D], br[D];
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) t += P[i * D + s] * r[i];
+            br[s] = t;
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                double m = 0.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+#pragma unroll
+                    for (int j = 0; j < D; ++j) m += P[i * D + s] * Mf[i][j] * P[j * D + u];
+                Ar[s][u] = m;
+            }
+        }
+        double al[D] = {};
+        if (na == 1) {
+            al[0] = br[0] / Ar[0][0];
+        } else {  // na == 2 < D == 3
+            double det = Ar[0][0] * Ar[1][1] - Ar[0][1] * Ar[1][0];
+            al[0] = (Ar[1][1] * br[0] - Ar[0][1] * br[1]) / det;
+            al[1] = (Ar[0][0] * br[1] - Ar[1][0] * br[0]) / det;
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < D; ++t) s += (t < na) ? P[i * D + t] * al[t] : 0.0;
+            vs[i] = s;
+        }
+    }
+    const double dt = mesh_dt(a.dt, a.node_mesh, p);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        a.vstar[i * nn + p] = vs[i];
+        a.x1[i * nn + p] = a.x[i * nn + p] + dt * vs[i];
+        a.vhat1[i * nn + p] = 2.0 * vs[i] - a.vhat[i * nn + p];
+    }
+}
+
+// -------------------------------------------------------- cell update
+// Subcell forces f_cp = M_cp v*_p - r_cp (eq. subforce^n), momentum and
+// total energy (eqs. v_c^n, e_c^n), tau = V(x^{n+1}) / m (reading R12), B by
+// Crank-Nicolson (P1) or Euler (P0) (eqs. CN_B, firstB; R10, R11), then
+// detection (eqs. PAD, RDMP; R16, R17) and the per-cell time-step bounds.
+template <int D>
+__global__ __launch_bounds__(256) void k_update(StepArgs a) {
+    using Dm = Dims<D>;
+    constexpr int NV = D + 1;
+    const int64_t c = gtid();
+    if (c >= a.nc) return;
+    const int64_t nc = a.nc, nn = a.nn;
+    int32_t nid[NV];
+    double X0[NV][D], X1[NV][D], vs[NV][D];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        nid[k] = a.c2n[c * NV + k];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            X0[k][i] = a.x[i * nn + nid[k]];
+            X1[k][i] = a.x1[i * nn + nid[k]];
+            vs[k][i] = a.vstar[i * nn + nid[k]];
+        }
+    }
+    // forces
+    double F[D] = {}, Wk = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double *rec = a.corner + (c * NV + k) * Dm::CW;
+        double f[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double s = -rec[Dm::NMS + i];
+#pragma unroll
+            for (int j = 0; j < D; ++j) s += rec[midx<D>(i, j)] * vs[k][j];
+            f[i] = s;
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            F[i] += f[i];
+            Wk += f[i] * vs[k][i];
+        }
+    }
+    const double m = a.mass[c];
+    const double dt = mesh_dt(a.dt, a.cell_mesh, c);
+    const double dtm = dt / m;
+    double v1[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) v1[i] = a.v[i * nc + c] + dtm * F[i];
+    const double e1 = a.e[c] + dtm * Wk;
+
+    Geo<D> g0, g1;
+    geom<D>(X0, g0);
+    geom<D>(X1, g1);
+    const double tau0 = a.tau[c];
+    const double tau1 = g1.V / m;
+
+    double b[6], b1[6];
+    load_B6<D>(a.B, nc, c, b);
+    const bool p1 = a.mask[c] == 0;
+    if (p1) {
+        double L0[D][D], L1[D][D];
+        const double r0 = 1.0 / g0.V, r1 = 1.0 / g1.V;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    s0 += a.vhat[i * nn + nid[k]] * g0.C[k][j];
+                    s1 += a.vhat1[i * nn + nid[k]] * g1.C[k][j];
+                }
+                L0[i][j] = s0 * r0;
+                L1[i][j] = s1 * r1;
+            }
+        cn_update<D>(b, L0, L1, 0.5 * dt, b1);
+    } else {
+        double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        const double r0 = 1.0 / g0.V;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < NV; ++k) s += vs[k][i] * g0.C[k][j];
+                L[i][j] = s * r0;
+            }
+        double B3[3][3] = {{b[0], b[3], b[4]}, {b[3], b[1], b[5]}, {b[4], b[5], b[2]}};
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            const int i = s < 3 ? s : (s == 5 ? 1 : 0);
+            const int j = s < 3 ? s : (s == 3 ? 1 : 2);
+            double y = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) y += L[i][k] * B3[k][j] + B3[i][k] * L[j][k];
+            b1[s] = b[s] + dt * y;
+        }
+        if (D == 2) {
+            b1[2] = 1.0;
+            b1[4] = 0.0;
+            b1[5] = 0.0;
+        }
+    }
+
+    // write the candidate
+    a.tau1[c] = tau1;
+    a.e1[c] = e1;
+#pragma unroll
+    for (int i = 0; i < D; ++i) a.v1[i * nc + c] = v1[i];
+    store_B6<D>(a.B1, nc, c, b1);
+
+    // detection
+    bool fin = isfinite(tau1) && isfinite(e1);
+#pragma unroll
+    for (int i = 0; i < D; ++i) fin = fin && isfinite(v1[i]);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) fin = fin && isfinite(b1[s]);
+    double k2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) k2 += v1[i] * v1[i];
+    const double eps = e1 - 0.5 * k2;
+    const bool pad_bad = !fin || !(tau1 > 0.0) || !(det6(b1) > 0.0) ||
+                         (eps < -a.eps_tol * (fabs(e1) + 0.5 * k2));
+    uint8_t fl = 0;
+    if (p1 && a.detect) {
+        double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const double *ag = a.agg + (int64_t)nid[k] * Dm::NA + Dm::O_RMM;
+            lo = fmin(lo, ag[0]);
+            hi = fmax(hi, ag[1]);
+        }
+        const double rho1 = 1.0 / tau1;
+        const double delta = fmax(a.delta0, a.delta1 * (hi - lo));
+        const bool bad = pad_bad || rho1 < lo - delta || rho1 > hi + delta;
+        if (bad) {
+            fl = 1;
+            atomicAdd(&a.counters[0], 1u);
+        }
+    } else if (!p1 && pad_bad) {
+        atomicAdd(&a.counters[1], 1u);
+    }
+    a.flag[c] = fl;
+
+    // time-step bounds at t^{n+1} (eq. CFL2; R20, R21)
+    double S1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) S1 += g1.cn[k];
+    const double Lc = 2.0 * g1.V / S1;
+    const double ac = sound(a.rho0[c], a.mu[c], a.K[c], tau1);
+    const double V0 = m * tau0, V1 = m * tau1;
+    const double dV = fabs(V1 - V0);
+    a.dtc[c] = Lc / ac;
+    a.dtc[nc + c] = dV > 0.0 ? V1 / dV : __builtin_huge_val();
+}
+
+// ------------------------------------------------------ mask handling
+__global__ __launch_bounds__(256) void k_apply_flags(int64_t nc, uint8_t *__restrict__ mask,
+                                                     const uint8_t *__restrict__ flag) {
+    int64_t c = gtid();
+    if (c >= nc) return;
+    mask[c] = mask[c] | flag[c];
+}
+
+// -------------------------------------------------------- reductions
+// Per-mesh minimum of non-negative doubles through their ordered bit
+// patterns (order independent, hence deterministic).
+__device__ __forceinline__ void atomic_min_pos(double *addr, double v) {
+    if (!(v >= 0.0)) return;  // NaN / negative: ignored
+    atomicMin(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_dt_reduce(int64_t nc, const double *__restrict__ dtc,
+                                                   const int32_t *__restrict__ cell_mesh,
+                                                   double *__restrict__ red /* [n_mesh][2] */) {
+    int64_t c = gtid();
+    double ac = __builtin_huge_val(), vol = __builtin_huge_val();
+    int mid = 0;
+    if (c < nc) {
+        ac = dtc[c];
+        vol = dtc[nc + c];
+        mid = cell_mesh ? cell_mesh[c] : 0;
+    }
+    if (!(ac >= 0.0)) ac = __builtin_huge_val();
+    if (!(vol >= 0.0)) vol = __builtin_huge_val();
+    // uniform mesh id across the wave? then reduce first
+    int m0 = __shfl(mid, 0, 64);
+    bool same = __all(mid == m0 || c >= nc);
+    if (same) {
+        ac = wave_min(ac);
+        vol = wave_min(vol);
+        if ((threadIdx.x & 63) == 0) {
+            atomic_min_pos(&red[2 * m0], ac);
+            atomic_min_pos(&red[2 * m0 + 1], vol);
+        }
+    } else if (c < nc) {
+        atomic_min_pos(&red[2 * mid], ac);
+        atomic_min_pos(&red[2 * mid + 1], vol);
+    }
+}
+
+__global__ void k_fill(double *p, int64_t n, double v) {
+    int64_t i = gtid();
+    if (i < n) p[i] = v;
+}
+
+// dt_next = min(C_CFL min L/a, C_v dt min V1/|dV|, (1 + C_i) dt)
+__global__ void k_dt_finalize(int n_mesh, const double *__restrict__ red, const double *__restrict__ dt,
+                              double c_cfl, double c_v, double c_i, int first, double *__restrict__ dt_next,
+                              double *__restrict__ parts /* [n_mesh][2]: acoustic, volume */) {
+    int m = gtid();
+    if (m >= n_mesh) return;
+    double ac = c_cfl * red[2 * m];
+    double vol = c_v * dt[m] * red[2 * m + 1];
+    double d = ac;
+    if (!first) d = fmin(fmin(ac, vol), (1.0 + c_i) * dt[m]);
+    dt_next[m] = d;
+    parts[2 * m] = ac;
+    parts[2 * m + 1] = first ? __builtin_huge_val() : vol;
+}
+
+// acoustic bound of the current state (initial time step)
+template <int D>
+__global__ __launch_bounds__(256) void k_acoustic(int64_t nc, int64_t nn, const int32_t *__restrict__ c2n,
+                                                  const double *__restrict__ x, const double *__restrict__ tau,
+                                                  const double *__restrict__ rho0, const double *__restrict__ mu,
+                                                  const double *__restrict__ K, double *__restrict__ dtc) {
+    constexpr int NV = D + 1;
+    int64_t c = gtid();
+    if (c >= nc) return;
+    double X[NV][D];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        int64_t p = c2n[c * NV + k];
+#pragma unroll
+        for (int i = 0; i < D; ++i) X[k][i] = x[i * nn + p];
+    }
+    Geo<D> g;
+    geom<D>(X, g);
+    double S = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) S += g.cn[k];
+    dtc[c] = 2.0 * g.V / S / sound(rho0[c], mu[c], K[c], tau[c]);
+    dtc[nc + c] = __builtin_huge_val();
+}
+
+// Diagnostics: per-block partial sums (fixed order), then one block adds
+// the partials in block order.  Sums: mass, mom[3], m e, kinetic, elastic,
+// n_p0.
+constexpr int NDIAG = 8;
+
+template <int D>
+__global__ __launch_bounds__(256) void k_diag(int64_t nc, const double *__restrict__ m, const double *__restrict__ tau,
+                                              const double *__restrict__ v, const double *__restrict__ e,
+                                              const double *__restrict__ B, const double *__restrict__ rho0,
+                                              const double *__restrict__ mu, const double *__restrict__ K,
+                                              const uint8_t *__restrict__ mask, double *__restrict__ part) {
+    __shared__ double sh[NDIAG][256];
+    int64_t c = gtid();
+    double q[NDIAG] = {};
+    if (c < nc) {
+        double mc = m[c];
+        double k2 = 0.0;
+        q[0] = mc;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double vi = v[i * nc + c];
+            q[1 + i] = mc * vi;
+            k2 += vi * vi;
+        }
+        q[4] = mc * e[c];
+        q[5] = 0.5 * mc * k2;
+        double b[6];
+        load_B6<D>(B, nc, c, b);
+        double J = rho0[c] * tau[c];
+        double lj = log(J);
+        double cJ = cbrt(J);
+        double I1b = (b[0] + b[1] + b[2]) / (cJ * cJ);
+        double psi = K[c] / (4.0 * rho0[c]) * ((J - 1.0) * (J - 1.0) + lj * lj) + mu[c] / (2.0 * rho0[c]) * (I1b - 3.0);
+        q[6] = mc * psi;
+        q[7] = mask[c] ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < NDIAG; ++s) sh[s][threadIdx.x] = q[s];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int s = 0; s < NDIAG; ++s) sh[s][threadIdx.x] += sh[s][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int s = 0; s < NDIAG; ++s) part[blockIdx.x * NDIAG + s] = sh[s][0];
+    }
+}
+
+__global__ void k_diag_finalize(int64_t nblocks, const double *__restrict__ part, double *__restrict__ out) {
+    int s = threadIdx.x;
+    if (s >= NDIAG) return;
+    double acc = 0.0;
+    for (int64_t b = 0; b < nblocks; ++b) acc += part[b * NDIAG + s];
+    out[s] = acc;
+}
+
+// AoS [n][w] <-> SoA [w][n] copies for the ABI
+__global__ void k_aos_to_soa(int64_t n, int w, const double *__restrict__ in, double *__restrict__ out) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    for (int k = 0; k < w; ++k) out[k * n + i] = in[i * w + k];
+}
+
+__global__ void k_soa_to_aos(int64_t n, int w, const double *__restrict__ in, double *__restrict__ out) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    for (int k = 0; k < w; ++k) out[i * w + k] = in[k * n + i];
+}
+
+// stress of the current state for queries: 3D (11,22,33,12,13,23),
+// 2D (11,22,12,33), AoS
+template <int D>
+__global__ void k_stress_query(int64_t nc, const double *__restrict__ tau, const double *__restrict__ B,
+                               const double *__restrict__ rho0, const double *__restrict__ mu,
+                               const double *__restrict__ K, double *__restrict__ out) {
+    int64_t c = gtid();
+    if (c >= nc) return;
+    double b[6], t[6];
+    load_B6<D>(B, nc, c, b);
+    stress6(rho0[c], mu[c], K[c], tau[c], b, t);
+    if (D == 3) {
+        for (int s = 0; s < 6; ++s) out[c * 6 + s] = t[s];
+    } else {
+        out[c * 4 + 0] = t[0];
+        out[c * 4 + 1] = t[1];
+        out[c * 4 + 2] = t[3];
+        out[c * 4 + 3] = t[2];
+    }
+}
+
+// ---------------------------------------------------------- launchers
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <int D>
+void launch_centroids(const StepArgs &a, hipStream_t s) {
+    if (a.nc) k_centroids<D><<<nblk(a.nc), 256, 0, s>>>(a.nc, a.nn, a.c2n, a.x, a.xc);
+}
+template <int D>
+void launch_node_agg(const StepArgs &a, hipStream_t s) {
+    if (a.nn) k_node_agg<D><<<nblk(a.nn), 256, 0, s>>>(a.nn, a.nc, a.n2c_off, a.n2c, a.x, a.xc, a.tau, a.v, a.B, a.agg);
+}
+template <int D>
+void launch_predict(const StepArgs &a, hipStream_t s) {
+    if (a.nc) k_predict<D><<<nblk(a.nc), 256, 0, s>>>(a);
+}
+template <int D>
+void launch_node_solve(const StepArgs &a, hipStream_t s) {
+    if (a.nn) k_node_solve<D><<<nblk(a.nn), 256, 0, s>>>(a);
+}
+template <int D>
+void launch_update(const StepArgs &a, hipStream_t s) {
+    if (a.nc) k_update<D><<<nblk(a.nc), 256, 0, s>>>(a);
+}
+void launch_apply_flags(int64_t nc, uint8_t *mask, const uint8_t *flag, hipStream_t s) {
+    if (nc) k_apply_flags<<<nblk(nc), 256, 0, s>>>(nc, mask, flag);
+}
+void launch_dt_reduce(int64_t nc, const double *dtc, const int32_t *cell_mesh, double *red, int n_mesh,
+                      hipStream_t s) {
+    k_fill<<<nblk(2 * n_mesh), 256, 0, s>>>(red, 2 * n_mesh, __builtin_huge_val());
+    if (nc) k_dt_reduce<<<nblk(nc), 256, 0, s>>>(nc, dtc, cell_mesh, red);
+}
+void launch_dt_finalize(int n_mesh, const double *red, const double *dt, const hl_params &p, int first,
+                        double *dt_next, double *parts, hipStream_t s) {
+    k_dt_finalize<<<nblk(n_mesh), 256, 0, s>>>(n_mesh, red, dt, p.c_cfl, p.c_v, p.c_i, first, dt_next, parts);
+}
+template <int D>
+void launch_acoustic(const StepArgs &a, hipStream_t s) {
+    if (a.nc) k_acoustic<D><<<nblk(a.nc), 256, 0, s>>>(a.nc, a.nn, a.c2n, a.x, a.tau, a.rho0, a.mu, a.K, a.dtc);
+}
+template <int D>
+int64_t launch_diag(const StepArgs &a, const double *tau, const double *v, const double *e, const double *B,
+                    double *part, double *out, hipStream_t s) {
+    int64_t nb = nblk(a.nc);
+    if (a.nc) k_diag<D><<<nb, 256, 0, s>>>(a.nc, a.mass, tau, v, e, B, a.rho0, a.mu, a.K, a.mask, part);
+    k_diag_finalize<<<1, 64, 0, s>>>(a.nc ? nb : 0, part, out);
+    return nb;
+}
+void launch_fill(double *p, int64_t n, double v, hipStream_t s) {
+    if (n) k_fill<<<nblk(n), 256, 0, s>>>(p, n, v);
+}
+void launch_aos_to_soa(int64_t n, int w, const double *in, double *out, hipStream_t s) {
+    if (n) k_aos_to_soa<<<nblk(n), 256, 0, s>>>(n, w, in, out);
+}
+void launch_soa_to_aos(int64_t n, int w, const double *in, double *out, hipStream_t s) {
+    if (n) k_soa_to_aos<<<nblk(n), 256, 0, s>>>(n, w, in, out);
+}
+template <int D>
+void launch_stress_query(const StepArgs &a, double *out, hipStream_t s) {
+    if (a.nc) k_stress_query<D><<<nblk(a.nc), 256, 0, s>>>(a.nc, a.tau, a.B, a.rho0, a.mu, a.K, out);
+}
+
+template void launch_centroids<2>(const StepArgs &, hipStream_t);
+template void launch_centroids<3>(const StepArgs &, hipStream_t);
+template void launch_node_agg<2>(const StepArgs &, hipStream_t);
+template void launch_node_agg<3>(const StepArgs &, hipStream_t);
+template void launch_predict<2>(const StepArgs &, hipStream_t);
+template void launch_predict<3>(const StepArgs &, hipStream_t);
+template void launch_node_solve<2>(const StepArgs &, hipStream_t);
+template void launch_node_solve<3>(const StepArgs &, hipStream_t);
+template void launch_update<2>(const StepArgs &, hipStream_t);
+template void launch_update<3>(const StepArgs &, hipStream_t);
+template void launch_acoustic<2>(const StepArgs &, hipStream_t);
+template void launch_acoustic<3>(const StepArgs &, hipStream_t);
+template int64_t launch_diag<2>(const StepArgs &, const double *, const double *, const double *, const double *,
+                                double *, double *, hipStream_t);
+template int64_t launch_diag<3>(const StepArgs &, const double *, const double *, const double *, const double *,
+                                double *, double *, hipStream_t);
+template void launch_stress_query<2>(const StepArgs &, double *, hipStream_t);
+template void launch_stress_query<3>(const StepArgs &, double *, hipStream_t);
+
+}  // namespace hl

@@ -1,0 +1,250 @@
+"""ctypes binding of libhyperlag.so (C-ABI in ``include/hyperlag.h``).
+
+Argument marshalling only: every step of the method runs in the HIP
+kernels of the library.  Arrays may be numpy arrays (host memory) or torch
+tensors on the GPU (device memory, passed by ``data_ptr()``).  There is no
+CPU fallback: if the library is missing or no GPU is present the calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhyperlag.so")
+
+HL_X, HL_VHAT, HL_TAU, HL_V, HL_E, HL_B, HL_VSTAR, HL_ORDER, HL_MASS, HL_T = range(10)
+FIELDS = dict(x=HL_X, vhat=HL_VHAT, tau=HL_TAU, v=HL_V, e=HL_E, B=HL_B, vstar=HL_VSTAR,
+              order=HL_ORDER, mass=HL_MASS, T=HL_T)
+
+# every exported symbol of the C-ABI
+EXPORTS = ["hl_create", "hl_destroy", "hl_mesh_upload", "hl_state_init", "hl_set_params",
+           "hl_compute_dt", "hl_step", "hl_step_replay", "hl_query", "hl_upload_field",
+           "hl_profile_enable", "hl_profile_reset", "hl_profile_get", "hl_status_str"]
+
+
+class Params(C.Structure):
+    _fields_ = [("c_cfl", C.c_double), ("c_v", C.c_double), ("c_i", C.c_double),
+                ("delta0", C.c_double), ("delta1", C.c_double), ("eps_tol", C.c_double),
+                ("detect", C.c_int32), ("reserved", C.c_int32)]
+
+
+def default_params(dim=3, detect=True, c_cfl=None):
+    return Params(c_cfl if c_cfl is not None else (0.4 if dim == 2 else 0.25),
+                  0.2, 0.1, 1e-4, 1e-3, 1e-12, 1 if detect else 0, 0)
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("dt_used", C.c_double), ("dt_next", C.c_double), ("dt_acoustic", C.c_double),
+                ("dt_volume", C.c_double), ("mass", C.c_double), ("mom", C.c_double * 3),
+                ("energy", C.c_double), ("kinetic", C.c_double), ("elastic", C.c_double),
+                ("n_p0", C.c_int64), ("n_flag_first", C.c_int64), ("mood_iters", C.c_int32),
+                ("status", C.c_int32)]
+
+    def as_dict(self):
+        return dict(dt_used=self.dt_used, dt_next=self.dt_next, dt_acoustic=self.dt_acoustic,
+                    dt_volume=self.dt_volume, mass=self.mass, mom=list(self.mom),
+                    energy=self.energy, kinetic=self.kinetic, elastic=self.elastic,
+                    n_p0=self.n_p0, n_flag_first=self.n_flag_first,
+                    mood_iters=self.mood_iters, status=self.status)
+
+
+class HyperLagError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    """Load libhyperlag.so from the package directory (raises if absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise HyperLagError(f"{LIB_PATH} is not built; run `python -m paper_2104_02139_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, dp = C.c_void_p, C.c_int64, C.c_double
+    L.hl_status_str.restype = C.c_char_p
+    L.hl_status_str.argtypes = [C.c_int]
+    L.hl_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+    L.hl_destroy.argtypes = [vp]
+    L.hl_mesh_upload.argtypes = [vp, C.c_int, i64, vp, i64, vp, vp, vp, C.c_int]
+    L.hl_state_init.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(Params), C.c_int]
+    L.hl_set_params.argtypes = [vp, C.POINTER(Params)]
+    L.hl_compute_dt.argtypes = [vp, C.POINTER(dp)]
+    L.hl_step.argtypes = [vp, dp, C.POINTER(StepInfo)]
+    L.hl_step_replay.argtypes = [vp, dp, vp, C.c_int, C.POINTER(StepInfo)]
+    L.hl_query.argtypes = [vp, C.c_int, vp, i64, C.c_int]
+    L.hl_upload_field.argtypes = [vp, C.c_int, vp, i64, C.c_int]
+    L.hl_profile_enable.argtypes = [vp, C.c_int]
+    L.hl_profile_reset.argtypes = [vp]
+    L.hl_profile_get.argtypes = [vp, C.c_char_p, C.POINTER(dp), C.POINTER(i64)]
+    for name in EXPORTS:
+        if name != "hl_status_str":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc, what):
+    if rc < 0:
+        msg = load().hl_status_str(rc).decode()
+        raise HyperLagError(f"{what} failed: {msg} ({rc})")
+    return rc
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _arg(a, dtype):
+    """(pointer, keep-alive, on_device) for a numpy array or torch tensor."""
+    if a is None:
+        return None, None, 0
+    if _is_torch(a):
+        import torch
+        tdt = {np.float64: torch.float64, np.int32: torch.int32, np.uint8: torch.uint8}[dtype]
+        t = a.contiguous()
+        if t.dtype != tdt:
+            t = t.to(tdt)
+        return C.c_void_p(t.data_ptr()), t, 1 if t.is_cuda else 0
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr.ctypes.data_as(C.c_void_p), arr, 0
+
+
+class Context:
+    """One mesh (or mesh batch) with its device state on one GPU."""
+
+    def __init__(self, device=0, stream=None):
+        L = load()
+        self._h = C.c_void_p()
+        handle = None
+        if stream is not None:
+            handle = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        _check(L.hl_create(C.byref(self._h), int(device), handle), "hl_create")
+        self.dim = None
+        self.n_nodes = self.n_cells = 0
+
+    def close(self):
+        if self._h:
+            load().hl_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def upload_mesh(self, dim, x, cells, nwall=None, normals=None):
+        px, kx, dev = _arg(x, np.float64)
+        pc, kc, _ = _arg(cells, np.int32)
+        pw, kw, _ = _arg(nwall, np.uint8)
+        pn, kn, _ = _arg(normals, np.float64)
+        nn = int(x.shape[0])
+        nc = int(cells.shape[0])
+        _check(load().hl_mesh_upload(self._h, int(dim), nn, px, nc, pc, pw, pn, dev),
+               "hl_mesh_upload")
+        self.dim, self.n_nodes, self.n_cells = int(dim), nn, nc
+
+    def init_state(self, rho0, mu, lam, v_cell, v_node, params=None):
+        args = [_arg(a, np.float64) for a in (rho0, mu, lam, v_cell, v_node)]
+        dev = args[0][2]
+        prm = params if params is not None else default_params(self.dim)
+        self.params = prm
+        _check(load().hl_state_init(self._h, *[a[0] for a in args], C.byref(prm), dev),
+               "hl_state_init")
+
+    def set_params(self, params):
+        self.params = params
+        _check(load().hl_set_params(self._h, C.byref(params)), "hl_set_params")
+
+    def compute_dt(self):
+        dt = C.c_double()
+        _check(load().hl_compute_dt(self._h, C.byref(dt)), "hl_compute_dt")
+        return dt.value
+
+    def step(self, dt=0.0, info=True):
+        inf = StepInfo() if info else None
+        rc = _check(load().hl_step(self._h, float(dt), C.byref(inf) if info else None), "hl_step")
+        out = inf.as_dict() if info else {}
+        out["rc"] = rc
+        return out
+
+    def step_replay(self, dt, mask, info=True):
+        pm, km, dev = _arg(mask, np.uint8)
+        inf = StepInfo() if info else None
+        rc = _check(load().hl_step_replay(self._h, float(dt), pm, dev,
+                                          C.byref(inf) if info else None), "hl_step_replay")
+        out = inf.as_dict() if info else {}
+        out["rc"] = rc
+        return out
+
+    def _shape(self, field):
+        d = self.dim
+        if field in (HL_X, HL_VHAT, HL_VSTAR):
+            return (self.n_nodes, d), np.float64
+        if field in (HL_TAU, HL_E, HL_MASS):
+            return (self.n_cells,), np.float64
+        if field == HL_V:
+            return (self.n_cells, d), np.float64
+        if field == HL_B:
+            return (self.n_cells, 6 if d == 3 else 3), np.float64
+        if field == HL_ORDER:
+            return (self.n_cells,), np.uint8
+        if field == HL_T:
+            return (self.n_cells, 6 if d == 3 else 4), np.float64
+        raise ValueError(field)
+
+    def query(self, field, out=None):
+        """Return a field as a numpy array, or fill the torch tensor ``out``."""
+        f = FIELDS[field] if isinstance(field, str) else int(field)
+        shape, dt = self._shape(f)
+        count = int(np.prod(shape))
+        if out is None:
+            arr = np.empty(shape, dtype=dt)
+            _check(load().hl_query(self._h, f, arr.ctypes.data_as(C.c_void_p), count, 0), "hl_query")
+            return arr
+        p, keep, dev = _arg(out, dt)
+        _check(load().hl_query(self._h, f, p, count, dev), "hl_query")
+        return out
+
+    def upload_field(self, field, values):
+        f = FIELDS[field] if isinstance(field, str) else int(field)
+        shape, dt = self._shape(f)
+        p, keep, dev = _arg(values, dt)
+        _check(load().hl_upload_field(self._h, f, p, int(np.prod(shape)), dev), "hl_upload_field")
+
+    def state(self):
+        return {k: self.query(k) for k in ("x", "vhat", "tau", "v", "e", "B")}
+
+    def set_state(self, st):
+        for k in ("x", "vhat", "tau", "v", "e", "B"):
+            self.upload_field(k, st[k])
+
+    # kernel timing with HIP events on the context's stream
+    def profile(self, on=True):
+        _check(load().hl_profile_enable(self._h, 1 if on else 0), "hl_profile_enable")
+
+    def profile_reset(self):
+        _check(load().hl_profile_reset(self._h), "hl_profile_reset")
+
+    def profile_get(self, name):
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(load().hl_profile_get(self._h, name.encode(), C.byref(ms), C.byref(n)),
+               "hl_profile_get")
+        return ms.value, n.value
+
+
+def from_workload(w, device=0, stream=None, params=None):
+    """Context initialised from a ``workloads.Workload``."""
+    ctx = Context(device, stream)
+    ctx.upload_mesh(w.dim, w.x, w.cells, w.nwall, w.normals)
+    ctx.init_state(w.rho0, w.mu, w.lam, w.v_cell, w.v_node,
+                   params if params is not None else default_params(w.dim, c_cfl=w.c_cfl))
+    return ctx

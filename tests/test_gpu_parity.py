@@ -1,0 +1,239 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+Bar (the benchmark spec's tolerances): normwise relative error <= 1e-12 after one
+step from identical input, <= 1e-9 after 100 steps, identical MOOD masks,
+time steps to 1e-12.  Full-size meshes are checked on sampled cells: the
+oracle recomputes a patch of two node-rings around each sample with the GPU's
+cascade choice replayed (the update of a cell only depends on that patch).
+"""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2104_02139_amd import workloads as W
+
+from .parity_util import (FIELDS, err, fmt, max_err, oracle_state, pair, patch_around, submesh,
+                          compare_states)
+
+pytestmark = pytest.mark.gpu
+
+ONE_STEP = 1e-12
+HUNDRED = 1e-9
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _single(dim):
+    import copy
+    base = W.plane_wave_2d(n=1) if dim == 2 else W.rotating_cube_3d(n=1)
+    w = copy.copy(base)
+    w.cells = base.cells[:1].copy()
+    nodes = np.unique(w.cells)
+    remap = {int(p): i for i, p in enumerate(nodes)}
+    w.cells = np.array([[remap[int(p)] for p in w.cells[0]]], dtype=np.int32)
+    w.x = base.x[nodes].copy()
+    w.nwall = np.zeros(len(nodes), np.uint8)
+    w.normals = np.zeros((len(nodes), dim, dim))
+    w.rho0, w.mu, w.lam = base.rho0[:1], base.mu[:1], base.lam[:1]
+    w.v_cell = base.v_cell[:1] + 0.01
+    w.v_node = base.v_node[nodes] + 0.02 * np.arange(len(nodes))[:, None]
+    return w
+
+
+CASES = {
+    "plane_wave_2d_n40": lambda: W.plane_wave_2d(n=40),
+    "ragged_2d_7x5": lambda: W.plane_wave_2d(n=7, amp=0.05),
+    "rotating_cube_n8": lambda: W.rotating_cube_3d(n=8),
+    "impact_bar_24x6x6": lambda: W.impact_bar_3d(nx=24, ny=6, graded=False),
+    "impact_bar_graded_ny4": lambda: W.impact_bar_3d(ny=4, graded=True),
+    "single_triangle": lambda: _single(2),
+    "single_tet": lambda: _single(3),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_one_step_parity(case):
+    w = CASES[case]()
+    _log(f"[parity] one step {case}: {w.n_cells} cells")
+    ctx, prob = pair(w)
+    dt_g = ctx.compute_dt()
+    dt_o = prob.initial_dt()
+    assert math.isclose(dt_g, dt_o, rel_tol=1e-13), (dt_g, dt_o)
+    st0 = ctx.state()
+    e0 = {f: err(st0[f], getattr(prob.state, f)) for f in FIELDS}
+    assert max_err(e0) <= 1e-15, fmt(e0)
+    info = ctx.step(dt_o)
+    s1, vs, mk, oi = prob.step(dt_o)
+    e = compare_states(ctx, s1, vs)
+    _log(f"  errs {fmt(e)}  mood {info['mood_iters']}/{oi.mood_iters} p0 {info['n_p0']}/{oi.n_p0}")
+    assert np.array_equal(ctx.query("order"), mk), "MOOD masks differ"
+    assert info["mood_iters"] == oi.mood_iters
+    assert max_err(e) <= ONE_STEP, fmt(e)
+    assert math.isclose(info["dt_next"], oi.dt_next, rel_tol=1e-12)
+    for k in ("mass", "energy", "kinetic"):
+        assert math.isclose(info[k], getattr(oi, k), rel_tol=1e-12, abs_tol=1e-300), k
+    # the stored energy m Psi cancels (I1bar - 3 ~ strain^2): compare it
+    # against the roundoff scale of its terms, sum m (K + mu) / rho0
+    scale = float(np.sum(prob.m * (prob.K + prob.mu) / prob.rho0))
+    assert abs(info["elastic"] - oi.elastic) <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("case", ["rotating_cube_n8", "impact_bar_24x6x6", "plane_wave_2d_n40"])
+@pytest.mark.parametrize("mode", ["random_mask", "all_p0", "no_detection"])
+def test_replay_and_modes(case, mode):
+    w = CASES[case]()
+    _log(f"[parity] {mode} {case}")
+    ctx, prob = pair(w, detect=(mode != "no_detection"))
+    dt = prob.initial_dt()
+    if mode == "no_detection":
+        info = ctx.step(dt)
+        s1, vs, mk, oi = prob.step(dt)
+        assert mk.sum() == 0 and info["n_p0"] == 0
+    else:
+        rng = np.random.default_rng(5)
+        mask = (rng.uniform(size=w.n_cells) < 0.3).astype(np.uint8) if mode == "random_mask" \
+            else np.ones(w.n_cells, np.uint8)
+        ctx.step_replay(dt, mask)
+        s1, vs, mk, oi = prob.step(dt, mask=mask, replay=True)
+        assert np.array_equal(ctx.query("order"), mask)
+    e = compare_states(ctx, s1, vs)
+    _log(f"  errs {fmt(e)}")
+    assert max_err(e) <= ONE_STEP, fmt(e)
+
+
+@pytest.mark.parametrize("case,steps", [("plane_wave_2d_n40", 100), ("rotating_cube_n8", 100),
+                                        ("impact_bar_24x6x6", 100)])
+def test_multi_step_parity(case, steps):
+    """CFL-controlled run: the GPU takes its device-side dt (hl_step(0)),
+    the oracle its own dt_next; masks must agree at every step."""
+    w = CASES[case]()
+    _log(f"[parity] {steps} steps {case}: {w.n_cells} cells")
+    ctx, prob = pair(w)
+    ctx.compute_dt()
+    dt = prob.initial_dt()
+    worst_dt = 0.0
+    flips = 0
+    for k in range(steps):
+        info = ctx.step(0.0)
+        worst_dt = max(worst_dt, abs(info["dt_used"] - dt) / dt)
+        s1, vs, mk, oi = prob.step(dt)
+        if not np.array_equal(ctx.query("order"), mk):
+            flips += 1
+        dt = oi.dt_next
+    e = compare_states(ctx, prob.state)
+    _log(f"  after {steps}: {fmt(e)}  dt err {worst_dt:.1e}  mask-differing steps {flips}")
+    assert flips == 0
+    assert worst_dt <= 1e-10
+    assert max_err(e) <= HUNDRED, fmt(e)
+
+
+def test_failure_injection_parity():
+    """A cell given a large velocity kick through hl_upload_field is
+    flagged and recomputed at first order on both sides."""
+    w = W.rotating_cube_3d(n=6)
+    ctx, prob = pair(w)
+    st = ctx.state()
+    st["v"][40] = [300.0, -200.0, 100.0]
+    st["e"][40] = 0.5 * np.sum(st["v"][40] ** 2)
+    ctx.set_state(st)
+    dt = prob.initial_dt()
+    info = ctx.step(dt)
+    s1, vs, mk, oi = prob.step(dt, state=oracle_state(st))
+    assert oi.n_flag_first > 0
+    assert info["n_flag_first"] == oi.n_flag_first
+    assert np.array_equal(ctx.query("order"), mk)
+    e = compare_states(ctx, s1, vs)
+    assert max_err(e) <= ONE_STEP, fmt(e)
+
+
+def test_empty_mesh():
+    from paper_2104_02139_amd import hyperlag as H
+    ctx = H.Context(0)
+    x = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0]])
+    ctx.upload_mesh(3, x, np.zeros((0, 4), np.int32))
+    ctx.init_state(np.zeros(0), np.zeros(0), np.zeros(0), np.zeros((0, 3)), np.ones((2, 3)))
+    ctx.step(1e-3)
+    assert np.array_equal(ctx.query("x"), x)
+
+
+def test_invalid_inputs_are_rejected():
+    from paper_2104_02139_amd import hyperlag as H
+    ctx = H.Context(0)
+    x = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    with pytest.raises(H.HyperLagError):
+        ctx.upload_mesh(2, x, np.array([[0, 2, 1]], np.int32))   # negative orientation
+    with pytest.raises(H.HyperLagError):
+        ctx.upload_mesh(2, x, np.array([[0, 1, 5]], np.int32))   # index out of range
+    with pytest.raises(H.HyperLagError):
+        ctx.step(1e-3)                                           # no state yet
+
+
+# ------------------------------------------------ full-size, sampled
+FULL = {
+    "rotating_cube_n56": lambda: W.rotating_cube_3d(n=56),
+    "impact_bar_graded_8.1M": lambda: W.impact_bar_3d(ny=60, graded=True),
+}
+
+
+@pytest.mark.parametrize("case", list(FULL))
+def test_full_size_sampled_parity(case):
+    """Full-size mesh, the launch configuration of the benchmark: one step
+    on the GPU; the oracle replays the GPU's cascade choice on two-ring
+    patches around sampled cells (including flagged ones); conservation of
+    mass and total energy holds over the whole mesh."""
+    t0 = time.time()
+    w = FULL[case]()
+    _log(f"[parity] full size {case}: {w.n_cells} cells, {w.n_nodes} nodes")
+    from paper_2104_02139_amd import hyperlag as H
+    ctx = H.from_workload(w)
+    dt = ctx.compute_dt()
+    st0 = ctx.state()
+    info = ctx.step(0.0)
+    _log(f"  gpu step done: mood {info['mood_iters']} p0 {info['n_p0']} dt {info['dt_used']:.3e}")
+    mask = ctx.query("order")
+    st1 = ctx.state()
+    vstar = ctx.query("vstar")
+    for f in FIELDS:
+        assert np.all(np.isfinite(st1[f])), f
+    assert info["status"] == 0
+    # sampled cells: random ones plus flagged ones
+    rng = np.random.default_rng(11)
+    seeds = list(rng.choice(w.n_cells, size=6, replace=False))
+    flagged = np.nonzero(mask)[0]
+    if flagged.size:
+        seeds += list(rng.choice(flagged, size=min(4, flagged.size), replace=False))
+    worst = {}
+    for s in seeds:
+        ids = patch_around(w.cells, w.n_nodes, [s], rings=2)
+        sub, nodes = submesh(w, ids)
+        prob = O.Problem(sub, O.default_params(w.c_cfl))
+        # identical input state restricted to the patch
+        sst = O.State(st0["x"][nodes], st0["vhat"][nodes], st0["tau"][ids], st0["v"][ids],
+                      st0["e"][ids], st0["B"][ids])
+        o1, ovs, _, _ = prob.step(dt, mask=mask[ids], replay=True, state=sst)
+        loc = int(np.nonzero(ids == s)[0][0])
+        ln = np.searchsorted(nodes, w.cells[s])
+        pairs = {"tau": (st1["tau"][s], o1.tau[loc]), "v": (st1["v"][s], o1.v[loc]),
+                 "e": (st1["e"][s], o1.e[loc]), "B": (st1["B"][s], o1.B[loc]),
+                 "x": (st1["x"][w.cells[s]], o1.x[ln]), "vhat": (st1["vhat"][w.cells[s]], o1.vhat[ln]),
+                 "vstar": (vstar[w.cells[s]], ovs[ln])}
+        for k, (g, o) in pairs.items():
+            # scale by the field's magnitude over the whole mesh
+            full = st1[k] if k in st1 else vstar
+            scale = np.abs(full).max()
+            e = np.abs(np.asarray(g) - np.asarray(o)).max() / scale if scale > 0 else 0.0
+            worst[k] = max(worst.get(k, 0.0), e)
+    _log(f"  sampled errs {fmt(worst)}  ({time.time() - t0:.1f}s)")
+    assert max(worst.values()) <= ONE_STEP, fmt(worst)
+    # whole-mesh conservation of mass and total energy
+    m = ctx.query("mass")
+    E0 = np.sum(m * st0["e"])
+    E1 = np.sum(m * st1["e"])
+    assert abs(E1 - E0) <= 1e-12 * np.sum(m * np.abs(st0["e"])) + 1e-300
