@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Throughput of the ADER-MOOD Lagrangian step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Times exactly K steps of the whole hot path (reconstruction, predictor,
+nodal solve, cell update, MOOD detection and first-order recompute until no
+new flag, CFL reduction) on synthetic input already resident in HBM, and
+prints ONE JSON line.  The default workload is the 8.1 M-tetrahedron graded
+impact bar.  Kernel durations come from HIP events recorded on the stream
+the kernels run on, over the timed region; the CPU baseline is the FP64
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "FP64 cell-updates/s per Lagrangian step; adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+PROFILED = ("centroids", "node_agg", "predict", "node_solve", "update", "reduce")
+
+
+def workloads():
+    from paper_2104_02139_amd import workloads as W
+    return {
+        "impact_bar_graded_8.1M": lambda: W.impact_bar_3d(ny=60, graded=True),
+        "impact_bar_5.2M": lambda: W.impact_bar_3d(nx=240, ny=60, graded=False),
+        "rotating_cube_1.05M": lambda: W.rotating_cube_3d(n=56),
+        "plane_wave_2d_3200": lambda: W.plane_wave_2d(n=40),
+    }
+
+
+def kernel_bytes(dim, nc, nn):
+    """Compulsory HBM bytes of one launch of each kernel: every input the
+    kernel needs read once, every output written once (FP64 = 8 B, int32 =
+    4 B, flags 1 B).  Corner records count their useful doubles."""
+    d = dim
+    nv = d + 1
+    ncor = nv * nc
+    nB = 6 if d == 3 else 3
+    nW = 1 + d + nB
+    nms = 6 if d == 3 else 3
+    cw = nms + d
+    na = 1 + d + nms + nW + d * nW + 2
+    csr = 4 * (nn + 1) + 4 * ncor
+    return {
+        "centroids": 4 * ncor + 8 * d * nn + 8 * d * nc,
+        "node_agg": csr + 8 * d * nn + 8 * d * nc + 8 * nW * nc + 8 * na * nn,
+        "predict": 4 * ncor + 8 * d * nn + 8 * nW * nc + 24 * nc + nc + 8 * na * nn + 8 * cw * ncor,
+        "node_solve": csr + 8 * cw * ncor + nn + 16 * d * nn + 24 * d * nn,
+        "update": (4 * ncor + 40 * d * nn + 8 * cw * ncor + 8 * (nW + 1) * nc + 32 * nc + nc
+                   + 16 * nn + 8 * (nW + 1) * nc + nc + 16 * nc),
+    }
+
+
+def step_alg_bytes(dim, nc, nn):
+    """Algorithmic bytes of a whole step: state in and out, constants,
+    connectivity, node data in and out, each once."""
+    d = dim
+    nB = 6 if d == 3 else 3
+    cell_state = 1 + d + 1 + nB
+    return (2 * 8 * cell_state * nc + 8 * nc + 4 * (d + 1) * nc
+            + 4 * (nn + 1) + 4 * (d + 1) * nc + 2 * 2 * 8 * d * nn + nc + nn)
+
+
+def kernel_source_hash():
+    h = hashlib.sha1()
+    for f in ("hl_kernels.hip", "hl_device.h"):
+        with open(os.path.join(ROOT, "paper_2104_02139_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def read_traffic(kernel, workload):
+    """HBM traffic of `kernel` from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha1") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(name, budget_s=25.0):
+    """The oracle as it stands (serial C, one thread) on a bounded sample of
+    the workload: the same mesh family at a reduced resolution, a few steps
+    from t = 0."""
+    from oracle import oracle as O
+    from paper_2104_02139_amd import workloads as W
+    if name.startswith("impact_bar"):
+        w = W.impact_bar_3d(ny=16, graded=True)
+        sample = "graded impact bar at ny=16 (%d tets), steps from t=0" % w.n_cells
+    elif name.startswith("rotating_cube"):
+        w = W.rotating_cube_3d(n=24)
+        sample = "rotating cube n=24 (%d tets), steps from t=0" % w.n_cells
+    else:
+        w = W.plane_wave_2d(n=40)
+        sample = "2D plane wave 40x40 (%d triangles), steps from t=0" % w.n_cells
+    prob = O.Problem(w)
+    dt = prob.initial_dt()
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        _, _, _, info = prob.step(dt)
+        dt = info.dt_next
+        steps += 1
+        if time.perf_counter() - t0 > budget_s * 0.5 or steps >= 50:
+            break
+    el = time.perf_counter() - t0
+    return {"value": w.n_cells * steps / el, "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle", "sample": f"{sample}; {steps} steps in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="impact_bar_graded_8.1M")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    if args.calibrate_copy:
+        n = (1 << 30) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 8}))
+        return
+
+    from paper_2104_02139_amd import hyperlag as H
+    name = args.workload
+    w = workloads()[name]()
+    print(f"[bench] workload {name}: {w.n_cells} cells, {w.n_nodes} nodes", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    ctx = H.from_workload(w, device=0, stream=stream)
+    ctx.compute_dt()
+
+    # warm-up (untimed), also the MOOD statistics
+    iters, p0 = [], []
+    for _ in range(args.warmup):
+        inf = ctx.step(0.0, info=True)
+        iters.append(inf["mood_iters"])
+        p0.append(inf["n_p0"])
+    torch.cuda.synchronize()
+
+    ctx.profile(True)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.step(0.0, info=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = {k: ctx.profile_get(k) for k in PROFILED}
+    ctx.profile(False)
+    inf = ctx.step(0.0, info=True)
+    iters.append(inf["mood_iters"])
+    p0.append(inf["n_p0"])
+
+    el = t1 - t0
+    ms_per_step = 1e3 * el / args.steps
+    value = w.n_cells * args.steps / el
+    print(f"[bench] {ms_per_step:.3f} ms/step, {value:.4g} cell-updates/s", file=sys.stderr, flush=True)
+
+    kb = kernel_bytes(w.dim, w.n_cells, w.n_nodes)
+    total = {k: kern[k][0] * kern[k][1] for k in kern}
+    dom = max(kb, key=lambda k: total.get(k, 0.0))
+    avg_ms, launches = kern[dom]
+    achieved = kb[dom] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = read_traffic(dom, name)
+    step_bytes = step_alg_bytes(w.dim, w.n_cells, w.n_nodes)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": name, "dim": w.dim, "n_cells": w.n_cells, "n_nodes": w.n_nodes,
+                   "cascade": "P1->P0", "cfl": w.c_cfl},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "alg_bytes_per_launch": kb[dom],
+                     "avg_launch_ms": avg_ms, "launches": launches},
+        "step_roofline": {"alg_bytes_per_step": step_bytes,
+                          "hbm_frac": (step_bytes / (HBM_PEAK_GBS * 1e9)) / (ms_per_step * 1e-3)},
+        "kernel_avg_ms": {k: kern[k][0] for k in kern},
+        "kernel_launches": {k: kern[k][1] for k in kern},
+        "mood": {"iters_mean": sum(iters) / len(iters), "first_order_frac_mean":
+                 sum(p0) / len(p0) / w.n_cells},
+        "adjoint_forward_ratio": None,
+        "kernel_source_sha1": kernel_source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(name)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -172,6 +172,10 @@ hl_status hl_profile_get(hl_ctx *ctx, const char *name, double *avg_ms, int64_t 
 
 const char *hl_status_str(hl_status s);
 
+/* Text of the last failed HIP runtime call on this thread (which call,
+ * where, and the runtime's message), or "" if none failed. */
+const char *hl_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

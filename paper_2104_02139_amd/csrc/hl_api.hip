@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -16,8 +17,9 @@
 
 namespace {
 
-enum { PK_CENTROIDS = 0, PK_NODE_AGG, PK_PREDICT, PK_NODE_SOLVE, PK_UPDATE, PK_REDUCE, PK_COUNT };
-const char *kProfNames[PK_COUNT] = {"centroids", "node_agg", "predict", "node_solve", "update", "reduce"};
+enum { PK_CENTROIDS = 0, PK_NODE_AGG, PK_PREDICT, PK_NODE_SOLVE, PK_UPDATE, PK_MOOD, PK_REDUCE, PK_COUNT };
+const char *kProfNames[PK_COUNT] = {"centroids", "node_agg", "predict", "node_solve", "update", "mood_sparse",
+                                    "reduce"};
 
 struct Prof {
     bool on = false;
@@ -49,7 +51,12 @@ struct hl_ctx {
     int cur = 0;
     // work
     double *vstar = nullptr, *xc = nullptr, *agg = nullptr, *corner = nullptr, *dtc = nullptr;
-    uint8_t *mask = nullptr, *flag = nullptr;
+    uint8_t *mask = nullptr, *pstat = nullptr;
+    int32_t *flist[2] = {}, *nlist = nullptr, *clist = nullptr, *nstamp = nullptr, *cstamp = nullptr;
+    int32_t stamp = 0;
+    int64_t max_deg = 0;
+    int64_t *mesh_cell_off = nullptr;
+    double *dt_part = nullptr;
     unsigned *counters = nullptr;
     unsigned *counters_host = nullptr;
     double *dt_cur = nullptr, *dt_next = nullptr, *dt_red = nullptr, *dt_parts = nullptr;
@@ -64,10 +71,18 @@ struct hl_ctx {
 
 namespace {
 
-#define HIPCHK(call)                                  \
-    do {                                              \
-        hipError_t _e = (call);                       \
-        if (_e != hipSuccess) return HL_E_HIP;        \
+// text of the last failed HIP call, for hl_last_error()
+thread_local char g_last_error[256] = "";
+
+hl_status hip_fail(hipError_t e, const char *what, int line) {
+    std::snprintf(g_last_error, sizeof g_last_error, "%s (line %d): %s", what, line, hipGetErrorString(e));
+    return HL_E_HIP;
+}
+
+#define HIPCHK(call)                                               \
+    do {                                                           \
+        hipError_t _e = (call);                                    \
+        if (_e != hipSuccess) return hip_fail(_e, #call, __LINE__); \
     } while (0)
 
 hl_params default_params(int dim) {
@@ -97,7 +112,11 @@ void free_all(hl_ctx *c) {
     c->allow = c->mass = c->rho0 = c->mu = c->K = nullptr;
     for (int b = 0; b < 2; ++b) c->x[b] = c->vhat[b] = c->tau[b] = c->v[b] = c->e[b] = c->B[b] = nullptr;
     c->vstar = c->xc = c->agg = c->corner = c->dtc = nullptr;
-    c->mask = c->flag = nullptr;
+    c->mask = c->pstat = nullptr;
+    c->flist[0] = c->flist[1] = c->nlist = c->clist = c->nstamp = c->cstamp = nullptr;
+    c->mesh_cell_off = nullptr;
+    c->dt_part = nullptr;
+    c->stamp = 0;
     c->counters = nullptr;
     c->dt_cur = c->dt_next = c->dt_red = c->dt_parts = c->diag_part = c->diag_out = c->scratch = nullptr;
     c->have_mesh = c->have_state = false;
@@ -238,7 +257,14 @@ hl::StepArgs make_args(hl_ctx *c, int src) {
     a.corner = c->corner;
     a.dtc = c->dtc;
     a.mask = c->mask;
-    a.flag = c->flag;
+    a.pstat = c->pstat;
+    a.flist_out = c->flist[0];
+    a.fcount_out = c->counters + hl::CNT_F0;
+    a.nlist = c->nlist;
+    a.clist = c->clist;
+    a.nstamp = c->nstamp;
+    a.cstamp = c->cstamp;
+    a.stamp = c->stamp;
     a.counters = c->counters;
     a.delta0 = c->prm.delta0;
     a.delta1 = c->prm.delta1;
@@ -319,35 +345,52 @@ hl_status run_step(hl_ctx *c, const uint8_t *replay_mask, int mask_on_device, hl
         if (info) std::memset(info, 0, sizeof(*info));
         return HL_OK;
     }
+    HIPCHK(hipMemsetAsync(c->counters, 0, hl::CNT_N * sizeof(unsigned), s));
     PROF(c, PK_CENTROIDS, hl::launch_centroids<D>(a, s));
     PROF(c, PK_NODE_AGG, hl::launch_node_agg<D>(a, s));
-    int iters = 0;
-    int64_t first = -1;
-    unsigned inadm = 0;
-    for (;;) {
-        HIPCHK(hipMemsetAsync(c->counters, 0, 2 * sizeof(unsigned), s));
-        PROF(c, PK_PREDICT, hl::launch_predict<D>(a, s));
-        PROF(c, PK_NODE_SOLVE, hl::launch_node_solve<D>(a, s));
-        PROF(c, PK_UPDATE, hl::launch_update<D>(a, s));
-        ++iters;
-        if (!a.detect) {
-            HIPCHK(hipMemcpyAsync(c->counters_host, c->counters, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            inadm = c->counters_host[1];
-            break;
+    // first candidate: every cell at its current order
+    a.flist_out = c->flist[0];
+    a.fcount_out = c->counters + hl::CNT_F0;
+    PROF(c, PK_PREDICT, hl::launch_predict<D>(a, s));
+    PROF(c, PK_NODE_SOLVE, hl::launch_node_solve<D>(a, s));
+    PROF(c, PK_UPDATE, hl::launch_update<D>(a, s));
+    int iters = 1;
+    HIPCHK(hipMemcpyAsync(c->counters_host, c->counters, hl::CNT_N * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int64_t nflag = c->counters_host[hl::CNT_F0];
+    const int64_t first = nflag;
+    int fb = 0;
+    // MOOD: cells flagged in the last candidate drop to first order; only
+    // their corners, their nodes and the cells around those nodes change
+    while (a.detect && nflag > 0) {
+        if (c->stamp >= INT32_MAX - 2) {
+            HIPCHK(hipMemsetAsync(c->nstamp, 0, sizeof(int32_t) * c->nn, s));
+            HIPCHK(hipMemsetAsync(c->cstamp, 0, sizeof(int32_t) * c->nc, s));
+            c->stamp = 0;
         }
-        HIPCHK(hipMemcpyAsync(c->counters_host, c->counters, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        a.stamp = ++c->stamp;
+        const int nb = 1 - fb;
+        HIPCHK(hipMemsetAsync(c->counters + hl::CNT_F0 + nb, 0, sizeof(unsigned), s));
+        HIPCHK(hipMemsetAsync(c->counters + hl::CNT_NODES, 0, 2 * sizeof(unsigned), s));
+        a.flist_out = c->flist[nb];
+        a.fcount_out = c->counters + hl::CNT_F0 + nb;
+        PROF(c, PK_MOOD,
+             hl::launch_mood_sparse<D>(a, c->flist[fb], c->counters + hl::CNT_F0 + fb, nflag, c->max_deg, s));
+        ++iters;
+        HIPCHK(hipMemcpyAsync(c->counters_host, c->counters, hl::CNT_N * sizeof(unsigned), hipMemcpyDeviceToHost,
+                              s));
         HIPCHK(hipStreamSynchronize(s));
-        unsigned nflag = c->counters_host[0];
-        inadm = c->counters_host[1];
-        if (first < 0) first = nflag;
-        if (nflag == 0) break;
-        hl::launch_apply_flags(c->nc, c->mask, c->flag, s);
+        nflag = c->counters_host[hl::CNT_F0 + nb];
+        fb = nb;
     }
     PROF(c, PK_REDUCE, {
-        hl::launch_dt_reduce(c->nc, c->dtc, nullptr, c->dt_red, c->n_mesh, s);
+        hl::launch_dt_reduce(c->nc, c->dtc, nullptr, c->pstat, c->dt_red, c->dt_part, c->mesh_cell_off, c->n_mesh,
+                             c->counters + hl::CNT_BAD, s);
         hl::launch_dt_finalize(c->n_mesh, c->dt_red, c->dt_cur, c->prm, 0, c->dt_next, c->dt_parts, s);
     });
+    HIPCHK(hipMemcpyAsync(c->counters_host, c->counters, hl::CNT_N * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const unsigned inadm = c->counters_host[hl::CNT_BAD];
     if (info) {
         std::memset(info, 0, sizeof(*info));
         const int dst = 1 - src;
@@ -370,7 +413,7 @@ hl_status run_step(hl_ctx *c, const uint8_t *replay_mask, int mask_on_device, hl
         info->kinetic = d[5];
         info->elastic = d[6];
         info->n_p0 = (int64_t)llround(d[7]);
-        info->n_flag_first = first < 0 ? 0 : first;
+        info->n_flag_first = first;
         info->mood_iters = iters;
         info->status = inadm ? 1 : 0;
     }
@@ -424,6 +467,8 @@ double *field_ptr(hl_ctx *c, int field) {
 }  // namespace
 
 extern "C" {
+
+const char *hl_last_error(void) { return g_last_error; }
 
 const char *hl_status_str(hl_status s) {
     switch (s) {
@@ -548,8 +593,16 @@ hl_status hl_mesh_upload(hl_ctx *c, int dim, int64_t n_nodes, const double *x0, 
     A_(c->corner, ncor * CW);
     A_(c->dtc, 2 * ncl);
     A_(c->mask, ncl);
-    A_(c->flag, ncl);
-    A_(c->counters, 4);
+    A_(c->pstat, ncl);
+    A_(c->flist[0], ncl);
+    A_(c->flist[1], ncl);
+    A_(c->nlist, nn);
+    A_(c->clist, ncl);
+    A_(c->nstamp, nn);
+    A_(c->cstamp, ncl);
+    A_(c->mesh_cell_off, 2);
+    A_(c->dt_part, 2 * (ncl / 256 + 2));
+    A_(c->counters, hl::CNT_N);
     A_(c->dt_cur, 16);
     A_(c->dt_next, 16);
     A_(c->dt_red, 32);
@@ -559,7 +612,7 @@ hl_status hl_mesh_upload(hl_ctx *c, int dim, int64_t n_nodes, const double *x0, 
     c->scratch_bytes = std::max<size_t>(sizeof(double) * std::max(nn * dim, ncl * 6), 256);
     A_(c->scratch, c->scratch_bytes / sizeof(double));
 #undef A_
-    if (hipHostMalloc((void **)&c->counters_host, 4 * sizeof(unsigned), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->counters_host, hl::CNT_N * sizeof(unsigned), hipHostMallocDefault) != hipSuccess) {
         free_all(c);
         return HL_E_OOM;
     }
@@ -574,7 +627,15 @@ hl_status hl_mesh_upload(hl_ctx *c, int dim, int64_t n_nodes, const double *x0, 
     for (size_t p = 0; p < nn; ++p)
         for (int i = 0; i < dim; ++i) xs[i * nn + p] = xh[p * dim + i];
     HIPCHK(hipMemcpyAsync(c->x[0], xs.data(), sizeof(double) * nn * dim, hipMemcpyHostToDevice, s));
+    if (nn) HIPCHK(hipMemsetAsync(c->nstamp, 0, sizeof(int32_t) * nn, s));
+    if (ncl) HIPCHK(hipMemsetAsync(c->cstamp, 0, sizeof(int32_t) * ncl, s));
+    if (ncl) HIPCHK(hipMemsetAsync(c->pstat, 0, ncl, s));
+    const int64_t mco[2] = {0, n_cells};
+    HIPCHK(hipMemcpyAsync(c->mesh_cell_off, mco, sizeof mco, hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
+    c->max_deg = 0;
+    for (int64_t p = 0; p < n_nodes; ++p) c->max_deg = std::max<int64_t>(c->max_deg, off[p + 1] - off[p]);
+    c->stamp = 0;
     c->x0_host.swap(xh);
     c->c2n_host.swap(ch);
     c->cur = 0;
@@ -678,7 +739,8 @@ hl_status hl_compute_dt(hl_ctx *c, double *dt_out) {
         hl::launch_acoustic<3>(a, s);
     else
         hl::launch_acoustic<2>(a, s);
-    hl::launch_dt_reduce(c->nc, c->dtc, nullptr, c->dt_red, c->n_mesh, s);
+    hl::launch_dt_reduce(c->nc, c->dtc, nullptr, c->pstat, c->dt_red, c->dt_part, c->mesh_cell_off, c->n_mesh,
+                         c->counters + hl::CNT_N - 1, s);
     hl::launch_dt_finalize(c->n_mesh, c->dt_red, c->dt_cur, c->prm, 1, c->dt_next, c->dt_parts, s);
     double dt = 0.0;
     HIPCHK(hipMemcpyAsync(&dt, c->dt_next, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -699,7 +761,8 @@ static hl_status step_common(hl_ctx *c, double dt, const uint8_t *mask, int on_d
         HIPCHK(hipMemcpyAsync(c->dt_cur, c->dt_next, sizeof(double) * c->n_mesh, hipMemcpyDeviceToDevice, s));
     hl_status st = c->dim == 3 ? run_step<3>(c, mask, on_device, info) : run_step<2>(c, mask, on_device, info);
     if (c->prof.on) prof_collect(c);
-    if (hipGetLastError() != hipSuccess) return HL_E_HIP;
+    hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return hip_fail(le, "kernel launch", __LINE__);
     return st;
 }
 

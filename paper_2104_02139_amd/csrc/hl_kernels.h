@@ -26,11 +26,20 @@ struct StepArgs {
     // work
     double *xc, *agg, *corner, *dtc;
     const uint8_t *mask;
-    uint8_t *flag;
-    unsigned int *counters;  // [0] troubled P1 cells, [1] inadmissible P0 cells
+    uint8_t *pstat;            // 1: first-order cell whose candidate is not admissible
+    // MOOD lists: flagged cells appended to flist_out (count fcount_out);
+    // re-solved nodes and recomputed cells, deduplicated by stamps
+    int32_t *flist_out;
+    unsigned *fcount_out;
+    int32_t *nlist, *clist;
+    int32_t *nstamp, *cstamp;
+    int32_t stamp;
+    unsigned int *counters;    // [CNT_NODES], [CNT_CELLS], [CNT_BAD]
     double delta0, delta1, eps_tol;
     int detect;
 };
+
+enum { CNT_F0 = 0, CNT_F1 = 1, CNT_NODES = 2, CNT_CELLS = 3, CNT_BAD = 4, CNT_N = 8 };
 
 template <int D> void launch_centroids(const StepArgs &a, hipStream_t s);
 template <int D> void launch_node_agg(const StepArgs &a, hipStream_t s);
@@ -42,9 +51,11 @@ template <int D>
 int64_t launch_diag(const StepArgs &a, const double *tau, const double *v, const double *e, const double *B,
                     double *part, double *out, hipStream_t s);
 template <int D> void launch_stress_query(const StepArgs &a, double *out, hipStream_t s);
-void launch_apply_flags(int64_t nc, uint8_t *mask, const uint8_t *flag, hipStream_t s);
-void launch_dt_reduce(int64_t nc, const double *dtc, const int32_t *cell_mesh, double *red, int n_mesh,
-                      hipStream_t s);
+template <int D>
+void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned *fcount, int64_t nflag,
+                        int64_t max_deg, hipStream_t s);
+void launch_dt_reduce(int64_t nc, const double *dtc, const int32_t *cell_mesh, const uint8_t *pstat, double *red,
+                      double *part, const int64_t *mesh_cell_off, int n_mesh, unsigned *bad_count, hipStream_t s);
 void launch_dt_finalize(int n_mesh, const double *red, const double *dt, const hl_params &p, int first,
                         double *dt_next, double *parts, hipStream_t s);
 void launch_fill(double *p, int64_t n, double v, hipStream_t s);

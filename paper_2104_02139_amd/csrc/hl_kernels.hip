@@ -19,6 +19,8 @@
 #include "hl_device.h"
 #include "hl_kernels.h"
 
+#include <algorithm>
+
 namespace hl {
 
 __device__ __forceinline__ int64_t gtid() {
@@ -150,11 +152,9 @@ __device__ __forceinline__ constexpr int bslot(int s) {
 // corner stress and impedance (R5), corner matrix M_cp (eq. Mcp, R4) and
 // r_cp = M_cp v*_cp - T*_cp C_cp (eq. nodal_solver^n).
 template <int D>
-__global__ __launch_bounds__(256) void k_predict(StepArgs a) {
+__device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c) {
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
-    const int64_t c = gtid();
-    if (c >= a.nc) return;
     const int64_t nc = a.nc, nn = a.nn;
     int32_t nid[NV];
     double X[NV][D];
@@ -371,16 +371,28 @@ __global__ __launch_bounds__(256) void k_predict(StepArgs a) {
     }
 }
 
+template <int D>
+__global__ __launch_bounds__(256) void k_predict(StepArgs a) {
+    const int64_t c = gtid();
+    if (c < a.nc) predict_cell<D>(a, c);
+}
+
+// list-driven variant: the cells just flagged, recomputed at first order
+template <int D>
+__global__ __launch_bounds__(256) void k_predict_list(StepArgs a, const int32_t *__restrict__ list,
+                                                      const unsigned *__restrict__ count) {
+    const int64_t n = *count;
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) predict_cell<D>(a, list[i]);
+}
+
 // ---------------------------------------------------------- node solve
 // M_p v*_p = sum_c (M_cp v*_cp - T*_cp C_cp) (eq. nodal_solver^n, readings
 // R14, R15); slip walls by Galerkin projection onto the allowed directions
 // (Appendix B eq. sBC1, reading R22).  Then x^{n+1} = x^n + dt v*_p and
 // vhat^{n+1} = 2 v*_p - vhat^n (Section 3.4, reading R9).
 template <int D>
-__global__ __launch_bounds__(256) void k_node_solve(StepArgs a) {
+__device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t p) {
     using Dm = Dims<D>;
-    const int64_t p = gtid();
-    if (p >= a.nn) return;
     const int64_t nn = a.nn;
     double M[Dm::NMS] = {}, r[D] = {};
     const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
@@ -456,17 +468,27 @@ __global__ __launch_bounds__(256) void k_node_solve(StepArgs a) {
     }
 }
 
+template <int D>
+__global__ __launch_bounds__(256) void k_node_solve(StepArgs a) {
+    const int64_t p = gtid();
+    if (p < a.nn) node_solve_one<D>(a, p);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_node_solve_list(StepArgs a) {
+    const int64_t n = a.counters[CNT_NODES];
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) node_solve_one<D>(a, a.nlist[i]);
+}
+
 // -------------------------------------------------------- cell update
 // Subcell forces f_cp = M_cp v*_p - r_cp (eq. subforce^n), momentum and
 // total energy (eqs. v_c^n, e_c^n), tau = V(x^{n+1}) / m (reading R12), B by
 // Crank-Nicolson (P1) or Euler (P0) (eqs. CN_B, firstB; R10, R11), then
 // detection (eqs. PAD, RDMP; R16, R17) and the per-cell time-step bounds.
 template <int D>
-__global__ __launch_bounds__(256) void k_update(StepArgs a) {
+__device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) {
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
-    const int64_t c = gtid();
-    if (c >= a.nc) return;
     const int64_t nc = a.nc, nn = a.nn;
     int32_t nid[NV];
     double X0[NV][D], X1[NV][D], vs[NV][D];
@@ -581,7 +603,6 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a) {
     const double eps = e1 - 0.5 * k2;
     const bool pad_bad = !fin || !(tau1 > 0.0) || !(det6(b1) > 0.0) ||
                          (eps < -a.eps_tol * (fabs(e1) + 0.5 * k2));
-    uint8_t fl = 0;
     if (p1 && a.detect) {
         double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
 #pragma unroll
@@ -593,14 +614,9 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a) {
         const double rho1 = 1.0 / tau1;
         const double delta = fmax(a.delta0, a.delta1 * (hi - lo));
         const bool bad = pad_bad || rho1 < lo - delta || rho1 > hi + delta;
-        if (bad) {
-            fl = 1;
-            atomicAdd(&a.counters[0], 1u);
-        }
-    } else if (!p1 && pad_bad) {
-        atomicAdd(&a.counters[1], 1u);
+        if (bad) a.flist_out[atomicAdd(a.fcount_out, 1u)] = (int32_t)c;
     }
-    a.flag[c] = fl;
+    a.pstat[c] = (!p1 && pad_bad) ? 1 : 0;
 
     // time-step bounds at t^{n+1} (eq. CFL2; R20, R21)
     double S1 = 0.0;
@@ -614,12 +630,54 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a) {
     a.dtc[nc + c] = dV > 0.0 ? V1 / dV : __builtin_huge_val();
 }
 
-// ------------------------------------------------------ mask handling
-__global__ __launch_bounds__(256) void k_apply_flags(int64_t nc, uint8_t *__restrict__ mask,
-                                                     const uint8_t *__restrict__ flag) {
-    int64_t c = gtid();
-    if (c >= nc) return;
-    mask[c] = mask[c] | flag[c];
+template <int D>
+__global__ __launch_bounds__(256) void k_update(StepArgs a) {
+    const int64_t c = gtid();
+    if (c < a.nc) update_cell<D>(a, c);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_update_list(StepArgs a) {
+    const int64_t n = a.counters[CNT_CELLS];
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) update_cell<D>(a, a.clist[i]);
+}
+
+// ------------------------------------------------------ MOOD bookkeeping
+// Cells flagged in the last candidate drop to first order.
+__global__ __launch_bounds__(256) void k_apply_list(uint8_t *__restrict__ mask, const int32_t *__restrict__ list,
+                                                    const unsigned *__restrict__ count) {
+    const int64_t n = *count;
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) mask[list[i]] = 1;
+}
+
+// Nodes of the flagged cells, each listed once (stamp = this iteration).
+template <int D>
+__global__ __launch_bounds__(256) void k_mark_nodes(StepArgs a, const int32_t *__restrict__ list,
+                                                    const unsigned *__restrict__ count) {
+    const int64_t n = *count;
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = list[i];
+#pragma unroll
+        for (int k = 0; k <= D; ++k) {
+            const int32_t p = a.c2n[c * (D + 1) + k];
+            if (atomicExch(&a.nstamp[p], a.stamp) != a.stamp)
+                a.nlist[atomicAdd(&a.counters[CNT_NODES], 1u)] = p;
+        }
+    }
+}
+
+// Cells around the re-solved nodes, each listed once.
+template <int D>
+__global__ __launch_bounds__(256) void k_mark_cells(StepArgs a) {
+    const int64_t n = a.counters[CNT_NODES];
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = a.nlist[i];
+        for (int32_t q = a.n2c_off[p]; q < a.n2c_off[p + 1]; ++q) {
+            const int32_t j = a.n2c[q] / (D + 1);
+            if (atomicExch(&a.cstamp[j], a.stamp) != a.stamp)
+                a.clist[atomicAdd(&a.counters[CNT_CELLS], 1u)] = j;
+        }
+    }
 }
 
 // -------------------------------------------------------- reductions
@@ -636,32 +694,83 @@ __device__ __forceinline__ double wave_min(double v) {
     return v;
 }
 
+// Stage 1: per-block minimum of the two time-step bounds (blocks inside
+// one mesh), or per-cell atomics for a block that straddles meshes; count
+// of inadmissible first-order cells.
 __global__ __launch_bounds__(256) void k_dt_reduce(int64_t nc, const double *__restrict__ dtc,
                                                    const int32_t *__restrict__ cell_mesh,
-                                                   double *__restrict__ red /* [n_mesh][2] */) {
-    int64_t c = gtid();
+                                                   const uint8_t *__restrict__ pstat,
+                                                   double *__restrict__ red /* [n_mesh][2] */,
+                                                   double *__restrict__ part /* [nblocks][2] */,
+                                                   unsigned *__restrict__ bad_count) {
+    __shared__ double sa[4], sv[4];
+    __shared__ int sbad[4];
+    const int64_t c = gtid();
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t last = min(first + (int64_t)blockDim.x, nc) - 1;
     double ac = __builtin_huge_val(), vol = __builtin_huge_val();
-    int mid = 0;
+    int bad = 0;
     if (c < nc) {
         ac = dtc[c];
         vol = dtc[nc + c];
-        mid = cell_mesh ? cell_mesh[c] : 0;
+        bad = pstat[c];
     }
     if (!(ac >= 0.0)) ac = __builtin_huge_val();
     if (!(vol >= 0.0)) vol = __builtin_huge_val();
-    // uniform mesh id across the wave? then reduce first
-    int m0 = __shfl(mid, 0, 64);
-    bool same = __all(mid == m0 || c >= nc);
-    if (same) {
-        ac = wave_min(ac);
-        vol = wave_min(vol);
-        if ((threadIdx.x & 63) == 0) {
-            atomic_min_pos(&red[2 * m0], ac);
-            atomic_min_pos(&red[2 * m0 + 1], vol);
+    const bool straddle = cell_mesh && cell_mesh[first] != cell_mesh[last];
+    if (straddle) {
+        if (c < nc) {
+            atomic_min_pos(&red[2 * cell_mesh[c]], ac);
+            atomic_min_pos(&red[2 * cell_mesh[c] + 1], vol);
         }
-    } else if (c < nc) {
-        atomic_min_pos(&red[2 * mid], ac);
-        atomic_min_pos(&red[2 * mid + 1], vol);
+        ac = vol = __builtin_huge_val();
+    }
+    ac = wave_min(ac);
+    vol = wave_min(vol);
+    unsigned long long bb = __ballot(bad != 0);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sa[w] = ac;
+        sv[w] = vol;
+        sbad[w] = __popcll(bb);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a0 = fmin(fmin(sa[0], sa[1]), fmin(sa[2], sa[3]));
+        double v0 = fmin(fmin(sv[0], sv[1]), fmin(sv[2], sv[3]));
+        part[2 * blockIdx.x] = a0;
+        part[2 * blockIdx.x + 1] = v0;
+        int nb = sbad[0] + sbad[1] + sbad[2] + sbad[3];
+        if (nb) atomicAdd(bad_count, (unsigned)nb);
+    }
+}
+
+// Stage 2: one block per mesh reduces the partials of its blocks.
+__global__ __launch_bounds__(256) void k_dt_reduce2(int n_mesh, const int64_t *__restrict__ mesh_cell_off,
+                                                    const double *__restrict__ part, double *__restrict__ red) {
+    __shared__ double sa[4], sv[4];
+    const int m = blockIdx.x;
+    if (m >= n_mesh) return;
+    const int64_t c0 = mesh_cell_off[m], c1 = mesh_cell_off[m + 1];
+    double ac = __builtin_huge_val(), vol = __builtin_huge_val();
+    if (c1 > c0) {
+        const int64_t b0 = c0 / 256, b1 = (c1 - 1) / 256;
+        for (int64_t b = b0 + threadIdx.x; b <= b1; b += blockDim.x) {
+            ac = fmin(ac, part[2 * b]);
+            vol = fmin(vol, part[2 * b + 1]);
+        }
+    }
+    ac = wave_min(ac);
+    vol = wave_min(vol);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sa[w] = ac;
+        sv[w] = vol;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomic_min_pos(&red[2 * m], fmin(fmin(sa[0], sa[1]), fmin(sa[2], sa[3])));
+        atomic_min_pos(&red[2 * m + 1], fmin(fmin(sv[0], sv[1]), fmin(sv[2], sv[3])));
     }
 }
 
@@ -762,12 +871,20 @@ __global__ __launch_bounds__(256) void k_diag(int64_t nc, const double *__restri
     }
 }
 
-__global__ void k_diag_finalize(int64_t nblocks, const double *__restrict__ part, double *__restrict__ out) {
-    int s = threadIdx.x;
-    if (s >= NDIAG) return;
+// one block per sum; fixed strided order then a fixed tree: deterministic
+__global__ __launch_bounds__(256) void k_diag_finalize(int64_t nblocks, const double *__restrict__ part,
+                                                       double *__restrict__ out) {
+    __shared__ double sh[256];
+    const int s = blockIdx.x;
     double acc = 0.0;
-    for (int64_t b = 0; b < nblocks; ++b) acc += part[b * NDIAG + s];
-    out[s] = acc;
+    for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) acc += part[b * NDIAG + s];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[s] = sh[0];
 }
 
 // AoS [n][w] <-> SoA [w][n] copies for the ABI
@@ -827,13 +944,26 @@ template <int D>
 void launch_update(const StepArgs &a, hipStream_t s) {
     if (a.nc) k_update<D><<<nblk(a.nc), 256, 0, s>>>(a);
 }
-void launch_apply_flags(int64_t nc, uint8_t *mask, const uint8_t *flag, hipStream_t s) {
-    if (nc) k_apply_flags<<<nblk(nc), 256, 0, s>>>(nc, mask, flag);
+template <int D>
+void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned *fcount, int64_t nflag,
+                        int64_t max_deg, hipStream_t s) {
+    auto grid = [](int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384)); };
+    const int64_t nnodes = std::min<int64_t>(a.nn, (D + 1) * nflag);
+    const int64_t ncells = std::min<int64_t>(a.nc, nnodes * max_deg);
+    k_apply_list<<<grid(nflag), 256, 0, s>>>(const_cast<uint8_t *>(a.mask), flist, fcount);
+    k_predict_list<D><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+    k_mark_nodes<D><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+    k_node_solve_list<D><<<grid(nnodes), 256, 0, s>>>(a);
+    k_mark_cells<D><<<grid(nnodes), 256, 0, s>>>(a);
+    k_update_list<D><<<grid(ncells), 256, 0, s>>>(a);
 }
-void launch_dt_reduce(int64_t nc, const double *dtc, const int32_t *cell_mesh, double *red, int n_mesh,
-                      hipStream_t s) {
+void launch_dt_reduce(int64_t nc, const double *dtc, const int32_t *cell_mesh, const uint8_t *pstat, double *red,
+                      double *part, const int64_t *mesh_cell_off, int n_mesh, unsigned *bad_count, hipStream_t s) {
     k_fill<<<nblk(2 * n_mesh), 256, 0, s>>>(red, 2 * n_mesh, __builtin_huge_val());
-    if (nc) k_dt_reduce<<<nblk(nc), 256, 0, s>>>(nc, dtc, cell_mesh, red);
+    if (nc) {
+        k_dt_reduce<<<nblk(nc), 256, 0, s>>>(nc, dtc, cell_mesh, pstat, red, part, bad_count);
+        k_dt_reduce2<<<n_mesh, 256, 0, s>>>(n_mesh, mesh_cell_off, part, red);
+    }
 }
 void launch_dt_finalize(int n_mesh, const double *red, const double *dt, const hl_params &p, int first,
                         double *dt_next, double *parts, hipStream_t s) {
@@ -848,7 +978,7 @@ int64_t launch_diag(const StepArgs &a, const double *tau, const double *v, const
                     double *part, double *out, hipStream_t s) {
     int64_t nb = nblk(a.nc);
     if (a.nc) k_diag<D><<<nb, 256, 0, s>>>(a.nc, a.mass, tau, v, e, B, a.rho0, a.mu, a.K, a.mask, part);
-    k_diag_finalize<<<1, 64, 0, s>>>(a.nc ? nb : 0, part, out);
+    k_diag_finalize<<<NDIAG, 256, 0, s>>>(a.nc ? nb : 0, part, out);
     return nb;
 }
 void launch_fill(double *p, int64_t n, double v, hipStream_t s) {
@@ -875,6 +1005,10 @@ template void launch_node_solve<2>(const StepArgs &, hipStream_t);
 template void launch_node_solve<3>(const StepArgs &, hipStream_t);
 template void launch_update<2>(const StepArgs &, hipStream_t);
 template void launch_update<3>(const StepArgs &, hipStream_t);
+template void launch_mood_sparse<2>(const StepArgs &, const int32_t *, const unsigned *, int64_t, int64_t,
+                                    hipStream_t);
+template void launch_mood_sparse<3>(const StepArgs &, const int32_t *, const unsigned *, int64_t, int64_t,
+                                    hipStream_t);
 template void launch_acoustic<2>(const StepArgs &, hipStream_t);
 template void launch_acoustic<3>(const StepArgs &, hipStream_t);
 template int64_t launch_diag<2>(const StepArgs &, const double *, const double *, const double *, const double *,

@@ -23,7 +23,8 @@ FIELDS = dict(x=HL_X, vhat=HL_VHAT, tau=HL_TAU, v=HL_V, e=HL_E, B=HL_B, vstar=HL
 # every exported symbol of the C-ABI
 EXPORTS = ["hl_create", "hl_destroy", "hl_mesh_upload", "hl_state_init", "hl_set_params",
            "hl_compute_dt", "hl_step", "hl_step_replay", "hl_query", "hl_upload_field",
-           "hl_profile_enable", "hl_profile_reset", "hl_profile_get", "hl_status_str"]
+           "hl_profile_enable", "hl_profile_reset", "hl_profile_get", "hl_status_str",
+           "hl_last_error"]
 
 
 class Params(C.Structure):
@@ -70,6 +71,8 @@ def load():
     vp, i64, dp = C.c_void_p, C.c_int64, C.c_double
     L.hl_status_str.restype = C.c_char_p
     L.hl_status_str.argtypes = [C.c_int]
+    L.hl_last_error.restype = C.c_char_p
+    L.hl_last_error.argtypes = []
     L.hl_create.argtypes = [C.POINTER(vp), C.c_int, vp]
     L.hl_destroy.argtypes = [vp]
     L.hl_mesh_upload.argtypes = [vp, C.c_int, i64, vp, i64, vp, vp, vp, C.c_int]
@@ -84,7 +87,7 @@ def load():
     L.hl_profile_reset.argtypes = [vp]
     L.hl_profile_get.argtypes = [vp, C.c_char_p, C.POINTER(dp), C.POINTER(i64)]
     for name in EXPORTS:
-        if name != "hl_status_str":
+        if name not in ("hl_status_str", "hl_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -93,6 +96,8 @@ def load():
 def _check(rc, what):
     if rc < 0:
         msg = load().hl_status_str(rc).decode()
+        if rc == -5:
+            msg += ": " + load().hl_last_error().decode()
         raise HyperLagError(f"{what} failed: {msg} ({rc})")
     return rc
 
