@@ -28,7 +28,7 @@ if ROOT not in sys.path:
 METRIC = "FP64 cell-updates/s per Lagrangian step; adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-PROFILED = ("centroids", "node_agg", "predict", "node_solve", "update", "reduce")
+PROFILED = ("pack", "node_agg", "predict", "node_solve", "update", "mood_sparse", "reduce")
 
 
 def workloads():
@@ -55,8 +55,8 @@ def kernel_bytes(dim, nc, nn):
     na = 1 + d + nms + nW + d * nW + 2
     csr = 4 * (nn + 1) + 4 * ncor
     return {
-        "centroids": 4 * ncor + 8 * d * nn + 8 * d * nc,
-        "node_agg": csr + 8 * d * nn + 8 * d * nc + 8 * nW * nc + 8 * na * nn,
+        "pack": 4 * ncor + 8 * d * nn + 8 * nW * nc + 8 * (nW + d) * nc,
+        "node_agg": csr + 8 * d * nn + 8 * (nW + d) * nc + 8 * na * nn,
         "predict": 4 * ncor + 8 * d * nn + 8 * nW * nc + 24 * nc + nc + 8 * na * nn + 8 * cw * ncor,
         "node_solve": csr + 8 * cw * ncor + nn + 16 * d * nn + 24 * d * nn,
         "update": (4 * ncor + 40 * d * nn + 8 * cw * ncor + 8 * (nW + 1) * nc + 32 * nc + nc

@@ -18,7 +18,7 @@
 namespace {
 
 enum { PK_CENTROIDS = 0, PK_NODE_AGG, PK_PREDICT, PK_NODE_SOLVE, PK_UPDATE, PK_MOOD, PK_REDUCE, PK_COUNT };
-const char *kProfNames[PK_COUNT] = {"centroids", "node_agg", "predict", "node_solve", "update", "mood_sparse",
+const char *kProfNames[PK_COUNT] = {"pack", "node_agg", "predict", "node_solve", "update", "mood_sparse",
                                     "reduce"};
 
 struct Prof {
@@ -588,7 +588,7 @@ hl_status hl_mesh_upload(hl_ctx *c, int dim, int64_t n_nodes, const double *x0, 
         A_(c->B[b], ncl * nB);
     }
     A_(c->vstar, nn * dim);
-    A_(c->xc, ncl * dim);
+    A_(c->xc, ncl * (dim == 3 ? hl::Dims<3>::GR : hl::Dims<2>::GR));
     A_(c->agg, nn * NA);
     A_(c->corner, ncor * CW);
     A_(c->dtc, 2 * ncl);

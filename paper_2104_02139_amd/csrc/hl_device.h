@@ -25,6 +25,7 @@ struct Dims {
     static constexpr int O_SYW = O_SW + NW;
     static constexpr int O_RMM = O_SYW + D * NW;
     static constexpr int NA = O_RMM + 2;             // 52 (3D) / 26 (2D)
+    static constexpr int GR = D == 3 ? 16 : 10;      // gather record: W, centroid, pad
 };
 
 // index of the symmetric entry (i, j) in the 6-vector

@@ -27,25 +27,50 @@ __device__ __forceinline__ int64_t gtid() {
     return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 }
 
+// Workgroups are dealt to the 8 XCDs round robin.  Launched with a block
+// count that is a multiple of 8, this remapping hands every XCD one
+// contiguous eighth of the index range, so blocks that share mesh nodes
+// share an L2.
+__device__ __forceinline__ int64_t gtid_xcd() {
+    const unsigned per = gridDim.x >> 3;
+    const unsigned b = blockIdx.x;
+    return ((int64_t)(b & 7u) * per + (b >> 3)) * blockDim.x + threadIdx.x;
+}
+
 __device__ __forceinline__ double mesh_dt(const double *dtm, const int32_t *mesh_id, int64_t i) {
     return dtm[mesh_id ? mesh_id[i] : 0];
 }
 
-// ----------------------------------------------------------- centroids
+// ------------------------------------------------------- gather record
+// Per cell, one 128-byte record {W = (tau, v, B stored comps), centroid}
+// read by the node-aggregate gather (one cache line per neighbour instead
+// of one per scalar array).
 template <int D>
-__global__ __launch_bounds__(256) void k_centroids(int64_t nc, int64_t nn, const int32_t *__restrict__ c2n,
-                                                   const double *__restrict__ x, double *__restrict__ xc) {
-    int64_t c = gtid();
-    if (c >= nc) return;
+__global__ __launch_bounds__(256) void k_pack(StepArgs a) {
+    using Dm = Dims<D>;
+    const int64_t c = gtid_xcd();
+    if (c >= a.nc) return;
+    const int64_t nc = a.nc, nn = a.nn;
     double s[D] = {};
 #pragma unroll
     for (int k = 0; k <= D; ++k) {
-        int64_t p = c2n[c * (D + 1) + k];
+        int64_t p = a.c2n[c * (D + 1) + k];
 #pragma unroll
-        for (int i = 0; i < D; ++i) s[i] += x[i * nn + p];
+        for (int i = 0; i < D; ++i) s[i] += a.x[i * nn + p];
     }
+    double r[Dm::GR];
+    r[0] = a.tau[c];
 #pragma unroll
-    for (int i = 0; i < D; ++i) xc[i * nc + c] = s[i] * (1.0 / (D + 1));
+    for (int i = 0; i < D; ++i) r[1 + i] = a.v[i * nc + c];
+#pragma unroll
+    for (int q = 0; q < Dm::NB; ++q) r[1 + D + q] = a.B[q * nc + c];
+#pragma unroll
+    for (int i = 0; i < D; ++i) r[Dm::NW + i] = s[i] * (1.0 / (D + 1));
+#pragma unroll
+    for (int q = Dm::NW + D; q < Dm::GR; ++q) r[q] = 0.0;
+    double2 *o = reinterpret_cast<double2 *>(a.xc + c * Dm::GR);
+#pragma unroll
+    for (int q = 0; q < Dm::GR / 2; ++q) o[q] = make_double2(r[2 * q], r[2 * q + 1]);
 }
 
 // ------------------------------------------------ node aggregates (R8)
@@ -55,13 +80,11 @@ __global__ __launch_bounds__(256) void k_centroids(int64_t nc, int64_t nn, const
 // least-squares normal equations over all cells sharing a node with it
 // (one visit per shared node) from the aggregates of its own nodes.
 template <int D>
-__global__ __launch_bounds__(256) void k_node_agg(int64_t nn, int64_t nc, const int32_t *__restrict__ off,
+__global__ __launch_bounds__(256) void k_node_agg(int64_t nn, const int32_t *__restrict__ off,
                                                   const int32_t *__restrict__ n2c, const double *__restrict__ x,
-                                                  const double *__restrict__ xc, const double *__restrict__ tau,
-                                                  const double *__restrict__ v, const double *__restrict__ B,
-                                                  double *__restrict__ agg) {
+                                                  const double *__restrict__ rec, double *__restrict__ agg) {
     using Dm = Dims<D>;
-    int64_t p = gtid();
+    int64_t p = gtid_xcd();
     if (p >= nn) return;
     double xp[D];
 #pragma unroll
@@ -71,15 +94,20 @@ __global__ __launch_bounds__(256) void k_node_agg(int64_t nn, int64_t nc, const 
     const int32_t q0 = off[p], q1 = off[p + 1];
     for (int32_t q = q0; q < q1; ++q) {
         const int64_t j = n2c[q] / (D + 1);
+        const double2 *rj = reinterpret_cast<const double2 *>(rec + j * Dm::GR);
+        double rr[Dm::GR];
+#pragma unroll
+        for (int h = 0; h < Dm::GR / 2; ++h) {
+            const double2 t = rj[h];
+            rr[2 * h] = t.x;
+            rr[2 * h + 1] = t.y;
+        }
         double y[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) y[i] = xc[i * nc + j] - xp[i];
+        for (int i = 0; i < D; ++i) y[i] = rr[Dm::NW + i] - xp[i];
         double W[Dm::NW];
-        W[0] = tau[j];
 #pragma unroll
-        for (int i = 0; i < D; ++i) W[1 + i] = v[i * nc + j];
-#pragma unroll
-        for (int s = 0; s < Dm::NB; ++s) W[1 + D + s] = B[s * nc + j];
+        for (int w = 0; w < Dm::NW; ++w) W[w] = rr[w];
         n += 1.0;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
@@ -373,7 +401,7 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
 
 template <int D>
 __global__ __launch_bounds__(256) void k_predict(StepArgs a) {
-    const int64_t c = gtid();
+    const int64_t c = gtid_xcd();
     if (c < a.nc) predict_cell<D>(a, c);
 }
 
@@ -470,7 +498,7 @@ __device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t 
 
 template <int D>
 __global__ __launch_bounds__(256) void k_node_solve(StepArgs a) {
-    const int64_t p = gtid();
+    const int64_t p = gtid_xcd();
     if (p < a.nn) node_solve_one<D>(a, p);
 }
 
@@ -632,7 +660,7 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
 
 template <int D>
 __global__ __launch_bounds__(256) void k_update(StepArgs a) {
-    const int64_t c = gtid();
+    const int64_t c = gtid_xcd();
     if (c < a.nc) update_cell<D>(a, c);
 }
 
@@ -923,26 +951,28 @@ __global__ void k_stress_query(int64_t nc, const double *__restrict__ tau, const
 
 // ---------------------------------------------------------- launchers
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+// block count rounded up to a multiple of 8 for gtid_xcd()
+static inline unsigned nblk8(int64_t n) { return (unsigned)(((n + 255) / 256 + 7) / 8 * 8); }
 
 template <int D>
 void launch_centroids(const StepArgs &a, hipStream_t s) {
-    if (a.nc) k_centroids<D><<<nblk(a.nc), 256, 0, s>>>(a.nc, a.nn, a.c2n, a.x, a.xc);
+    if (a.nc) k_pack<D><<<nblk8(a.nc), 256, 0, s>>>(a);
 }
 template <int D>
 void launch_node_agg(const StepArgs &a, hipStream_t s) {
-    if (a.nn) k_node_agg<D><<<nblk(a.nn), 256, 0, s>>>(a.nn, a.nc, a.n2c_off, a.n2c, a.x, a.xc, a.tau, a.v, a.B, a.agg);
+    if (a.nn) k_node_agg<D><<<nblk8(a.nn), 256, 0, s>>>(a.nn, a.n2c_off, a.n2c, a.x, a.xc, a.agg);
 }
 template <int D>
 void launch_predict(const StepArgs &a, hipStream_t s) {
-    if (a.nc) k_predict<D><<<nblk(a.nc), 256, 0, s>>>(a);
+    if (a.nc) k_predict<D><<<nblk8(a.nc), 256, 0, s>>>(a);
 }
 template <int D>
 void launch_node_solve(const StepArgs &a, hipStream_t s) {
-    if (a.nn) k_node_solve<D><<<nblk(a.nn), 256, 0, s>>>(a);
+    if (a.nn) k_node_solve<D><<<nblk8(a.nn), 256, 0, s>>>(a);
 }
 template <int D>
 void launch_update(const StepArgs &a, hipStream_t s) {
-    if (a.nc) k_update<D><<<nblk(a.nc), 256, 0, s>>>(a);
+    if (a.nc) k_update<D><<<nblk8(a.nc), 256, 0, s>>>(a);
 }
 template <int D>
 void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned *fcount, int64_t nflag,
