@@ -131,6 +131,52 @@ def cpu_baseline(name, budget_s=25.0):
             "kind": "oracle", "sample": f"{sample}; {steps} steps in {el:.1f} s"}
 
 
+def batch_measure(steps=5, warmup=2, n_meshes=256):
+    """Many independent meshes (a seeded mix of 2D and 3D, log-uniform
+    sizes in [5e3, 2e5] cells): one batched context per dimension, one
+    launch per stage over all meshes, per-mesh CFL dt; against the same
+    meshes stepped one after another on the same stream."""
+    import torch
+    from paper_2104_02139_amd import hyperlag as H
+    from paper_2104_02139_amd import workloads as W
+    ws = W.mesh_family(n_meshes)
+    total = sum(w.n_cells for w in ws)
+    stream = torch.cuda.current_stream()
+    groups = [[w for w in ws if w.dim == d] for d in (2, 3)]
+    bctx = [H.from_workloads(g, stream=stream) for g in groups if g]
+    for c in bctx:
+        c.compute_dt()
+    for _ in range(warmup):
+        for c in bctx:
+            c.step_batch(None, info=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for c in bctx:
+            c.step_batch(None, info=False)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    del bctx
+    singles = [H.from_workload(w, stream=stream) for w in ws]
+    for c in singles:
+        c.compute_dt()
+    for _ in range(warmup):
+        for c in singles:
+            c.step(0.0, info=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for c in singles:
+            c.step(0.0, info=False)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    return {"workload": f"mesh_family_{n_meshes}", "n_meshes": n_meshes, "n_cells_total": total,
+            "n_2d": len(groups[0]), "n_3d": len(groups[1]), "steps": steps,
+            "batched_cell_updates_per_s": total * steps / tb,
+            "sequential_cell_updates_per_s": total * steps / ts,
+            "speedup": ts / tb}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +184,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="impact_bar_graded_8.1M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the many-mesh batched-vs-sequential measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -236,6 +284,9 @@ def main():
         "adjoint_forward_ratio": None,
         "kernel_source_sha1": kernel_source_hash(),
     }
+    if not args.no_batch:
+        print("[bench] batched many-mesh step vs mesh-after-mesh launches", file=sys.stderr, flush=True)
+        out["batch"] = batch_measure()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(name)

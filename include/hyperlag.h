@@ -108,6 +108,17 @@ hl_status hl_create(hl_ctx **out, int device, void *hip_stream);
 /* Free every device buffer and the context.  NULL is accepted. */
 hl_status hl_destroy(hl_ctx *ctx);
 
+/* Batch of independent meshes of one dimension in one context: every stage
+ * of hl_step runs as one launch over all of them, the CFL reduction gives
+ * one dt per mesh (not in the paper: a throughput mode for many small
+ * meshes).  node_offsets / cell_offsets: [n_meshes + 1] host arrays, first
+ * entry 0, non-decreasing; x0, nwall, normals and the per-cell arrays of
+ * hl_state_init are the meshes' arrays concatenated in order; `cells`
+ * holds mesh-local node numbers (0 .. nodes of that mesh - 1). */
+hl_status hl_mesh_upload_batch(hl_ctx *ctx, int dim, int n_meshes, const int64_t *node_offsets,
+                               const int64_t *cell_offsets, const double *x0, const int32_t *cells,
+                               const uint8_t *nwall, const double *normals, int on_device);
+
 /* Upload a simplicial mesh (Section 3.1, "Mesh and notation").
  *   dim           2 (triangles) or 3 (tetrahedra)
  *   x0            [n_nodes][dim] initial node positions
@@ -149,6 +160,15 @@ hl_status hl_compute_dt(hl_ctx *ctx, double *dt_out);
  * HL_WARN_PARACHUTE_INADMISSIBLE (with the step applied) if a first-order
  * cell is not physically admissible. */
 hl_status hl_step(hl_ctx *ctx, double dt, hl_step_info *info_or_null);
+
+/* One step of every mesh of a batch with its own dt: dt_per_mesh is
+ * [n_meshes] (host or device), or NULL for each mesh's CFL-controlled dt
+ * computed on the device by the previous step (eqs. CFL, CFL2). */
+hl_status hl_step_batch(hl_ctx *ctx, const double *dt_per_mesh, int on_device,
+                        hl_step_info *info_or_null);
+
+/* The next dt of every mesh, [n_meshes] (n_meshes must match). */
+hl_status hl_query_dt(hl_ctx *ctx, double *dt_next, int n_meshes, int on_device);
 
 /* One step with a frozen cascade choice: mask[c] = 1 advances cell c at
  * first order, 0 at second order; no detection.  mask: [n_cells] uint8. */

@@ -44,6 +44,8 @@ struct hl_ctx {
     double *allow = nullptr;
     std::vector<double> x0_host;
     std::vector<int32_t> c2n_host;
+    std::vector<int64_t> cell_off_host, node_off_host;
+    int32_t *cell_mesh = nullptr, *node_mesh = nullptr;
     // material
     double *mass = nullptr, *rho0 = nullptr, *mu = nullptr, *K = nullptr;
     // state, double buffered
@@ -115,6 +117,7 @@ void free_all(hl_ctx *c) {
     c->mask = c->pstat = nullptr;
     c->flist[0] = c->flist[1] = c->nlist = c->clist = c->nstamp = c->cstamp = nullptr;
     c->mesh_cell_off = nullptr;
+    c->cell_mesh = c->node_mesh = nullptr;
     c->dt_part = nullptr;
     c->stamp = 0;
     c->counters = nullptr;
@@ -236,8 +239,8 @@ hl::StepArgs make_args(hl_ctx *c, int src) {
     a.rho0 = c->rho0;
     a.mu = c->mu;
     a.K = c->K;
-    a.cell_mesh = nullptr;
-    a.node_mesh = nullptr;
+    a.cell_mesh = c->cell_mesh;
+    a.node_mesh = c->node_mesh;
     a.dt = c->dt_cur;
     a.x = c->x[src];
     a.vhat = c->vhat[src];
@@ -384,7 +387,7 @@ hl_status run_step(hl_ctx *c, const uint8_t *replay_mask, int mask_on_device, hl
         fb = nb;
     }
     PROF(c, PK_REDUCE, {
-        hl::launch_dt_reduce(c->nc, c->dtc, nullptr, c->pstat, c->dt_red, c->dt_part, c->mesh_cell_off, c->n_mesh,
+        hl::launch_dt_reduce(c->nc, c->dtc, c->cell_mesh, c->pstat, c->dt_red, c->dt_part, c->mesh_cell_off, c->n_mesh,
                              c->counters + hl::CNT_BAD, s);
         hl::launch_dt_finalize(c->n_mesh, c->dt_red, c->dt_cur, c->prm, 0, c->dt_next, c->dt_parts, s);
     });
@@ -507,28 +510,48 @@ hl_status hl_destroy(hl_ctx *c) {
     return HL_OK;
 }
 
-hl_status hl_mesh_upload(hl_ctx *c, int dim, int64_t n_nodes, const double *x0, int64_t n_cells,
-                         const int32_t *cells, const uint8_t *nwall, const double *normals, int on_device) {
-    if (!c || (dim != 2 && dim != 3) || n_nodes < 0 || n_cells < 0) return HL_E_INVALID;
-    if (n_cells * (dim + 1) >= (int64_t)INT32_MAX) return HL_E_INVALID;
-    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
-    const int nv = dim + 1;
-    std::vector<double> xh, nrm;
-    std::vector<int32_t> ch;
+}  // extern "C"
+
+namespace {
+
+// Mesh inputs brought to the host, cells in global node numbering.
+struct HostMesh {
+    std::vector<double> x, nrm;
+    std::vector<int32_t> cells;
     std::vector<uint8_t> nw;
+};
+
+hl_status gather_mesh(int dim, int64_t n_nodes, const double *x0, int64_t n_cells, const int32_t *cells,
+                      const uint8_t *nwall, const double *normals, int on_device, HostMesh &h) {
+    const int nv = dim + 1;
     hl_status st;
-    if ((st = to_host(x0, (size_t)(n_nodes * dim), on_device, xh)) != HL_OK) return st;
-    if ((st = to_host(cells, (size_t)(n_cells * nv), on_device, ch)) != HL_OK) return st;
+    if ((st = to_host(x0, (size_t)(n_nodes * dim), on_device, h.x)) != HL_OK) return st;
+    if ((st = to_host(cells, (size_t)(n_cells * nv), on_device, h.cells)) != HL_OK) return st;
     if (nwall) {
-        if ((st = to_host(nwall, (size_t)n_nodes, on_device, nw)) != HL_OK) return st;
+        if ((st = to_host(nwall, (size_t)n_nodes, on_device, h.nw)) != HL_OK) return st;
         if (!normals) return HL_E_INVALID;
-        if ((st = to_host(normals, (size_t)(n_nodes * dim * dim), on_device, nrm)) != HL_OK) return st;
+        if ((st = to_host(normals, (size_t)(n_nodes * dim * dim), on_device, h.nrm)) != HL_OK) return st;
     } else {
-        nw.assign((size_t)n_nodes, 0);
-        nrm.assign((size_t)(n_nodes * dim * dim), 0.0);
+        h.nw.assign((size_t)n_nodes, 0);
+        h.nrm.assign((size_t)(n_nodes * dim * dim), 0.0);
     }
-    for (int64_t q = 0; q < n_cells * nv; ++q)
-        if (ch[q] < 0 || ch[q] >= n_nodes) return HL_E_INVALID;
+    return HL_OK;
+}
+
+// Validate, build the node -> corner lists and wall bases, allocate the
+// device buffers and upload.  node_off / cell_off delimit the meshes of a
+// batch (n_mesh >= 1); cells already use global node numbers.
+hl_status upload_impl(hl_ctx *c, int dim, int n_mesh, const std::vector<int64_t> &node_off,
+                      const std::vector<int64_t> &cell_off, HostMesh &h) {
+    const int nv = dim + 1;
+    const int64_t n_nodes = node_off[n_mesh], n_cells = cell_off[n_mesh];
+    std::vector<double> &xh = h.x, &nrm = h.nrm;
+    std::vector<int32_t> &ch = h.cells;
+    std::vector<uint8_t> &nw = h.nw;
+    hl_status st;
+    for (int m = 0; m < n_mesh; ++m)
+        for (int64_t q = cell_off[m] * nv; q < cell_off[m + 1] * nv; ++q)
+            if (ch[q] < node_off[m] || ch[q] >= node_off[m + 1]) return HL_E_INVALID;
     for (int64_t p = 0; p < n_nodes; ++p)
         if (nw[p] > dim) return HL_E_INVALID;
     for (double v : xh)
@@ -558,7 +581,7 @@ hl_status hl_mesh_upload(hl_ctx *c, int dim, int64_t n_nodes, const double *x0, 
     c->dim = dim;
     c->nn = n_nodes;
     c->nc = n_cells;
-    c->n_mesh = 1;
+    c->n_mesh = n_mesh;
     const size_t nn = (size_t)n_nodes, ncl = (size_t)n_cells, ncor = ncl * nv;
     const int NA = dim == 3 ? hl::Dims<3>::NA : hl::Dims<2>::NA;
     const int CW = dim == 3 ? hl::Dims<3>::CW : hl::Dims<2>::CW;
@@ -600,13 +623,17 @@ hl_status hl_mesh_upload(hl_ctx *c, int dim, int64_t n_nodes, const double *x0, 
     A_(c->clist, ncl);
     A_(c->nstamp, nn);
     A_(c->cstamp, ncl);
-    A_(c->mesh_cell_off, 2);
+    A_(c->mesh_cell_off, (size_t)n_mesh + 1);
+    if (n_mesh > 1) {
+        A_(c->cell_mesh, ncl);
+        A_(c->node_mesh, nn);
+    }
     A_(c->dt_part, 2 * (ncl / 256 + 2));
     A_(c->counters, hl::CNT_N);
-    A_(c->dt_cur, 16);
-    A_(c->dt_next, 16);
-    A_(c->dt_red, 32);
-    A_(c->dt_parts, 32);
+    A_(c->dt_cur, (size_t)n_mesh);
+    A_(c->dt_next, (size_t)n_mesh);
+    A_(c->dt_red, 2 * (size_t)n_mesh);
+    A_(c->dt_parts, 2 * (size_t)n_mesh);
     A_(c->diag_part, 8 * (ncl / 256 + 2));
     A_(c->diag_out, 16);
     c->scratch_bytes = std::max<size_t>(sizeof(double) * std::max(nn * dim, ncl * 6), 256);
@@ -630,9 +657,22 @@ hl_status hl_mesh_upload(hl_ctx *c, int dim, int64_t n_nodes, const double *x0, 
     if (nn) HIPCHK(hipMemsetAsync(c->nstamp, 0, sizeof(int32_t) * nn, s));
     if (ncl) HIPCHK(hipMemsetAsync(c->cstamp, 0, sizeof(int32_t) * ncl, s));
     if (ncl) HIPCHK(hipMemsetAsync(c->pstat, 0, ncl, s));
-    const int64_t mco[2] = {0, n_cells};
-    HIPCHK(hipMemcpyAsync(c->mesh_cell_off, mco, sizeof mco, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->mesh_cell_off, cell_off.data(), sizeof(int64_t) * (n_mesh + 1), hipMemcpyHostToDevice,
+                          s));
+    std::vector<int32_t> cm, nm;
+    if (n_mesh > 1) {
+        cm.resize(ncl);
+        nm.resize(nn);
+        for (int m = 0; m < n_mesh; ++m) {
+            for (int64_t q = cell_off[m]; q < cell_off[m + 1]; ++q) cm[q] = m;
+            for (int64_t q = node_off[m]; q < node_off[m + 1]; ++q) nm[q] = m;
+        }
+        if (ncl) HIPCHK(hipMemcpyAsync(c->cell_mesh, cm.data(), sizeof(int32_t) * ncl, hipMemcpyHostToDevice, s));
+        if (nn) HIPCHK(hipMemcpyAsync(c->node_mesh, nm.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, s));
+    }
     HIPCHK(hipStreamSynchronize(s));
+    c->cell_off_host = cell_off;
+    c->node_off_host = node_off;
     c->max_deg = 0;
     for (int64_t p = 0; p < n_nodes; ++p) c->max_deg = std::max<int64_t>(c->max_deg, off[p + 1] - off[p]);
     c->stamp = 0;
@@ -643,6 +683,47 @@ hl_status hl_mesh_upload(hl_ctx *c, int dim, int64_t n_nodes, const double *x0, 
     c->have_mesh = true;
     c->have_state = false;
     return HL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hl_status hl_mesh_upload(hl_ctx *c, int dim, int64_t n_nodes, const double *x0, int64_t n_cells,
+                         const int32_t *cells, const uint8_t *nwall, const double *normals, int on_device) {
+    if (!c || (dim != 2 && dim != 3) || n_nodes < 0 || n_cells < 0) return HL_E_INVALID;
+    if (n_cells * (dim + 1) >= (int64_t)INT32_MAX || n_nodes >= (int64_t)INT32_MAX) return HL_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    HostMesh h;
+    hl_status st = gather_mesh(dim, n_nodes, x0, n_cells, cells, nwall, normals, on_device, h);
+    if (st != HL_OK) return st;
+    std::vector<int64_t> no = {0, n_nodes}, co = {0, n_cells};
+    return upload_impl(c, dim, 1, no, co, h);
+}
+
+hl_status hl_mesh_upload_batch(hl_ctx *c, int dim, int n_meshes, const int64_t *node_offsets,
+                               const int64_t *cell_offsets, const double *x0, const int32_t *cells,
+                               const uint8_t *nwall, const double *normals, int on_device) {
+    if (!c || (dim != 2 && dim != 3) || n_meshes < 1 || !node_offsets || !cell_offsets) return HL_E_INVALID;
+    std::vector<int64_t> no(node_offsets, node_offsets + n_meshes + 1), co(cell_offsets, cell_offsets + n_meshes + 1);
+    if (no[0] != 0 || co[0] != 0) return HL_E_INVALID;
+    for (int m = 0; m < n_meshes; ++m)
+        if (no[m + 1] < no[m] || co[m + 1] < co[m]) return HL_E_INVALID;
+    const int64_t n_nodes = no[n_meshes], n_cells = co[n_meshes];
+    if (n_cells * (dim + 1) >= (int64_t)INT32_MAX || n_nodes >= (int64_t)INT32_MAX) return HL_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    HostMesh h;
+    hl_status st = gather_mesh(dim, n_nodes, x0, n_cells, cells, nwall, normals, on_device, h);
+    if (st != HL_OK) return st;
+    // mesh-local node numbers -> global
+    const int nv = dim + 1;
+    for (int m = 0; m < n_meshes; ++m)
+        for (int64_t q = co[m] * nv; q < co[m + 1] * nv; ++q) {
+            const int64_t g = (int64_t)h.cells[q] + no[m];
+            if (h.cells[q] < 0 || g >= no[m + 1]) return HL_E_INVALID;
+            h.cells[q] = (int32_t)g;
+        }
+    return upload_impl(c, dim, n_meshes, no, co, h);
 }
 
 hl_status hl_set_params(hl_ctx *c, const hl_params *p) {
@@ -739,7 +820,7 @@ hl_status hl_compute_dt(hl_ctx *c, double *dt_out) {
         hl::launch_acoustic<3>(a, s);
     else
         hl::launch_acoustic<2>(a, s);
-    hl::launch_dt_reduce(c->nc, c->dtc, nullptr, c->pstat, c->dt_red, c->dt_part, c->mesh_cell_off, c->n_mesh,
+    hl::launch_dt_reduce(c->nc, c->dtc, c->cell_mesh, c->pstat, c->dt_red, c->dt_part, c->mesh_cell_off, c->n_mesh,
                          c->counters + hl::CNT_N - 1, s);
     hl::launch_dt_finalize(c->n_mesh, c->dt_red, c->dt_cur, c->prm, 1, c->dt_next, c->dt_parts, s);
     double dt = 0.0;
@@ -767,6 +848,32 @@ static hl_status step_common(hl_ctx *c, double dt, const uint8_t *mask, int on_d
 }
 
 hl_status hl_step(hl_ctx *c, double dt, hl_step_info *info) { return step_common(c, dt, nullptr, 0, info); }
+
+hl_status hl_step_batch(hl_ctx *c, const double *dt_per_mesh, int on_device, hl_step_info *info) {
+    if (!c) return HL_E_INVALID;
+    if (!c->have_state) return HL_E_STATE;
+    if (!dt_per_mesh) return step_common(c, 0.0, nullptr, 0, info);
+    std::vector<double> h;
+    hl_status st = to_host(dt_per_mesh, (size_t)c->n_mesh, on_device, h);
+    if (st != HL_OK) return st;
+    for (double d : h)
+        if (!(d > 0.0) || !std::isfinite(d)) return HL_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    HIPCHK(hipMemcpyAsync(c->dt_next, h.data(), sizeof(double) * c->n_mesh, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return step_common(c, 0.0, nullptr, 0, info);
+}
+
+hl_status hl_query_dt(hl_ctx *c, double *dt_next, int n_meshes, int on_device) {
+    if (!c || !dt_next) return HL_E_INVALID;
+    if (!c->have_state) return HL_E_STATE;
+    if (n_meshes != c->n_mesh) return HL_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    HIPCHK(hipMemcpyAsync(dt_next, c->dt_next, sizeof(double) * c->n_mesh,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return HL_OK;
+}
 
 hl_status hl_step_replay(hl_ctx *c, double dt, const uint8_t *mask, int on_device, hl_step_info *info) {
     if (!mask && c && c->nc) return HL_E_INVALID;

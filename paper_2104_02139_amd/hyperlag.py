@@ -24,7 +24,7 @@ FIELDS = dict(x=HL_X, vhat=HL_VHAT, tau=HL_TAU, v=HL_V, e=HL_E, B=HL_B, vstar=HL
 EXPORTS = ["hl_create", "hl_destroy", "hl_mesh_upload", "hl_state_init", "hl_set_params",
            "hl_compute_dt", "hl_step", "hl_step_replay", "hl_query", "hl_upload_field",
            "hl_profile_enable", "hl_profile_reset", "hl_profile_get", "hl_status_str",
-           "hl_last_error"]
+           "hl_last_error", "hl_mesh_upload_batch", "hl_step_batch", "hl_query_dt"]
 
 
 class Params(C.Structure):
@@ -76,6 +76,9 @@ def load():
     L.hl_create.argtypes = [C.POINTER(vp), C.c_int, vp]
     L.hl_destroy.argtypes = [vp]
     L.hl_mesh_upload.argtypes = [vp, C.c_int, i64, vp, i64, vp, vp, vp, C.c_int]
+    L.hl_mesh_upload_batch.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, C.c_int]
+    L.hl_step_batch.argtypes = [vp, vp, C.c_int, C.POINTER(StepInfo)]
+    L.hl_query_dt.argtypes = [vp, vp, C.c_int, C.c_int]
     L.hl_state_init.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(Params), C.c_int]
     L.hl_set_params.argtypes = [vp, C.POINTER(Params)]
     L.hl_compute_dt.argtypes = [vp, C.POINTER(dp)]
@@ -155,6 +158,39 @@ class Context:
         _check(load().hl_mesh_upload(self._h, int(dim), nn, px, nc, pc, pw, pn, dev),
                "hl_mesh_upload")
         self.dim, self.n_nodes, self.n_cells = int(dim), nn, nc
+
+    def upload_mesh_batch(self, dim, node_offsets, cell_offsets, x, cells, nwall=None, normals=None):
+        """Concatenated meshes; ``cells`` in mesh-local node numbers."""
+        no = np.ascontiguousarray(node_offsets, dtype=np.int64)
+        co = np.ascontiguousarray(cell_offsets, dtype=np.int64)
+        px, kx, dev = _arg(x, np.float64)
+        pc, kc, _ = _arg(cells, np.int32)
+        pw, kw, _ = _arg(nwall, np.uint8)
+        pn, kn, _ = _arg(normals, np.float64)
+        _check(load().hl_mesh_upload_batch(self._h, int(dim), len(no) - 1,
+                                           no.ctypes.data_as(C.c_void_p), co.ctypes.data_as(C.c_void_p),
+                                           px, pc, pw, pn, dev), "hl_mesh_upload_batch")
+        self.dim, self.n_nodes, self.n_cells = int(dim), int(no[-1]), int(co[-1])
+        self.n_meshes = len(no) - 1
+        self.node_offsets, self.cell_offsets = no, co
+
+    def step_batch(self, dt_per_mesh=None, info=True):
+        inf = StepInfo() if info else None
+        if dt_per_mesh is None:
+            p, keep, dev = None, None, 0
+        else:
+            p, keep, dev = _arg(dt_per_mesh, np.float64)
+        rc = _check(load().hl_step_batch(self._h, p, dev, C.byref(inf) if info else None),
+                    "hl_step_batch")
+        out = inf.as_dict() if info else {}
+        out["rc"] = rc
+        return out
+
+    def next_dt(self):
+        n = getattr(self, "n_meshes", 1)
+        out = np.empty(n, dtype=np.float64)
+        _check(load().hl_query_dt(self._h, out.ctypes.data_as(C.c_void_p), n, 0), "hl_query_dt")
+        return out
 
     def init_state(self, rho0, mu, lam, v_cell, v_node, params=None):
         args = [_arg(a, np.float64) for a in (rho0, mu, lam, v_cell, v_node)]
@@ -244,6 +280,22 @@ class Context:
         _check(load().hl_profile_get(self._h, name.encode(), C.byref(ms), C.byref(n)),
                "hl_profile_get")
         return ms.value, n.value
+
+
+def from_workloads(ws, device=0, stream=None, params=None):
+    """One batched context from several workloads of the same dimension."""
+    dims = {w.dim for w in ws}
+    if len(dims) != 1:
+        raise ValueError("a batch holds meshes of one dimension")
+    dim = dims.pop()
+    no = np.concatenate([[0], np.cumsum([w.n_nodes for w in ws])])
+    co = np.concatenate([[0], np.cumsum([w.n_cells for w in ws])])
+    cat = lambda f: np.concatenate([getattr(w, f) for w in ws])
+    ctx = Context(device, stream)
+    ctx.upload_mesh_batch(dim, no, co, cat("x"), cat("cells"), cat("nwall"), cat("normals"))
+    ctx.init_state(cat("rho0"), cat("mu"), cat("lam"), cat("v_cell"), cat("v_node"),
+                   params if params is not None else default_params(dim, c_cfl=ws[0].c_cfl))
+    return ctx
 
 
 def from_workload(w, device=0, stream=None, params=None):
