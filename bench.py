@@ -134,8 +134,9 @@ def cpu_baseline(name, budget_s=25.0):
 def batch_measure(steps=5, warmup=2, n_meshes=256):
     """Many independent meshes (a seeded mix of 2D and 3D, log-uniform
     sizes in [5e3, 2e5] cells): one batched context per dimension, one
-    launch per stage over all meshes, per-mesh CFL dt; against the same
-    meshes stepped one after another on the same stream."""
+    launch per stage over all meshes, the step captured in a hipGraph,
+    per-mesh CFL dt; against the same meshes stepped one after another on
+    the same stream."""
     import torch
     from paper_2104_02139_amd import hyperlag as H
     from paper_2104_02139_amd import workloads as W
@@ -145,6 +146,7 @@ def batch_measure(steps=5, warmup=2, n_meshes=256):
     groups = [[w for w in ws if w.dim == d] for d in (2, 3)]
     bctx = [H.from_workloads(g, stream=stream) for g in groups if g]
     for c in bctx:
+        c.use_graph(True, 6)
         c.compute_dt()
     for _ in range(warmup):
         for c in bctx:

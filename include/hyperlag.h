@@ -175,6 +175,16 @@ hl_status hl_query_dt(hl_ctx *ctx, double *dt_next, int n_meshes, int on_device)
 hl_status hl_step_replay(hl_ctx *ctx, double dt, const uint8_t *mask, int on_device,
                          hl_step_info *info_or_null);
 
+/* Run each step as a captured hipGraph (one per buffer parity, built on
+ * first use): the first candidate, `max_mood_passes` sparse MOOD passes
+ * whose kernels read their list sizes from device memory (a pass with
+ * nothing to do exits at once) and the CFL reduction.  One host read per
+ * step checks for flags left after the captured passes; the fixpoint is
+ * then finished eagerly, so results equal the eager path's bitwise.
+ * Profiling (hl_profile_enable) and hl_step_replay run eagerly.
+ * max_mood_passes: 0..64. */
+hl_status hl_use_graph(hl_ctx *ctx, int on, int max_mood_passes);
+
 /* Copy a field of the current state to `out` (count = number of elements
  * of the field's type, checked). */
 hl_status hl_query(hl_ctx *ctx, int field, void *out, int64_t count, int on_device);

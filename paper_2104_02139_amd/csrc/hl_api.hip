@@ -55,8 +55,16 @@ struct hl_ctx {
     double *vstar = nullptr, *xc = nullptr, *agg = nullptr, *corner = nullptr, *dtc = nullptr;
     uint8_t *mask = nullptr, *pstat = nullptr;
     int32_t *flist[2] = {}, *nlist = nullptr, *clist = nullptr, *nstamp = nullptr, *cstamp = nullptr;
-    int32_t stamp = 0;
+    int32_t *stamp_dev = nullptr;   // device stamp of the current MOOD pass
+    int64_t stamp_host = 0;         // passes since the stamps were last cleared
+    unsigned *pass_log = nullptr;   // input flag count of each pass (graph mode)
     int64_t max_deg = 0;
+    // captured step, one per buffer parity
+    bool graph_on = false;
+    int graph_passes = 6;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int64_t *mesh_cell_off = nullptr;
     double *dt_part = nullptr;
     unsigned *counters = nullptr;
@@ -104,7 +112,17 @@ bool params_valid(const hl_params &p) {
     return p.c_cfl > 0 && p.c_v > 0 && p.c_i >= 0 && p.delta0 >= 0 && p.delta1 >= 0 && p.eps_tol >= 0;
 }
 
+void drop_graphs(hl_ctx *c) {
+    for (int b = 0; b < 2; ++b) {
+        if (c->gexec[b]) (void)hipGraphExecDestroy(c->gexec[b]);
+        if (c->graph[b]) (void)hipGraphDestroy(c->graph[b]);
+        c->gexec[b] = nullptr;
+        c->graph[b] = nullptr;
+    }
+}
+
 void free_all(hl_ctx *c) {
+    drop_graphs(c);
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->counters_host) (void)hipHostFree(c->counters_host);
@@ -119,7 +137,9 @@ void free_all(hl_ctx *c) {
     c->mesh_cell_off = nullptr;
     c->cell_mesh = c->node_mesh = nullptr;
     c->dt_part = nullptr;
-    c->stamp = 0;
+    c->stamp_dev = nullptr;
+    c->pass_log = nullptr;
+    c->stamp_host = 0;
     c->counters = nullptr;
     c->dt_cur = c->dt_next = c->dt_red = c->dt_parts = c->diag_part = c->diag_out = c->scratch = nullptr;
     c->have_mesh = c->have_state = false;
@@ -267,7 +287,7 @@ hl::StepArgs make_args(hl_ctx *c, int src) {
     a.clist = c->clist;
     a.nstamp = c->nstamp;
     a.cstamp = c->cstamp;
-    a.stamp = c->stamp;
+    a.stamp = c->stamp_dev;
     a.counters = c->counters;
     a.delta0 = c->prm.delta0;
     a.delta1 = c->prm.delta1;
@@ -322,77 +342,143 @@ void prof_collect(hl_ctx *c) {
     } while (0)
 
 template <int D>
-hl_status run_step(hl_ctx *c, const uint8_t *replay_mask, int mask_on_device, hl_step_info *info) {
+void enqueue_first(hl_ctx *c, hl::StepArgs &a, bool copy_dt, bool clear_mask, hipStream_t s) {
+    hl::launch_step_begin(c->counters, c->dt_cur, c->dt_next, c->n_mesh, copy_dt ? 1 : 0, s);
+    if (clear_mask) hl::launch_fill_u8(c->mask, c->nc, 0, s);
+    a.flist_out = c->flist[0];
+    a.fcount_out = c->counters + hl::CNT_F0;
+    PROF(c, PK_CENTROIDS, hl::launch_centroids<D>(a, s));
+    PROF(c, PK_NODE_AGG, hl::launch_node_agg<D>(a, s));
+    PROF(c, PK_PREDICT, hl::launch_predict<D>(a, s));
+    PROF(c, PK_NODE_SOLVE, hl::launch_node_solve<D>(a, s));
+    PROF(c, PK_UPDATE, hl::launch_update<D>(a, s));
+}
+
+// MOOD pass reading flag list fb: the flagged cells drop to first order and
+// only their corners, their nodes and the cells around those nodes change.
+template <int D>
+void enqueue_pass(hl_ctx *c, hl::StepArgs a, int fb, int pass, int64_t nflag, bool fixed, hipStream_t s) {
+    const int nb = 1 - fb;
+    hl::launch_pass_begin(c->counters, fb, c->stamp_dev, pass < 64 ? c->pass_log : nullptr, pass < 64 ? pass : 0,
+                          s);
+    a.flist_out = c->flist[nb];
+    a.fcount_out = c->counters + hl::CNT_F0 + nb;
+    PROF(c, PK_MOOD,
+         hl::launch_mood_sparse<D>(a, c->flist[fb], c->counters + hl::CNT_F0 + fb, nflag, c->max_deg, fixed, s));
+}
+
+void enqueue_reduce(hl_ctx *c, hipStream_t s) {
+    PROF(c, PK_REDUCE, {
+        hl::launch_dt_reduce(c->nc, c->dtc, c->cell_mesh, c->pstat, c->dt_red, c->dt_part, c->mesh_cell_off,
+                             c->n_mesh, c->counters + hl::CNT_BAD, s);
+        hl::launch_dt_finalize(c->n_mesh, c->dt_red, c->dt_cur, c->prm, 0, c->dt_next, c->dt_parts, s);
+    });
+}
+
+hl_status read_counters(hl_ctx *c, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(c->counters_host, c->counters, hl::CNT_N * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HL_OK;
+}
+
+template <int D>
+hl_status capture_step(hl_ctx *c, int src) {
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = c->cap_stream;
+    hl::StepArgs a = make_args(c, src);
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    enqueue_first<D>(c, a, true, true, cs);
+    for (int p = 0; p < c->graph_passes; ++p) enqueue_pass<D>(c, a, p & 1, p, 0, true, cs);
+    enqueue_reduce(c, cs);
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamEndCapture(cs, &g));
+    c->graph[src] = g;
+    HIPCHK(hipGraphInstantiate(&c->gexec[src], g, nullptr, nullptr, 0));
+    return HL_OK;
+}
+
+template <int D>
+hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on_device, hl_step_info *info) {
     hipStream_t s = c->stream;
     const int src = c->cur;
     hl::StepArgs a = make_args(c, src);
-    // start from a clean mask (or the frozen one)
-    if (replay_mask) {
-        if (c->nc) {
-            HIPCHK(hipMemcpyAsync(c->mask, replay_mask, (size_t)c->nc,
-                                  mask_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
-        }
-        a.detect = 0;
-    } else if (c->nc) {
-        HIPCHK(hipMemsetAsync(c->mask, 0, (size_t)c->nc, s));
-    }
     if (c->nc == 0) {
         // nothing moves: copy the node state through
-        for (int i = 0; i < 1; ++i) {
-            HIPCHK(hipMemcpyAsync(c->x[1 - src], c->x[src], sizeof(double) * c->nn * D, hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(c->vhat[1 - src], c->vhat[src], sizeof(double) * c->nn * D, hipMemcpyDeviceToDevice, s));
-        }
+        HIPCHK(hipMemcpyAsync(c->x[1 - src], c->x[src], sizeof(double) * c->nn * D, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(c->vhat[1 - src], c->vhat[src], sizeof(double) * c->nn * D, hipMemcpyDeviceToDevice, s));
         if (c->nn) HIPCHK(hipMemsetAsync(c->vstar, 0, sizeof(double) * c->nn * D, s));
         HIPCHK(hipStreamSynchronize(s));
         c->cur = 1 - src;
         if (info) std::memset(info, 0, sizeof(*info));
         return HL_OK;
     }
-    HIPCHK(hipMemsetAsync(c->counters, 0, hl::CNT_N * sizeof(unsigned), s));
-    PROF(c, PK_CENTROIDS, hl::launch_centroids<D>(a, s));
-    PROF(c, PK_NODE_AGG, hl::launch_node_agg<D>(a, s));
-    // first candidate: every cell at its current order
-    a.flist_out = c->flist[0];
-    a.fcount_out = c->counters + hl::CNT_F0;
-    PROF(c, PK_PREDICT, hl::launch_predict<D>(a, s));
-    PROF(c, PK_NODE_SOLVE, hl::launch_node_solve<D>(a, s));
-    PROF(c, PK_UPDATE, hl::launch_update<D>(a, s));
-    int iters = 1;
-    HIPCHK(hipMemcpyAsync(c->counters_host, c->counters, hl::CNT_N * sizeof(unsigned), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    int64_t nflag = c->counters_host[hl::CNT_F0];
-    const int64_t first = nflag;
-    int fb = 0;
-    // MOOD: cells flagged in the last candidate drop to first order; only
-    // their corners, their nodes and the cells around those nodes change
-    while (a.detect && nflag > 0) {
-        if (c->stamp >= INT32_MAX - 2) {
-            HIPCHK(hipMemsetAsync(c->nstamp, 0, sizeof(int32_t) * c->nn, s));
-            HIPCHK(hipMemsetAsync(c->cstamp, 0, sizeof(int32_t) * c->nc, s));
-            c->stamp = 0;
-        }
-        a.stamp = ++c->stamp;
-        const int nb = 1 - fb;
-        HIPCHK(hipMemsetAsync(c->counters + hl::CNT_F0 + nb, 0, sizeof(unsigned), s));
-        HIPCHK(hipMemsetAsync(c->counters + hl::CNT_NODES, 0, 2 * sizeof(unsigned), s));
-        a.flist_out = c->flist[nb];
-        a.fcount_out = c->counters + hl::CNT_F0 + nb;
-        PROF(c, PK_MOOD,
-             hl::launch_mood_sparse<D>(a, c->flist[fb], c->counters + hl::CNT_F0 + fb, nflag, c->max_deg, s));
-        ++iters;
-        HIPCHK(hipMemcpyAsync(c->counters_host, c->counters, hl::CNT_N * sizeof(unsigned), hipMemcpyDeviceToHost,
-                              s));
-        HIPCHK(hipStreamSynchronize(s));
-        nflag = c->counters_host[hl::CNT_F0 + nb];
-        fb = nb;
+    // stamps are 32-bit: clear them long before they could wrap
+    if (c->stamp_host > INT32_MAX - 4096) {
+        HIPCHK(hipMemsetAsync(c->nstamp, 0, sizeof(int32_t) * c->nn, s));
+        HIPCHK(hipMemsetAsync(c->cstamp, 0, sizeof(int32_t) * c->nc, s));
+        HIPCHK(hipMemsetAsync(c->stamp_dev, 0, sizeof(int32_t), s));
+        c->stamp_host = 0;
     }
-    PROF(c, PK_REDUCE, {
-        hl::launch_dt_reduce(c->nc, c->dtc, c->cell_mesh, c->pstat, c->dt_red, c->dt_part, c->mesh_cell_off, c->n_mesh,
-                             c->counters + hl::CNT_BAD, s);
-        hl::launch_dt_finalize(c->n_mesh, c->dt_red, c->dt_cur, c->prm, 0, c->dt_next, c->dt_parts, s);
-    });
-    HIPCHK(hipMemcpyAsync(c->counters_host, c->counters, hl::CNT_N * sizeof(unsigned), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    if (replay_mask) {
+        HIPCHK(hipMemcpyAsync(c->mask, replay_mask, (size_t)c->nc,
+                              mask_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        a.detect = 0;
+    }
+    const bool graph = c->graph_on && !replay_mask && !c->prof.on;
+    int iters = 1;
+    int64_t first = 0, nflag = 0;
+    int fb = 0, pass = 0;
+    if (graph) {
+        if (dt > 0.0) hl::launch_fill(c->dt_next, c->n_mesh, dt, s);
+        if (!c->gexec[src]) {
+            hl_status st = capture_step<D>(c, src);
+            if (st != HL_OK) return st;
+        }
+        HIPCHK(hipGraphLaunch(c->gexec[src], s));
+        c->stamp_host += c->graph_passes;
+        unsigned log[64];
+        const int np = std::min(c->graph_passes, 64);
+        if (np) HIPCHK(hipMemcpyAsync(log, c->pass_log, sizeof(unsigned) * np, hipMemcpyDeviceToHost, s));
+        hl_status st = read_counters(c, s);
+        if (st != HL_OK) return st;
+        pass = c->graph_passes;
+        fb = pass & 1;  // list written by the last pass
+        nflag = c->counters_host[hl::CNT_F0 + fb];
+        first = np ? log[0] : nflag;
+        for (int p = 0; p < np; ++p) iters += log[p] > 0;
+        if (a.detect && nflag > 0) {
+            // the captured passes did not reach the fixpoint: finish eagerly
+            while (nflag > 0) {
+                enqueue_pass<D>(c, a, fb, pass, nflag, false, s);
+                c->stamp_host++;
+                ++iters;
+                ++pass;
+                if ((st = read_counters(c, s)) != HL_OK) return st;
+                fb = 1 - fb;
+                nflag = c->counters_host[hl::CNT_F0 + fb];
+            }
+            enqueue_reduce(c, s);
+            if ((st = read_counters(c, s)) != HL_OK) return st;
+        }
+    } else {
+        if (dt > 0.0) hl::launch_fill(c->dt_cur, c->n_mesh, dt, s);
+        enqueue_first<D>(c, a, !(dt > 0.0), !replay_mask, s);
+        hl_status st = read_counters(c, s);
+        if (st != HL_OK) return st;
+        nflag = c->counters_host[hl::CNT_F0];
+        first = nflag;
+        while (a.detect && nflag > 0) {
+            enqueue_pass<D>(c, a, fb, pass, nflag, false, s);
+            c->stamp_host++;
+            ++iters;
+            ++pass;
+            if ((st = read_counters(c, s)) != HL_OK) return st;
+            fb = 1 - fb;
+            nflag = c->counters_host[hl::CNT_F0 + fb];
+        }
+        enqueue_reduce(c, s);
+        if ((st = read_counters(c, s)) != HL_OK) return st;
+    }
     const unsigned inadm = c->counters_host[hl::CNT_BAD];
     if (info) {
         std::memset(info, 0, sizeof(*info));
@@ -506,6 +592,7 @@ hl_status hl_destroy(hl_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
     free_all(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return HL_OK;
 }
@@ -630,6 +717,8 @@ hl_status upload_impl(hl_ctx *c, int dim, int n_mesh, const std::vector<int64_t>
     }
     A_(c->dt_part, 2 * (ncl / 256 + 2));
     A_(c->counters, hl::CNT_N);
+    A_(c->stamp_dev, 1);
+    A_(c->pass_log, 64);
     A_(c->dt_cur, (size_t)n_mesh);
     A_(c->dt_next, (size_t)n_mesh);
     A_(c->dt_red, 2 * (size_t)n_mesh);
@@ -675,7 +764,9 @@ hl_status upload_impl(hl_ctx *c, int dim, int n_mesh, const std::vector<int64_t>
     c->node_off_host = node_off;
     c->max_deg = 0;
     for (int64_t p = 0; p < n_nodes; ++p) c->max_deg = std::max<int64_t>(c->max_deg, off[p + 1] - off[p]);
-    c->stamp = 0;
+    HIPCHK(hipMemsetAsync(c->stamp_dev, 0, sizeof(int32_t), s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->stamp_host = 0;
     c->x0_host.swap(xh);
     c->c2n_host.swap(ch);
     c->cur = 0;
@@ -729,6 +820,7 @@ hl_status hl_mesh_upload_batch(hl_ctx *c, int dim, int n_meshes, const int64_t *
 hl_status hl_set_params(hl_ctx *c, const hl_params *p) {
     if (!c || !p || !params_valid(*p)) return HL_E_INVALID;
     c->prm = *p;
+    drop_graphs(c);
     return HL_OK;
 }
 
@@ -804,6 +896,7 @@ hl_status hl_state_init(hl_ctx *c, const double *rho0, const double *mu, const d
     if (nn) HIPCHK(hipMemsetAsync(c->vstar, 0, sizeof(double) * nn * d, s));
     HIPCHK(hipStreamSynchronize(s));
     c->prm = prm;
+    drop_graphs(c);
     c->have_state = true;
     double dt0;
     return hl_compute_dt(c, &dt0);
@@ -835,12 +928,7 @@ static hl_status step_common(hl_ctx *c, double dt, const uint8_t *mask, int on_d
     if (!c->have_state) return HL_E_STATE;
     if (!std::isfinite(dt)) return HL_E_INVALID;
     if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
-    hipStream_t s = c->stream;
-    if (dt > 0.0)
-        hl::launch_fill(c->dt_cur, c->n_mesh, dt, s);
-    else
-        HIPCHK(hipMemcpyAsync(c->dt_cur, c->dt_next, sizeof(double) * c->n_mesh, hipMemcpyDeviceToDevice, s));
-    hl_status st = c->dim == 3 ? run_step<3>(c, mask, on_device, info) : run_step<2>(c, mask, on_device, info);
+    hl_status st = c->dim == 3 ? run_step<3>(c, dt, mask, on_device, info) : run_step<2>(c, dt, mask, on_device, info);
     if (c->prof.on) prof_collect(c);
     hipError_t le = hipGetLastError();
     if (le != hipSuccess) return hip_fail(le, "kernel launch", __LINE__);
@@ -935,6 +1023,14 @@ hl_status hl_upload_field(hl_ctx *c, int field, const void *in, int64_t count, i
         hl::launch_aos_to_soa(n, w, c->scratch, dst, s);
     }
     HIPCHK(hipStreamSynchronize(s));
+    return HL_OK;
+}
+
+hl_status hl_use_graph(hl_ctx *c, int on, int max_mood_passes) {
+    if (!c || max_mood_passes < 0 || max_mood_passes > 64) return HL_E_INVALID;
+    if (c->graph_passes != max_mood_passes || !on) drop_graphs(c);
+    c->graph_on = on != 0;
+    c->graph_passes = max_mood_passes;
     return HL_OK;
 }
 

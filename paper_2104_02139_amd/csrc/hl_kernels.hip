@@ -683,12 +683,13 @@ template <int D>
 __global__ __launch_bounds__(256) void k_mark_nodes(StepArgs a, const int32_t *__restrict__ list,
                                                     const unsigned *__restrict__ count) {
     const int64_t n = *count;
+    const int32_t st = *a.stamp;
     for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = list[i];
 #pragma unroll
         for (int k = 0; k <= D; ++k) {
             const int32_t p = a.c2n[c * (D + 1) + k];
-            if (atomicExch(&a.nstamp[p], a.stamp) != a.stamp)
+            if (atomicExch(&a.nstamp[p], st) != st)
                 a.nlist[atomicAdd(&a.counters[CNT_NODES], 1u)] = p;
         }
     }
@@ -698,14 +699,40 @@ __global__ __launch_bounds__(256) void k_mark_nodes(StepArgs a, const int32_t *_
 template <int D>
 __global__ __launch_bounds__(256) void k_mark_cells(StepArgs a) {
     const int64_t n = a.counters[CNT_NODES];
+    const int32_t st = *a.stamp;
     for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t p = a.nlist[i];
         for (int32_t q = a.n2c_off[p]; q < a.n2c_off[p + 1]; ++q) {
             const int32_t j = a.n2c[q] / (D + 1);
-            if (atomicExch(&a.cstamp[j], a.stamp) != a.stamp)
+            if (atomicExch(&a.cstamp[j], st) != st)
                 a.clist[atomicAdd(&a.counters[CNT_CELLS], 1u)] = j;
         }
     }
+}
+
+// Start of a step: clear the counters, take the device-side dt.
+__global__ void k_step_begin(unsigned *__restrict__ counters, double *__restrict__ dt_cur,
+                             const double *__restrict__ dt_next, int n_mesh, int copy_dt) {
+    const int64_t i = gtid();
+    if (i < CNT_N) counters[i] = 0u;
+    if (copy_dt)
+        for (int64_t m = i; m < n_mesh; m += (int64_t)gridDim.x * blockDim.x) dt_cur[m] = dt_next[m];
+}
+
+// Start of a sparse MOOD pass reading flag list `in_list`: clear the output
+// list and the node/cell lists, advance the stamp, log the input count.
+__global__ void k_pass_begin(unsigned *__restrict__ counters, int in_list, int32_t *__restrict__ stamp,
+                             unsigned *__restrict__ log, int pass) {
+    if (gtid() != 0) return;
+    counters[CNT_F0 + (1 - in_list)] = 0u;
+    counters[CNT_NODES] = 0u;
+    counters[CNT_CELLS] = 0u;
+    *stamp = *stamp + 1;
+    if (log) log[pass] = counters[CNT_F0 + in_list];
+}
+
+__global__ void k_fill_u8(uint8_t *__restrict__ p, int64_t n, uint8_t v) {
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
 // -------------------------------------------------------- reductions
@@ -976,8 +1003,9 @@ void launch_update(const StepArgs &a, hipStream_t s) {
 }
 template <int D>
 void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned *fcount, int64_t nflag,
-                        int64_t max_deg, hipStream_t s) {
+                        int64_t max_deg, bool fixed_grid, hipStream_t s) {
     auto grid = [](int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384)); };
+    if (fixed_grid) nflag = std::min<int64_t>(a.nc, 256 * 1024);
     const int64_t nnodes = std::min<int64_t>(a.nn, (D + 1) * nflag);
     const int64_t ncells = std::min<int64_t>(a.nc, nnodes * max_deg);
     k_apply_list<<<grid(nflag), 256, 0, s>>>(const_cast<uint8_t *>(a.mask), flist, fcount);
@@ -986,6 +1014,16 @@ void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned 
     k_node_solve_list<D><<<grid(nnodes), 256, 0, s>>>(a);
     k_mark_cells<D><<<grid(nnodes), 256, 0, s>>>(a);
     k_update_list<D><<<grid(ncells), 256, 0, s>>>(a);
+}
+void launch_step_begin(unsigned *counters, double *dt_cur, const double *dt_next, int n_mesh, int copy_dt,
+                       hipStream_t s) {
+    k_step_begin<<<std::max(1, (n_mesh + 255) / 256), 256, 0, s>>>(counters, dt_cur, dt_next, n_mesh, copy_dt);
+}
+void launch_pass_begin(unsigned *counters, int in_list, int32_t *stamp, unsigned *log, int pass, hipStream_t s) {
+    k_pass_begin<<<1, 64, 0, s>>>(counters, in_list, stamp, log, pass);
+}
+void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s) {
+    if (n) k_fill_u8<<<std::min<unsigned>(nblk(n), 4096), 256, 0, s>>>(p, n, v);
 }
 void launch_dt_reduce(int64_t nc, const double *dtc, const int32_t *cell_mesh, const uint8_t *pstat, double *red,
                       double *part, const int64_t *mesh_cell_off, int n_mesh, unsigned *bad_count, hipStream_t s) {
@@ -1035,9 +1073,9 @@ template void launch_node_solve<2>(const StepArgs &, hipStream_t);
 template void launch_node_solve<3>(const StepArgs &, hipStream_t);
 template void launch_update<2>(const StepArgs &, hipStream_t);
 template void launch_update<3>(const StepArgs &, hipStream_t);
-template void launch_mood_sparse<2>(const StepArgs &, const int32_t *, const unsigned *, int64_t, int64_t,
+template void launch_mood_sparse<2>(const StepArgs &, const int32_t *, const unsigned *, int64_t, int64_t, bool,
                                     hipStream_t);
-template void launch_mood_sparse<3>(const StepArgs &, const int32_t *, const unsigned *, int64_t, int64_t,
+template void launch_mood_sparse<3>(const StepArgs &, const int32_t *, const unsigned *, int64_t, int64_t, bool,
                                     hipStream_t);
 template void launch_acoustic<2>(const StepArgs &, hipStream_t);
 template void launch_acoustic<3>(const StepArgs &, hipStream_t);

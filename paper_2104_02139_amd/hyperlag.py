@@ -24,7 +24,7 @@ FIELDS = dict(x=HL_X, vhat=HL_VHAT, tau=HL_TAU, v=HL_V, e=HL_E, B=HL_B, vstar=HL
 EXPORTS = ["hl_create", "hl_destroy", "hl_mesh_upload", "hl_state_init", "hl_set_params",
            "hl_compute_dt", "hl_step", "hl_step_replay", "hl_query", "hl_upload_field",
            "hl_profile_enable", "hl_profile_reset", "hl_profile_get", "hl_status_str",
-           "hl_last_error", "hl_mesh_upload_batch", "hl_step_batch", "hl_query_dt"]
+           "hl_last_error", "hl_mesh_upload_batch", "hl_step_batch", "hl_query_dt", "hl_use_graph"]
 
 
 class Params(C.Structure):
@@ -79,6 +79,7 @@ def load():
     L.hl_mesh_upload_batch.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, C.c_int]
     L.hl_step_batch.argtypes = [vp, vp, C.c_int, C.POINTER(StepInfo)]
     L.hl_query_dt.argtypes = [vp, vp, C.c_int, C.c_int]
+    L.hl_use_graph.argtypes = [vp, C.c_int, C.c_int]
     L.hl_state_init.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(Params), C.c_int]
     L.hl_set_params.argtypes = [vp, C.POINTER(Params)]
     L.hl_compute_dt.argtypes = [vp, C.POINTER(dp)]
@@ -266,6 +267,9 @@ class Context:
     def set_state(self, st):
         for k in ("x", "vhat", "tau", "v", "e", "B"):
             self.upload_field(k, st[k])
+
+    def use_graph(self, on=True, max_mood_passes=6):
+        _check(load().hl_use_graph(self._h, 1 if on else 0, int(max_mood_passes)), "hl_use_graph")
 
     # kernel timing with HIP events on the context's stream
     def profile(self, on=True):
