@@ -60,7 +60,7 @@ def kernel_bytes(dim, nc, nn):
         "predict": 4 * ncor + 8 * d * nn + 8 * nW * nc + 24 * nc + nc + 8 * na * nn + 8 * cw * ncor,
         "node_solve": csr + 8 * cw * ncor + nn + 16 * d * nn + 24 * d * nn,
         "update": (4 * ncor + 40 * d * nn + 8 * cw * ncor + 8 * (nW + 1) * nc + 32 * nc + nc
-                   + 16 * nn + 8 * (nW + 1) * nc + nc + 16 * nc),
+                   + 16 * nn + 8 * (nW + 1) * nc + nc + 16 * nc + 8 * (nW + d) * nc),
     }
 
 

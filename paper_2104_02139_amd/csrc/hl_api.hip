@@ -74,6 +74,7 @@ struct hl_ctx {
     double *scratch = nullptr;
     size_t scratch_bytes = 0;
     bool have_mesh = false, have_state = false;
+    bool rec_valid = false;  // gather records hold the current state
     hl_params prm{};
     std::vector<void *> allocs;
     Prof prof;
@@ -143,6 +144,7 @@ void free_all(hl_ctx *c) {
     c->counters = nullptr;
     c->dt_cur = c->dt_next = c->dt_red = c->dt_parts = c->diag_part = c->diag_out = c->scratch = nullptr;
     c->have_mesh = c->have_state = false;
+    c->rec_valid = false;
 }
 
 template <class T>
@@ -347,7 +349,6 @@ void enqueue_first(hl_ctx *c, hl::StepArgs &a, bool copy_dt, bool clear_mask, hi
     if (clear_mask) hl::launch_fill_u8(c->mask, c->nc, 0, s);
     a.flist_out = c->flist[0];
     a.fcount_out = c->counters + hl::CNT_F0;
-    PROF(c, PK_CENTROIDS, hl::launch_centroids<D>(a, s));
     PROF(c, PK_NODE_AGG, hl::launch_node_agg<D>(a, s));
     PROF(c, PK_PREDICT, hl::launch_predict<D>(a, s));
     PROF(c, PK_NODE_SOLVE, hl::launch_node_solve<D>(a, s));
@@ -425,6 +426,12 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
         a.detect = 0;
     }
     const bool graph = c->graph_on && !replay_mask && !c->prof.on;
+    // the update kernel leaves the gather records of the state it writes;
+    // after an upload they are rebuilt here
+    if (!c->rec_valid) {
+        PROF(c, PK_CENTROIDS, hl::launch_centroids<D>(a, s));
+        c->rec_valid = true;
+    }
     int iters = 1;
     int64_t first = 0, nflag = 0;
     int fb = 0, pass = 0;
@@ -898,6 +905,7 @@ hl_status hl_state_init(hl_ctx *c, const double *rho0, const double *mu, const d
     c->prm = prm;
     drop_graphs(c);
     c->have_state = true;
+    c->rec_valid = false;
     double dt0;
     return hl_compute_dt(c, &dt0);
 }
@@ -1016,6 +1024,7 @@ hl_status hl_upload_field(hl_ctx *c, int field, const void *in, int64_t count, i
     hipStream_t s = c->stream;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     double *dst = field_ptr(c, field);
+    c->rec_valid = false;
     if (w == 1) {
         HIPCHK(hipMemcpyAsync(dst, in, sizeof(double) * n, k, s));
     } else {

@@ -171,20 +171,19 @@ __device__ __forceinline__ void gepp(double A[N][N], double b[N]) {
                 piv = r;
             }
         }
-        // swap rows col <-> piv
+        // swap rows col <-> piv with selects (no dynamic register indexing)
 #pragma unroll
         for (int r = col + 1; r < N; ++r) {
-            if (piv == r) {
+            const bool sw = piv == r;
 #pragma unroll
-                for (int k = col; k < N; ++k) {
-                    double t = A[col][k];
-                    A[col][k] = A[r][k];
-                    A[r][k] = t;
-                }
-                double t = b[col];
-                b[col] = b[r];
-                b[r] = t;
+            for (int k = col; k < N; ++k) {
+                const double u = A[col][k], t = A[r][k];
+                A[col][k] = sw ? t : u;
+                A[r][k] = sw ? u : t;
             }
+            const double u = b[col], t = b[r];
+            b[col] = sw ? t : u;
+            b[r] = sw ? u : t;
         }
         double inv = 1.0 / A[col][col];
 #pragma unroll
@@ -204,59 +203,90 @@ __device__ __forceinline__ void gepp(double A[N][N], double b[N]) {
     }
 }
 
+// Matrix of X -> L X + X L^T on the symmetric components, unknowns in the
+// order (11, 22, 33, 12, 13, 23) in 3D and (11, 22, 12) in 2D; entry
+// (row (i,j), col (a,c)) is the coefficient of X_ac in
+// (L X + X L^T)_ij = sum_k L_ik X_kj + X_ik L_jk.
+__device__ __forceinline__ void lie_matrix3(const double L[3][3], double M[6][6]) {
+    const double l00 = L[0][0], l01 = L[0][1], l02 = L[0][2];
+    const double l10 = L[1][0], l11 = L[1][1], l12 = L[1][2];
+    const double l20 = L[2][0], l21 = L[2][1], l22 = L[2][2];
+    M[0][0] = 2 * l00; M[0][1] = 0;       M[0][2] = 0;       M[0][3] = 2 * l01;   M[0][4] = 2 * l02;   M[0][5] = 0;
+    M[1][0] = 0;       M[1][1] = 2 * l11; M[1][2] = 0;       M[1][3] = 2 * l10;   M[1][4] = 0;         M[1][5] = 2 * l12;
+    M[2][0] = 0;       M[2][1] = 0;       M[2][2] = 2 * l22; M[2][3] = 0;         M[2][4] = 2 * l20;   M[2][5] = 2 * l21;
+    M[3][0] = l10;     M[3][1] = l01;     M[3][2] = 0;       M[3][3] = l00 + l11; M[3][4] = l12;       M[3][5] = l02;
+    M[4][0] = l20;     M[4][1] = 0;       M[4][2] = l02;     M[4][3] = l21;       M[4][4] = l00 + l22; M[4][5] = l01;
+    M[5][0] = 0;       M[5][1] = l21;     M[5][2] = l12;     M[5][3] = l20;       M[5][4] = l10;       M[5][5] = l11 + l22;
+}
+
+__device__ __forceinline__ void lie_matrix2(const double L[2][2], double M[3][3]) {
+    M[0][0] = 2 * L[0][0]; M[0][1] = 0;           M[0][2] = 2 * L[0][1];
+    M[1][0] = 0;           M[1][1] = 2 * L[1][1]; M[1][2] = 2 * L[1][0];
+    M[2][0] = L[1][0];     M[2][1] = L[0][1];     M[2][2] = L[0][0] + L[1][1];
+}
+
 // Crank-Nicolson update of B (Section 3.4, eq. CN_B with dt/2 on both
 // sides):  X - h (L1 X + X L1^T) = Bn + h (Ln Bn + Bn Ln^T),  h = dt/2,
 // for the symmetric unknown X.  L are DxD (L_ij = dv_i/dx_j).
-template <int D>
-__device__ __forceinline__ void cn_update(const double b[6], const double Ln[D][D],
-                                          const double L1[D][D], double h, double out[6]) {
-    constexpr int N = D == 3 ? 6 : 3;
-    // unknown slot s -> (i, j)
-    constexpr int PI[6] = {0, 1, 2, 0, 0, 1};
-    constexpr int PJ[6] = {0, 1, 2, 1, 2, 2};
-    constexpr int PI2[3] = {0, 1, 0};
-    constexpr int PJ2[3] = {0, 1, 1};
-    double B3[3][3] = {{b[0], b[3], b[4]}, {b[3], b[1], b[5]}, {b[4], b[5], b[2]}};
-    double L0[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    double L1f[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+__device__ __forceinline__ void cn_update3(const double b[6], const double Ln[3][3], const double L1[3][3], double h,
+                                           double out[6]) {
+    double A[6][6], r[6];
+    lie_matrix3(Ln, A);
 #pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            L0[i][j] = Ln[i][j];
-            L1f[i][j] = L1[i][j];
-        }
-    double A[N][N], r[N];
-#pragma unroll
-    for (int row = 0; row < N; ++row) {
-        const int i = D == 3 ? PI[row] : PI2[row];
-        const int j = D == 3 ? PJ[row] : PJ2[row];
+    for (int i = 0; i < 6; ++i) {
         double y = 0.0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) y += L0[i][k] * B3[k][j] + B3[i][k] * L0[j][k];
-        r[row] = B3[i][j] + h * y;
-#pragma unroll
-        for (int col = 0; col < N; ++col) {
-            const int a = D == 3 ? PI[col] : PI2[col];
-            const int c = D == 3 ? PJ[col] : PJ2[col];
-            // coefficient of X_ac (= X_ca) in (L X + X L^T)_ij
-            double m = L1f[i][a] * (j == c ? 1.0 : 0.0) + L1f[j][c] * (i == a ? 1.0 : 0.0);
-            if (a != c) m += L1f[i][c] * (j == a ? 1.0 : 0.0) + L1f[j][a] * (i == c ? 1.0 : 0.0);
-            A[row][col] = (row == col ? 1.0 : 0.0) - h * m;
-        }
+        for (int j = 0; j < 6; ++j) y += A[i][j] * b[j];
+        r[i] = b[i] + h * y;
     }
-    gepp<N>(A, r);
-    if (D == 3) {
+    lie_matrix3(L1, A);
 #pragma unroll
-        for (int s = 0; s < 6; ++s) out[s] = r[s < N ? s : 0];
-    } else {
-        out[0] = r[0];
-        out[1] = r[1];
-        out[2] = 1.0;
-        out[3] = r[2];
-        out[4] = 0.0;
-        out[5] = 0.0;
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) A[i][j] = (i == j ? 1.0 : 0.0) - h * A[i][j];
+    gepp<6>(A, r);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) out[s] = r[s];
+}
+
+__device__ __forceinline__ void cn_update2(const double b[6], const double Ln[2][2], const double L1[2][2], double h,
+                                           double out[6]) {
+    double A[3][3], r[3];
+    const double bs[3] = {b[0], b[1], b[3]};
+    lie_matrix2(Ln, A);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double y = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) y += A[i][j] * bs[j];
+        r[i] = bs[i] + h * y;
     }
+    lie_matrix2(L1, A);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) A[i][j] = (i == j ? 1.0 : 0.0) - h * A[i][j];
+    gepp<3>(A, r);
+    out[0] = r[0];
+    out[1] = r[1];
+    out[2] = 1.0;
+    out[3] = r[2];
+    out[4] = 0.0;
+    out[5] = 0.0;
+}
+
+template <int D>
+__device__ __forceinline__ void cn_update(const double b[6], const double Ln[D][D], const double L1[D][D], double h,
+                                          double out[6]);
+template <>
+__device__ __forceinline__ void cn_update<3>(const double b[6], const double Ln[3][3], const double L1[3][3], double h,
+                                             double out[6]) {
+    cn_update3(b, Ln, L1, h, out);
+}
+template <>
+__device__ __forceinline__ void cn_update<2>(const double b[6], const double Ln[2][2], const double L1[2][2], double h,
+                                             double out[6]) {
+    cn_update2(b, Ln, L1, h, out);
 }
 
 }  // namespace hl

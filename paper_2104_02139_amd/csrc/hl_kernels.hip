@@ -184,13 +184,12 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
     const int64_t nc = a.nc, nn = a.nn;
-    int32_t nid[NV];
     double X[NV][D];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        nid[k] = a.c2n[c * NV + k];
+        const int64_t p = a.c2n[c * NV + k];
 #pragma unroll
-        for (int i = 0; i < D; ++i) X[k][i] = a.x[i * nn + nid[k]];
+        for (int i = 0; i < D; ++i) X[k][i] = a.x[i * nn + p];
     }
     Geo<D> g;
     geom<D>(X, g);
@@ -202,54 +201,43 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
         for (int k = 0; k < NV; ++k) s += X[k][i];
         xc[i] = s * (1.0 / NV);
     }
-    const double tau = a.tau[c];
-    double vc[D];
+    // corner offsets from the centroid
 #pragma unroll
-    for (int i = 0; i < D; ++i) vc[i] = a.v[i * nc + c];
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int i = 0; i < D; ++i) X[k][i] -= xc[i];
+
+    const double tau = a.tau[c];
     double b[6];
     load_B6<D>(a.B, nc, c, b);
     const double rho0 = a.rho0[c], mu = a.mu[c], K = a.K[c];
-    const double dt = mesh_dt(a.dt, a.cell_mesh, c);
     const bool p1 = a.mask[c] == 0;
 
-    // S = sum_j C_j C_j^T / |C_j|; corner shape N_k = S - C_k C_k^T / |C_k|
-    double S[Dm::NMS] = {};
+    // W0 = W_c + (dt/2) dW/dt at the centroid; corner value W0 + grad W . delta
+    double W0[Dm::NW];
+    W0[0] = tau;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        double r = 1.0 / g.cn[j];
+    for (int i = 0; i < D; ++i) W0[1 + i] = a.v[i * nc + c];
 #pragma unroll
-        for (int i = 0; i < D; ++i)
+    for (int q = 0; q < Dm::NB; ++q) W0[1 + D + q] = b[bslot<D>(q)];
+    double grad[Dm::NW][D];
 #pragma unroll
-            for (int k = i; k < D; ++k) S[midx<D>(i, k)] += g.C[j][i] * g.C[j][k] * r;
-    }
-
-    double ts[NV], vs[NV][D], bs[NV][6];
+    for (int w = 0; w < Dm::NW; ++w)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        ts[k] = tau;
-#pragma unroll
-        for (int i = 0; i < D; ++i) vs[k][i] = vc[i];
-#pragma unroll
-        for (int s = 0; s < 6; ++s) bs[k][s] = b[s];
-    }
+        for (int i = 0; i < D; ++i) grad[w][i] = 0.0;
 
     if (p1) {
-        // ---- least-squares normal equations from the node aggregates
+        // ---- least-squares normal equations from the node aggregates (R8)
         double A[Dm::NMS] = {};
         double rhs[Dm::NW][D] = {};
         double visits = 0.0;  // neighbour visits: sum over nodes of (n - 1)
-        double Wc[Dm::NW];
-        Wc[0] = tau;
-#pragma unroll
-        for (int i = 0; i < D; ++i) Wc[1 + i] = vc[i];
-#pragma unroll
-        for (int s = 0; s < Dm::NB; ++s) Wc[1 + D + s] = b[bslot<D>(s)];
-#pragma unroll
+#pragma unroll 1
         for (int k = 0; k < NV; ++k) {
-            const double *ag = a.agg + (int64_t)nid[k] * Dm::NA;
+            const int64_t p = a.c2n[c * NV + k];
             double u[D];
 #pragma unroll
-            for (int i = 0; i < D; ++i) u[i] = xc[i] - X[k][i];
+            for (int i = 0; i < D; ++i) u[i] = xc[i] - a.x[i * nn + p];
+            const double *ag = a.agg + p * Dm::NA;
             const double n = ag[0];
             visits += n - 1.0;
             double Sy[D];
@@ -265,7 +253,7 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
                 const double sw = ag[Dm::O_SW + w];
 #pragma unroll
                 for (int j = 0; j < D; ++j)
-                    rhs[w][j] += ag[Dm::O_SYW + w * D + j] - u[j] * sw - Sy[j] * Wc[w] + n * u[j] * Wc[w];
+                    rhs[w][j] += ag[Dm::O_SYW + w * D + j] - u[j] * sw - Sy[j] * W0[w] + n * u[j] * W0[w];
             }
         }
         double inv[Dm::NMS];
@@ -276,10 +264,9 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
             det = sym_inv2(A, inv);
 #pragma unroll
         for (int i = 0; i < D; ++i) tr += A[midx<D>(i, i)];
-        double scl = tr / D;
-        double scale = D == 3 ? scl * scl * scl : scl * scl;
+        const double scl = tr / D;
+        const double scale = D == 3 ? scl * scl * scl : scl * scl;
         const bool ok = (visits >= D) && (tr > 0.0) && (det > 1e-12 * scale);
-        double grad[Dm::NW][D];
 #pragma unroll
         for (int w = 0; w < Dm::NW; ++w)
 #pragma unroll
@@ -296,30 +283,25 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
         for (int i = 0; i < D; ++i)
 #pragma unroll
             for (int j = 0; j < D; ++j) G[i][j] = grad[1 + i][j];
-        double gB[6][D];  // d b_s / d x_j in 6-vector order
-#pragma unroll
-        for (int s = 0; s < 6; ++s)
-#pragma unroll
-            for (int j = 0; j < D; ++j) gB[s][j] = 0.0;
-#pragma unroll
-        for (int s = 0; s < Dm::NB; ++s)
-#pragma unroll
-            for (int j = 0; j < D; ++j) gB[bslot<D>(s)][j] = grad[1 + D + s][j];
-
+        auto gB = [&](int s6, int j) -> double {  // d b_s6 / d x_j (6-vector order)
+            if (D == 3) return grad[1 + D + s6][j];
+            return s6 == 0 ? grad[1 + D][j] : (s6 == 1 ? grad[2 + D][j] : (s6 == 3 ? grad[3 + D][j] : 0.0));
+        };
         double trG = 0.0;
 #pragma unroll
         for (int i = 0; i < D; ++i) trG += G[i][i];
-        const double dtau = tau * trG;
-        double B3[3][3] = {{b[0], b[3], b[4]}, {b[3], b[1], b[5]}, {b[4], b[5], b[2]}};
-        double dB[6];
+        const double h = 0.5 * mesh_dt(a.dt, a.cell_mesh, c);
+        const double B3[3][3] = {{b[0], b[3], b[4]}, {b[3], b[1], b[5]}, {b[4], b[5], b[2]}};
+        // dB/dt = G B + B G^T, stored components only
 #pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            const int i = s < 3 ? s : (s == 5 ? 1 : 0);
-            const int j = s < 3 ? s : (s == 3 ? 1 : 2);
+        for (int q = 0; q < Dm::NB; ++q) {
+            const int s6 = bslot<D>(q);
+            const int i = s6 < 3 ? s6 : (s6 == 5 ? 1 : 0);
+            const int j = s6 < 3 ? s6 : (s6 == 3 ? 1 : 2);
             double y = 0.0;
 #pragma unroll
             for (int k = 0; k < 3; ++k) y += G[i][k] * B3[k][j] + B3[i][k] * G[j][k];
-            dB[s] = y;
+            W0[1 + D + q] += h * y;
         }
         // div T by the chain rule through T(tau, B)
         const double J = rho0 * tau;
@@ -329,7 +311,6 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
         const double J83 = J53 / J;               // J^{-8/3}
         const double mdpdJ = 0.5 * K * (1.0 + (1.0 - lj) / (J * J));  // -dp/dJ
         const double trB3 = (b[0] + b[1] + b[2]) * (1.0 / 3.0);
-        double divT[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             double s1 = 0.0, s2 = 0.0;
@@ -337,45 +318,53 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
             for (int j = 0; j < D; ++j) {
                 const double devB = B3[i][j] - (i == j ? trB3 : 0.0);
                 s1 += devB * grad[0][j];
-                s2 += gB[sidx(i, j)][j];
+                s2 += gB(sidx(i, j), j);
             }
-            const double dtr = gB[0][i] + gB[1][i] + gB[2][i];
-            divT[i] = rho0 * (mdpdJ * grad[0][i] - (5.0 / 3.0) * mu * J83 * s1) + mu * J53 * (s2 - dtr * (1.0 / 3.0));
+            const double dtr = gB(0, i) + gB(1, i) + gB(2, i);
+            const double divT = rho0 * (mdpdJ * grad[0][i] - (5.0 / 3.0) * mu * J83 * s1) +
+                                mu * J53 * (s2 - dtr * (1.0 / 3.0));
+            W0[1 + i] += h * tau * divT;
         }
-        const double h = 0.5 * dt;
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double dl[D];
-#pragma unroll
-            for (int i = 0; i < D; ++i) dl[i] = X[k][i] - xc[i];
-            double st = 0.0;
-#pragma unroll
-            for (int j = 0; j < D; ++j) st += grad[0][j] * dl[j];
-            ts[k] = tau + st + h * dtau;
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                double sv = 0.0;
-#pragma unroll
-                for (int j = 0; j < D; ++j) sv += G[i][j] * dl[j];
-                vs[k][i] = vc[i] + sv + h * tau * divT[i];
-            }
-#pragma unroll
-            for (int s = 0; s < 6; ++s) {
-                if (D == 2 && (s == 2 || s == 4 || s == 5)) continue;
-                double sb = 0.0;
-#pragma unroll
-                for (int j = 0; j < D; ++j) sb += gB[s][j] * dl[j];
-                bs[k][s] = b[s] + sb + h * dB[s];
-            }
-        }
+        W0[0] += h * tau * trG;
     }
 
-    // ---- corner records
+    // S = sum_j C_j C_j^T / |C_j|; corner shape N_k = S - C_k C_k^T / |C_k|
+    double S[Dm::NMS] = {};
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const double r = 1.0 / g.cn[j];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int k = i; k < D; ++k) S[midx<D>(i, k)] += g.C[j][i] * g.C[j][k] * r;
+    }
+
+    // ---- corner records: predicted state, stress, impedance, M_cp, r_cp
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
+        double Wk[Dm::NW];
+#pragma unroll
+        for (int w = 0; w < Dm::NW; ++w) {
+            double s = W0[w];
+#pragma unroll
+            for (int j = 0; j < D; ++j) s += grad[w][j] * X[k][j];
+            Wk[w] = s;
+        }
+        double bk[6];
+        if (D == 3) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) bk[q] = Wk[1 + D + q];
+        } else {
+            bk[0] = Wk[1 + D];
+            bk[1] = Wk[2 + D];
+            bk[2] = 1.0;
+            bk[3] = Wk[3 + D];
+            bk[4] = 0.0;
+            bk[5] = 0.0;
+        }
         double T[6];
-        stress6(rho0, mu, K, ts[k], bs[k], T);
-        const double z = sound(rho0, mu, K, ts[k]) / ts[k];
+        stress6(rho0, mu, K, Wk[0], bk, T);
+        const double z = sound(rho0, mu, K, Wk[0]) / Wk[0];
         const double rk = 1.0 / g.cn[k];
         double M[Dm::NMS];
 #pragma unroll
@@ -383,19 +372,16 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
 #pragma unroll
             for (int j = i; j < D; ++j)
                 M[midx<D>(i, j)] = z * (S[midx<D>(i, j)] - g.C[k][i] * g.C[k][j] * rk);
-        double r[D];
+        double* o = a.corner + (c * NV + k) * Dm::CW;
+#pragma unroll
+        for (int q = 0; q < Dm::NMS; ++q) o[q] = M[q];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             double s = 0.0;
 #pragma unroll
-            for (int j = 0; j < D; ++j) s += M[midx<D>(i, j)] * vs[k][j] - T[sidx(i, j)] * g.C[k][j];
-            r[i] = s;
+            for (int j = 0; j < D; ++j) s += M[midx<D>(i, j)] * Wk[1 + j] - T[sidx(i, j)] * g.C[k][j];
+            o[Dm::NMS + i] = s;
         }
-        double *o = a.corner + (c * NV + k) * Dm::CW;
-#pragma unroll
-        for (int s = 0; s < Dm::NMS; ++s) o[s] = M[s];
-#pragma unroll
-        for (int i = 0; i < D; ++i) o[Dm::NMS + i] = r[i];
     }
 }
 
@@ -518,84 +504,114 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
     const int64_t nc = a.nc, nn = a.nn;
-    int32_t nid[NV];
-    double X0[NV][D], X1[NV][D], vs[NV][D];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        nid[k] = a.c2n[c * NV + k];
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            X0[k][i] = a.x[i * nn + nid[k]];
-            X1[k][i] = a.x1[i * nn + nid[k]];
-            vs[k][i] = a.vstar[i * nn + nid[k]];
-        }
-    }
-    // forces
-    double F[D] = {}, Wk = 0.0;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const double *rec = a.corner + (c * NV + k) * Dm::CW;
-        double f[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            double s = -rec[Dm::NMS + i];
-#pragma unroll
-            for (int j = 0; j < D; ++j) s += rec[midx<D>(i, j)] * vs[k][j];
-            f[i] = s;
-        }
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            F[i] += f[i];
-            Wk += f[i] * vs[k][i];
-        }
-    }
     const double m = a.mass[c];
     const double dt = mesh_dt(a.dt, a.cell_mesh, c);
     const double dtm = dt / m;
+
+    // ---- subcell forces and the compatible momentum / energy update
+    double F[D] = {}, Wk = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < NV; ++k) {
+        const int64_t p = a.c2n[c * NV + k];
+        double vs[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) vs[i] = a.vstar[i * nn + p];
+        const double *rec = a.corner + (c * NV + k) * Dm::CW;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double f = -rec[Dm::NMS + i];
+#pragma unroll
+            for (int j = 0; j < D; ++j) f += rec[midx<D>(i, j)] * vs[j];
+            F[i] += f;
+            Wk += f * vs[i];
+        }
+    }
     double v1[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) v1[i] = a.v[i * nc + c] + dtm * F[i];
+    for (int i = 0; i < D; ++i) {
+        v1[i] = a.v[i * nc + c] + dtm * F[i];
+        a.v1[i * nc + c] = v1[i];
+    }
     const double e1 = a.e[c] + dtm * Wk;
+    a.e1[c] = e1;
 
-    Geo<D> g0, g1;
-    geom<D>(X0, g0);
-    geom<D>(X1, g1);
-    const double tau0 = a.tau[c];
-    const double tau1 = g1.V / m;
-
-    double b[6], b1[6];
-    load_B6<D>(a.B, nc, c, b);
+    // ---- geometry at t^n and t^{n+1}; velocity gradients
     const bool p1 = a.mask[c] == 0;
-    if (p1) {
-        double L0[D][D], L1[D][D];
+    double L0[D][D], L1[D][D];
+    double tau1, Lc, xc1[D];
+    {
+        double X0[NV][D], X1[NV][D];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int64_t p = a.c2n[c * NV + k];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                X0[k][i] = a.x[i * nn + p];
+                X1[k][i] = a.x1[i * nn + p];
+            }
+        }
+        Geo<D> g0, g1;
+        geom<D>(X0, g0);
+        geom<D>(X1, g1);
+        tau1 = g1.V / m;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double sx = 0.0;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) sx += X1[k][i];
+            xc1[i] = sx * (1.0 / NV);
+        }
+        double S1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) S1 += g1.cn[k];
+        Lc = 2.0 * g1.V / S1;
+        // P1: L^n from vhat^n on x^n and L^{n+1} from vhat^{n+1} on x^{n+1};
+        // P0: L* from v* on x^n (L0 only)
+        const double *u0 = p1 ? a.vhat : a.vstar;
         const double r0 = 1.0 / g0.V, r1 = 1.0 / g1.V;
 #pragma unroll
         for (int i = 0; i < D; ++i)
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-                for (int k = 0; k < NV; ++k) {
-                    s0 += a.vhat[i * nn + nid[k]] * g0.C[k][j];
-                    s1 += a.vhat1[i * nn + nid[k]] * g1.C[k][j];
-                }
-                L0[i][j] = s0 * r0;
-                L1[i][j] = s1 * r1;
+                L0[i][j] = 0.0;
+                L1[i][j] = 0.0;
             }
-        cn_update<D>(b, L0, L1, 0.5 * dt, b1);
-    } else {
-        double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        const double r0 = 1.0 / g0.V;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int64_t p = a.c2n[c * NV + k];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const double w0 = u0[i * nn + p];
+                const double w1 = p1 ? a.vhat1[i * nn + p] : 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    L0[i][j] += w0 * g0.C[k][j];
+                    L1[i][j] += w1 * g1.C[k][j];
+                }
+            }
+        }
 #pragma unroll
         for (int i = 0; i < D; ++i)
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                double s = 0.0;
-#pragma unroll
-                for (int k = 0; k < NV; ++k) s += vs[k][i] * g0.C[k][j];
-                L[i][j] = s * r0;
+                L0[i][j] *= r0;
+                L1[i][j] *= r1;
             }
-        double B3[3][3] = {{b[0], b[3], b[4]}, {b[3], b[1], b[5]}, {b[4], b[5], b[2]}};
+    }
+    a.tau1[c] = tau1;
+
+    // ---- B: Crank-Nicolson (P1) or Euler (P0)
+    double b[6], b1[6];
+    load_B6<D>(a.B, nc, c, b);
+    if (p1) {
+        cn_update<D>(b, L0, L1, 0.5 * dt, b1);
+    } else {
+        double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) L[i][j] = L0[i][j];
+        const double B3[3][3] = {{b[0], b[3], b[4]}, {b[3], b[1], b[5]}, {b[4], b[5], b[2]}};
 #pragma unroll
         for (int s = 0; s < 6; ++s) {
             const int i = s < 3 ? s : (s == 5 ? 1 : 0);
@@ -611,15 +627,26 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
             b1[5] = 0.0;
         }
     }
-
-    // write the candidate
-    a.tau1[c] = tau1;
-    a.e1[c] = e1;
-#pragma unroll
-    for (int i = 0; i < D; ++i) a.v1[i * nc + c] = v1[i];
     store_B6<D>(a.B1, nc, c, b1);
 
-    // detection
+    // gather record of the candidate for the next step's reconstruction
+    {
+        double r[Dm::GR];
+        r[0] = tau1;
+#pragma unroll
+        for (int i = 0; i < D; ++i) r[1 + i] = v1[i];
+#pragma unroll
+        for (int q = 0; q < Dm::NB; ++q) r[1 + D + q] = b1[bslot<D>(q)];
+#pragma unroll
+        for (int i = 0; i < D; ++i) r[Dm::NW + i] = xc1[i];
+#pragma unroll
+        for (int q = Dm::NW + D; q < Dm::GR; ++q) r[q] = 0.0;
+        double2 *o = reinterpret_cast<double2 *>(a.xc + c * Dm::GR);
+#pragma unroll
+        for (int q = 0; q < Dm::GR / 2; ++q) o[q] = make_double2(r[2 * q], r[2 * q + 1]);
+    }
+
+    // ---- detection (eqs. PAD, RDMP; R16, R17)
     bool fin = isfinite(tau1) && isfinite(e1);
 #pragma unroll
     for (int i = 0; i < D; ++i) fin = fin && isfinite(v1[i]);
@@ -635,7 +662,8 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
         double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
-            const double *ag = a.agg + (int64_t)nid[k] * Dm::NA + Dm::O_RMM;
+            const int64_t p = a.c2n[c * NV + k];
+            const double *ag = a.agg + p * Dm::NA + Dm::O_RMM;
             lo = fmin(lo, ag[0]);
             hi = fmax(hi, ag[1]);
         }
@@ -646,13 +674,9 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
     }
     a.pstat[c] = (!p1 && pad_bad) ? 1 : 0;
 
-    // time-step bounds at t^{n+1} (eq. CFL2; R20, R21)
-    double S1 = 0.0;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) S1 += g1.cn[k];
-    const double Lc = 2.0 * g1.V / S1;
+    // ---- time-step bounds at t^{n+1} (eq. CFL2; R20, R21)
     const double ac = sound(a.rho0[c], a.mu[c], a.K[c], tau1);
-    const double V0 = m * tau0, V1 = m * tau1;
+    const double V0 = m * a.tau[c], V1 = m * tau1;
     const double dV = fabs(V1 - V0);
     a.dtc[c] = Lc / ac;
     a.dtc[nc + c] = dV > 0.0 ? V1 / dV : __builtin_huge_val();
