@@ -185,6 +185,37 @@ hl_status hl_step_replay(hl_ctx *ctx, double dt, const uint8_t *mask, int on_dev
  * max_mood_passes: 0..64. */
 hl_status hl_use_graph(hl_ctx *ctx, int on, int max_mood_passes);
 
+/* ---------------------------------------------------------------------
+ * Adjoint (not in the paper: differentiation of the step for parameter
+ * identification).  The map from (mu, initial cell velocity, initial node
+ * velocity) to the final node positions is differentiated with the dt and
+ * the cascade choice of every step frozen as recorded by the forward pass.
+ * ------------------------------------------------------------------- */
+
+/* Run nsteps CFL-controlled ADER-MOOD steps from the current state,
+ * recording each step's dt and cascade mask and a state checkpoint every
+ * ckpt_every steps (device memory owned by the context). */
+hl_status hl_forward_record(hl_ctx *ctx, int nsteps, int ckpt_every);
+
+/* Re-run the recorded steps from the current state with the recorded dt and
+ * masks (for finite-difference checks after hl_state_init with other
+ * parameters). */
+hl_status hl_forward_replay(hl_ctx *ctx);
+
+/* Reverse sweep over the recorded steps (each checkpoint segment replayed
+ * forward, then stepped back with hand-written adjoint kernels).
+ *   dL_dx_final [n_nodes][dim]  gradient of the loss w.r.t. the final
+ *                               node positions (input)
+ *   dL_dmu      [n_cells]       gradient w.r.t. the per-cell shear modulus
+ *   dL_dvcell   [n_cells][dim]  gradient w.r.t. the initial cell velocity
+ *   dL_dvnode   [n_nodes][dim]  gradient w.r.t. the initial node velocity
+ * The context is left at the final forward state. */
+hl_status hl_adjoint_run(hl_ctx *ctx, const double *dL_dx_final, double *dL_dmu, double *dL_dvcell,
+                         double *dL_dvnode, int on_device);
+
+/* Recorded cascade mask [n_cells] and dt [n_meshes] of step `step` (host). */
+hl_status hl_tape_get(hl_ctx *ctx, int step, uint8_t *mask, double *dt);
+
 /* Copy a field of the current state to `out` (count = number of elements
  * of the field's type, checked). */
 hl_status hl_query(hl_ctx *ctx, int field, void *out, int64_t count, int on_device);

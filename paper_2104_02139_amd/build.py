@@ -13,7 +13,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhyperlag.so")
-SOURCES = [os.path.join(CSRC, "hl_kernels.hip"), os.path.join(CSRC, "hl_api.hip")]
+SELFTEST_LIB = os.path.join(PKG, "libhl_selftest.so")
+SELFTEST_SRC = os.path.join(CSRC, "hl_selftest.hip")
+SOURCES = [os.path.join(CSRC, "hl_kernels.hip"), os.path.join(CSRC, "hl_adjoint.hip"),
+           os.path.join(CSRC, "hl_api.hip")]
 ARCH = os.environ.get("HL_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -33,6 +36,13 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # host-side finite-difference self-test of the adjoint building blocks
+    tmp = SELFTEST_LIB + ".tmp"
+    cmd = [hipcc, *FLAGS, SELFTEST_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, SELFTEST_LIB)
     return LIB
 
 

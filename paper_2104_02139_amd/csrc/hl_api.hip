@@ -78,6 +78,17 @@ struct hl_ctx {
     hl_params prm{};
     std::vector<void *> allocs;
     Prof prof;
+    // adjoint tapes (own allocations, freed with the mesh)
+    struct {
+        int nsteps = 0, every = 0, nckpt = 0;
+        size_t state_sz = 0;  // doubles per state snapshot
+        double *ckpt = nullptr, *seg = nullptr, *dts = nullptr;
+        uint8_t *masks = nullptr;
+        double *lam[2] = {nullptr, nullptr};
+        double *cadj = nullptr, *nadj = nullptr, *cell = nullptr, *agg = nullptr, *xadj = nullptr;
+        double *mu_bar = nullptr, *out = nullptr;
+        std::vector<void *> mem;
+    } tape;
 };
 
 namespace {
@@ -122,8 +133,19 @@ void drop_graphs(hl_ctx *c) {
     }
 }
 
+void free_tape(hl_ctx *c) {
+    for (void *p : c->tape.mem) (void)hipFree(p);
+    c->tape.mem.clear();
+    c->tape.nsteps = c->tape.every = c->tape.nckpt = 0;
+    c->tape.ckpt = c->tape.seg = c->tape.dts = nullptr;
+    c->tape.masks = nullptr;
+    c->tape.lam[0] = c->tape.lam[1] = nullptr;
+    c->tape.cadj = c->tape.nadj = c->tape.cell = c->tape.agg = c->tape.xadj = c->tape.mu_bar = c->tape.out = nullptr;
+}
+
 void free_all(hl_ctx *c) {
     drop_graphs(c);
+    free_tape(c);
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->counters_host) (void)hipHostFree(c->counters_host);
@@ -515,6 +537,193 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
     }
     c->cur = 1 - src;
     return inadm ? HL_WARN_PARACHUTE_INADMISSIBLE : HL_OK;
+}
+
+// ------------------------------------------------------------- adjoint
+template <class T>
+hl_status talloc(hl_ctx *c, T **p, size_t n) {
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(n * sizeof(T), 256)) != hipSuccess) return HL_E_OOM;
+    c->tape.mem.push_back(q);
+    *p = reinterpret_cast<T *>(q);
+    return HL_OK;
+}
+
+// state snapshot: x, vhat [D][nn], tau [nc], v [D][nc], e [nc], B [nB][nc]
+size_t snapshot_size(const hl_ctx *c) {
+    const size_t d = c->dim, nn = c->nn, nc = c->nc, nB = d == 3 ? 6 : 3;
+    return 2 * d * nn + (2 + d + nB) * nc;
+}
+
+hl_status copy_state(hl_ctx *c, int buf, double *dst, bool to_snapshot) {
+    const size_t d = c->dim, nn = c->nn, nc = c->nc, nB = d == 3 ? 6 : 3;
+    double *parts[6] = {c->x[buf], c->vhat[buf], c->tau[buf], c->v[buf], c->e[buf], c->B[buf]};
+    const size_t sz[6] = {d * nn, d * nn, nc, d * nc, nc, nB * nc};
+    size_t off = 0;
+    for (int k = 0; k < 6; ++k) {
+        if (sz[k]) {
+            if (to_snapshot)
+                HIPCHK(hipMemcpyAsync(dst + off, parts[k], sizeof(double) * sz[k], hipMemcpyDeviceToDevice, c->stream));
+            else
+                HIPCHK(hipMemcpyAsync(parts[k], dst + off, sizeof(double) * sz[k], hipMemcpyDeviceToDevice, c->stream));
+        }
+        off += sz[k];
+    }
+    return HL_OK;
+}
+
+// one step with the recorded dt and cascade choice of step n
+template <int D>
+hl_status replay_recorded(hl_ctx *c, int n) {
+    hipStream_t s = c->stream;
+    HIPCHK(hipMemcpyAsync(c->dt_next, c->tape.dts + (size_t)n * c->n_mesh, sizeof(double) * c->n_mesh,
+                          hipMemcpyDeviceToDevice, s));
+    return run_step<D>(c, 0.0, c->tape.masks + (size_t)n * c->nc, 1, nullptr) < 0 ? HL_E_HIP : HL_OK;
+}
+
+// forward intermediates of step n for the reverse sweep: state n in buffer 0
+template <int D>
+void recompute_step(hl_ctx *c, int n) {
+    hipStream_t s = c->stream;
+    (void)hipMemcpyAsync(c->dt_cur, c->tape.dts + (size_t)n * c->n_mesh, sizeof(double) * c->n_mesh,
+                         hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(c->mask, c->tape.masks + (size_t)n * c->nc, (size_t)c->nc, hipMemcpyDeviceToDevice, s);
+    hl::StepArgs a = make_args(c, 0);
+    a.detect = 0;
+    hl::launch_step_begin(c->counters, c->dt_cur, c->dt_next, c->n_mesh, 0, s);
+    hl::launch_centroids<D>(a, s);
+    hl::launch_node_agg<D>(a, s);
+    hl::launch_predict<D>(a, s);
+    hl::launch_node_solve<D>(a, s);
+    hl::launch_update<D>(a, s);
+}
+
+hl::AdjArgs adj_args(hl_ctx *c, int in) {
+    const size_t d = c->dim, nn = c->nn, nc = c->nc;
+    hl::AdjArgs j{};
+    const double *li = c->tape.lam[in];
+    double *lo = c->tape.lam[1 - in];
+    j.lx_in = li;
+    j.lvh_in = li + d * nn;
+    j.ltau_in = li + 2 * d * nn;
+    j.lv_in = li + 2 * d * nn + nc;
+    j.lB_in = li + 2 * d * nn + (1 + d) * nc;
+    j.lx_out = lo;
+    j.lvh_out = lo + d * nn;
+    j.ltau_out = lo + 2 * d * nn;
+    j.lv_out = lo + 2 * d * nn + nc;
+    j.lB_out = lo + 2 * d * nn + (1 + d) * nc;
+    j.cadj = c->tape.cadj;
+    j.nadj = c->tape.nadj;
+    j.cell = c->tape.cell;
+    j.agg = c->tape.agg;
+    j.xadj = c->tape.xadj;
+    j.mu_bar = c->tape.mu_bar;
+    return j;
+}
+
+template <int D>
+hl_status forward_record(hl_ctx *c, int nsteps, int every) {
+    free_tape(c);
+    auto &t = c->tape;
+    t.nsteps = nsteps;
+    t.every = every;
+    t.nckpt = (nsteps + every - 1) / every + 1;
+    t.state_sz = snapshot_size(c);
+    const size_t nn = c->nn, nc = c->nc, ncor = nc * (D + 1), lam_sz = 2 * D * nn + (1 + D + (D == 3 ? 6 : 3)) * nc;
+    hl_status st;
+    if ((st = talloc(c, &t.ckpt, t.nckpt * t.state_sz)) != HL_OK) return st;
+    if ((st = talloc(c, &t.seg, (size_t)every * t.state_sz)) != HL_OK) return st;
+    if ((st = talloc(c, &t.dts, (size_t)nsteps * c->n_mesh)) != HL_OK) return st;
+    if ((st = talloc(c, &t.masks, (size_t)nsteps * nc)) != HL_OK) return st;
+    for (int b = 0; b < 2; ++b)
+        if ((st = talloc(c, &t.lam[b], lam_sz)) != HL_OK) return st;
+    if ((st = talloc(c, &t.cadj, ncor * hl::AdjArgs::CA)) != HL_OK) return st;
+    if ((st = talloc(c, &t.nadj, nn * hl::AdjArgs::NAD)) != HL_OK) return st;
+    if ((st = talloc(c, &t.cell, nc * hl::AdjArgs::CL)) != HL_OK) return st;
+    if ((st = talloc(c, &t.agg, nn * hl::AdjArgs::NAA)) != HL_OK) return st;
+    if ((st = talloc(c, &t.xadj, ncor * 3)) != HL_OK) return st;
+    if ((st = talloc(c, &t.mu_bar, nc)) != HL_OK) return st;
+    if ((st = talloc(c, &t.out, std::max(nn, nc) * 3)) != HL_OK) return st;
+    for (int n = 0; n < nsteps; ++n) {
+        if (n % every == 0) {
+            if ((st = copy_state(c, c->cur, t.ckpt + (size_t)(n / every) * t.state_sz, true)) != HL_OK) return st;
+        }
+        hl_status r = run_step<D>(c, 0.0, nullptr, 0, nullptr);
+        if (r < 0) return r;
+        HIPCHK(hipMemcpyAsync(t.masks + (size_t)n * nc, c->mask, nc, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(t.dts + (size_t)n * c->n_mesh, c->dt_cur, sizeof(double) * c->n_mesh,
+                              hipMemcpyDeviceToDevice, c->stream));
+    }
+    if ((st = copy_state(c, c->cur, t.ckpt + (size_t)(t.nckpt - 1) * t.state_sz, true)) != HL_OK) return st;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return HL_OK;
+}
+
+template <int D>
+hl_status forward_replay(hl_ctx *c) {
+    for (int n = 0; n < c->tape.nsteps; ++n) {
+        hl_status st = replay_recorded<D>(c, n);
+        if (st != HL_OK) return st;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return HL_OK;
+}
+
+template <int D>
+hl_status adjoint_run(hl_ctx *c, const double *dLdx, double *dLdmu, double *dLdvc, double *dLdvn, int on_device) {
+    auto &t = c->tape;
+    hipStream_t s = c->stream;
+    const size_t nn = c->nn, nc = c->nc, lam_sz = 2 * D * nn + (1 + D + (D == 3 ? 6 : 3)) * nc;
+    const hipMemcpyKind kin = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    // lambda at the final time: dL/dx, nothing on the other fields
+    HIPCHK(hipMemsetAsync(t.lam[0], 0, sizeof(double) * lam_sz, s));
+    HIPCHK(hipMemsetAsync(t.mu_bar, 0, sizeof(double) * nc, s));
+    if (nn) {
+        HIPCHK(hipMemcpyAsync(t.out, dLdx, sizeof(double) * nn * D, kin, s));
+        hl::launch_aos_to_soa(nn, D, t.out, t.lam[0], s);
+    }
+    int in = 0;
+    const int nseg = (t.nsteps + t.every - 1) / t.every;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int s0 = seg * t.every, s1 = std::min(t.nsteps, s0 + t.every);
+        // rebuild the segment's states from its checkpoint
+        c->cur = 0;
+        hl_status st = copy_state(c, 0, t.ckpt + (size_t)seg * t.state_sz, false);
+        if (st != HL_OK) return st;
+        c->rec_valid = false;
+        for (int n = s0; n < s1; ++n) {
+            if ((st = copy_state(c, c->cur, t.seg + (size_t)(n - s0) * t.state_sz, true)) != HL_OK) return st;
+            if (n + 1 < s1 && (st = replay_recorded<D>(c, n)) != HL_OK) return st;
+        }
+        for (int n = s1 - 1; n >= s0; --n) {
+            if ((st = copy_state(c, 0, t.seg + (size_t)(n - s0) * t.state_sz, false)) != HL_OK) return st;
+            recompute_step<D>(c, n);
+            hl::launch_adjoint_step<D>(make_args(c, 0), adj_args(c, in), s);
+            in = 1 - in;
+        }
+    }
+    // lambda at t = 0 -> gradients of the inputs
+    const double *lam = t.lam[in];
+    if (nc) {
+        HIPCHK(hipMemcpyAsync(dLdmu, t.mu_bar, sizeof(double) * nc, kout, s));
+        hl::launch_soa_to_aos(nc, D, lam + 2 * D * nn + nc, t.out, s);
+        HIPCHK(hipMemcpyAsync(dLdvc, t.out, sizeof(double) * nc * D, kout, s));
+    }
+    if (nn) {
+        hl::launch_adj_project<D>(nn, c->nallow, c->allow, lam + D * nn, t.out, s);
+        HIPCHK(hipMemcpyAsync(dLdvn, t.out, sizeof(double) * nn * D, kout, s));
+    }
+    // leave the context at the final forward state
+    c->cur = 0;
+    hl_status st = copy_state(c, 0, t.ckpt + (size_t)(t.nckpt - 1) * t.state_sz, false);
+    if (st != HL_OK) return st;
+    c->rec_valid = false;
+    HIPCHK(hipStreamSynchronize(s));
+    hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return hip_fail(le, "adjoint kernel launch", __LINE__);
+    return HL_OK;
 }
 
 int field_width(const hl_ctx *c, int field, bool *node, bool *is_u8) {
@@ -1032,6 +1241,47 @@ hl_status hl_upload_field(hl_ctx *c, int field, const void *in, int64_t count, i
         hl::launch_aos_to_soa(n, w, c->scratch, dst, s);
     }
     HIPCHK(hipStreamSynchronize(s));
+    return HL_OK;
+}
+
+hl_status hl_forward_record(hl_ctx *c, int nsteps, int ckpt_every) {
+    if (!c || nsteps < 1 || ckpt_every < 1) return HL_E_INVALID;
+    if (!c->have_state) return HL_E_STATE;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    const bool prof = c->prof.on, graph = c->graph_on;
+    c->prof.on = false;
+    c->graph_on = false;
+    hl_status st = c->dim == 3 ? forward_record<3>(c, nsteps, ckpt_every) : forward_record<2>(c, nsteps, ckpt_every);
+    c->prof.on = prof;
+    c->graph_on = graph;
+    if (st != HL_OK) free_tape(c);
+    return st;
+}
+
+hl_status hl_forward_replay(hl_ctx *c) {
+    if (!c) return HL_E_INVALID;
+    if (!c->have_state || c->tape.nsteps == 0) return HL_E_STATE;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    return c->dim == 3 ? forward_replay<3>(c) : forward_replay<2>(c);
+}
+
+hl_status hl_adjoint_run(hl_ctx *c, const double *dL_dx_final, double *dL_dmu, double *dL_dvcell,
+                         double *dL_dvnode, int on_device) {
+    if (!c || !dL_dx_final || !dL_dmu || !dL_dvcell || !dL_dvnode) return HL_E_INVALID;
+    if (!c->have_state || c->tape.nsteps == 0) return HL_E_STATE;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    return c->dim == 3 ? adjoint_run<3>(c, dL_dx_final, dL_dmu, dL_dvcell, dL_dvnode, on_device)
+                       : adjoint_run<2>(c, dL_dx_final, dL_dmu, dL_dvcell, dL_dvnode, on_device);
+}
+
+hl_status hl_tape_get(hl_ctx *c, int step, uint8_t *mask, double *dt) {
+    if (!c || step < 0 || step >= c->tape.nsteps) return HL_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    if (mask && c->nc)
+        HIPCHK(hipMemcpy(mask, c->tape.masks + (size_t)step * c->nc, (size_t)c->nc, hipMemcpyDeviceToHost));
+    if (dt)
+        HIPCHK(hipMemcpy(dt, c->tape.dts + (size_t)step * c->n_mesh, sizeof(double) * c->n_mesh,
+                         hipMemcpyDeviceToHost));
     return HL_OK;
 }
 

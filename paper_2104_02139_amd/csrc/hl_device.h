@@ -9,6 +9,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
+// callable from kernels and, for the self-tests, from host code
+#define HL_HD __host__ __device__ __forceinline__
+
 namespace hl {
 
 template <int D>
@@ -50,7 +55,7 @@ struct Geo {
     double cn[D + 1];   // |C_k|
 };
 
-__device__ __forceinline__ void geom3(const double X[4][3], Geo<3> &g) {
+HL_HD void geom3(const double X[4][3], Geo<3> &g) {
     double e1[3], e2[3], e3[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -76,7 +81,7 @@ __device__ __forceinline__ void geom3(const double X[4][3], Geo<3> &g) {
         g.cn[k] = sqrt(g.C[k][0] * g.C[k][0] + g.C[k][1] * g.C[k][1] + g.C[k][2] * g.C[k][2]);
 }
 
-__device__ __forceinline__ void geom2(const double X[3][2], Geo<2> &g) {
+HL_HD void geom2(const double X[3][2], Geo<2> &g) {
     double e1x = X[1][0] - X[0][0], e1y = X[1][1] - X[0][1];
     double e2x = X[2][0] - X[0][0], e2y = X[2][1] - X[0][1];
     g.C[1][0] = 0.5 * e2y;
@@ -91,17 +96,17 @@ __device__ __forceinline__ void geom2(const double X[3][2], Geo<2> &g) {
 }
 
 template <int D>
-__device__ __forceinline__ void geom(const double X[D + 1][D], Geo<D> &g);
+HL_HD void geom(const double X[D + 1][D], Geo<D> &g);
 template <>
-__device__ __forceinline__ void geom<3>(const double X[4][3], Geo<3> &g) { geom3(X, g); }
+HL_HD void geom<3>(const double X[4][3], Geo<3> &g) { geom3(X, g); }
 template <>
-__device__ __forceinline__ void geom<2>(const double X[3][2], Geo<2> &g) { geom2(X, g); }
+HL_HD void geom<2>(const double X[3][2], Geo<2> &g) { geom2(X, g); }
 
 // ------------------------------------------------------- constitutive law
 // Neo-Hookean law (Section 2.2.4) with the bulk modulus K in the
 // volumetric energy: p = -(K/2)(J - 1 + ln J / J), T = -p I + mu J^{-5/3}
 // dev(B), J = rho0 tau.
-__device__ __forceinline__ void stress6(double rho0, double mu, double K, double tau,
+HL_HD void stress6(double rho0, double mu, double K, double tau,
                                         const double b[6], double t[6]) {
     double J = rho0 * tau;
     double lj = log(J);
@@ -118,20 +123,20 @@ __device__ __forceinline__ void stress6(double rho0, double mu, double K, double
 }
 
 // a = sqrt(tau (K_t + 4 mu / 3)), K_t = (K/2)(J + (1 - ln J)/J) = -J dp/dJ
-__device__ __forceinline__ double sound(double rho0, double mu, double K, double tau) {
+HL_HD double sound(double rho0, double mu, double K, double tau) {
     double J = rho0 * tau;
     double Kt = 0.5 * K * (J + (1.0 - log(J)) / J);
     return sqrt(tau * (Kt + (4.0 / 3.0) * mu));
 }
 
-__device__ __forceinline__ double det6(const double b[6]) {
+HL_HD double det6(const double b[6]) {
     return b[0] * (b[1] * b[2] - b[5] * b[5]) - b[3] * (b[3] * b[2] - b[5] * b[4]) +
            b[4] * (b[3] * b[5] - b[1] * b[4]);
 }
 
 // ------------------------------------------------------------- solves
 // inverse of a symmetric DxD matrix given in midx storage; returns det
-__device__ __forceinline__ double sym_inv3(const double a[6], double inv[6]) {
+HL_HD double sym_inv3(const double a[6], double inv[6]) {
     double c00 = a[1] * a[2] - a[5] * a[5];
     double c01 = a[4] * a[5] - a[3] * a[2];
     double c02 = a[3] * a[5] - a[4] * a[1];
@@ -146,7 +151,7 @@ __device__ __forceinline__ double sym_inv3(const double a[6], double inv[6]) {
     return det;
 }
 
-__device__ __forceinline__ double sym_inv2(const double a[3], double inv[3]) {
+HL_HD double sym_inv2(const double a[3], double inv[3]) {
     double det = a[0] * a[1] - a[2] * a[2];
     double r = 1.0 / det;
     inv[0] = a[1] * r;
@@ -157,7 +162,7 @@ __device__ __forceinline__ double sym_inv2(const double a[3], double inv[3]) {
 
 // Dense n x n solve with partial pivoting, fully unrolled; A row-major.
 template <int N>
-__device__ __forceinline__ void gepp(double A[N][N], double b[N]) {
+HL_HD void gepp(double A[N][N], double b[N]) {
 #pragma unroll
     for (int col = 0; col < N; ++col) {
         // pivot search
@@ -207,7 +212,7 @@ __device__ __forceinline__ void gepp(double A[N][N], double b[N]) {
 // order (11, 22, 33, 12, 13, 23) in 3D and (11, 22, 12) in 2D; entry
 // (row (i,j), col (a,c)) is the coefficient of X_ac in
 // (L X + X L^T)_ij = sum_k L_ik X_kj + X_ik L_jk.
-__device__ __forceinline__ void lie_matrix3(const double L[3][3], double M[6][6]) {
+HL_HD void lie_matrix3(const double L[3][3], double M[6][6]) {
     const double l00 = L[0][0], l01 = L[0][1], l02 = L[0][2];
     const double l10 = L[1][0], l11 = L[1][1], l12 = L[1][2];
     const double l20 = L[2][0], l21 = L[2][1], l22 = L[2][2];
@@ -219,7 +224,7 @@ __device__ __forceinline__ void lie_matrix3(const double L[3][3], double M[6][6]
     M[5][0] = 0;       M[5][1] = l21;     M[5][2] = l12;     M[5][3] = l20;       M[5][4] = l10;       M[5][5] = l11 + l22;
 }
 
-__device__ __forceinline__ void lie_matrix2(const double L[2][2], double M[3][3]) {
+HL_HD void lie_matrix2(const double L[2][2], double M[3][3]) {
     M[0][0] = 2 * L[0][0]; M[0][1] = 0;           M[0][2] = 2 * L[0][1];
     M[1][0] = 0;           M[1][1] = 2 * L[1][1]; M[1][2] = 2 * L[1][0];
     M[2][0] = L[1][0];     M[2][1] = L[0][1];     M[2][2] = L[0][0] + L[1][1];
@@ -228,7 +233,7 @@ __device__ __forceinline__ void lie_matrix2(const double L[2][2], double M[3][3]
 // Crank-Nicolson update of B (Section 3.4, eq. CN_B with dt/2 on both
 // sides):  X - h (L1 X + X L1^T) = Bn + h (Ln Bn + Bn Ln^T),  h = dt/2,
 // for the symmetric unknown X.  L are DxD (L_ij = dv_i/dx_j).
-__device__ __forceinline__ void cn_update3(const double b[6], const double Ln[3][3], const double L1[3][3], double h,
+HL_HD void cn_update3(const double b[6], const double Ln[3][3], const double L1[3][3], double h,
                                            double out[6]) {
     double A[6][6], r[6];
     lie_matrix3(Ln, A);
@@ -249,7 +254,7 @@ __device__ __forceinline__ void cn_update3(const double b[6], const double Ln[3]
     for (int s = 0; s < 6; ++s) out[s] = r[s];
 }
 
-__device__ __forceinline__ void cn_update2(const double b[6], const double Ln[2][2], const double L1[2][2], double h,
+HL_HD void cn_update2(const double b[6], const double Ln[2][2], const double L1[2][2], double h,
                                            double out[6]) {
     double A[3][3], r[3];
     const double bs[3] = {b[0], b[1], b[3]};
@@ -276,15 +281,15 @@ __device__ __forceinline__ void cn_update2(const double b[6], const double Ln[2]
 }
 
 template <int D>
-__device__ __forceinline__ void cn_update(const double b[6], const double Ln[D][D], const double L1[D][D], double h,
+HL_HD void cn_update(const double b[6], const double Ln[D][D], const double L1[D][D], double h,
                                           double out[6]);
 template <>
-__device__ __forceinline__ void cn_update<3>(const double b[6], const double Ln[3][3], const double L1[3][3], double h,
+HL_HD void cn_update<3>(const double b[6], const double Ln[3][3], const double L1[3][3], double h,
                                              double out[6]) {
     cn_update3(b, Ln, L1, h, out);
 }
 template <>
-__device__ __forceinline__ void cn_update<2>(const double b[6], const double Ln[2][2], const double L1[2][2], double h,
+HL_HD void cn_update<2>(const double b[6], const double Ln[2][2], const double L1[2][2], double h,
                                              double out[6]) {
     cn_update2(b, Ln, L1, h, out);
 }

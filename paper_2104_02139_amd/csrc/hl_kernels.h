@@ -41,6 +41,29 @@ struct StepArgs {
 
 enum { CNT_F0 = 0, CNT_F1 = 1, CNT_NODES = 2, CNT_CELLS = 3, CNT_BAD = 4, CNT_N = 8 };
 
+// Adjoint of one step (frozen dt and cascade choice).  Layouts are sized for
+// 3D; 2D uses the leading components of each slot.
+struct AdjArgs {
+    // lambda after the step (in) and before it (out), laid out like the state
+    const double *lx_in, *lvh_in, *ltau_in, *lv_in, *lB_in;
+    double *lx_out, *lvh_out, *ltau_out, *lv_out, *lB_out;
+    double *cadj;    // [corners][CA]  update^T contributions per corner
+    double *nadj;    // [nodes][NAD]   nodal-solve^T: rbar_p, Mbar_p
+    double *cell;    // [cells][CL]    least-squares adjoint, W adjoint
+    double *agg;     // [nodes][NAA]   aggregates of the least-squares adjoint
+    double *xadj;    // [corners][3]   position adjoint per corner
+    double *mu_bar;  // [cells]        accumulated adjoint of mu
+    static constexpr int O_X0 = 0, O_X1 = 3, O_VH0 = 6, O_VS = 9, O_VH1 = 12, O_M = 15, O_R = 21, CA = 24;
+    static constexpr int NAD = 9;
+    static constexpr int O_BB = 0, O_AH = 30, O_WB = 36, CL = 46;
+    static constexpr int NAA = 52;
+};
+
+template <int D> void launch_adjoint_step(const StepArgs &a, const AdjArgs &j, hipStream_t s);
+template <int D>
+void launch_adj_project(int64_t nn, const uint8_t *nallow, const double *allow, const double *lvh, double *out,
+                        hipStream_t s);
+
 template <int D> void launch_centroids(const StepArgs &a, hipStream_t s);
 template <int D> void launch_node_agg(const StepArgs &a, hipStream_t s);
 template <int D> void launch_predict(const StepArgs &a, hipStream_t s);

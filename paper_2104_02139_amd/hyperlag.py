@@ -24,7 +24,8 @@ FIELDS = dict(x=HL_X, vhat=HL_VHAT, tau=HL_TAU, v=HL_V, e=HL_E, B=HL_B, vstar=HL
 EXPORTS = ["hl_create", "hl_destroy", "hl_mesh_upload", "hl_state_init", "hl_set_params",
            "hl_compute_dt", "hl_step", "hl_step_replay", "hl_query", "hl_upload_field",
            "hl_profile_enable", "hl_profile_reset", "hl_profile_get", "hl_status_str",
-           "hl_last_error", "hl_mesh_upload_batch", "hl_step_batch", "hl_query_dt", "hl_use_graph"]
+           "hl_last_error", "hl_mesh_upload_batch", "hl_step_batch", "hl_query_dt", "hl_use_graph",
+           "hl_forward_record", "hl_forward_replay", "hl_adjoint_run", "hl_tape_get"]
 
 
 class Params(C.Structure):
@@ -80,6 +81,10 @@ def load():
     L.hl_step_batch.argtypes = [vp, vp, C.c_int, C.POINTER(StepInfo)]
     L.hl_query_dt.argtypes = [vp, vp, C.c_int, C.c_int]
     L.hl_use_graph.argtypes = [vp, C.c_int, C.c_int]
+    L.hl_forward_record.argtypes = [vp, C.c_int, C.c_int]
+    L.hl_forward_replay.argtypes = [vp]
+    L.hl_adjoint_run.argtypes = [vp, vp, vp, vp, vp, C.c_int]
+    L.hl_tape_get.argtypes = [vp, C.c_int, vp, vp]
     L.hl_state_init.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(Params), C.c_int]
     L.hl_set_params.argtypes = [vp, C.POINTER(Params)]
     L.hl_compute_dt.argtypes = [vp, C.POINTER(dp)]
@@ -270,6 +275,44 @@ class Context:
 
     def use_graph(self, on=True, max_mood_passes=6):
         _check(load().hl_use_graph(self._h, 1 if on else 0, int(max_mood_passes)), "hl_use_graph")
+
+    # ----------------------------------------------------------- adjoint
+    def forward_record(self, nsteps, ckpt_every=20):
+        _check(load().hl_forward_record(self._h, int(nsteps), int(ckpt_every)), "hl_forward_record")
+
+    def forward_replay(self):
+        _check(load().hl_forward_replay(self._h), "hl_forward_replay")
+
+    def adjoint_run(self, dL_dx):
+        """Gradients (dL/dmu [n_cells], dL/dv_cell [n_cells, d], dL/dv_node
+        [n_nodes, d]) for dL/dx_final; numpy in -> numpy out, CUDA tensor in
+        -> CUDA tensors out."""
+        d = self.dim
+        if _is_torch(dL_dx) and dL_dx.is_cuda:
+            import torch
+            g = dL_dx.contiguous().to(torch.float64)
+            mu = torch.empty(self.n_cells, dtype=torch.float64, device=g.device)
+            vc = torch.empty((self.n_cells, d), dtype=torch.float64, device=g.device)
+            vn = torch.empty((self.n_nodes, d), dtype=torch.float64, device=g.device)
+            _check(load().hl_adjoint_run(self._h, C.c_void_p(g.data_ptr()), C.c_void_p(mu.data_ptr()),
+                                         C.c_void_p(vc.data_ptr()), C.c_void_p(vn.data_ptr()), 1),
+                   "hl_adjoint_run")
+            return mu, vc, vn
+        g = np.ascontiguousarray(dL_dx, dtype=np.float64)
+        mu = np.empty(self.n_cells)
+        vc = np.empty((self.n_cells, d))
+        vn = np.empty((self.n_nodes, d))
+        _check(load().hl_adjoint_run(self._h, g.ctypes.data_as(C.c_void_p), mu.ctypes.data_as(C.c_void_p),
+                                     vc.ctypes.data_as(C.c_void_p), vn.ctypes.data_as(C.c_void_p), 0),
+               "hl_adjoint_run")
+        return mu, vc, vn
+
+    def tape(self, step):
+        mask = np.empty(self.n_cells, np.uint8)
+        dt = np.empty(getattr(self, "n_meshes", 1))
+        _check(load().hl_tape_get(self._h, int(step), mask.ctypes.data_as(C.c_void_p),
+                                  dt.ctypes.data_as(C.c_void_p)), "hl_tape_get")
+        return mask, dt
 
     # kernel timing with HIP events on the context's stream
     def profile(self, on=True):
