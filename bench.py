@@ -179,6 +179,40 @@ def batch_measure(steps=5, warmup=2, n_meshes=256):
             "speedup": ts / tb}
 
 
+def adjoint_measure(n=32, steps=200, every=20):
+    """Shear-modulus identification cube (32^3 Kuhn cells, lognormal mu):
+    time of the checkpointed forward record, of the same steps without
+    recording, and of the reverse sweep."""
+    import numpy as np
+    import torch
+    from paper_2104_02139_amd import hyperlag as H
+    from paper_2104_02139_amd import workloads as W
+    w = W.identification_cube_3d(n=n, steps=steps)
+    ctx = H.from_workload(w, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(0.0, info=False)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    ctx.init_state(w.rho0, w.mu, w.lam, w.v_cell, w.v_node, ctx.params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.forward_record(steps, every)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    g = np.random.default_rng(0).standard_normal((w.n_nodes, w.dim))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gmu, _, _ = ctx.adjoint_run(g)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    return {"workload": f"identification_cube_{w.n_cells}", "n_cells": w.n_cells, "steps": steps,
+            "ckpt_every": every, "forward_ms_per_step": 1e3 * t_plain / steps,
+            "forward_record_ms_per_step": 1e3 * t_rec / steps, "adjoint_ms_per_step": 1e3 * t_adj / steps,
+            "adjoint_forward_ratio": t_adj / t_plain, "grad_finite": bool(np.all(np.isfinite(gmu)))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +222,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the many-mesh batched-vs-sequential measurement")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward time measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -286,6 +322,10 @@ def main():
         "adjoint_forward_ratio": None,
         "kernel_source_sha1": kernel_source_hash(),
     }
+    if not args.no_adjoint:
+        print("[bench] adjoint vs forward on the identification cube", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_measure()
+        out["adjoint_forward_ratio"] = out["adjoint"]["adjoint_forward_ratio"]
     if not args.no_batch:
         print("[bench] batched many-mesh step vs mesh-after-mesh launches", file=sys.stderr, flush=True)
         out["batch"] = batch_measure()

@@ -68,6 +68,14 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise HyperLagError(f"{LIB_PATH} is not built; run `python -m paper_2104_02139_amd.build`")
+    # PyTorch ships its own HIP runtime.  Loading it first makes the
+    # library bind to that same runtime (one runtime per process), so
+    # torch's streams and device pointers are valid handles here and torch
+    # can still initialise the GPU after the library has used it.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, i64, dp = C.c_void_p, C.c_int64, C.c_double
     L.hl_status_str.restype = C.c_char_p

@@ -122,3 +122,38 @@ def test_adjoint_against_oracle_gradient():
         rel = abs(gmu[c] - fd) / max(abs(fd), 1e-300)
         print(f"  cell {c}: adjoint {gmu[c]:.10e} oracle fd {fd:.10e} rel {rel:.2e}", flush=True)
         assert rel <= 1e-5
+
+
+def test_autograd_function_identification_step():
+    """torch.autograd through the library: L = sum |x(T) - x_target|^2 with
+    x_target from another shear-modulus field; the gradient from backward
+    equals the adjoint of dL/dx = 2 (x(T) - x_target), and a small step
+    along -grad lowers L (replayed with the recorded dt and masks)."""
+    import torch
+    from paper_2104_02139_amd.autograd import run
+
+    w = W.identification_cube_3d(n=3, steps=12)
+    dev = torch.device("cuda:0")
+    hctx = H.from_workload(w)
+    # target: final positions with a second seeded modulus field
+    mu_t = torch.tensor(W.shear_modulus_field(w.n_cells, seed=9), dtype=torch.float64, device=dev)
+    vc = torch.tensor(w.v_cell * 50.0, dtype=torch.float64, device=dev)
+    vn = torch.tensor(w.v_node * 50.0, dtype=torch.float64, device=dev)
+    with torch.no_grad():
+        x_target = run(mu_t, vc, vn, hctx, w, 12, 5).clone()
+    mu = torch.tensor(w.mu, dtype=torch.float64, device=dev, requires_grad=True)
+    x = run(mu, vc, vn, hctx, w, 12, 5)
+    loss = ((x - x_target) ** 2).sum()
+    loss.backward()
+    g = mu.grad.detach().cpu().numpy()
+    assert np.all(np.isfinite(g)) and np.abs(g).max() > 0
+    gmu, _, _ = hctx.adjoint_run((2 * (x - x_target)).detach())
+    assert np.allclose(g, gmu.cpu().numpy(), rtol=1e-12, atol=0)
+    # descent along -grad with the recorded dt / masks
+    mu_np = mu.detach().cpu().numpy()
+    mu2 = mu_np - 1e-3 * mu_np.max() * g / np.abs(g).max()
+    hctx.init_state(w.rho0, mu2, w.lam, vc.cpu().numpy(), vn.cpu().numpy(), hctx.params)
+    hctx.forward_replay()
+    l2 = float(np.sum((hctx.query("x") - x_target.cpu().numpy()) ** 2))
+    print(f"  L {float(loss):.6e} -> {l2:.6e}", flush=True)
+    assert l2 < float(loss)
