@@ -335,7 +335,7 @@ __global__ __launch_bounds__(256) void k_adj_predict(StepArgs a, AdjArgs j) {
             double u[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) u[i] = xc[i] - a.x[i * nn + p];
-            const double *ag = a.agg + p * Dm::NA;
+            const AggRef ag(a.agg, nn, p);
             const double n = ag[0];
             visits += n - 1.0;
 #pragma unroll
@@ -728,7 +728,7 @@ __global__ __launch_bounds__(256) void k_adj_lsq(StepArgs a, AdjArgs j) {
 #pragma unroll
         for (int i = 0; i < D; ++i) y[i] = xc[i] - X[k][i];
         const double *ad = j.agg + p * AdjArgs::NAA;
-        const double *fg = a.agg + p * Dm::NA;
+        const AggRef fg(a.agg, a.nn, p);
         const double n = fg[0];
         // as a neighbour of the cells around p
 #pragma unroll

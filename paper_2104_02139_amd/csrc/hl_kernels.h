@@ -41,6 +41,30 @@ struct StepArgs {
 
 enum { CNT_F0 = 0, CNT_F1 = 1, CNT_NODES = 2, CNT_CELLS = 3, CNT_BAD = 4, CNT_N = 8 };
 
+// Node aggregates are stored pair-interleaved over nodes: values (2j, 2j+1)
+// of node p form the double2 at index j * nn + p.  A cell gathers the same
+// values of its nodes in every lane, and the nodes of neighbouring cells are
+// close in number, so one wave-wide load touches a few cache lines instead of
+// one line per lane.
+struct AggRef {
+    const double2 *b;
+    int64_t nn;
+    __device__ __forceinline__ AggRef(const double *agg, int64_t nn_, int64_t p)
+        : b(reinterpret_cast<const double2 *>(agg) + p), nn(nn_) {}
+    __device__ __forceinline__ double operator[](int j) const {
+        const double2 t = b[(int64_t)(j >> 1) * nn];
+        return (j & 1) ? t.y : t.x;
+    }
+};
+
+template <int N>
+__device__ __forceinline__ void agg_store(double *agg, int64_t nn, int64_t p, const double (&o)[N]) {
+    static_assert(N % 2 == 0, "aggregate records hold value pairs");
+    double2 *b = reinterpret_cast<double2 *>(agg) + p;
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) b[(int64_t)j * nn] = make_double2(o[2 * j], o[2 * j + 1]);
+}
+
 // Adjoint of one step (frozen dt and cascade choice).  Layouts are sized for
 // 3D; 2D uses the leading components of each slot.
 struct AdjArgs {

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_node_agg(int64_t nn, const int32_t *__r
         rmin = fmin(rmin, r);
         rmax = fmax(rmax, r);
     }
-    double *o = agg + p * Dm::NA;
+    double o[Dm::NA];
     o[0] = n;
 #pragma unroll
     for (int i = 0; i < D; ++i) o[Dm::O_SY + i] = Sy[i];
@@ -139,6 +139,7 @@ __global__ __launch_bounds__(256) void k_node_agg(int64_t nn, const int32_t *__r
     }
     o[Dm::O_RMM] = rmin;
     o[Dm::O_RMM + 1] = rmax;
+    agg_store(agg, nn, p, o);
 }
 
 // ---------------------------------------------------------- helpers
@@ -237,7 +238,7 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
             double u[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) u[i] = xc[i] - a.x[i * nn + p];
-            const double *ag = a.agg + p * Dm::NA;
+            const AggRef ag(a.agg, nn, p);
             const double n = ag[0];
             visits += n - 1.0;
             double Sy[D];
@@ -663,9 +664,9 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             const int64_t p = a.c2n[c * NV + k];
-            const double *ag = a.agg + p * Dm::NA + Dm::O_RMM;
-            lo = fmin(lo, ag[0]);
-            hi = fmax(hi, ag[1]);
+            const AggRef ag(a.agg, a.nn, p);
+            lo = fmin(lo, ag[Dm::O_RMM]);
+            hi = fmax(hi, ag[Dm::O_RMM + 1]);
         }
         const double rho1 = 1.0 / tau1;
         const double delta = fmax(a.delta0, a.delta1 * (hi - lo));
