@@ -131,7 +131,7 @@ def cpu_baseline(name, budget_s=25.0):
             "kind": "oracle", "sample": f"{sample}; {steps} steps in {el:.1f} s"}
 
 
-def batch_measure(steps=5, warmup=2, n_meshes=256):
+def batch_measure(steps=5, warmup=2, n_meshes=256, autotune=True):
     """Many independent meshes (a seeded mix of 2D and 3D, log-uniform
     sizes in [5e3, 2e5] cells): one batched context per dimension, one
     launch per stage over all meshes, the step captured in a hipGraph,
@@ -144,20 +144,34 @@ def batch_measure(steps=5, warmup=2, n_meshes=256):
     total = sum(w.n_cells for w in ws)
     stream = torch.cuda.current_stream()
     groups = [[w for w in ws if w.dim == d] for d in (2, 3)]
-    bctx = [H.from_workloads(g, stream=stream) for g in groups if g]
+    groups = [g for g in groups if g]
+    bctx = [H.from_workloads(g, stream=stream) for g in groups]
     for c in bctx:
         c.use_graph(True, 6)
-        c.compute_dt()
-    for _ in range(warmup):
+
+    def run_batched():
+        # every measurement starts from t = 0: the MOOD work of a step
+        # depends on the state
+        for c, g in zip(bctx, groups):
+            H.init_from_workloads(c, g)
+            c.compute_dt()
+        for _ in range(warmup):
+            for c in bctx:
+                c.step_batch(None, info=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for c in bctx:
+                c.step_batch(None, info=False)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    tb_default = run_batched()
+    tuned = []
+    if autotune:
         for c in bctx:
-            c.step_batch(None, info=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        for c in bctx:
-            c.step_batch(None, info=False)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
+            tuned.append({k: v[0] for k, v in c.autotune(reps=3).items()})
+    tb = run_batched()
     del bctx
     singles = [H.from_workload(w, stream=stream) for w in ws]
     for c in singles:
@@ -173,10 +187,11 @@ def batch_measure(steps=5, warmup=2, n_meshes=256):
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
     return {"workload": f"mesh_family_{n_meshes}", "n_meshes": n_meshes, "n_cells_total": total,
-            "n_2d": len(groups[0]), "n_3d": len(groups[1]), "steps": steps,
+            "n_2d": sum(w.dim == 2 for w in ws), "n_3d": sum(w.dim == 3 for w in ws), "steps": steps,
             "batched_cell_updates_per_s": total * steps / tb,
+            "batched_default_schedule_cell_updates_per_s": total * steps / tb_default,
             "sequential_cell_updates_per_s": total * steps / ts,
-            "speedup": ts / tb}
+            "speedup": ts / tb, "schedules": tuned}
 
 
 def adjoint_measure(n=32, steps=200, every=20):
@@ -224,6 +239,8 @@ def main():
                     help="skip the many-mesh batched-vs-sequential measurement")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward time measurement")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch schedules")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -258,6 +275,11 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = H.from_workload(w, device=0, stream=stream)
     ctx.compute_dt()
+    schedules = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        schedules = {k: v[0] for k, v in ctx.autotune(reps=3).items()}
+        print(f"[bench] autotune {time.perf_counter() - t0:.1f} s: {schedules}", file=sys.stderr, flush=True)
 
     # warm-up (untimed), also the MOOD statistics
     iters, p0 = [], []
@@ -320,6 +342,7 @@ def main():
         "mood": {"iters_mean": sum(iters) / len(iters), "first_order_frac_mean":
                  sum(p0) / len(p0) / w.n_cells},
         "adjoint_forward_ratio": None,
+        "schedules": schedules,
         "kernel_source_sha1": kernel_source_hash(),
     }
     if not args.no_adjoint:
@@ -328,7 +351,7 @@ def main():
         out["adjoint_forward_ratio"] = out["adjoint"]["adjoint_forward_ratio"]
     if not args.no_batch:
         print("[bench] batched many-mesh step vs mesh-after-mesh launches", file=sys.stderr, flush=True)
-        out["batch"] = batch_measure()
+        out["batch"] = batch_measure(autotune=not args.no_autotune)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(name)

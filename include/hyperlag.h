@@ -185,6 +185,43 @@ hl_status hl_step_replay(hl_ctx *ctx, double dt, const uint8_t *mask, int on_dev
  * max_mood_passes: 0..64. */
 hl_status hl_use_graph(hl_ctx *ctx, int on, int max_mood_passes);
 
+/* Stages of the full-mesh part of a step, for launch schedules. */
+enum {
+    HL_STAGE_PACK = 0,       /* per cell: gather record of the state */
+    HL_STAGE_NODE_AGG = 1,   /* per node: least-squares aggregates */
+    HL_STAGE_PREDICT = 2,    /* per cell: reconstruction, predictor, corners */
+    HL_STAGE_NODE_SOLVE = 3, /* per node: nodal solver */
+    HL_STAGE_UPDATE = 4,     /* per cell: update and detection */
+    HL_STAGE_COUNT = 5
+};
+
+/* Launch schedule of one stage.  Each mesh's entities (cells or nodes) are
+ * cut into work items of at most `tile` consecutive entities; items of the
+ * largest mesh come first.  One launch per stage covers all meshes of the
+ * context: blocks of `block` threads walk the items, each XCD a contiguous
+ * eighth of the list; with blocks_per_cu > 0 the launch has that many blocks
+ * per compute unit (persistent blocks), with 0 one block per item.  Results
+ * do not depend on the schedule (bitwise). */
+typedef struct {
+    int32_t tile;          /* 1 .. 2^20 */
+    int32_t block;         /* 64, 128, 192 or 256 */
+    int32_t blocks_per_cu; /* 0 .. 64 */
+    int32_t reserved;
+} hl_schedule;
+
+/* Set / get the schedule of stage `stage` (HL_STAGE_*).  The default is
+ * {256, 256, 0}.  Setting one drops captured graphs. */
+hl_status hl_set_schedule(hl_ctx *ctx, int stage, const hl_schedule *sched);
+hl_status hl_get_schedule(hl_ctx *ctx, int stage, hl_schedule *sched);
+
+/* Autotuner: times each stage on the current mesh and state under every
+ * candidate schedule (block 64/128/256, tile 1/2/4 blocks, 0/2/4/8 blocks
+ * per compute unit; `reps` timed launches each, HIP events on the context's
+ * stream) and keeps the fastest per stage.  The state is not changed; the
+ * next step rebuilds its work buffers.  best_ms: NULL or [HL_STAGE_COUNT],
+ * the chosen schedule's mean launch time.  reps: 1..100. */
+hl_status hl_autotune(hl_ctx *ctx, int reps, double *best_ms);
+
 /* ---------------------------------------------------------------------
  * Adjoint (not in the paper: differentiation of the step for parameter
  * identification).  The map from (mu, initial cell velocity, initial node

@@ -8,7 +8,10 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <numeric>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "hl_device.h"
@@ -28,6 +31,19 @@ struct Prof {
     size_t used = 0;                // pairs in use
     double total_ms[PK_COUNT] = {};
     int64_t count[PK_COUNT] = {};
+};
+
+// Launch schedule of one stage: entities per work item, threads per block,
+// blocks per compute unit (0: one block per item).
+struct StageCfg {
+    int tile = 256, block = 256, blocks_per_cu = 0;
+};
+// entity kind of each stage (HL_STAGE_* order): 0 cells, 1 nodes
+constexpr int kStageKind[HL_STAGE_COUNT] = {0, 1, 0, 1, 0};
+struct DevList {
+    int64_t *start = nullptr;
+    int32_t *len = nullptr;
+    int64_t n = 0;
 };
 
 }  // namespace
@@ -78,6 +94,12 @@ struct hl_ctx {
     hl_params prm{};
     std::vector<void *> allocs;
     Prof prof;
+    // stage schedules and their work lists (device memory in allocs)
+    int n_cu = 0;
+    StageCfg cfg[HL_STAGE_COUNT];
+    hl::Sched sk[HL_STAGE_COUNT] = {};
+    bool sched_ready = false;
+    std::map<std::pair<int, int>, DevList> wlists;  // (entity kind, tile) -> list
     // adjoint tapes (own allocations, freed with the mesh)
     struct {
         int nsteps = 0, every = 0, nckpt = 0;
@@ -167,6 +189,8 @@ void free_all(hl_ctx *c) {
     c->dt_cur = c->dt_next = c->dt_red = c->dt_parts = c->diag_part = c->diag_out = c->scratch = nullptr;
     c->have_mesh = c->have_state = false;
     c->rec_valid = false;
+    c->wlists.clear();
+    c->sched_ready = false;
 }
 
 template <class T>
@@ -177,6 +201,72 @@ hl_status dalloc(hl_ctx *c, T **p, size_t n) {
     c->allocs.push_back(q);
     *p = reinterpret_cast<T *>(q);
     return HL_OK;
+}
+
+// Work list of entity kind `kind` cut into items of at most `tile`
+// entities, items of the largest mesh first (ties in mesh order).
+hl_status work_list(hl_ctx *c, int kind, int tile, DevList *out) {
+    const auto key = std::make_pair(kind, tile);
+    auto it = c->wlists.find(key);
+    if (it != c->wlists.end()) {
+        *out = it->second;
+        return HL_OK;
+    }
+    const std::vector<int64_t> &off = kind == 0 ? c->cell_off_host : c->node_off_host;
+    std::vector<int> order((size_t)c->n_mesh);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
+    std::vector<int64_t> st;
+    std::vector<int32_t> ln;
+    for (int m : order)
+        for (int64_t b = off[m]; b < off[m + 1]; b += tile) {
+            st.push_back(b);
+            ln.push_back((int32_t)std::min<int64_t>(tile, off[m + 1] - b));
+        }
+    DevList d;
+    d.n = (int64_t)st.size();
+    hl_status r;
+    if ((r = dalloc(c, &d.start, st.size())) != HL_OK) return r;
+    if ((r = dalloc(c, &d.len, ln.size())) != HL_OK) return r;
+    if (d.n) {
+        HIPCHK(hipMemcpy(d.start, st.data(), sizeof(int64_t) * st.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d.len, ln.data(), sizeof(int32_t) * ln.size(), hipMemcpyHostToDevice));
+    }
+    c->wlists.emplace(key, d);
+    *out = d;
+    return HL_OK;
+}
+
+hl_status build_sched(hl_ctx *c, int stage, const StageCfg &g, hl::Sched *k) {
+    DevList d;
+    hl_status r = work_list(c, kStageKind[stage], g.tile, &d);
+    if (r != HL_OK) return r;
+    k->w.start = d.start;
+    k->w.len = d.len;
+    k->w.n_items = d.n;
+    int64_t grid = (d.n + 7) / 8 * 8;
+    if (g.blocks_per_cu > 0) grid = std::min<int64_t>(grid, ((int64_t)g.blocks_per_cu * c->n_cu + 7) / 8 * 8);
+    k->grid = (unsigned)std::max<int64_t>(8, grid);
+    k->block = (unsigned)g.block;
+    k->loop = g.blocks_per_cu > 0 || g.tile > g.block;
+    return HL_OK;
+}
+
+// Device work lists are built before any launch that may be captured.
+hl_status ensure_scheds(hl_ctx *c) {
+    if (c->sched_ready) return HL_OK;
+    for (int st = 0; st < HL_STAGE_COUNT; ++st) {
+        hl_status r = build_sched(c, st, c->cfg[st], &c->sk[st]);
+        if (r != HL_OK) return r;
+    }
+    c->sched_ready = true;
+    return HL_OK;
+}
+
+bool cfg_valid(const StageCfg &g) {
+    return g.tile >= 1 && g.tile <= (1 << 20) && g.block >= 64 && g.block <= 256 && g.block % 64 == 0 &&
+           g.blocks_per_cu >= 0 && g.blocks_per_cu <= 64;
 }
 
 // bring a borrowed input array to the host
@@ -371,10 +461,10 @@ void enqueue_first(hl_ctx *c, hl::StepArgs &a, bool copy_dt, bool clear_mask, hi
     if (clear_mask) hl::launch_fill_u8(c->mask, c->nc, 0, s);
     a.flist_out = c->flist[0];
     a.fcount_out = c->counters + hl::CNT_F0;
-    PROF(c, PK_NODE_AGG, hl::launch_node_agg<D>(a, s));
-    PROF(c, PK_PREDICT, hl::launch_predict<D>(a, s));
-    PROF(c, PK_NODE_SOLVE, hl::launch_node_solve<D>(a, s));
-    PROF(c, PK_UPDATE, hl::launch_update<D>(a, s));
+    PROF(c, PK_NODE_AGG, hl::launch_node_agg<D>(a, c->sk[HL_STAGE_NODE_AGG], s));
+    PROF(c, PK_PREDICT, hl::launch_predict<D>(a, c->sk[HL_STAGE_PREDICT], s));
+    PROF(c, PK_NODE_SOLVE, hl::launch_node_solve<D>(a, c->sk[HL_STAGE_NODE_SOLVE], s));
+    PROF(c, PK_UPDATE, hl::launch_update<D>(a, c->sk[HL_STAGE_UPDATE], s));
 }
 
 // MOOD pass reading flag list fb: the flagged cells drop to first order and
@@ -447,11 +537,15 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
                               mask_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         a.detect = 0;
     }
+    {
+        hl_status st = ensure_scheds(c);
+        if (st != HL_OK) return st;
+    }
     const bool graph = c->graph_on && !replay_mask && !c->prof.on;
     // the update kernel leaves the gather records of the state it writes;
     // after an upload they are rebuilt here
     if (!c->rec_valid) {
-        PROF(c, PK_CENTROIDS, hl::launch_centroids<D>(a, s));
+        PROF(c, PK_CENTROIDS, hl::launch_centroids<D>(a, c->sk[HL_STAGE_PACK], s));
         c->rec_valid = true;
     }
     int iters = 1;
@@ -591,11 +685,11 @@ void recompute_step(hl_ctx *c, int n) {
     hl::StepArgs a = make_args(c, 0);
     a.detect = 0;
     hl::launch_step_begin(c->counters, c->dt_cur, c->dt_next, c->n_mesh, 0, s);
-    hl::launch_centroids<D>(a, s);
-    hl::launch_node_agg<D>(a, s);
-    hl::launch_predict<D>(a, s);
-    hl::launch_node_solve<D>(a, s);
-    hl::launch_update<D>(a, s);
+    hl::launch_centroids<D>(a, c->sk[HL_STAGE_PACK], s);
+    hl::launch_node_agg<D>(a, c->sk[HL_STAGE_NODE_AGG], s);
+    hl::launch_predict<D>(a, c->sk[HL_STAGE_PREDICT], s);
+    hl::launch_node_solve<D>(a, c->sk[HL_STAGE_NODE_SOLVE], s);
+    hl::launch_update<D>(a, c->sk[HL_STAGE_UPDATE], s);
 }
 
 hl::AdjArgs adj_args(hl_ctx *c, int in) {
@@ -677,6 +771,10 @@ hl_status adjoint_run(hl_ctx *c, const double *dLdx, double *dLdmu, double *dLdv
     const size_t nn = c->nn, nc = c->nc, lam_sz = 2 * D * nn + (1 + D + (D == 3 ? 6 : 3)) * nc;
     const hipMemcpyKind kin = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     const hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    {
+        hl_status st = ensure_scheds(c);
+        if (st != HL_OK) return st;
+    }
     // lambda at the final time: dL/dx, nothing on the other fields
     HIPCHK(hipMemsetAsync(t.lam[0], 0, sizeof(double) * lam_sz, s));
     HIPCHK(hipMemsetAsync(t.mu_bar, 0, sizeof(double) * nc, s));
@@ -724,6 +822,90 @@ hl_status adjoint_run(hl_ctx *c, const double *dLdx, double *dLdmu, double *dLdv
     hipError_t le = hipGetLastError();
     if (le != hipSuccess) return hip_fail(le, "adjoint kernel launch", __LINE__);
     return HL_OK;
+}
+
+// ------------------------------------------------------------ autotuner
+template <int D>
+void launch_stage(hl_ctx *c, const hl::StepArgs &a, int stage, const hl::Sched &k, hipStream_t s) {
+    switch (stage) {
+        case HL_STAGE_PACK: hl::launch_centroids<D>(a, k, s); break;
+        case HL_STAGE_NODE_AGG: hl::launch_node_agg<D>(a, k, s); break;
+        case HL_STAGE_PREDICT: hl::launch_predict<D>(a, k, s); break;
+        case HL_STAGE_NODE_SOLVE: hl::launch_node_solve<D>(a, k, s); break;
+        default:
+            // the update appends flagged cells: start every run from empty lists
+            hl::launch_step_begin(c->counters, c->dt_cur, c->dt_next, c->n_mesh, 0, s);
+            hl::launch_update<D>(a, k, s);
+            break;
+    }
+}
+
+// Times every candidate schedule of every stage on the current mesh and
+// state (the stages read the state and write only work buffers and the
+// candidate buffers) and keeps the fastest.  Results do not depend on the
+// schedule: every entity is computed by one thread in a fixed order.
+template <int D>
+hl_status autotune(hl_ctx *c, int reps, double *best_ms) {
+    hipStream_t s = c->stream;
+    hl_status st = ensure_scheds(c);
+    if (st != HL_OK) return st;
+    const bool prof = c->prof.on;
+    c->prof.on = false;
+    hl::StepArgs a = make_args(c, c->cur);
+    hl::launch_step_begin(c->counters, c->dt_cur, c->dt_next, c->n_mesh, 1, s);
+    for (int stage = 0; stage < HL_STAGE_COUNT; ++stage) launch_stage<D>(c, a, stage, c->sk[stage], s);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    static const int kBlock[] = {64, 128, 256};
+    static const int kMult[] = {1, 2, 4};
+    static const int kPerCu[] = {0, 2, 4, 8};
+    auto sweep = [&](int stage, StageCfg *keep, double *best) -> hl_status {
+        for (int b : kBlock)
+            for (int m : kMult)
+                for (int q : kPerCu) {
+                    StageCfg g;
+                    g.tile = b * m;
+                    g.block = b;
+                    g.blocks_per_cu = q;
+                    hl::Sched k;
+                    hl_status r = build_sched(c, stage, g, &k);
+                    if (r != HL_OK) return r;
+                    launch_stage<D>(c, a, stage, k, s);
+                    HIPCHK(hipEventRecord(e0, s));
+                    for (int i = 0; i < reps; ++i) launch_stage<D>(c, a, stage, k, s);
+                    HIPCHK(hipEventRecord(e1, s));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < *best) {
+                        *best = ms;
+                        *keep = g;
+                    }
+                }
+        return HL_OK;
+    };
+    for (int stage = 0; stage < HL_STAGE_COUNT && st == HL_OK; ++stage) {
+        double best = 1e300;
+        StageCfg keep = c->cfg[stage];
+        st = sweep(stage, &keep, &best);
+        if (st != HL_OK) break;
+        c->cfg[stage] = keep;
+        if (best_ms) best_ms[stage] = best < 1e300 ? best / reps : 0.0;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->prof.on = prof;
+    // leave empty lists behind; the gather records now hold the candidate
+    hl::launch_step_begin(c->counters, c->dt_cur, c->dt_next, c->n_mesh, 0, s);
+    c->rec_valid = false;
+    c->sched_ready = false;
+    drop_graphs(c);
+    if (st != HL_OK) return st;
+    HIPCHK(hipStreamSynchronize(s));
+    hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return hip_fail(le, "autotune launch", __LINE__);
+    return ensure_scheds(c);
 }
 
 int field_width(const hl_ctx *c, int field, bool *node, bool *is_u8) {
@@ -797,6 +979,9 @@ hl_status hl_create(hl_ctx **out, int device, void *hip_stream) {
     if (hipSetDevice(device) != hipSuccess) return HL_E_HIP;
     hl_ctx *c = new hl_ctx();
     c->device = device;
+    if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        c->n_cu < 1)
+        c->n_cu = 256;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     *out = c;
     return HL_OK;
@@ -1291,6 +1476,36 @@ hl_status hl_use_graph(hl_ctx *c, int on, int max_mood_passes) {
     c->graph_on = on != 0;
     c->graph_passes = max_mood_passes;
     return HL_OK;
+}
+
+hl_status hl_set_schedule(hl_ctx *c, int stage, const hl_schedule *sch) {
+    if (!c || !sch || stage < 0 || stage >= HL_STAGE_COUNT) return HL_E_INVALID;
+    StageCfg g;
+    g.tile = sch->tile;
+    g.block = sch->block;
+    g.blocks_per_cu = sch->blocks_per_cu;
+    if (!cfg_valid(g)) return HL_E_INVALID;
+    c->cfg[stage] = g;
+    c->sched_ready = false;
+    drop_graphs(c);
+    return HL_OK;
+}
+
+hl_status hl_get_schedule(hl_ctx *c, int stage, hl_schedule *sch) {
+    if (!c || !sch || stage < 0 || stage >= HL_STAGE_COUNT) return HL_E_INVALID;
+    sch->tile = c->cfg[stage].tile;
+    sch->block = c->cfg[stage].block;
+    sch->blocks_per_cu = c->cfg[stage].blocks_per_cu;
+    sch->reserved = 0;
+    return HL_OK;
+}
+
+hl_status hl_autotune(hl_ctx *c, int reps, double *best_ms) {
+    if (!c || reps < 1 || reps > 100) return HL_E_INVALID;
+    if (!c->have_state) return HL_E_STATE;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    if (c->nc == 0) return HL_OK;
+    return c->dim == 3 ? autotune<3>(c, reps, best_ms) : autotune<2>(c, reps, best_ms);
 }
 
 hl_status hl_profile_enable(hl_ctx *c, int on) {

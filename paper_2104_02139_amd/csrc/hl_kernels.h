@@ -88,11 +88,30 @@ template <int D>
 void launch_adj_project(int64_t nn, const uint8_t *nallow, const double *allow, const double *lvh, double *out,
                         hipStream_t s);
 
-template <int D> void launch_centroids(const StepArgs &a, hipStream_t s);
-template <int D> void launch_node_agg(const StepArgs &a, hipStream_t s);
-template <int D> void launch_predict(const StepArgs &a, hipStream_t s);
-template <int D> void launch_node_solve(const StepArgs &a, hipStream_t s);
-template <int D> void launch_update(const StepArgs &a, hipStream_t s);
+// Work list of one stage launch.  An item is a run of at most `tile`
+// consecutive entities (cells or nodes) of one mesh; the items of the largest
+// mesh come first.  The launch has a multiple of 8 blocks and blocks are dealt
+// to the 8 XCDs round robin: the blocks on XCD x walk the x-th eighth of the
+// list in order (block slot s takes items s, s + nslot, ...), so the items one
+// L2 serves are neighbours in the mesh.  With fewer blocks than items the
+// blocks are persistent.
+struct WorkList {
+    const int64_t *start;  // first entity of each item
+    const int32_t *len;    // entities in each item
+    int64_t n_items;
+};
+struct Sched {
+    WorkList w;
+    unsigned grid, block;  // grid: multiple of 8; block: multiple of 64, <= 256
+    bool loop;             // false: one block per item and item <= block, so
+                           // each thread has at most one entity (no loop)
+};
+
+template <int D> void launch_centroids(const StepArgs &a, const Sched &k, hipStream_t s);
+template <int D> void launch_node_agg(const StepArgs &a, const Sched &k, hipStream_t s);
+template <int D> void launch_predict(const StepArgs &a, const Sched &k, hipStream_t s);
+template <int D> void launch_node_solve(const StepArgs &a, const Sched &k, hipStream_t s);
+template <int D> void launch_update(const StepArgs &a, const Sched &k, hipStream_t s);
 template <int D> void launch_acoustic(const StepArgs &a, hipStream_t s);
 template <int D>
 int64_t launch_diag(const StepArgs &a, const double *tau, const double *v, const double *e, const double *B,

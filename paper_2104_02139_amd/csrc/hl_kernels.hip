@@ -27,14 +27,38 @@ __device__ __forceinline__ int64_t gtid() {
     return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 }
 
-// Workgroups are dealt to the 8 XCDs round robin.  Launched with a block
-// count that is a multiple of 8, this remapping hands every XCD one
-// contiguous eighth of the index range, so blocks that share mesh nodes
-// share an L2.
-__device__ __forceinline__ int64_t gtid_xcd() {
-    const unsigned per = gridDim.x >> 3;
-    const unsigned b = blockIdx.x;
-    return ((int64_t)(b & 7u) * per + (b >> 3)) * blockDim.x + threadIdx.x;
+// Walk the items of a work list (see WorkList); f(entity) for each entity.
+template <class F>
+__device__ __forceinline__ void walk_items(const WorkList &w, F f) {
+    const int64_t nslot = gridDim.x >> 3;
+    const int64_t per = (w.n_items + 7) >> 3;
+    const int64_t i0 = (int64_t)(blockIdx.x & 7u) * per;
+    const int64_t i1 = i0 + per < w.n_items ? i0 + per : w.n_items;
+    for (int64_t i = i0 + (blockIdx.x >> 3); i < i1; i += nslot) {
+        const int64_t s0 = w.start[i];
+        const int n = w.len[i];
+        for (int j = threadIdx.x; j < n; j += blockDim.x) f(s0 + j);
+    }
+}
+
+// One block per item (grid >= 8 * ceil(n_items / 8)) and items no longer
+// than a block: the same XCD grouping without a loop around the body, which
+// keeps the body's register allocation as low as a plain launch's.
+template <class F>
+__device__ __forceinline__ void one_item(const WorkList &w, F f) {
+    const int64_t per = (w.n_items + 7) >> 3;
+    const int64_t slot = blockIdx.x >> 3;
+    const int64_t i = (int64_t)(blockIdx.x & 7u) * per + slot;
+    if (slot >= per || i >= w.n_items) return;
+    if ((int)threadIdx.x < w.len[i]) f(w.start[i] + threadIdx.x);
+}
+
+template <bool LOOP, class F>
+__device__ __forceinline__ void for_items(const WorkList &w, F f) {
+    if (LOOP)
+        walk_items(w, f);
+    else
+        one_item(w, f);
 }
 
 __device__ __forceinline__ double mesh_dt(const double *dtm, const int32_t *mesh_id, int64_t i) {
@@ -46,10 +70,8 @@ __device__ __forceinline__ double mesh_dt(const double *dtm, const int32_t *mesh
 // read by the node-aggregate gather (one cache line per neighbour instead
 // of one per scalar array).
 template <int D>
-__global__ __launch_bounds__(256) void k_pack(StepArgs a) {
+__device__ __forceinline__ void pack_cell(const StepArgs &a, const int64_t c) {
     using Dm = Dims<D>;
-    const int64_t c = gtid_xcd();
-    if (c >= a.nc) return;
     const int64_t nc = a.nc, nn = a.nn;
     double s[D] = {};
 #pragma unroll
@@ -73,6 +95,11 @@ __global__ __launch_bounds__(256) void k_pack(StepArgs a) {
     for (int q = 0; q < Dm::GR / 2; ++q) o[q] = make_double2(r[2 * q], r[2 * q + 1]);
 }
 
+template <int D, bool LOOP>
+__global__ __launch_bounds__(256) void k_pack(StepArgs a, WorkList w) {
+    for_items<LOOP>(w, [&](int64_t c) { pack_cell<D>(a, c); });
+}
+
 // ------------------------------------------------ node aggregates (R8)
 // For node p and every cell j around it, with y = x_j - x_p (centroid
 // relative to the node): n, sum y, sum y y^T, sum W_j, sum y W_j^T, and the
@@ -80,12 +107,11 @@ __global__ __launch_bounds__(256) void k_pack(StepArgs a) {
 // least-squares normal equations over all cells sharing a node with it
 // (one visit per shared node) from the aggregates of its own nodes.
 template <int D>
-__global__ __launch_bounds__(256) void k_node_agg(int64_t nn, const int32_t *__restrict__ off,
-                                                  const int32_t *__restrict__ n2c, const double *__restrict__ x,
-                                                  const double *__restrict__ rec, double *__restrict__ agg) {
+__device__ __forceinline__ void node_agg_one(int64_t nn, const int32_t *__restrict__ off,
+                                             const int32_t *__restrict__ n2c, const double *__restrict__ x,
+                                             const double *__restrict__ rec, double *__restrict__ agg,
+                                             const int64_t p) {
     using Dm = Dims<D>;
-    int64_t p = gtid_xcd();
-    if (p >= nn) return;
     double xp[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) xp[i] = x[i * nn + p];
@@ -140,6 +166,11 @@ __global__ __launch_bounds__(256) void k_node_agg(int64_t nn, const int32_t *__r
     o[Dm::O_RMM] = rmin;
     o[Dm::O_RMM + 1] = rmax;
     agg_store(agg, nn, p, o);
+}
+
+template <int D, bool LOOP>
+__global__ __launch_bounds__(256) void k_node_agg(StepArgs a, WorkList w) {
+    for_items<LOOP>(w, [&](int64_t p) { node_agg_one<D>(a.nn, a.n2c_off, a.n2c, a.x, a.xc, a.agg, p); });
 }
 
 // ---------------------------------------------------------- helpers
@@ -386,10 +417,9 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
     }
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void k_predict(StepArgs a) {
-    const int64_t c = gtid_xcd();
-    if (c < a.nc) predict_cell<D>(a, c);
+template <int D, bool LOOP>
+__global__ __launch_bounds__(256) void k_predict(StepArgs a, WorkList w) {
+    for_items<LOOP>(w, [&](int64_t c) { predict_cell<D>(a, c); });
 }
 
 // list-driven variant: the cells just flagged, recomputed at first order
@@ -483,10 +513,9 @@ __device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t 
     }
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void k_node_solve(StepArgs a) {
-    const int64_t p = gtid_xcd();
-    if (p < a.nn) node_solve_one<D>(a, p);
+template <int D, bool LOOP>
+__global__ __launch_bounds__(256) void k_node_solve(StepArgs a, WorkList w) {
+    for_items<LOOP>(w, [&](int64_t p) { node_solve_one<D>(a, p); });
 }
 
 template <int D>
@@ -683,10 +712,9 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
     a.dtc[nc + c] = dV > 0.0 ? V1 / dV : __builtin_huge_val();
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void k_update(StepArgs a) {
-    const int64_t c = gtid_xcd();
-    if (c < a.nc) update_cell<D>(a, c);
+template <int D, bool LOOP>
+__global__ __launch_bounds__(256) void k_update(StepArgs a, WorkList w) {
+    for_items<LOOP>(w, [&](int64_t c) { update_cell<D>(a, c); });
 }
 
 template <int D>
@@ -1003,28 +1031,46 @@ __global__ void k_stress_query(int64_t nc, const double *__restrict__ tau, const
 
 // ---------------------------------------------------------- launchers
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
-// block count rounded up to a multiple of 8 for gtid_xcd()
-static inline unsigned nblk8(int64_t n) { return (unsigned)(((n + 255) / 256 + 7) / 8 * 8); }
 
 template <int D>
-void launch_centroids(const StepArgs &a, hipStream_t s) {
-    if (a.nc) k_pack<D><<<nblk8(a.nc), 256, 0, s>>>(a);
+void launch_centroids(const StepArgs &a, const Sched &k, hipStream_t s) {
+    if (!k.w.n_items) return;
+    if (k.loop)
+        k_pack<D, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+    else
+        k_pack<D, false><<<k.grid, k.block, 0, s>>>(a, k.w);
 }
 template <int D>
-void launch_node_agg(const StepArgs &a, hipStream_t s) {
-    if (a.nn) k_node_agg<D><<<nblk8(a.nn), 256, 0, s>>>(a.nn, a.n2c_off, a.n2c, a.x, a.xc, a.agg);
+void launch_node_agg(const StepArgs &a, const Sched &k, hipStream_t s) {
+    if (!k.w.n_items) return;
+    if (k.loop)
+        k_node_agg<D, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+    else
+        k_node_agg<D, false><<<k.grid, k.block, 0, s>>>(a, k.w);
 }
 template <int D>
-void launch_predict(const StepArgs &a, hipStream_t s) {
-    if (a.nc) k_predict<D><<<nblk8(a.nc), 256, 0, s>>>(a);
+void launch_predict(const StepArgs &a, const Sched &k, hipStream_t s) {
+    if (!k.w.n_items) return;
+    if (k.loop)
+        k_predict<D, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+    else
+        k_predict<D, false><<<k.grid, k.block, 0, s>>>(a, k.w);
 }
 template <int D>
-void launch_node_solve(const StepArgs &a, hipStream_t s) {
-    if (a.nn) k_node_solve<D><<<nblk8(a.nn), 256, 0, s>>>(a);
+void launch_node_solve(const StepArgs &a, const Sched &k, hipStream_t s) {
+    if (!k.w.n_items) return;
+    if (k.loop)
+        k_node_solve<D, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+    else
+        k_node_solve<D, false><<<k.grid, k.block, 0, s>>>(a, k.w);
 }
 template <int D>
-void launch_update(const StepArgs &a, hipStream_t s) {
-    if (a.nc) k_update<D><<<nblk8(a.nc), 256, 0, s>>>(a);
+void launch_update(const StepArgs &a, const Sched &k, hipStream_t s) {
+    if (!k.w.n_items) return;
+    if (k.loop)
+        k_update<D, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+    else
+        k_update<D, false><<<k.grid, k.block, 0, s>>>(a, k.w);
 }
 template <int D>
 void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned *fcount, int64_t nflag,
@@ -1088,16 +1134,16 @@ void launch_stress_query(const StepArgs &a, double *out, hipStream_t s) {
     if (a.nc) k_stress_query<D><<<nblk(a.nc), 256, 0, s>>>(a.nc, a.tau, a.B, a.rho0, a.mu, a.K, out);
 }
 
-template void launch_centroids<2>(const StepArgs &, hipStream_t);
-template void launch_centroids<3>(const StepArgs &, hipStream_t);
-template void launch_node_agg<2>(const StepArgs &, hipStream_t);
-template void launch_node_agg<3>(const StepArgs &, hipStream_t);
-template void launch_predict<2>(const StepArgs &, hipStream_t);
-template void launch_predict<3>(const StepArgs &, hipStream_t);
-template void launch_node_solve<2>(const StepArgs &, hipStream_t);
-template void launch_node_solve<3>(const StepArgs &, hipStream_t);
-template void launch_update<2>(const StepArgs &, hipStream_t);
-template void launch_update<3>(const StepArgs &, hipStream_t);
+template void launch_centroids<2>(const StepArgs &, const Sched &, hipStream_t);
+template void launch_centroids<3>(const StepArgs &, const Sched &, hipStream_t);
+template void launch_node_agg<2>(const StepArgs &, const Sched &, hipStream_t);
+template void launch_node_agg<3>(const StepArgs &, const Sched &, hipStream_t);
+template void launch_predict<2>(const StepArgs &, const Sched &, hipStream_t);
+template void launch_predict<3>(const StepArgs &, const Sched &, hipStream_t);
+template void launch_node_solve<2>(const StepArgs &, const Sched &, hipStream_t);
+template void launch_node_solve<3>(const StepArgs &, const Sched &, hipStream_t);
+template void launch_update<2>(const StepArgs &, const Sched &, hipStream_t);
+template void launch_update<3>(const StepArgs &, const Sched &, hipStream_t);
 template void launch_mood_sparse<2>(const StepArgs &, const int32_t *, const unsigned *, int64_t, int64_t, bool,
                                     hipStream_t);
 template void launch_mood_sparse<3>(const StepArgs &, const int32_t *, const unsigned *, int64_t, int64_t, bool,

@@ -25,7 +25,11 @@ EXPORTS = ["hl_create", "hl_destroy", "hl_mesh_upload", "hl_state_init", "hl_set
            "hl_compute_dt", "hl_step", "hl_step_replay", "hl_query", "hl_upload_field",
            "hl_profile_enable", "hl_profile_reset", "hl_profile_get", "hl_status_str",
            "hl_last_error", "hl_mesh_upload_batch", "hl_step_batch", "hl_query_dt", "hl_use_graph",
-           "hl_forward_record", "hl_forward_replay", "hl_adjoint_run", "hl_tape_get"]
+           "hl_forward_record", "hl_forward_replay", "hl_adjoint_run", "hl_tape_get",
+           "hl_set_schedule", "hl_get_schedule", "hl_autotune"]
+
+# stages of the full-mesh part of a step (launch schedules)
+STAGES = ("pack", "node_agg", "predict", "node_solve", "update")
 
 
 class Params(C.Structure):
@@ -52,6 +56,11 @@ class StepInfo(C.Structure):
                     energy=self.energy, kinetic=self.kinetic, elastic=self.elastic,
                     n_p0=self.n_p0, n_flag_first=self.n_flag_first,
                     mood_iters=self.mood_iters, status=self.status)
+
+
+class Schedule(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("block", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class HyperLagError(RuntimeError):
@@ -100,6 +109,9 @@ def load():
     L.hl_step_replay.argtypes = [vp, dp, vp, C.c_int, C.POINTER(StepInfo)]
     L.hl_query.argtypes = [vp, C.c_int, vp, i64, C.c_int]
     L.hl_upload_field.argtypes = [vp, C.c_int, vp, i64, C.c_int]
+    L.hl_set_schedule.argtypes = [vp, C.c_int, C.POINTER(Schedule)]
+    L.hl_get_schedule.argtypes = [vp, C.c_int, C.POINTER(Schedule)]
+    L.hl_autotune.argtypes = [vp, C.c_int, vp]
     L.hl_profile_enable.argtypes = [vp, C.c_int]
     L.hl_profile_reset.argtypes = [vp]
     L.hl_profile_get.argtypes = [vp, C.c_char_p, C.POINTER(dp), C.POINTER(i64)]
@@ -284,6 +296,23 @@ class Context:
     def use_graph(self, on=True, max_mood_passes=6):
         _check(load().hl_use_graph(self._h, 1 if on else 0, int(max_mood_passes)), "hl_use_graph")
 
+    # --------------------------------------------------------- schedules
+    def set_schedule(self, stage, tile=256, block=256, blocks_per_cu=0):
+        st = Schedule(int(tile), int(block), int(blocks_per_cu), 0)
+        _check(load().hl_set_schedule(self._h, STAGES.index(stage), C.byref(st)), "hl_set_schedule")
+
+    def get_schedule(self, stage):
+        st = Schedule()
+        _check(load().hl_get_schedule(self._h, STAGES.index(stage), C.byref(st)), "hl_get_schedule")
+        return dict(tile=st.tile, block=st.block, blocks_per_cu=st.blocks_per_cu)
+
+    def autotune(self, reps=3):
+        """Pick the fastest launch schedule of every stage on the current
+        mesh and state; returns {stage: (schedule, mean launch ms)}."""
+        best = np.zeros(len(STAGES))
+        _check(load().hl_autotune(self._h, int(reps), best.ctypes.data_as(C.c_void_p)), "hl_autotune")
+        return {k: (self.get_schedule(k), float(best[i])) for i, k in enumerate(STAGES)}
+
     # ----------------------------------------------------------- adjoint
     def forward_record(self, nsteps, ckpt_every=20):
         _check(load().hl_forward_record(self._h, int(nsteps), int(ckpt_every)), "hl_forward_record")
@@ -348,9 +377,15 @@ def from_workloads(ws, device=0, stream=None, params=None):
     cat = lambda f: np.concatenate([getattr(w, f) for w in ws])
     ctx = Context(device, stream)
     ctx.upload_mesh_batch(dim, no, co, cat("x"), cat("cells"), cat("nwall"), cat("normals"))
-    ctx.init_state(cat("rho0"), cat("mu"), cat("lam"), cat("v_cell"), cat("v_node"),
-                   params if params is not None else default_params(dim, c_cfl=ws[0].c_cfl))
+    init_from_workloads(ctx, ws, params)
     return ctx
+
+
+def init_from_workloads(ctx, ws, params=None):
+    """(Re)initialise the state of a batched context built from ``ws``."""
+    cat = lambda f: np.concatenate([getattr(w, f) for w in ws])
+    ctx.init_state(cat("rho0"), cat("mu"), cat("lam"), cat("v_cell"), cat("v_node"),
+                   params if params is not None else default_params(ws[0].dim, c_cfl=ws[0].c_cfl))
 
 
 def from_workload(w, device=0, stream=None, params=None):

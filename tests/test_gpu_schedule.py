@@ -1,0 +1,105 @@
+"""Launch schedules of the stage kernels: work items of `tile` consecutive
+entities of one mesh (largest mesh first), walked by blocks of `block`
+threads, optionally persistent (a few blocks per compute unit).  Every
+entity is computed by one thread in a fixed order, so any schedule, and the
+one the autotuner picks, must give bitwise the same steps as the default."""
+import numpy as np
+import pytest
+
+from paper_2104_02139_amd import hyperlag as H
+from paper_2104_02139_amd import workloads as W
+
+from .parity_util import FIELDS
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [
+    dict(tile=64, block=64, blocks_per_cu=1),      # persistent, few blocks
+    dict(tile=512, block=128, blocks_per_cu=2),    # persistent, several items per block
+    dict(tile=100, block=192, blocks_per_cu=0),    # ragged items, idle lanes
+    dict(tile=1024, block=256, blocks_per_cu=8),
+]
+
+
+def _run(ctx, steps, batch):
+    masks = []
+    for _ in range(steps):
+        if batch:
+            ctx.step_batch(None)
+        else:
+            ctx.step(0.0)
+        masks.append(ctx.query("order").copy())
+    return ctx.state(), masks
+
+
+def _same(a, b):
+    sa, ma = a
+    sb, mb = b
+    for f in FIELDS:
+        assert np.array_equal(sa[f], sb[f]), f
+    for x, y in zip(ma, mb):
+        assert np.array_equal(x, y)
+
+
+def _bar():
+    # MOOD active: first-order cells appear within the first steps
+    return W.impact_bar_3d(nx=16, ny=4, graded=True, seed=11)
+
+
+def _family():
+    ws = [W.rotating_cube_3d(n=3, seed=1), W.impact_bar_3d(nx=10, ny=3, graded=False, seed=2),
+          W.rotating_cube_3d(n=5, seed=3), W.rotating_cube_3d(n=1, seed=4)]
+    ws[2].mu = ws[2].mu * 1.7
+    return ws
+
+
+@pytest.mark.parametrize("sched", range(len(SCHEDULES)))
+def test_schedule_does_not_change_results(sched):
+    w = _bar()
+    steps = 8
+    ref = _run(H.from_workload(w), steps, False)
+    assert sum(int(m.sum()) for m in ref[1]) > 0, "the case should exercise MOOD"
+    ctx = H.from_workload(w)
+    for stage in H.STAGES:
+        ctx.set_schedule(stage, **SCHEDULES[sched])
+        assert ctx.get_schedule(stage) == SCHEDULES[sched]
+    print(f"[schedule] {SCHEDULES[sched]} on {w.n_cells} cells", flush=True)
+    _same(ref, _run(ctx, steps, False))
+
+
+def test_schedules_on_batch_with_graph():
+    ws = _family()
+    ref = _run(H.from_workloads(ws), 6, True)
+    ctx = H.from_workloads(ws)
+    for i, stage in enumerate(H.STAGES):
+        ctx.set_schedule(stage, **SCHEDULES[i % len(SCHEDULES)])
+    ctx.use_graph(True, 4)
+    print(f"[schedule] batch of {len(ws)} meshes, graph, mixed schedules", flush=True)
+    _same(ref, _run(ctx, 6, True))
+
+
+def test_autotune_keeps_state_and_results():
+    w = _bar()
+    steps = 6
+    ref = _run(H.from_workload(w), steps, False)
+    ctx = H.from_workload(w)
+    before = ctx.state()
+    picked = ctx.autotune(reps=1)
+    print(f"[autotune] {picked}", flush=True)
+    after = ctx.state()
+    for f in FIELDS:
+        assert np.array_equal(before[f], after[f]), f
+    for stage, (sch, ms) in picked.items():
+        assert sch["block"] in (64, 128, 256) and sch["tile"] % sch["block"] == 0
+        assert ms > 0.0
+    _same(ref, _run(ctx, steps, False))
+
+
+def test_invalid_schedules_rejected():
+    ctx = H.from_workload(W.rotating_cube_3d(n=2, seed=1))
+    for bad in (dict(tile=0), dict(block=32), dict(block=320), dict(block=100),
+                dict(blocks_per_cu=-1), dict(blocks_per_cu=65), dict(tile=(1 << 20) + 1)):
+        with pytest.raises(H.HyperLagError):
+            ctx.set_schedule("predict", **bad)
+    with pytest.raises(ValueError):
+        ctx.set_schedule("no_such_stage")
