@@ -106,71 +106,128 @@ __global__ __launch_bounds__(256) void k_pack(StepArgs a, WorkList w) {
 // min / max of rho_j = 1 / tau_j.  A cell c then assembles its
 // least-squares normal equations over all cells sharing a node with it
 // (one visit per shared node) from the aggregates of its own nodes.
+// Cooperative gather: AGG_G lanes per node, lane l holding values
+// (2l, 2l+1) of each cell's gather record, so one wave-wide 16-byte load
+// brings whole records (8 cache lines for 8 nodes) instead of one line per
+// lane.  Each lane keeps, over the node's cells in CSR order, the sums of
+// its two values and of their products with y; y reaches every lane of the
+// group by shuffles from the lanes holding the centroid.  The products and
+// the summation order are the per-node loop's, so the sums are bitwise
+// those of one thread per node.
+constexpr int AGG_G = 8;
+
 template <int D>
-__device__ __forceinline__ void node_agg_one(int64_t nn, const int32_t *__restrict__ off,
-                                             const int32_t *__restrict__ n2c, const double *__restrict__ x,
-                                             const double *__restrict__ rec, double *__restrict__ agg,
-                                             const int64_t p) {
+__device__ __forceinline__ void node_agg_group(const StepArgs &a, const int64_t p, const int l,
+                                               double *__restrict__ o) {
     using Dm = Dims<D>;
+    constexpr int NW = Dm::NW;
+    const int64_t nn = a.nn;
+    const int v0 = 2 * l, v1 = 2 * l + 1;   // record values held by this lane
+    const bool has = v0 < Dm::GR;           // 2D records have 5 pairs
     double xp[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) xp[i] = x[i * nn + p];
-    double n = 0.0, Sy[D] = {}, Syy[Dm::NMS] = {}, SW[Dm::NW] = {}, SyW[Dm::NW][D] = {};
-    double rmin = __builtin_huge_val(), rmax = -__builtin_huge_val();
-    const int32_t q0 = off[p], q1 = off[p + 1];
-    for (int32_t q = q0; q < q1; ++q) {
-        const int64_t j = n2c[q] / (D + 1);
-        const double2 *rj = reinterpret_cast<const double2 *>(rec + j * Dm::GR);
-        double rr[Dm::GR];
+    for (int i = 0; i < D; ++i) xp[i] = a.x[i * nn + p];
+    // centroid values become y = x_c - x_p
+    double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int h = 0; h < Dm::GR / 2; ++h) {
-            const double2 t = rj[h];
-            rr[2 * h] = t.x;
-            rr[2 * h + 1] = t.y;
-        }
-        double y[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) y[i] = rr[Dm::NW + i] - xp[i];
-        double W[Dm::NW];
-#pragma unroll
-        for (int w = 0; w < Dm::NW; ++w) W[w] = rr[w];
-        n += 1.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            Sy[i] += y[i];
-#pragma unroll
-            for (int k = i; k < D; ++k) Syy[midx<D>(i, k)] += y[i] * y[k];
-        }
-#pragma unroll
-        for (int w = 0; w < Dm::NW; ++w) {
-            SW[w] += W[w];
-#pragma unroll
-            for (int i = 0; i < D; ++i) SyW[w][i] += y[i] * W[w];
-        }
-        double r = 1.0 / W[0];
-        rmin = fmin(rmin, r);
-        rmax = fmax(rmax, r);
+    for (int i = 0; i < D; ++i) {
+        s0 = v0 == NW + i ? xp[i] : s0;
+        s1 = v1 == NW + i ? xp[i] : s1;
     }
-    double o[Dm::NA];
-    o[0] = n;
+    double n = 0.0, Sa = 0.0, Sb = 0.0, Sya[D] = {}, Syb[D] = {};
+    double tmin = __builtin_huge_val(), tmax = -__builtin_huge_val();
+    const double2 *rec = reinterpret_cast<const double2 *>(a.xc);
+    const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
+    // corners in chunks of AGG_G: lane l reads the cell of corner qb + l,
+    // then all AGG_G record loads are issued before the sums, which run in
+    // CSR order
+    for (int32_t qb = q0; qb < q1; qb += AGG_G) {
+        const int32_t ql = qb + l;
+        const int jl = ql < q1 ? a.n2c[ql] / (D + 1) : 0;
+        double2 t[AGG_G];
 #pragma unroll
-    for (int i = 0; i < D; ++i) o[Dm::O_SY + i] = Sy[i];
+        for (int m = 0; m < AGG_G; ++m) {
+            const int jm = __shfl(jl, m, AGG_G);
+            t[m] = (has && qb + m < q1) ? rec[(int64_t)jm * (Dm::GR / 2) + l] : make_double2(0.0, 0.0);
+        }
 #pragma unroll
-    for (int s = 0; s < Dm::NMS; ++s) o[Dm::O_SYY + s] = Syy[s];
+        for (int m = 0; m < AGG_G; ++m) {
+            if (qb + m >= q1) break;
+            const double va = t[m].x - s0, vb = t[m].y - s1;
+            double y[D];
 #pragma unroll
-    for (int w = 0; w < Dm::NW; ++w) {
-        o[Dm::O_SW + w] = SW[w];
+            for (int i = 0; i < D; ++i) {
+                const int v = NW + i;
+                y[i] = __shfl((v & 1) ? vb : va, v >> 1, AGG_G);
+            }
+            n += 1.0;
+            Sa += va;
+            Sb += vb;
 #pragma unroll
-        for (int i = 0; i < D; ++i) o[Dm::O_SYW + w * D + i] = SyW[w][i];
+            for (int i = 0; i < D; ++i) {
+                Sya[i] += y[i] * va;
+                Syb[i] += y[i] * vb;
+            }
+            tmin = fmin(tmin, va);  // tau of the cell in lane 0
+            tmax = fmax(tmax, va);
+        }
     }
-    o[Dm::O_RMM] = rmin;
-    o[Dm::O_RMM + 1] = rmax;
-    agg_store(agg, nn, p, o);
+    // rho = 1/tau: a correctly rounded reciprocal is monotone on tau > 0, so
+    // these equal the min / max of the cells' 1/tau bitwise
+    const double rmin = 1.0 / tmax, rmax = 1.0 / tmin;
+    // this lane's share of the aggregate record
+    auto put = [&](int v, double S, const double (&Sy)[D]) {
+        if (v < NW) {
+            o[Dm::O_SW + v] = S;
+#pragma unroll
+            for (int i = 0; i < D; ++i) o[Dm::O_SYW + v * D + i] = Sy[i];
+        } else if (v < NW + D) {
+            const int k = v - NW;
+            o[Dm::O_SY + k] = S;
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+                if (i <= k) o[Dm::O_SYY + midx<D>(i, k)] = Sy[i];
+        }
+    };
+    put(v0, Sa, Sya);
+    put(v1, Sb, Syb);
+    if (l == 0) {
+        o[0] = n;
+        o[Dm::O_RMM] = rmin;
+        o[Dm::O_RMM + 1] = rmax;
+    }
 }
 
 template <int D, bool LOOP>
 __global__ __launch_bounds__(256) void k_node_agg(StepArgs a, WorkList w) {
-    for_items<LOOP>(w, [&](int64_t p) { node_agg_one<D>(a.nn, a.n2c_off, a.n2c, a.x, a.xc, a.agg, p); });
+    using Dm = Dims<D>;
+    __shared__ double sh[256 / AGG_G][Dm::NA + 1];
+    const int l = threadIdx.x & (AGG_G - 1);
+    const int g = threadIdx.x / AGG_G;
+    const int per_pass = blockDim.x / AGG_G;
+    const int64_t nn = a.nn;
+    // items as in walk_items; every thread of the block runs the same passes
+    const int64_t nslot = gridDim.x >> 3;
+    const int64_t per = (w.n_items + 7) >> 3;
+    const int64_t i0 = (int64_t)(blockIdx.x & 7u) * per;
+    const int64_t i1 = i0 + per < w.n_items ? i0 + per : w.n_items;
+    for (int64_t it = i0 + (blockIdx.x >> 3); it < i1; it += nslot) {
+        const int64_t s0 = w.start[it];
+        const int len = w.len[it];
+        for (int base = 0; base < len; base += per_pass) {
+            const bool act = base + g < len;
+            const int64_t p = s0 + base + g;
+            if (act) node_agg_group<D>(a, p, l, sh[g]);
+            __syncthreads();
+            if (act) {
+                double2 *b = reinterpret_cast<double2 *>(a.agg) + p;
+                for (int j = l; j < Dm::NA / 2; j += AGG_G)
+                    b[(int64_t)j * nn] = make_double2(sh[g][2 * j], sh[g][2 * j + 1]);
+            }
+            __syncthreads();
+        }
+        if (!LOOP) break;
+    }
 }
 
 // ---------------------------------------------------------- helpers
@@ -436,9 +493,13 @@ __global__ __launch_bounds__(256) void k_predict_list(StepArgs a, const int32_t 
 // (Appendix B eq. sBC1, reading R22).  Then x^{n+1} = x^n + dt v*_p and
 // vhat^{n+1} = 2 v*_p - vhat^n (Section 3.4, reading R9).
 template <int D>
+__device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64_t p, const bool any,
+                                                  const double (&M)[Dims<D>::NMS], const double (&r)[D],
+                                                  const int comp);
+
+template <int D>
 __device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t p) {
     using Dm = Dims<D>;
-    const int64_t nn = a.nn;
     double M[Dm::NMS] = {}, r[D] = {};
     const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
     for (int32_t q = q0; q < q1; ++q) {
@@ -448,9 +509,62 @@ __device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t 
 #pragma unroll
         for (int i = 0; i < D; ++i) r[i] += rec[Dm::NMS + i];
     }
+    node_solve_finish<D>(a, p, q1 > q0, M, r, -1);
+}
+
+// Cooperative corner gather (as for the node aggregates): lane l of a group
+// of AGG_G sums value pair l of the node's corner records in CSR order, so a
+// wave-wide load brings whole records; the sums then meet in every lane of
+// the group, which all run the solve.  Lane i < D writes component i.
+template <int D>
+__device__ __forceinline__ void node_solve_group(const StepArgs &a, const int64_t p, const int l) {
+    using Dm = Dims<D>;
+    constexpr int NP = Dm::CW / 2;  // value pairs per corner record
+    const bool has = l < NP;
+    const double2 *rec = reinterpret_cast<const double2 *>(a.corner);
+    double Sa = 0.0, Sb = 0.0;
+    const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
+    for (int32_t qb = q0; qb < q1; qb += AGG_G) {
+        const int32_t ql = qb + l;
+        const int kl = ql < q1 ? a.n2c[ql] : 0;
+        double2 t[AGG_G];
+#pragma unroll
+        for (int m = 0; m < AGG_G; ++m) {
+            const int km = __shfl(kl, m, AGG_G);
+            t[m] = (has && qb + m < q1) ? rec[(int64_t)km * NP + l] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int m = 0; m < AGG_G; ++m) {
+            if (qb + m >= q1) break;
+            Sa += t[m].x;
+            Sb += t[m].y;
+        }
+    }
+    double v[2 * NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        v[2 * j] = __shfl(Sa, j, AGG_G);
+        v[2 * j + 1] = __shfl(Sb, j, AGG_G);
+    }
+    double M[Dm::NMS], r[D];
+#pragma unroll
+    for (int s = 0; s < Dm::NMS; ++s) M[s] = v[s];
+#pragma unroll
+    for (int i = 0; i < D; ++i) r[i] = v[Dm::NMS + i];
+    node_solve_finish<D>(a, p, q1 > q0, M, r, l);
+}
+
+// v* from the summed corner matrices and right-hand sides; comp < 0 writes
+// every component, otherwise only component comp (if < D)
+template <int D>
+__device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64_t p, const bool any,
+                                                  const double (&M)[Dims<D>::NMS], const double (&r)[D],
+                                                  const int comp) {
+    using Dm = Dims<D>;
+    const int64_t nn = a.nn;
     double vs[D] = {};
     const int na = a.nallow[p];
-    if (q1 > q0 && na == D) {
+    if (any && na == D) {
         double inv[Dm::NMS];
         if (D == 3)
             sym_inv3(M, inv);
@@ -463,7 +577,7 @@ __device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t 
             for (int j = 0; j < D; ++j) s += inv[midx<D>(i, j)] * r[j];
             vs[i] = s;
         }
-    } else if (q1 > q0 && na > 0) {
+    } else if (any && na > 0) {
         // P: D x na orthonormal columns, P[i][t] = allow[p*D*D + i*D + t]
         const double *P = a.allow + p * D * D;
         double Mf[D][D];
@@ -507,6 +621,7 @@ __device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t 
     const double dt = mesh_dt(a.dt, a.node_mesh, p);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
+        if (comp >= 0 && comp != i) continue;
         a.vstar[i * nn + p] = vs[i];
         a.x1[i * nn + p] = a.x[i * nn + p] + dt * vs[i];
         a.vhat1[i * nn + p] = 2.0 * vs[i] - a.vhat[i * nn + p];
@@ -515,7 +630,19 @@ __device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t 
 
 template <int D, bool LOOP>
 __global__ __launch_bounds__(256) void k_node_solve(StepArgs a, WorkList w) {
-    for_items<LOOP>(w, [&](int64_t p) { node_solve_one<D>(a, p); });
+    const int l = threadIdx.x & (AGG_G - 1);
+    const int g = threadIdx.x / AGG_G;
+    const int per_pass = blockDim.x / AGG_G;
+    const int64_t nslot = gridDim.x >> 3;
+    const int64_t per = (w.n_items + 7) >> 3;
+    const int64_t i0 = (int64_t)(blockIdx.x & 7u) * per;
+    const int64_t i1 = i0 + per < w.n_items ? i0 + per : w.n_items;
+    for (int64_t it = i0 + (blockIdx.x >> 3); it < i1; it += nslot) {
+        const int64_t s0 = w.start[it];
+        const int len = w.len[it];
+        for (int base = g; base < len; base += per_pass) node_solve_group<D>(a, s0 + base, l);
+        if (!LOOP) break;
+    }
 }
 
 template <int D>
