@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void k_adj_update(StepArgs a, AdjArgs j) {
         for (int q = 0; q < AdjArgs::CA; ++q) rec[k][q] = 0.0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        const double *cr = a.corner + (c * NV + k) * Dm::CW;
+        const double *cr = a.corner + corner_slot<D>(c, k) * Dm::CW;
         double Mk[NMS];
 #pragma unroll
         for (int q = 0; q < NMS; ++q) Mk[q] = cr[q];
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256) void k_adj_node1(StepArgs a, AdjArgs j) {
     for (int32_t q = q0; q < q1; ++q) {
         const int64_t cid = a.n2c[q];
         const double *r = j.cadj + cid * AdjArgs::CA;
-        const double *cr = a.corner + cid * Dm::CW;
+        const double *cr = a.corner + corner_slot_of<D>(cid) * Dm::CW;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             x1b[i] += r[AdjArgs::O_X1 + i];

@@ -41,6 +41,20 @@ struct StepArgs {
 
 enum { CNT_F0 = 0, CNT_F1 = 1, CNT_NODES = 2, CNT_CELLS = 3, CNT_BAD = 4, CNT_N = 8 };
 
+// Corner records are stored corner-major within tiles of 256 cells: the
+// record of corner k of cell c is number ((c / 256) (D + 1) + k) 256 +
+// c % 256.  Lanes of consecutive cells then write and read consecutive
+// records, while each record stays contiguous for the nodes that gather it.
+// The array holds whole tiles: ceil(n_cells / 256) 256 (D + 1) records.
+template <int D>
+__host__ __device__ __forceinline__ int64_t corner_slot(int64_t c, int k) {
+    return ((((c >> 8) * (D + 1)) + k) << 8) + (c & 255);
+}
+template <int D>
+__host__ __device__ __forceinline__ int64_t corner_slot_of(int64_t corner_id) {
+    return corner_slot<D>(corner_id / (D + 1), (int)(corner_id % (D + 1)));
+}
+
 // Node aggregates are stored pair-interleaved over nodes: values (2j, 2j+1)
 // of node p form the double2 at index j * nn + p.  A cell gathers the same
 // values of its nodes in every lane, and the nodes of neighbouring cells are

@@ -461,7 +461,7 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
 #pragma unroll
             for (int j = i; j < D; ++j)
                 M[midx<D>(i, j)] = z * (S[midx<D>(i, j)] - g.C[k][i] * g.C[k][j] * rk);
-        double* o = a.corner + (c * NV + k) * Dm::CW;
+        double *o = a.corner + corner_slot<D>(c, k) * Dm::CW;
 #pragma unroll
         for (int q = 0; q < Dm::NMS; ++q) o[q] = M[q];
 #pragma unroll
@@ -503,7 +503,7 @@ __device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t 
     double M[Dm::NMS] = {}, r[D] = {};
     const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
     for (int32_t q = q0; q < q1; ++q) {
-        const double *rec = a.corner + (int64_t)a.n2c[q] * Dm::CW;
+        const double *rec = a.corner + corner_slot_of<D>(a.n2c[q]) * Dm::CW;
 #pragma unroll
         for (int s = 0; s < Dm::NMS; ++s) M[s] += rec[s];
 #pragma unroll
@@ -531,7 +531,7 @@ __device__ __forceinline__ void node_solve_group(const StepArgs &a, const int64_
 #pragma unroll
         for (int m = 0; m < AGG_G; ++m) {
             const int km = __shfl(kl, m, AGG_G);
-            t[m] = (has && qb + m < q1) ? rec[(int64_t)km * NP + l] : make_double2(0.0, 0.0);
+            t[m] = (has && qb + m < q1) ? rec[corner_slot_of<D>(km) * NP + l] : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int m = 0; m < AGG_G; ++m) {
@@ -673,7 +673,7 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
         double vs[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) vs[i] = a.vstar[i * nn + p];
-        const double *rec = a.corner + (c * NV + k) * Dm::CW;
+        const double *rec = a.corner + corner_slot<D>(c, k) * Dm::CW;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             double f = -rec[Dm::NMS + i];
