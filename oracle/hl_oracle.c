@@ -34,8 +34,15 @@
  *  R12 tau^{n+1} = V(x^{n+1}) / m.
  *  R16 admissibility: finite, V > 0, det B > 0, eps >= -tol (|e|+|v|^2/2).
  *  R17 relaxed DMP on rho with absolute delta0 and relative delta1.
- *  R18 flagged cells fall back to first order; the step is recomputed from
- *      t^n until no new flag appears.
+ *  R18 a flagged cell drops to the next scheme of the cascade; the step is
+ *      recomputed from t^n until no new flag appears.  Cascade level per
+ *      cell (the mask): 0 unlimited P1, 1 P1 with the Barth-Jespersen
+ *      limiter, 2 P0 (the parachute).  The two-level cascade goes 0 -> 2,
+ *      the three-level one 0 -> 1 -> 2.
+ *  R26 Barth-Jespersen: per reconstructed scalar, bounds = min / max over
+ *      {c} and its reconstruction stencil at t^n, ratio evaluated at the
+ *      d+1 vertices of c; the limited gradient replaces the unlimited one
+ *      in the corner values and in the predictor's time derivatives.
  *  R20 dt_vol = C_v dt min V1/|V1 - V0|, dt_incr = (1 + C_i) dt.
  *  R21 L_c = in-sphere diameter.
  *  R22 slip walls: v = P (P^T M P)^{-1} P^T r with P an orthonormal basis of
@@ -54,7 +61,7 @@ typedef struct {
     double delta0, delta1;  /* relaxed DMP tolerances (eq. RDMP)          */
     double eps_tol;         /* relative tolerance of the eps >= 0 test    */
     int detect;             /* 0: accept the unlimited candidate          */
-    int pad;
+    int cascade;            /* 2: P1 -> P0; 3: P1 -> P1+BJ -> P0 (R18)    */
 } orc_params;
 
 typedef struct {
@@ -64,6 +71,7 @@ typedef struct {
     int64_t n_flag_first;  /* cells flagged on the first candidate         */
     int32_t mood_iters;    /* number of candidate evaluations              */
     int32_t status;        /* 0 ok, 1 a parachute cell is not admissible   */
+    int64_t n_lim;         /* cells computed with the limited slopes       */
 } orc_info;
 
 typedef struct {
@@ -523,6 +531,51 @@ static void lsq_gradients(const orc_mesh *M, const double *xc, const double *tau
     }
 }
 
+/* Barth-Jespersen limiter, the second scheme of the cascade (Section 3.5;
+ * reading R26).  For every reconstructed scalar W_w of cell c, with m and M
+ * the min and max of W_w over {c} and its reconstruction stencil and
+ * D_k = grad W_w . (x_k - x_c) at the vertices x_k of c,
+ *   phi = min over k of  min(1, (M - W_c) / D_k)  if D_k > 0,
+ *                        min(1, (m - W_c) / D_k)  if D_k < 0,
+ *                        1                        if D_k = 0,
+ * and the limited gradient is phi grad W_w. */
+static void bj_limit(const orc_mesh *M, const double *x, const double *xc, const double *tau,
+                     const double *v, const double *B, const double *grad, double *glim) {
+    int d = M->dim, nW = M->nW, nv = M->nv;
+    for (int64_t c = 0; c < M->nc; ++c) {
+        double Wc[10], Wk[10], lo[10], hi[10];
+        cell_W(M, tau, v, B, c, Wc);
+        for (int w = 0; w < nW; ++w) lo[w] = hi[w] = Wc[w];
+        for (int k = 0; k < nv; ++k) {
+            int64_t p = M->c2n[c * nv + k];
+            for (int64_t q = M->n2c_off[p]; q < M->n2c_off[p + 1]; ++q) {
+                cell_W(M, tau, v, B, M->n2c[q] / nv, Wk);
+                for (int w = 0; w < nW; ++w) {
+                    lo[w] = fmin(lo[w], Wk[w]);
+                    hi[w] = fmax(hi[w], Wk[w]);
+                }
+            }
+        }
+        const double *g = grad + c * nW * 3;
+        double *o = glim + c * nW * 3;
+        for (int w = 0; w < nW; ++w) {
+            double phi = 1.0;
+            for (int k = 0; k < nv; ++k) {
+                int64_t p = M->c2n[c * nv + k];
+                double D = 0.0;
+                for (int i = 0; i < d; ++i) D += g[w * 3 + i] * (x[p * d + i] - xc[c * 3 + i]);
+                double r = 1.0;
+                if (D > 0.0)
+                    r = fmin(1.0, (hi[w] - Wc[w]) / D);
+                else if (D < 0.0)
+                    r = fmin(1.0, (lo[w] - Wc[w]) / D);
+                phi = fmin(phi, r);
+            }
+            for (int i = 0; i < 3; ++i) o[w * 3 + i] = phi * g[w * 3 + i];
+        }
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* ADER predictor (Section 3.4, eq. NCPDE2; reading R7)                */
 /* ------------------------------------------------------------------ */
@@ -660,6 +713,7 @@ typedef struct {
     orc_geo *geo;
     double *xc;      /* [nc][3] */
     double *grad;    /* [nc][nW][3] */
+    double *glim;    /* [nc][nW][3] Barth-Jespersen limited gradients */
     double *rmin, *rmax;
     /* candidate */
     orc_corner *cor; /* [nc*nv] */
@@ -684,8 +738,9 @@ static void candidate(orc_work *w, const uint8_t *mask) {
             int64_t p = M->c2n[c * nv + k];
             double X[3] = {0, 0, 0};
             for (int i = 0; i < d; ++i) X[i] = w->x[p * d + i];
-            predict_corner(M, &mat, &w->geo[c], X, w->tau[c], w->v + c * d, Bc,
-                           w->grad + c * M->nW * 3, mask[c] == 0, w->dt, &w->cor[c * nv + k]);
+            const double *gc = (mask[c] == 1 ? w->glim : w->grad) + c * M->nW * 3;
+            predict_corner(M, &mat, &w->geo[c], X, w->tau[c], w->v + c * d, Bc, gc, mask[c] < 2,
+                           w->dt, &w->cor[c * nv + k]);
         }
     }
     /* nodal solver (eq. nodal_solver^n, readings R14, R15, R22) */
@@ -767,7 +822,7 @@ static void candidate(orc_work *w, const uint8_t *mask) {
         w->tau1[c] = g1.V / mc;
         double Bn[3][3], Bnew[3][3];
         unpack_B(d, w->B + c * M->nB, Bn);
-        if (mask[c] == 0) {
+        if (mask[c] < 2) {
             double Ln[3][3], L1[3][3];
             velocity_gradient(d, g, vhn, Ln);
             velocity_gradient(d, &g1, vh1, L1);
@@ -910,6 +965,7 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
     w.geo = (orc_geo *)malloc(sizeof(orc_geo) * (size_t)(M->nc + 1));
     w.xc = (double *)malloc(sizeof(double) * (size_t)(M->nc * 3 + 1));
     w.grad = (double *)malloc(sizeof(double) * (size_t)(M->nc * M->nW * 3 + 1));
+    w.glim = (double *)malloc(sizeof(double) * (size_t)(M->nc * M->nW * 3 + 1));
     w.rmin = (double *)malloc(sizeof(double) * (size_t)(M->nc + 1));
     w.rmax = (double *)malloc(sizeof(double) * (size_t)(M->nc + 1));
     w.cor = (orc_corner *)malloc(sizeof(orc_corner) * (size_t)(M->nc * nv + 1));
@@ -925,6 +981,7 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
         V0[c] = m[c] * tau[c];
     }
     lsq_gradients(M, w.xc, tau, v, B, w.grad);
+    bj_limit(M, x, w.xc, tau, v, B, w.grad, w.glim);
     /* relaxed-DMP bounds of rho^n over {c} and its reconstruction stencil */
     for (int64_t c = 0; c < M->nc; ++c) {
         double lo = 1.0 / tau[c], hi = lo;
@@ -949,7 +1006,7 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
         int64_t nflag = 0;
         for (int64_t c = 0; c < M->nc; ++c) {
             flag[c] = 0;
-            if (mask[c] == 0 && troubled(&w, prm, c)) {
+            if (mask[c] < 2 && troubled(&w, prm, c)) {
                 flag[c] = 1;
                 ++nflag;
             }
@@ -957,14 +1014,15 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
         if (first < 0) first = nflag;
         if (nflag == 0) break;
         for (int64_t c = 0; c < M->nc; ++c)
-            if (flag[c]) mask[c] = 1;
+            if (flag[c]) mask[c] = (prm->cascade == 3 && mask[c] == 0) ? 1 : 2;
     }
 
     memset(info, 0, sizeof(*info));
     info->mood_iters = iters;
     info->n_flag_first = first < 0 ? 0 : first;
     for (int64_t c = 0; c < M->nc; ++c) {
-        if (mask[c]) {
+        if (mask[c] == 1) info->n_lim++;
+        if (mask[c] == 2) {
             info->n_p0++;
             if (inadmissible(&w, prm, c)) info->status = 1;
         }
@@ -978,6 +1036,7 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
     free(w.geo);
     free(w.xc);
     free(w.grad);
+    free(w.glim);
     free(w.rmin);
     free(w.rmax);
     free(w.cor);
@@ -1070,15 +1129,36 @@ void orc_lsq(const orc_mesh *M, const double *x, const double *tau, const double
     free(xc);
 }
 
-/* predicted corner states for every corner: tau*[nc*nv], v*[nc*nv][3],
- * B*[nc*nv][9], T*[nc*nv][9], z*[nc*nv] */
+/* Barth-Jespersen limited gradients of all cells: glim [nc][nW][3] */
+void orc_bj(const orc_mesh *M, const double *x, const double *tau, const double *v,
+            const double *B, double *glim) {
+    double *xc = (double *)malloc(sizeof(double) * (size_t)(M->nc * 3 + 1));
+    double *grad = (double *)malloc(sizeof(double) * (size_t)(M->nc * M->nW * 3 + 1));
+    for (int64_t c = 0; c < M->nc; ++c) {
+        double X[4][3];
+        orc_geo g;
+        cell_nodes(M, x, c, X);
+        geometry(M->dim, X, &g);
+        for (int i = 0; i < 3; ++i) xc[c * 3 + i] = g.xc[i];
+    }
+    lsq_gradients(M, xc, tau, v, B, grad);
+    bj_limit(M, x, xc, tau, v, B, grad, glim);
+    free(grad);
+    free(xc);
+}
+
+/* predicted corner states for every corner at the cascade level of each
+ * cell (mask: 0 unlimited, 1 limited, 2 first order): tau*[nc*nv],
+ * v*[nc*nv][3], B*[nc*nv][9], T*[nc*nv][9], z*[nc*nv] */
 void orc_predict(const orc_mesh *M, const double *rho0, const double *mu, const double *K,
                  const double *x, const double *tau, const double *v, const double *B, double dt,
                  const uint8_t *mask, double *tau_s, double *v_s, double *B_s, double *T_s,
                  double *z_s) {
     int d = M->dim, nv = M->nv;
     double *grad = (double *)malloc(sizeof(double) * (size_t)(M->nc * M->nW * 3 + 1));
+    double *glim = (double *)malloc(sizeof(double) * (size_t)(M->nc * M->nW * 3 + 1));
     orc_lsq(M, x, tau, v, B, grad);
+    orc_bj(M, x, tau, v, B, glim);
     for (int64_t c = 0; c < M->nc; ++c) {
         double X[4][3];
         orc_geo g;
@@ -1089,8 +1169,8 @@ void orc_predict(const orc_mesh *M, const double *rho0, const double *mu, const 
         unpack_B(d, B + c * M->nB, Bc);
         for (int k = 0; k < nv; ++k) {
             orc_corner cr;
-            predict_corner(M, &mat, &g, X[k], tau[c], v + c * d, Bc, grad + c * M->nW * 3,
-                           mask[c] == 0, dt, &cr);
+            predict_corner(M, &mat, &g, X[k], tau[c], v + c * d, Bc,
+                           (mask[c] == 1 ? glim : grad) + c * M->nW * 3, mask[c] < 2, dt, &cr);
             int64_t q = c * nv + k;
             tau_s[q] = cr.tau;
             for (int i = 0; i < 3; ++i) v_s[q * 3 + i] = cr.v[i];
@@ -1100,6 +1180,7 @@ void orc_predict(const orc_mesh *M, const double *rho0, const double *mu, const 
         }
     }
     free(grad);
+    free(glim);
 }
 
 void orc_diagnostics(const orc_mesh *M, const double *rho0, const double *mu, const double *K,

@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
 class Params(C.Structure):
     _fields_ = [("c_cfl", C.c_double), ("c_v", C.c_double), ("c_i", C.c_double),
                 ("delta0", C.c_double), ("delta1", C.c_double), ("eps_tol", C.c_double),
-                ("detect", C.c_int), ("pad", C.c_int)]
+                ("detect", C.c_int), ("cascade", C.c_int)]
 
 
 class Info(C.Structure):
@@ -45,20 +45,21 @@ class Info(C.Structure):
                 ("dt_volume", C.c_double), ("mass", C.c_double), ("mom", C.c_double * 3),
                 ("energy", C.c_double), ("kinetic", C.c_double), ("elastic", C.c_double),
                 ("n_p0", C.c_int64), ("n_flag_first", C.c_int64), ("mood_iters", C.c_int32),
-                ("status", C.c_int32)]
+                ("status", C.c_int32), ("n_lim", C.c_int64)]
 
     def as_dict(self):
         return dict(dt_next=self.dt_next, dt_acoustic=self.dt_acoustic,
                     dt_volume=self.dt_volume, mass=self.mass, mom=list(self.mom),
                     energy=self.energy, kinetic=self.kinetic, elastic=self.elastic,
                     n_p0=self.n_p0, n_flag_first=self.n_flag_first,
-                    mood_iters=self.mood_iters, status=self.status)
+                    mood_iters=self.mood_iters, status=self.status, n_lim=self.n_lim)
 
 
-def default_params(c_cfl=0.25, detect=True):
+def default_params(c_cfl=0.25, detect=True, cascade=2):
     """Paper values: C_v = 0.2, C_i = 0.1, delta0 = 1e-4, delta1 = 1e-3
-    (Sections 3.5 and 3.6)."""
-    return Params(c_cfl, 0.2, 0.1, 1e-4, 1e-3, 1e-12, 1 if detect else 0, 0)
+    (Sections 3.5 and 3.6).  cascade 2: P1 -> P0; 3: P1 -> P1 with the
+    Barth-Jespersen limiter -> P0 (Section 3.5)."""
+    return Params(c_cfl, 0.2, 0.1, 1e-4, 1e-3, 1e-12, 1 if detect else 0, int(cascade))
 
 
 _lib = None
@@ -90,6 +91,7 @@ def lib():
         L.orc_point_cn.restype = C.c_int
         L.orc_point_cn.argtypes = [C.c_int, _P, _P, _P, C.c_double, _P]
         L.orc_lsq.argtypes = [C.c_void_p] + [_P] * 5
+        L.orc_bj.argtypes = [C.c_void_p] + [_P] * 5
         L.orc_predict.argtypes = ([C.c_void_p] + [_P] * 7 + [C.c_double, _U8] + [_P] * 5)
         L.orc_diagnostics.argtypes = [C.c_void_p] + [_P] * 8 + [C.POINTER(Info)]
         L.orc_info_size.restype = C.c_int
@@ -280,6 +282,14 @@ class Problem:
         g = np.zeros((self.mesh.nc, 1 + self.dim + self.mesh.nB, 3))
         ins = [_f64(a) for a in (s.x, s.tau, s.v, s.B)]
         lib().orc_lsq(self.mesh.h, *[_ptr(a) for a in ins], _ptr(g))
+        return g[:, :, :self.dim]
+
+    def bj(self, state=None):
+        """Barth-Jespersen limited gradients [nc, nW, d] (Section 3.5)."""
+        s = self.state if state is None else state
+        g = np.zeros((self.mesh.nc, 1 + self.dim + self.mesh.nB, 3))
+        ins = [_f64(a) for a in (s.x, s.tau, s.v, s.B)]
+        lib().orc_bj(self.mesh.h, *[_ptr(a) for a in ins], _ptr(g))
         return g[:, :, :self.dim]
 
     def predict(self, dt, mask=None, state=None):

@@ -98,8 +98,9 @@ def test_replay_and_modes(case, mode):
         assert mk.sum() == 0 and info["n_p0"] == 0
     else:
         rng = np.random.default_rng(5)
-        mask = (rng.uniform(size=w.n_cells) < 0.3).astype(np.uint8) if mode == "random_mask" \
-            else np.ones(w.n_cells, np.uint8)
+        # cascade levels: 0 unlimited, 1 Barth-Jespersen limited, 2 first order
+        mask = rng.choice(np.array([0, 0, 1, 2], np.uint8), size=w.n_cells) if mode == "random_mask" \
+            else np.full(w.n_cells, 2, np.uint8)
         ctx.step_replay(dt, mask)
         s1, vs, mk, oi = prob.step(dt, mask=mask, replay=True)
         assert np.array_equal(ctx.query("order"), mask)

@@ -514,7 +514,7 @@ def _pwave_error(dim, n, tend, p0=False):
     P = O.Problem(w, O.default_params(w.c_cfl, detect=False))
     N = int(math.ceil(tend / P.initial_dt()))
     dt = tend / N
-    mask = np.ones(w.n_cells, np.uint8) if p0 else None
+    mask = np.full(w.n_cells, 2, np.uint8) if p0 else None  # cascade level 2: first order
     for _ in range(N):
         P.step(dt, mask=mask, replay=p0)
     s = P.state
