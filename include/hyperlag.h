@@ -69,7 +69,8 @@ typedef struct {
     double delta1;  /* relative relaxed-DMP tolerance on rho               */
     double eps_tol; /* eps = e - |v|^2/2 is troubled below -eps_tol (|e| + |v|^2/2) */
     int32_t detect; /* 0: accept the unlimited second-order candidate      */
-    int32_t reserved;
+    int32_t cascade;/* MOOD cascade (Section 3.5): 2 (or 0) P1 -> P0;
+                       3 P1 -> P1 with the Barth-Jespersen limiter -> P0    */
 } hl_params;
 
 /* Per-step report.  Filled by hl_step / hl_step_replay when non-NULL. */
@@ -83,6 +84,7 @@ typedef struct {
     int64_t n_flag_first;/* cells flagged on the first candidate            */
     int32_t mood_iters;  /* candidate evaluations (1 = nothing flagged)     */
     int32_t status;      /* 1: some first-order cell is not admissible      */
+    int64_t n_limited;   /* cells advanced with limited slopes (cascade 3)  */
 } hl_step_info;
 
 /* Fields for hl_query / hl_upload_field. */
@@ -94,8 +96,9 @@ enum {
     HL_E = 4,     /* specific total energy   [n_cells]        double       */
     HL_B = 5,     /* left Cauchy-Green       [n_cells][nB]    double       */
     HL_VSTAR = 6, /* node velocity of the last step [n_nodes][dim] (query) */
-    HL_ORDER = 7, /* 1 = cell advanced at first order in the last step,
-                     [n_cells] uint8 (query)                               */
+    HL_ORDER = 7, /* cascade level of each cell in the last step: 0
+                     unlimited second order, 1 Barth-Jespersen limited,
+                     2 first order; [n_cells] uint8 (query)                */
     HL_MASS = 8,  /* cell mass               [n_cells]        double (query) */
     HL_T = 9      /* Cauchy stress [n_cells][6] (11,22,33,12,13,23) in 3D,
                      [n_cells][4] (11,22,12,33) in 2D (query)              */
@@ -170,8 +173,9 @@ hl_status hl_step_batch(hl_ctx *ctx, const double *dt_per_mesh, int on_device,
 /* The next dt of every mesh, [n_meshes] (n_meshes must match). */
 hl_status hl_query_dt(hl_ctx *ctx, double *dt_next, int n_meshes, int on_device);
 
-/* One step with a frozen cascade choice: mask[c] = 1 advances cell c at
- * first order, 0 at second order; no detection.  mask: [n_cells] uint8. */
+/* One step with a frozen cascade choice: mask[c] is the cascade level of
+ * cell c (0 unlimited second order, 1 Barth-Jespersen limited, 2 first
+ * order; levels above 2 act as 2); no detection.  mask: [n_cells] uint8. */
 hl_status hl_step_replay(hl_ctx *ctx, double dt, const uint8_t *mask, int on_device,
                          hl_step_info *info_or_null);
 
@@ -231,7 +235,9 @@ hl_status hl_autotune(hl_ctx *ctx, int reps, double *best_ms);
 
 /* Run nsteps CFL-controlled ADER-MOOD steps from the current state,
  * recording each step's dt and cascade mask and a state checkpoint every
- * ckpt_every steps (device memory owned by the context). */
+ * ckpt_every steps (device memory owned by the context).  The adjoint
+ * covers the two-level cascade: with cascade 3 this returns HL_E_INVALID
+ * (the limiter's factor is not differentiated). */
 hl_status hl_forward_record(hl_ctx *ctx, int nsteps, int ckpt_every);
 
 /* Re-run the recorded steps from the current state with the recorded dt and

@@ -138,12 +138,13 @@ hl_params default_params(int dim) {
     p.delta1 = 1e-3;
     p.eps_tol = 1e-12;
     p.detect = 1;
-    p.reserved = 0;
+    p.cascade = 2;
     return p;
 }
 
 bool params_valid(const hl_params &p) {
-    return p.c_cfl > 0 && p.c_v > 0 && p.c_i >= 0 && p.delta0 >= 0 && p.delta1 >= 0 && p.eps_tol >= 0;
+    return p.c_cfl > 0 && p.c_v > 0 && p.c_i >= 0 && p.delta0 >= 0 && p.delta1 >= 0 && p.eps_tol >= 0 &&
+           (p.cascade == 0 || p.cascade == 2 || p.cascade == 3);
 }
 
 void drop_graphs(hl_ctx *c) {
@@ -407,6 +408,8 @@ hl::StepArgs make_args(hl_ctx *c, int src) {
     a.delta1 = c->prm.delta1;
     a.eps_tol = c->prm.eps_tol;
     a.detect = c->prm.detect;
+    a.cascade = c->prm.cascade == 3 ? 3 : 2;
+    a.limited = a.cascade == 3 ? 1 : 0;
     return a;
 }
 
@@ -536,6 +539,7 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
         HIPCHK(hipMemcpyAsync(c->mask, replay_mask, (size_t)c->nc,
                               mask_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         a.detect = 0;
+        a.limited = 1;  // the given levels may include the limited one
     }
     {
         hl_status st = ensure_scheds(c);
@@ -607,7 +611,7 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
         std::memset(info, 0, sizeof(*info));
         const int dst = 1 - src;
         hl::launch_diag<D>(a, c->tau[dst], c->v[dst], c->e[dst], c->B[dst], c->diag_part, c->diag_out, s);
-        double d[8], dts[4];
+        double d[9], dts[4];
         HIPCHK(hipMemcpyAsync(d, c->diag_out, sizeof d, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(&dts[0], c->dt_cur, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(&dts[1], c->dt_next, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -625,6 +629,7 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
         info->kinetic = d[5];
         info->elastic = d[6];
         info->n_p0 = (int64_t)llround(d[7]);
+        info->n_limited = (int64_t)llround(d[8]);
         info->n_flag_first = first;
         info->mood_iters = iters;
         info->status = inadm ? 1 : 0;
@@ -1124,7 +1129,7 @@ hl_status upload_impl(hl_ctx *c, int dim, int n_mesh, const std::vector<int64_t>
     A_(c->dt_next, (size_t)n_mesh);
     A_(c->dt_red, 2 * (size_t)n_mesh);
     A_(c->dt_parts, 2 * (size_t)n_mesh);
-    A_(c->diag_part, 8 * (ncl / 256 + 2));
+    A_(c->diag_part, 9 * (ncl / 256 + 2));
     A_(c->diag_out, 16);
     c->scratch_bytes = std::max<size_t>(sizeof(double) * std::max(nn * dim, ncl * 6), 256);
     A_(c->scratch, c->scratch_bytes / sizeof(double));
@@ -1432,6 +1437,11 @@ hl_status hl_upload_field(hl_ctx *c, int field, const void *in, int64_t count, i
 hl_status hl_forward_record(hl_ctx *c, int nsteps, int ckpt_every) {
     if (!c || nsteps < 1 || ckpt_every < 1) return HL_E_INVALID;
     if (!c->have_state) return HL_E_STATE;
+    if (c->prm.cascade == 3) {
+        std::snprintf(g_last_error, sizeof g_last_error,
+                      "the adjoint covers the two-level cascade; the limiter of cascade 3 is not differentiated");
+        return HL_E_INVALID;
+    }
     if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
     const bool prof = c->prof.on, graph = c->graph_on;
     c->prof.on = false;

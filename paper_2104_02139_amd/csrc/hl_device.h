@@ -23,13 +23,18 @@ struct Dims {
     static constexpr int NW = 1 + D + NB;            // reconstructed scalars
     static constexpr int NMS = D == 3 ? 6 : 3;       // symmetric DxD entries
     static constexpr int CW = D == 3 ? 10 : 6;       // corner record (padded)
-    // node aggregate record: n, Sy, Syy, SW, SyW, rho min, rho max
+    // node aggregate record: n, Sy, Syy, SW, SyW, rho min, rho max, W min,
+    // W max
     static constexpr int O_SY = 1;
     static constexpr int O_SYY = 1 + D;
     static constexpr int O_SW = 1 + D + NMS;
     static constexpr int O_SYW = O_SW + NW;
     static constexpr int O_RMM = O_SYW + D * NW;
-    static constexpr int NA = O_RMM + 2;             // 52 (3D) / 26 (2D)
+    static constexpr int NA_BASE = O_RMM + 2;        // 52 (3D) / 26 (2D)
+    // min / max of each W over the node's cells (limited cascade level only)
+    static constexpr int O_WMIN = NA_BASE;
+    static constexpr int O_WMAX = O_WMIN + NW;
+    static constexpr int NA = O_WMAX + NW;           // 72 (3D) / 38 (2D)
     static constexpr int GR = D == 3 ? 16 : 10;      // gather record: W, centroid, pad
 };
 

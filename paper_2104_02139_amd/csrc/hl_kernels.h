@@ -37,6 +37,8 @@ struct StepArgs {
     unsigned int *counters;    // [CNT_NODES], [CNT_CELLS], [CNT_BAD]
     double delta0, delta1, eps_tol;
     int detect;
+    int cascade;   // 2: a flagged cell goes to first order; 3: to limited first
+    int limited;   // cells may be at the limited level (node W bounds needed)
 };
 
 enum { CNT_F0 = 0, CNT_F1 = 1, CNT_NODES = 2, CNT_CELLS = 3, CNT_BAD = 4, CNT_N = 8 };

@@ -136,6 +136,8 @@ __device__ __forceinline__ void node_agg_group(const StepArgs &a, const int64_t 
     }
     double n = 0.0, Sa = 0.0, Sb = 0.0, Sya[D] = {}, Syb[D] = {};
     double tmin = __builtin_huge_val(), tmax = -__builtin_huge_val();
+    double lo0 = __builtin_huge_val(), hi0 = -__builtin_huge_val();  // W bounds (limiter)
+    double lo1 = lo0, hi1 = hi0;
     const double2 *rec = reinterpret_cast<const double2 *>(a.xc);
     const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
     // corners in chunks of AGG_G: lane l reads the cell of corner qb + l,
@@ -170,6 +172,10 @@ __device__ __forceinline__ void node_agg_group(const StepArgs &a, const int64_t 
             }
             tmin = fmin(tmin, va);  // tau of the cell in lane 0
             tmax = fmax(tmax, va);
+            lo0 = fmin(lo0, va);
+            hi0 = fmax(hi0, va);
+            lo1 = fmin(lo1, vb);
+            hi1 = fmax(hi1, vb);
         }
     }
     // rho = 1/tau: a correctly rounded reciprocal is monotone on tau > 0, so
@@ -191,6 +197,16 @@ __device__ __forceinline__ void node_agg_group(const StepArgs &a, const int64_t 
     };
     put(v0, Sa, Sya);
     put(v1, Sb, Syb);
+    if (a.limited) {
+        if (v0 < NW) {
+            o[Dm::O_WMIN + v0] = lo0;
+            o[Dm::O_WMAX + v0] = hi0;
+        }
+        if (v1 < NW) {
+            o[Dm::O_WMIN + v1] = lo1;
+            o[Dm::O_WMAX + v1] = hi1;
+        }
+    }
     if (l == 0) {
         o[0] = n;
         o[Dm::O_RMM] = rmin;
@@ -221,7 +237,8 @@ __global__ __launch_bounds__(256) void k_node_agg(StepArgs a, WorkList w) {
             __syncthreads();
             if (act) {
                 double2 *b = reinterpret_cast<double2 *>(a.agg) + p;
-                for (int j = l; j < Dm::NA / 2; j += AGG_G)
+                const int np = (a.limited ? Dm::NA : Dm::NA_BASE) / 2;
+                for (int j = l; j < np; j += AGG_G)
                     b[(int64_t)j * nn] = make_double2(sh[g][2 * j], sh[g][2 * j + 1]);
             }
             __syncthreads();
@@ -268,7 +285,7 @@ __device__ __forceinline__ constexpr int bslot(int s) {
 // Reconstruction (R8), ADER midpoint predictor (Section 3.4, reading R7),
 // corner stress and impedance (R5), corner matrix M_cp (eq. Mcp, R4) and
 // r_cp = M_cp v*_cp - T*_cp C_cp (eq. nodal_solver^n).
-template <int D>
+template <int D, bool LIM>
 __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c) {
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
@@ -300,7 +317,8 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
     double b[6];
     load_B6<D>(a.B, nc, c, b);
     const double rho0 = a.rho0[c], mu = a.mu[c], K = a.K[c];
-    const bool p1 = a.mask[c] == 0;
+    const int level = a.mask[c];   // cascade level: 0 unlimited, 1 limited, 2 first order
+    const bool p1 = level < 2;
 
     // W0 = W_c + (dt/2) dW/dt at the centroid; corner value W0 + grad W . delta
     double W0[Dm::NW];
@@ -365,6 +383,37 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
                 for (int j = 0; j < D; ++j) s += inv[midx<D>(i, j)] * rhs[w][j];
                 grad[w][i] = ok ? s : 0.0;
             }
+
+        // ---- Barth-Jespersen limiter (the cascade's second scheme, Section
+        // 3.5; reading R26): per scalar, bounds over {c} and its stencil from
+        // the node aggregates, ratio at the vertices, slope scaled by phi
+        if (LIM && level == 1) {
+#pragma unroll
+            for (int w = 0; w < Dm::NW; ++w) {
+                double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    const AggRef ag(a.agg, nn, a.c2n[c * NV + k]);
+                    lo = fmin(lo, ag[Dm::O_WMIN + w]);
+                    hi = fmax(hi, ag[Dm::O_WMAX + w]);
+                }
+                double phi = 1.0;
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    double Dk = 0.0;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) Dk += grad[w][j] * X[k][j];
+                    double r = 1.0;
+                    if (Dk > 0.0)
+                        r = fmin(1.0, (hi - W0[w]) / Dk);
+                    else if (Dk < 0.0)
+                        r = fmin(1.0, (lo - W0[w]) / Dk);
+                    phi = fmin(phi, r);
+                }
+#pragma unroll
+                for (int j = 0; j < D; ++j) grad[w][j] *= phi;
+            }
+        }
 
         // ---- time derivatives at the cell centre (reading R7)
         double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -474,17 +523,17 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
     }
 }
 
-template <int D, bool LOOP>
+template <int D, bool LOOP, bool LIM>
 __global__ __launch_bounds__(256) void k_predict(StepArgs a, WorkList w) {
-    for_items<LOOP>(w, [&](int64_t c) { predict_cell<D>(a, c); });
+    for_items<LOOP>(w, [&](int64_t c) { predict_cell<D, LIM>(a, c); });
 }
 
 // list-driven variant: the cells just flagged, recomputed at first order
-template <int D>
+template <int D, bool LIM>
 __global__ __launch_bounds__(256) void k_predict_list(StepArgs a, const int32_t *__restrict__ list,
                                                       const unsigned *__restrict__ count) {
     const int64_t n = *count;
-    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) predict_cell<D>(a, list[i]);
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) predict_cell<D, LIM>(a, list[i]);
 }
 
 // ---------------------------------------------------------- node solve
@@ -693,7 +742,7 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
     a.e1[c] = e1;
 
     // ---- geometry at t^n and t^{n+1}; velocity gradients
-    const bool p1 = a.mask[c] == 0;
+    const bool p1 = a.mask[c] < 2;   // unlimited or limited second order
     double L0[D][D], L1[D][D];
     double tau1, Lc, xc1[D];
     {
@@ -851,11 +900,14 @@ __global__ __launch_bounds__(256) void k_update_list(StepArgs a) {
 }
 
 // ------------------------------------------------------ MOOD bookkeeping
-// Cells flagged in the last candidate drop to first order.
+// Cells flagged in the last candidate drop to the next scheme of the cascade.
 __global__ __launch_bounds__(256) void k_apply_list(uint8_t *__restrict__ mask, const int32_t *__restrict__ list,
-                                                    const unsigned *__restrict__ count) {
+                                                    const unsigned *__restrict__ count, int cascade) {
     const int64_t n = *count;
-    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) mask[list[i]] = 1;
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = list[i];
+        mask[c] = (cascade == 3 && mask[c] == 0) ? 1 : 2;  // next scheme of the cascade
+    }
 }
 
 // Nodes of the flagged cells, each listed once (stamp = this iteration).
@@ -1057,7 +1109,7 @@ __global__ __launch_bounds__(256) void k_acoustic(int64_t nc, int64_t nn, const 
 // Diagnostics: per-block partial sums (fixed order), then one block adds
 // the partials in block order.  Sums: mass, mom[3], m e, kinetic, elastic,
 // n_p0.
-constexpr int NDIAG = 8;
+constexpr int NDIAG = 9;
 
 template <int D>
 __global__ __launch_bounds__(256) void k_diag(int64_t nc, const double *__restrict__ m, const double *__restrict__ tau,
@@ -1088,7 +1140,8 @@ __global__ __launch_bounds__(256) void k_diag(int64_t nc, const double *__restri
         double I1b = (b[0] + b[1] + b[2]) / (cJ * cJ);
         double psi = K[c] / (4.0 * rho0[c]) * ((J - 1.0) * (J - 1.0) + lj * lj) + mu[c] / (2.0 * rho0[c]) * (I1b - 3.0);
         q[6] = mc * psi;
-        q[7] = mask[c] ? 1.0 : 0.0;
+        q[7] = mask[c] >= 2 ? 1.0 : 0.0;   // first order
+        q[8] = mask[c] == 1 ? 1.0 : 0.0;   // limited slopes
     }
 #pragma unroll
     for (int s = 0; s < NDIAG; ++s) sh[s][threadIdx.x] = q[s];
@@ -1178,10 +1231,17 @@ void launch_node_agg(const StepArgs &a, const Sched &k, hipStream_t s) {
 template <int D>
 void launch_predict(const StepArgs &a, const Sched &k, hipStream_t s) {
     if (!k.w.n_items) return;
-    if (k.loop)
-        k_predict<D, true><<<k.grid, k.block, 0, s>>>(a, k.w);
-    else
-        k_predict<D, false><<<k.grid, k.block, 0, s>>>(a, k.w);
+    if (a.limited) {
+        if (k.loop)
+            k_predict<D, true, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+        else
+            k_predict<D, false, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+    } else {
+        if (k.loop)
+            k_predict<D, true, false><<<k.grid, k.block, 0, s>>>(a, k.w);
+        else
+            k_predict<D, false, false><<<k.grid, k.block, 0, s>>>(a, k.w);
+    }
 }
 template <int D>
 void launch_node_solve(const StepArgs &a, const Sched &k, hipStream_t s) {
@@ -1206,8 +1266,11 @@ void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned 
     if (fixed_grid) nflag = std::min<int64_t>(a.nc, 256 * 1024);
     const int64_t nnodes = std::min<int64_t>(a.nn, (D + 1) * nflag);
     const int64_t ncells = std::min<int64_t>(a.nc, nnodes * max_deg);
-    k_apply_list<<<grid(nflag), 256, 0, s>>>(const_cast<uint8_t *>(a.mask), flist, fcount);
-    k_predict_list<D><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+    k_apply_list<<<grid(nflag), 256, 0, s>>>(const_cast<uint8_t *>(a.mask), flist, fcount, a.cascade);
+    if (a.limited)
+        k_predict_list<D, true><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+    else
+        k_predict_list<D, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
     k_mark_nodes<D><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
     k_node_solve_list<D><<<grid(nnodes), 256, 0, s>>>(a);
     k_mark_cells<D><<<grid(nnodes), 256, 0, s>>>(a);

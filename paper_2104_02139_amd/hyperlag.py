@@ -35,12 +35,14 @@ STAGES = ("pack", "node_agg", "predict", "node_solve", "update")
 class Params(C.Structure):
     _fields_ = [("c_cfl", C.c_double), ("c_v", C.c_double), ("c_i", C.c_double),
                 ("delta0", C.c_double), ("delta1", C.c_double), ("eps_tol", C.c_double),
-                ("detect", C.c_int32), ("reserved", C.c_int32)]
+                ("detect", C.c_int32), ("cascade", C.c_int32)]
 
 
-def default_params(dim=3, detect=True, c_cfl=None):
+def default_params(dim=3, detect=True, c_cfl=None, cascade=2):
+    """Paper values (Sections 3.5, 3.6); cascade 2: P1 -> P0, 3: P1 -> P1
+    with the Barth-Jespersen limiter -> P0."""
     return Params(c_cfl if c_cfl is not None else (0.4 if dim == 2 else 0.25),
-                  0.2, 0.1, 1e-4, 1e-3, 1e-12, 1 if detect else 0, 0)
+                  0.2, 0.1, 1e-4, 1e-3, 1e-12, 1 if detect else 0, int(cascade))
 
 
 class StepInfo(C.Structure):
@@ -48,14 +50,14 @@ class StepInfo(C.Structure):
                 ("dt_volume", C.c_double), ("mass", C.c_double), ("mom", C.c_double * 3),
                 ("energy", C.c_double), ("kinetic", C.c_double), ("elastic", C.c_double),
                 ("n_p0", C.c_int64), ("n_flag_first", C.c_int64), ("mood_iters", C.c_int32),
-                ("status", C.c_int32)]
+                ("status", C.c_int32), ("n_limited", C.c_int64)]
 
     def as_dict(self):
         return dict(dt_used=self.dt_used, dt_next=self.dt_next, dt_acoustic=self.dt_acoustic,
                     dt_volume=self.dt_volume, mass=self.mass, mom=list(self.mom),
                     energy=self.energy, kinetic=self.kinetic, elastic=self.elastic,
                     n_p0=self.n_p0, n_flag_first=self.n_flag_first,
-                    mood_iters=self.mood_iters, status=self.status)
+                    mood_iters=self.mood_iters, status=self.status, n_limited=self.n_limited)
 
 
 class Schedule(C.Structure):

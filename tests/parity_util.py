@@ -25,18 +25,18 @@ def oracle_state(st):
     return O.State(st["x"], st["vhat"], st["tau"], st["v"], st["e"], st["B"])
 
 
-def gpu_params(w, detect=True):
-    return H.default_params(w.dim, detect=detect, c_cfl=w.c_cfl)
+def gpu_params(w, detect=True, cascade=2):
+    return H.default_params(w.dim, detect=detect, c_cfl=w.c_cfl, cascade=cascade)
 
 
-def orc_params(w, detect=True):
-    return O.default_params(w.c_cfl, detect=detect)
+def orc_params(w, detect=True, cascade=2):
+    return O.default_params(w.c_cfl, detect=detect, cascade=cascade)
 
 
-def pair(w, detect=True):
+def pair(w, detect=True, cascade=2):
     """(gpu context, oracle problem) initialised from the same workload."""
-    ctx = H.from_workload(w, params=gpu_params(w, detect))
-    prob = O.Problem(w, orc_params(w, detect))
+    ctx = H.from_workload(w, params=gpu_params(w, detect, cascade))
+    prob = O.Problem(w, orc_params(w, detect, cascade))
     return ctx, prob
 
 
