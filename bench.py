@@ -194,6 +194,37 @@ def batch_measure(steps=5, warmup=2, n_meshes=256, autotune=True):
             "speedup": ts / tb, "schedules": tuned}
 
 
+def cascade3_measure(ctx, w, steps, warmup, graph):
+    """The same workload from t = 0 with the three-level cascade P1 -> P1
+    with the Barth-Jespersen limiter -> P0 (Section 3.5)."""
+    import torch
+    from paper_2104_02139_amd import hyperlag as H
+    ctx.init_state(w.rho0, w.mu, w.lam, w.v_cell, w.v_node,
+                   H.default_params(w.dim, c_cfl=w.c_cfl, cascade=3))
+    ctx.use_graph(graph, 6)
+    lim, p0, it = [], [], []
+    for _ in range(warmup):
+        inf = ctx.step(0.0, info=True)
+        lim.append(inf["n_limited"])
+        p0.append(inf["n_p0"])
+        it.append(inf["mood_iters"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(0.0, info=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    inf = ctx.step(0.0, info=True)
+    lim.append(inf["n_limited"])
+    p0.append(inf["n_p0"])
+    it.append(inf["mood_iters"])
+    return {"cascade": "P1->P1+BJ->P0", "steps": steps, "ms_per_step": 1e3 * el / steps,
+            "cell_updates_per_s": w.n_cells * steps / el,
+            "limited_frac_mean": sum(lim) / len(lim) / w.n_cells,
+            "first_order_frac_mean": sum(p0) / len(p0) / w.n_cells,
+            "mood_iters_mean": sum(it) / len(it)}
+
+
 def adjoint_measure(n=32, steps=200, every=20):
     """Shear-modulus identification cube (32^3 Kuhn cells, lognormal mu):
     time of the checkpointed forward record, of the same steps without
@@ -237,6 +268,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the many-mesh batched-vs-sequential measurement")
+    ap.add_argument("--no-cascade3", action="store_true",
+                    help="skip the three-level-cascade measurement")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward time measurement")
     ap.add_argument("--eager", action="store_true",
@@ -359,6 +392,9 @@ def main():
         "schedules": schedules,
         "kernel_source_sha1": kernel_source_hash(),
     }
+    if not args.no_cascade3:
+        print("[bench] three-level cascade on the same workload", file=sys.stderr, flush=True)
+        out["cascade3"] = cascade3_measure(ctx, w, args.steps, args.warmup, not args.eager)
     if not args.no_adjoint:
         print("[bench] adjoint vs forward on the identification cube", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_measure()

@@ -539,7 +539,7 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
         HIPCHK(hipMemcpyAsync(c->mask, replay_mask, (size_t)c->nc,
                               mask_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         a.detect = 0;
-        a.limited = 1;  // the given levels may include the limited one
+        a.limited = 2;  // the given levels may include the limited one
     }
     {
         hl_status st = ensure_scheds(c);

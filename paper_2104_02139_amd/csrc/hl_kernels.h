@@ -38,7 +38,9 @@ struct StepArgs {
     double delta0, delta1, eps_tol;
     int detect;
     int cascade;   // 2: a flagged cell goes to first order; 3: to limited first
-    int limited;   // cells may be at the limited level (node W bounds needed)
+    int limited;   // 0: no limited cells; 1: they appear in the MOOD passes
+                   // (node W bounds, limiter in the pass kernels); 2: also in
+                   // the full-mesh pass (replayed levels)
 };
 
 enum { CNT_F0 = 0, CNT_F1 = 1, CNT_NODES = 2, CNT_CELLS = 3, CNT_BAD = 4, CNT_N = 8 };

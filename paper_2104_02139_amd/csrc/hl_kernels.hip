@@ -1231,7 +1231,7 @@ void launch_node_agg(const StepArgs &a, const Sched &k, hipStream_t s) {
 template <int D>
 void launch_predict(const StepArgs &a, const Sched &k, hipStream_t s) {
     if (!k.w.n_items) return;
-    if (a.limited) {
+    if (a.limited == 2) {
         if (k.loop)
             k_predict<D, true, true><<<k.grid, k.block, 0, s>>>(a, k.w);
         else
