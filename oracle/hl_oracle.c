@@ -39,6 +39,11 @@
  *      cell (the mask): 0 unlimited P1, 1 P1 with the Barth-Jespersen
  *      limiter, 2 P0 (the parachute).  The two-level cascade goes 0 -> 2,
  *      the three-level one 0 -> 1 -> 2.
+ *  R27 shear energy family (eq. familiy_energies) with parameter a:
+ *      T = -p I + (mu / J) [-a dev(Bbar) - ((1 + a)/3) I2(Bbar) dev(Bbar^-1)]
+ *      (eq. cst), I2 the principal invariant, Bbar^-1 the matrix inverse;
+ *      a = -1 is neo-Hookean.  The sound speed of R5 is kept for every a
+ *      (the family's small-strain shear modulus is mu).
  *  R26 Barth-Jespersen: per reconstructed scalar, bounds = min / max over
  *      {c} and its reconstruction stencil at t^n, ratio evaluated at the
  *      d+1 vertices of c; the limited gradient replaces the unlimited one
@@ -62,6 +67,7 @@ typedef struct {
     double eps_tol;         /* relative tolerance of the eps >= 0 test    */
     int detect;             /* 0: accept the unlimited candidate          */
     int cascade;            /* 2: P1 -> P0; 3: P1 -> P1+BJ -> P0 (R18)    */
+    double shear_a;         /* shear energy family parameter (R27)        */
 } orc_params;
 
 typedef struct {
@@ -238,6 +244,7 @@ static void corner_matrix_shape(int d, const orc_geo *g, int p, double N[3][3]) 
 /* ------------------------------------------------------------------ */
 typedef struct {
     double rho0, mu, K;
+    double a; /* shear energy family (eq. familiy_energies); -1: neo-Hookean */
 } orc_mat;
 
 /* p = -(K/2)(J - 1 + ln J / J) */
@@ -245,7 +252,31 @@ static double pressure(const orc_mat *m, double J) {
     return -0.5 * m->K * (J - 1.0 + log(J) / J);
 }
 
-/* T = -p I + (mu / J) (Bbar - tr(Bbar)/3 I),  Bbar = J^{-2/3} B */
+/* inverse of a 3x3 matrix by cofactors */
+static void inv33(const double A[3][3], double Ai[3][3]) {
+    double det = det33(A);
+    Ai[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / det;
+    Ai[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+    Ai[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+    Ai[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / det;
+    Ai[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+    Ai[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+    Ai[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / det;
+    Ai[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+    Ai[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+}
+
+/* second principal invariant 1/2 ((tr A)^2 - tr(A A)) */
+static double inv2(const double A[3][3]) {
+    double tr = A[0][0] + A[1][1] + A[2][2], tr2 = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) tr2 += A[i][k] * A[k][i];
+    return 0.5 * (tr * tr - tr2);
+}
+
+/* T = -p I + (mu / J) [-a dev(Bbar) - ((1+a)/3) I2(Bbar) dev(Bbar^-1)],
+ * Bbar = J^{-2/3} B (eqs. cst, familiy_energies; R27).  For a = -1 this is
+ * (mu / J) dev(Bbar) - p I (eq. cstnh). */
 static void stress(const orc_mat *m, double tau, const double B[3][3], double T[3][3]) {
     double J = m->rho0 * tau;
     double p = pressure(m, J);
@@ -254,9 +285,20 @@ static void stress(const orc_mat *m, double tau, const double B[3][3], double T[
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) Bb[i][j] = s * B[i][j];
     double tr = Bb[0][0] + Bb[1][1] + Bb[2][2];
+    double c = (1.0 + m->a) / 3.0;
+    double Bi[3][3] = {{0}}, tri = 0.0, I2 = 0.0;
+    if (c != 0.0) {
+        inv33(Bb, Bi);
+        tri = Bi[0][0] + Bi[1][1] + Bi[2][2];
+        I2 = inv2(Bb);
+    }
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            T[i][j] = (m->mu / J) * (Bb[i][j] - (i == j ? tr / 3.0 : 0.0)) - (i == j ? p : 0.0);
+        for (int j = 0; j < 3; ++j) {
+            double dev = Bb[i][j] - (i == j ? tr / 3.0 : 0.0);
+            double sh = -m->a * dev;
+            if (c != 0.0) sh -= c * I2 * (Bi[i][j] - (i == j ? tri / 3.0 : 0.0));
+            T[i][j] = (m->mu / J) * sh - (i == j ? p : 0.0);
+        }
 }
 
 /* sound speed a = sqrt(tau (K_t + 4 mu / 3)), K_t = -J dp/dJ (R5) */
@@ -266,41 +308,87 @@ static double sound_speed(const orc_mat *m, double tau) {
     return sqrt(tau * (Kt + 4.0 * m->mu / 3.0));
 }
 
-/* Specific free energy Psi_v + Psi_s (Section 2.2.4), used by the energy
- * diagnostics only. */
+/* Specific free energy Psi_v + Psi_s (Section 2.2.4, eq. familiy_energies),
+ * used by the energy diagnostics only. */
 static double free_energy(const orc_mat *m, double tau, const double B[3][3]) {
     double J = m->rho0 * tau;
     double lj = log(J);
-    double I1b = pow(J, -2.0 / 3.0) * (B[0][0] + B[1][1] + B[2][2]);
-    return m->K / (4.0 * m->rho0) * ((J - 1.0) * (J - 1.0) + lj * lj) +
-           m->mu / (2.0 * m->rho0) * (I1b - 3.0);
+    double s = pow(J, -2.0 / 3.0);
+    double I1b = s * (B[0][0] + B[1][1] + B[2][2]);
+    double psi_v = m->K / (4.0 * m->rho0) * ((J - 1.0) * (J - 1.0) + lj * lj);
+    if (m->a == -1.0) return psi_v + m->mu / (2.0 * m->rho0) * (I1b - 3.0);
+    double Bb[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Bb[i][j] = s * B[i][j];
+    double I2b = inv2(Bb);
+    return psi_v + m->mu / (4.0 * m->rho0) *
+                       (-2.0 * m->a * (I1b - 3.0) + (1.0 + m->a) / 3.0 * (I2b * I2b - 9.0));
 }
 
-/* Derivative of T(tau, B) along a direction (dtau, dB):
- *   with T = -p(J) I + mu J^{-5/3} dev(B),  J = rho0 tau,
- *   dT = rho0 [ -p'(J) I - (5/3) mu J^{-8/3} dev(B) ] dtau
- *        + mu J^{-5/3} dev(dB)                                         */
+/* Derivative of T(tau, B) along a direction (dtau, dB), J = rho0 tau:
+ *   neo-Hookean (a = -1), T = -p(J) I + mu J^{-5/3} dev(B):
+ *     dT = rho0 [ -p'(J) I - (5/3) mu J^{-8/3} dev(B) ] dtau + mu J^{-5/3} dev(dB)
+ *   family (R27), with dJ = rho0 dtau, dBbar = J^{-2/3} dB - (2/3)(dJ/J) Bbar,
+ *   d(Bbar^-1) = -Bbar^-1 dBbar Bbar^-1, dI2 = tr(Bbar) tr(dBbar) - tr(Bbar dBbar):
+ *     dT = -p'(J) dJ I - (dJ/J) T_0 + (mu/J) [-a dev(dBbar)
+ *          - c (dI2 dev(Bbar^-1) + I2 dev(d(Bbar^-1)))],  c = (1+a)/3. */
 static void stress_direction(const orc_mat *m, double tau, const double B[3][3], double dtau,
                              const double dB[3][3], double dT[3][3]) {
     double J = m->rho0 * tau;
     double lj = log(J);
     double dpdJ = -0.5 * m->K * (1.0 + (1.0 - lj) / (J * J));
-    double J53 = pow(J, -5.0 / 3.0);
-    double J83 = pow(J, -8.0 / 3.0);
-    double trB = B[0][0] + B[1][1] + B[2][2];
-    double trdB = dB[0][0] + dB[1][1] + dB[2][2];
+    if (m->a == -1.0) {
+        double J53 = pow(J, -5.0 / 3.0);
+        double J83 = pow(J, -8.0 / 3.0);
+        double trB = B[0][0] + B[1][1] + B[2][2];
+        double trdB = dB[0][0] + dB[1][1] + dB[2][2];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double devB = B[i][j] - (i == j ? trB / 3.0 : 0.0);
+                double devdB = dB[i][j] - (i == j ? trdB / 3.0 : 0.0);
+                dT[i][j] = m->rho0 * ((i == j ? -dpdJ : 0.0) - (5.0 / 3.0) * m->mu * J83 * devB) * dtau +
+                           m->mu * J53 * devdB;
+            }
+        return;
+    }
+    double dJ = m->rho0 * dtau;
+    double s = pow(J, -2.0 / 3.0);
+    double Bb[3][3], dBb[3][3], Bi[3][3], dBi[3][3], tmp[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Bb[i][j] = s * B[i][j];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) dBb[i][j] = s * dB[i][j] - (2.0 / 3.0) * (dJ / J) * Bb[i][j];
+    inv33(Bb, Bi);
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
-            double devB = B[i][j] - (i == j ? trB / 3.0 : 0.0);
-            double devdB = dB[i][j] - (i == j ? trdB / 3.0 : 0.0);
-            dT[i][j] = m->rho0 * ((i == j ? -dpdJ : 0.0) - (5.0 / 3.0) * m->mu * J83 * devB) * dtau +
-                       m->mu * J53 * devdB;
+            double t = 0.0;
+            for (int k = 0; k < 3; ++k) t += dBb[i][k] * Bi[k][j];
+            tmp[i][j] = t;
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double t = 0.0;
+            for (int k = 0; k < 3; ++k) t += Bi[i][k] * tmp[k][j];
+            dBi[i][j] = -t;
+        }
+    double c = (1.0 + m->a) / 3.0;
+    double I2 = inv2(Bb);
+    double trBb = Bb[0][0] + Bb[1][1] + Bb[2][2], trdBb = dBb[0][0] + dBb[1][1] + dBb[2][2];
+    double BdB = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) BdB += Bb[i][k] * dBb[k][i];
+    double dI2 = trBb * trdBb - BdB;
+    double trBi = Bi[0][0] + Bi[1][1] + Bi[2][2], trdBi = dBi[0][0] + dBi[1][1] + dBi[2][2];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double e = (i == j) ? 1.0 : 0.0;
+            double T0 = (m->mu / J) * (-m->a * (Bb[i][j] - e * trBb / 3.0) - c * I2 * (Bi[i][j] - e * trBi / 3.0));
+            double dsh = -m->a * (dBb[i][j] - e * trdBb / 3.0) -
+                         c * (dI2 * (Bi[i][j] - e * trBi / 3.0) + I2 * (dBi[i][j] - e * trdBi / 3.0));
+            dT[i][j] = -dpdJ * dJ * e - (dJ / J) * T0 + (m->mu / J) * dsh;
         }
 }
 
-/* ------------------------------------------------------------------ */
-/* state packing                                                       */
-/* ------------------------------------------------------------------ */
 static void unpack_B(int d, const double *b, double B[3][3]) {
     zero33(B);
     const int(*sp)[2] = sym_pairs(d);
@@ -709,6 +797,7 @@ typedef struct {
     const double *rho0, *mu, *K, *m;
     const double *x, *vhat, *tau, *v, *e, *B;
     double dt;
+    double a;        /* shear energy family parameter (R27) */
     /* derived at t^n */
     orc_geo *geo;
     double *xc;      /* [nc][3] */
@@ -722,7 +811,7 @@ typedef struct {
 } orc_work;
 
 static orc_mat mat_of(const orc_work *w, int64_t c) {
-    orc_mat m = {w->rho0[c], w->mu[c], w->K[c]};
+    orc_mat m = {w->rho0[c], w->mu[c], w->K[c], w->a};
     return m;
 }
 
@@ -873,13 +962,13 @@ static int troubled(const orc_work *w, const orc_params *prm, int64_t c) {
 }
 
 static void diagnostics(const orc_mesh *M, const double *rho0, const double *mu, const double *K,
-                        const double *m, const double *tau, const double *v, const double *e,
+                        double a, const double *m, const double *tau, const double *v, const double *e,
                         const double *B, orc_info *info) {
     int d = M->dim;
     info->mass = info->energy = info->kinetic = info->elastic = 0.0;
     info->mom[0] = info->mom[1] = info->mom[2] = 0.0;
     for (int64_t c = 0; c < M->nc; ++c) {
-        orc_mat mat = {rho0[c], mu[c], K[c]};
+        orc_mat mat = {rho0[c], mu[c], K[c], a};
         double Bc[3][3];
         unpack_B(d, B + c * M->nB, Bc);
         double k2 = 0.0;
@@ -906,7 +995,7 @@ static void time_step(const orc_mesh *M, const double *rho0, const double *mu, c
         orc_geo g;
         cell_nodes(M, x1, c, X);
         geometry(d, X, &g);
-        orc_mat mat = {rho0[c], mu[c], K[c]};
+        orc_mat mat = {rho0[c], mu[c], K[c], prm->shear_a};
         double a = sound_speed(&mat, tau1[c]);
         ac = fmin(ac, g.Lc / a);
         if (V0) {
@@ -956,6 +1045,7 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
     w.e = e;
     w.B = B;
     w.dt = dt;
+    w.a = prm->shear_a;
     w.x1 = x1;
     w.vhat1 = vhat1;
     w.tau1 = tau1;
@@ -1031,7 +1121,7 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
         for (int64_t p = 0; p < M->nn; ++p)
             for (int i = 0; i < d; ++i) vstar_out[p * d + i] = w.vstar[p * 3 + i];
     time_step(M, rho0, mu, K, x1, tau1, m, V0, dt, prm, info);
-    diagnostics(M, rho0, mu, K, m, tau1, v1, e1, B1, info);
+    diagnostics(M, rho0, mu, K, prm->shear_a, m, tau1, v1, e1, B1, info);
 
     free(w.geo);
     free(w.xc);
@@ -1081,8 +1171,8 @@ void orc_corner_shape(int d, const double *Xin, int p, double *N) {
 
 /* full 3x3 B in, full 3x3 T out, plus p, a, Psi */
 void orc_point_stress(double rho0, double mu, double K, double tau, const double *B, double *T,
-                      double *p, double *a, double *psi) {
-    orc_mat m = {rho0, mu, K};
+                      double *p, double *a, double *psi, double shear_a) {
+    orc_mat m = {rho0, mu, K, shear_a};
     double Bm[3][3], Tm[3][3];
     memcpy(Bm, B, sizeof Bm);
     stress(&m, tau, Bm, Tm);
@@ -1093,8 +1183,8 @@ void orc_point_stress(double rho0, double mu, double K, double tau, const double
 }
 
 void orc_point_stress_direction(double rho0, double mu, double K, double tau, const double *B,
-                                double dtau, const double *dB, double *dT) {
-    orc_mat m = {rho0, mu, K};
+                                double dtau, const double *dB, double *dT, double shear_a) {
+    orc_mat m = {rho0, mu, K, shear_a};
     double Bm[3][3], dBm[3][3], dTm[3][3];
     memcpy(Bm, B, sizeof Bm);
     memcpy(dBm, dB, sizeof dBm);
@@ -1152,7 +1242,7 @@ void orc_bj(const orc_mesh *M, const double *x, const double *tau, const double 
  * v*[nc*nv][3], B*[nc*nv][9], T*[nc*nv][9], z*[nc*nv] */
 void orc_predict(const orc_mesh *M, const double *rho0, const double *mu, const double *K,
                  const double *x, const double *tau, const double *v, const double *B, double dt,
-                 const uint8_t *mask, double *tau_s, double *v_s, double *B_s, double *T_s,
+                 double shear_a, const uint8_t *mask, double *tau_s, double *v_s, double *B_s, double *T_s,
                  double *z_s) {
     int d = M->dim, nv = M->nv;
     double *grad = (double *)malloc(sizeof(double) * (size_t)(M->nc * M->nW * 3 + 1));
@@ -1164,7 +1254,7 @@ void orc_predict(const orc_mesh *M, const double *rho0, const double *mu, const 
         orc_geo g;
         cell_nodes(M, x, c, X);
         geometry(d, X, &g);
-        orc_mat mat = {rho0[c], mu[c], K[c]};
+        orc_mat mat = {rho0[c], mu[c], K[c], shear_a};
         double Bc[3][3];
         unpack_B(d, B + c * M->nB, Bc);
         for (int k = 0; k < nv; ++k) {
@@ -1185,9 +1275,9 @@ void orc_predict(const orc_mesh *M, const double *rho0, const double *mu, const 
 
 void orc_diagnostics(const orc_mesh *M, const double *rho0, const double *mu, const double *K,
                      const double *m, const double *tau, const double *v, const double *e,
-                     const double *B, orc_info *info) {
+                     const double *B, orc_info *info, double shear_a) {
     memset(info, 0, sizeof(*info));
-    diagnostics(M, rho0, mu, K, m, tau, v, e, B, info);
+    diagnostics(M, rho0, mu, K, shear_a, m, tau, v, e, B, info);
 }
 
 int orc_info_size(void) { return (int)sizeof(orc_info); }

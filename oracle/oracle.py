@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
 class Params(C.Structure):
     _fields_ = [("c_cfl", C.c_double), ("c_v", C.c_double), ("c_i", C.c_double),
                 ("delta0", C.c_double), ("delta1", C.c_double), ("eps_tol", C.c_double),
-                ("detect", C.c_int), ("cascade", C.c_int)]
+                ("detect", C.c_int), ("cascade", C.c_int), ("shear_a", C.c_double)]
 
 
 class Info(C.Structure):
@@ -55,11 +55,12 @@ class Info(C.Structure):
                     mood_iters=self.mood_iters, status=self.status, n_lim=self.n_lim)
 
 
-def default_params(c_cfl=0.25, detect=True, cascade=2):
+def default_params(c_cfl=0.25, detect=True, cascade=2, shear_a=-1.0):
     """Paper values: C_v = 0.2, C_i = 0.1, delta0 = 1e-4, delta1 = 1e-3
     (Sections 3.5 and 3.6).  cascade 2: P1 -> P0; 3: P1 -> P1 with the
-    Barth-Jespersen limiter -> P0 (Section 3.5)."""
-    return Params(c_cfl, 0.2, 0.1, 1e-4, 1e-3, 1e-12, 1 if detect else 0, int(cascade))
+    Barth-Jespersen limiter -> P0 (Section 3.5).  shear_a: parameter of the
+    shear energy family (eq. familiy_energies); -1 is neo-Hookean."""
+    return Params(c_cfl, 0.2, 0.1, 1e-4, 1e-3, 1e-12, 1 if detect else 0, int(cascade), float(shear_a))
 
 
 _lib = None
@@ -86,14 +87,14 @@ def lib():
         L.orc_initial_dt.argtypes = [C.c_void_p] + [_P] * 6 + [C.POINTER(Params)]
         L.orc_cell_geometry.argtypes = [C.c_int, _P, _P, _P, _P, _P, _P]
         L.orc_corner_shape.argtypes = [C.c_int, _P, C.c_int, _P]
-        L.orc_point_stress.argtypes = [C.c_double] * 4 + [_P, _P, _P, _P, _P]
-        L.orc_point_stress_direction.argtypes = [C.c_double] * 4 + [_P, C.c_double, _P, _P]
+        L.orc_point_stress.argtypes = [C.c_double] * 4 + [_P, _P, _P, _P, _P, C.c_double]
+        L.orc_point_stress_direction.argtypes = [C.c_double] * 4 + [_P, C.c_double, _P, _P, C.c_double]
         L.orc_point_cn.restype = C.c_int
         L.orc_point_cn.argtypes = [C.c_int, _P, _P, _P, C.c_double, _P]
         L.orc_lsq.argtypes = [C.c_void_p] + [_P] * 5
         L.orc_bj.argtypes = [C.c_void_p] + [_P] * 5
-        L.orc_predict.argtypes = ([C.c_void_p] + [_P] * 7 + [C.c_double, _U8] + [_P] * 5)
-        L.orc_diagnostics.argtypes = [C.c_void_p] + [_P] * 8 + [C.POINTER(Info)]
+        L.orc_predict.argtypes = ([C.c_void_p] + [_P] * 7 + [C.c_double, C.c_double, _U8] + [_P] * 5)
+        L.orc_diagnostics.argtypes = [C.c_void_p] + [_P] * 8 + [C.POINTER(Info), C.c_double]
         L.orc_info_size.restype = C.c_int
         L.orc_params_size.restype = C.c_int
         assert L.orc_info_size() == C.sizeof(Info)
@@ -137,22 +138,23 @@ def corner_shape(X, p):
     return N
 
 
-def point_stress(rho0, mu, K, tau, B):
-    """Full 3x3 B -> (T 3x3, p, a, Psi)."""
+def point_stress(rho0, mu, K, tau, B, shear_a=-1.0):
+    """Full 3x3 B -> (T 3x3, p, a, Psi); shear_a selects the shear energy
+    of the family (eq. familiy_energies), -1 neo-Hookean."""
     B = _f64(B)
     T = np.zeros((3, 3))
     p = np.zeros(1)
     a = np.zeros(1)
     psi = np.zeros(1)
-    lib().orc_point_stress(rho0, mu, K, tau, _ptr(B), _ptr(T), _ptr(p), _ptr(a), _ptr(psi))
+    lib().orc_point_stress(rho0, mu, K, tau, _ptr(B), _ptr(T), _ptr(p), _ptr(a), _ptr(psi), float(shear_a))
     return T, p[0], a[0], psi[0]
 
 
-def point_stress_direction(rho0, mu, K, tau, B, dtau, dB):
+def point_stress_direction(rho0, mu, K, tau, B, dtau, dB, shear_a=-1.0):
     B = _f64(B)
     dB = _f64(dB)
     dT = np.zeros((3, 3))
-    lib().orc_point_stress_direction(rho0, mu, K, tau, _ptr(B), dtau, _ptr(dB), _ptr(dT))
+    lib().orc_point_stress_direction(rho0, mu, K, tau, _ptr(B), dtau, _ptr(dB), _ptr(dT), float(shear_a))
     return dT
 
 
@@ -300,7 +302,7 @@ class Problem:
         B_s, T_s, z_s = np.zeros((nq, 3, 3)), np.zeros((nq, 3, 3)), np.zeros(nq)
         ins = [_f64(a) for a in (s.x, s.tau, s.v, s.B)]
         lib().orc_predict(self.mesh.h, _ptr(self.rho0), _ptr(self.mu), _ptr(self.K),
-                          *[_ptr(a) for a in ins], float(dt), mk.ctypes.data_as(_U8),
+                          *[_ptr(a) for a in ins], float(dt), float(self.params.shear_a), mk.ctypes.data_as(_U8),
                           _ptr(tau_s), _ptr(v_s), _ptr(B_s), _ptr(T_s), _ptr(z_s))
         return dict(tau=tau_s, v=v_s, B=B_s, T=T_s, z=z_s)
 
@@ -309,5 +311,6 @@ class Problem:
         info = Info()
         ins = [_f64(a) for a in (s.tau, s.v, s.e, s.B)]
         lib().orc_diagnostics(self.mesh.h, _ptr(self.rho0), _ptr(self.mu), _ptr(self.K),
-                              _ptr(self.m), *[_ptr(a) for a in ins], C.byref(info))
+                              _ptr(self.m), *[_ptr(a) for a in ins], C.byref(info),
+                              float(self.params.shear_a))
         return info.as_dict()
