@@ -71,6 +71,9 @@ typedef struct {
     int32_t detect; /* 0: accept the unlimited second-order candidate      */
     int32_t cascade;/* MOOD cascade (Section 3.5): 2 (or 0) P1 -> P0;
                        3 P1 -> P1 with the Barth-Jespersen limiter -> P0    */
+    double shear_a; /* shear energy family (eq. familiy_energies), in
+                       [-1, 1/2] (the hyperbolic range): -1 neo-Hookean
+                       (the default), 0 the paper's non-linear law          */
 } hl_params;
 
 /* Per-step report.  Filled by hl_step / hl_step_replay when non-NULL. */
@@ -236,8 +239,8 @@ hl_status hl_autotune(hl_ctx *ctx, int reps, double *best_ms);
 /* Run nsteps CFL-controlled ADER-MOOD steps from the current state,
  * recording each step's dt and cascade mask and a state checkpoint every
  * ckpt_every steps (device memory owned by the context).  The adjoint
- * covers the two-level cascade: with cascade 3 this returns HL_E_INVALID
- * (the limiter's factor is not differentiated). */
+ * covers the two-level cascade and the neo-Hookean law: with cascade 3 or
+ * shear_a != -1 this returns HL_E_INVALID. */
 hl_status hl_forward_record(hl_ctx *ctx, int nsteps, int ckpt_every);
 
 /* Re-run the recorded steps from the current state with the recorded dt and

@@ -139,12 +139,13 @@ hl_params default_params(int dim) {
     p.eps_tol = 1e-12;
     p.detect = 1;
     p.cascade = 2;
+    p.shear_a = -1.0;
     return p;
 }
 
 bool params_valid(const hl_params &p) {
     return p.c_cfl > 0 && p.c_v > 0 && p.c_i >= 0 && p.delta0 >= 0 && p.delta1 >= 0 && p.eps_tol >= 0 &&
-           (p.cascade == 0 || p.cascade == 2 || p.cascade == 3);
+           (p.cascade == 0 || p.cascade == 2 || p.cascade == 3) && p.shear_a >= -1.0 && p.shear_a <= 0.5;
 }
 
 void drop_graphs(hl_ctx *c) {
@@ -409,6 +410,7 @@ hl::StepArgs make_args(hl_ctx *c, int src) {
     a.eps_tol = c->prm.eps_tol;
     a.detect = c->prm.detect;
     a.cascade = c->prm.cascade == 3 ? 3 : 2;
+    a.shear_a = c->prm.shear_a;
     a.limited = a.cascade == 3 ? 1 : 0;
     return a;
 }
@@ -1437,9 +1439,9 @@ hl_status hl_upload_field(hl_ctx *c, int field, const void *in, int64_t count, i
 hl_status hl_forward_record(hl_ctx *c, int nsteps, int ckpt_every) {
     if (!c || nsteps < 1 || ckpt_every < 1) return HL_E_INVALID;
     if (!c->have_state) return HL_E_STATE;
-    if (c->prm.cascade == 3) {
+    if (c->prm.cascade == 3 || c->prm.shear_a != -1.0) {
         std::snprintf(g_last_error, sizeof g_last_error,
-                      "the adjoint covers the two-level cascade; the limiter of cascade 3 is not differentiated");
+                      "the adjoint covers the two-level cascade and the neo-Hookean law (cascade 2, shear_a -1)");
         return HL_E_INVALID;
     }
     if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;

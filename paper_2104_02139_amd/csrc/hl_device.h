@@ -127,6 +127,116 @@ HL_HD void stress6(double rho0, double mu, double K, double tau,
     t[5] = s * b[5];
 }
 
+// Shear energy family (eq. familiy_energies) with the stress of eq. cst:
+// T = -p I + (mu / J) [-a dev(Bbar) - c I2(Bbar) dev(Bbar^-1)], c = (1+a)/3,
+// Bbar = J^{-2/3} B, I2 the second principal invariant.  a = -1 is the
+// neo-Hookean law of stress6.  6-vectors in sidx order.
+HL_HD double inv2_6(const double b[6]) {
+    const double tr = b[0] + b[1] + b[2];
+    const double tr2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2] + 2.0 * (b[3] * b[3] + b[4] * b[4] + b[5] * b[5]);
+    return 0.5 * (tr * tr - tr2);
+}
+
+HL_HD double sym_inv3(const double a[6], double inv[6]);
+
+HL_HD void stress6_family(double rho0, double mu, double K, double a, double tau, const double b[6],
+                          double t[6]) {
+    const double J = rho0 * tau;
+    const double lj = log(J);
+    const double p = -0.5 * K * (J - 1.0 + lj / J);
+    const double cJ = cbrt(J);
+    const double s = 1.0 / (cJ * cJ);
+    double bb[6], bi[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) bb[q] = s * b[q];
+    sym_inv3(bb, bi);
+    const double tr = bb[0] + bb[1] + bb[2], tri = bi[0] + bi[1] + bi[2];
+    const double c = (1.0 + a) / 3.0;
+    const double I2 = inv2_6(bb);
+    const double mj = mu / J;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const double e = q < 3 ? 1.0 : 0.0;
+        t[q] = mj * (-a * (bb[q] - e * tr / 3.0) - c * I2 * (bi[q] - e * tri / 3.0)) - e * p;
+    }
+}
+
+// Derivative of stress6_family along (dtau, db): with dJ = rho0 dtau,
+// dBbar = J^{-2/3} dB - (2/3)(dJ/J) Bbar, d(Bbar^-1) = -Bbar^-1 dBbar Bbar^-1,
+// dI2 = tr(Bbar) tr(dBbar) - Bbar : dBbar,
+// dT = -p'(J) dJ I - (dJ/J) T_0 + (mu/J) [-a dev(dBbar)
+//      - c (dI2 dev(Bbar^-1) + I2 dev(d(Bbar^-1)))].
+HL_HD void stress6_dir_family(double rho0, double mu, double K, double a, double tau, const double b[6],
+                              double dtau, const double db[6], double dt[6]) {
+    const double J = rho0 * tau;
+    const double lj = log(J);
+    const double dpdJ = -0.5 * K * (1.0 + (1.0 - lj) / (J * J));
+    const double dJ = rho0 * dtau;
+    const double cJ = cbrt(J);
+    const double s = 1.0 / (cJ * cJ);
+    double bb[6], dbb[6], bi[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        bb[q] = s * b[q];
+        dbb[q] = s * db[q] - (2.0 / 3.0) * (dJ / J) * bb[q];
+    }
+    sym_inv3(bb, bi);
+    const double Bi[3][3] = {{bi[0], bi[3], bi[4]}, {bi[3], bi[1], bi[5]}, {bi[4], bi[5], bi[2]}};
+    const double dB[3][3] = {{dbb[0], dbb[3], dbb[4]}, {dbb[3], dbb[1], dbb[5]}, {dbb[4], dbb[5], dbb[2]}};
+    double tmp[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double u = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) u += dB[i][k] * Bi[k][j];
+            tmp[i][j] = u;
+        }
+    double dbi[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const int i = q < 3 ? q : (q == 5 ? 1 : 0);
+        const int j = q < 3 ? q : (q == 3 ? 1 : 2);
+        double u = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) u += Bi[i][k] * tmp[k][j];
+        dbi[q] = -u;
+    }
+    const double c = (1.0 + a) / 3.0;
+    const double I2 = inv2_6(bb);
+    const double trB = bb[0] + bb[1] + bb[2], trdB = dbb[0] + dbb[1] + dbb[2];
+    const double BdB = bb[0] * dbb[0] + bb[1] * dbb[1] + bb[2] * dbb[2] +
+                       2.0 * (bb[3] * dbb[3] + bb[4] * dbb[4] + bb[5] * dbb[5]);
+    const double dI2 = trB * trdB - BdB;
+    const double trBi = bi[0] + bi[1] + bi[2], trdBi = dbi[0] + dbi[1] + dbi[2];
+    const double mj = mu / J;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const double e = q < 3 ? 1.0 : 0.0;
+        const double T0 = mj * (-a * (bb[q] - e * trB / 3.0) - c * I2 * (bi[q] - e * trBi / 3.0));
+        const double dsh = -a * (dbb[q] - e * trdB / 3.0) -
+                           c * (dI2 * (bi[q] - e * trBi / 3.0) + I2 * (dbi[q] - e * trdBi / 3.0));
+        dt[q] = -dpdJ * dJ * e - (dJ / J) * T0 + mj * dsh;
+    }
+}
+
+// specific free energy Psi_v + Psi_s of the family (energy diagnostics)
+HL_HD double free_energy_family(double rho0, double mu, double K, double a, double tau, const double b[6]) {
+    const double J = rho0 * tau;
+    const double lj = log(J);
+    const double cJ = cbrt(J);
+    const double s = 1.0 / (cJ * cJ);
+    const double I1b = (b[0] + b[1] + b[2]) * s;
+    const double psi_v = K / (4.0 * rho0) * ((J - 1.0) * (J - 1.0) + lj * lj);
+    if (a == -1.0) return psi_v + mu / (2.0 * rho0) * (I1b - 3.0);
+    double bb[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) bb[q] = s * b[q];
+    const double I2b = inv2_6(bb);
+    return psi_v + mu / (4.0 * rho0) * (-2.0 * a * (I1b - 3.0) + (1.0 + a) / 3.0 * (I2b * I2b - 9.0));
+}
+
 // a = sqrt(tau (K_t + 4 mu / 3)), K_t = (K/2)(J + (1 - ln J)/J) = -J dp/dJ
 HL_HD double sound(double rho0, double mu, double K, double tau) {
     double J = rho0 * tau;

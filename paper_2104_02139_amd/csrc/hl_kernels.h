@@ -38,6 +38,7 @@ struct StepArgs {
     double delta0, delta1, eps_tol;
     int detect;
     int cascade;   // 2: a flagged cell goes to first order; 3: to limited first
+    double shear_a;  // shear energy family parameter; -1: neo-Hookean
     int limited;   // 0: no limited cells; 1: they appear in the MOOD passes
                    // (node W bounds, limiter in the pass kernels); 2: also in
                    // the full-mesh pass (replayed levels)

@@ -285,7 +285,7 @@ __device__ __forceinline__ constexpr int bslot(int s) {
 // Reconstruction (R8), ADER midpoint predictor (Section 3.4, reading R7),
 // corner stress and impedance (R5), corner matrix M_cp (eq. Mcp, R4) and
 // r_cp = M_cp v*_cp - T*_cp C_cp (eq. nodal_solver^n).
-template <int D, bool LIM>
+template <int D, bool LIM, bool FAM>
 __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c) {
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
@@ -442,26 +442,43 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
             W0[1 + D + q] += h * y;
         }
         // div T by the chain rule through T(tau, B)
-        const double J = rho0 * tau;
-        const double lj = log(J);
-        const double cJ = cbrt(J);
-        const double J53 = 1.0 / (J * cJ * cJ);   // J^{-5/3}
-        const double J83 = J53 / J;               // J^{-8/3}
-        const double mdpdJ = 0.5 * K * (1.0 + (1.0 - lj) / (J * J));  // -dp/dJ
-        const double trB3 = (b[0] + b[1] + b[2]) * (1.0 / 3.0);
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            double s1 = 0.0, s2 = 0.0;
+        if (FAM) {
+            // shear energy family: column j of grad T from the derivative of
+            // T along (d tau / d x_j, d B / d x_j)
+            double divT[D] = {};
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                const double devB = B3[i][j] - (i == j ? trB3 : 0.0);
-                s1 += devB * grad[0][j];
-                s2 += gB(sidx(i, j), j);
+                double db[6], dT[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) db[q] = gB(q, j);
+                stress6_dir_family(rho0, mu, K, a.shear_a, tau, b, grad[0][j], db, dT);
+#pragma unroll
+                for (int i = 0; i < D; ++i) divT[i] += dT[sidx(i, j)];
             }
-            const double dtr = gB(0, i) + gB(1, i) + gB(2, i);
-            const double divT = rho0 * (mdpdJ * grad[0][i] - (5.0 / 3.0) * mu * J83 * s1) +
-                                mu * J53 * (s2 - dtr * (1.0 / 3.0));
-            W0[1 + i] += h * tau * divT;
+#pragma unroll
+            for (int i = 0; i < D; ++i) W0[1 + i] += h * tau * divT[i];
+        } else {
+            const double J = rho0 * tau;
+            const double lj = log(J);
+            const double cJ = cbrt(J);
+            const double J53 = 1.0 / (J * cJ * cJ);   // J^{-5/3}
+            const double J83 = J53 / J;               // J^{-8/3}
+            const double mdpdJ = 0.5 * K * (1.0 + (1.0 - lj) / (J * J));  // -dp/dJ
+            const double trB3 = (b[0] + b[1] + b[2]) * (1.0 / 3.0);
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const double devB = B3[i][j] - (i == j ? trB3 : 0.0);
+                    s1 += devB * grad[0][j];
+                    s2 += gB(sidx(i, j), j);
+                }
+                const double dtr = gB(0, i) + gB(1, i) + gB(2, i);
+                const double divT = rho0 * (mdpdJ * grad[0][i] - (5.0 / 3.0) * mu * J83 * s1) +
+                                    mu * J53 * (s2 - dtr * (1.0 / 3.0));
+                W0[1 + i] += h * tau * divT;
+            }
         }
         W0[0] += h * tau * trG;
     }
@@ -501,7 +518,10 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
             bk[5] = 0.0;
         }
         double T[6];
-        stress6(rho0, mu, K, Wk[0], bk, T);
+        if (FAM)
+            stress6_family(rho0, mu, K, a.shear_a, Wk[0], bk, T);
+        else
+            stress6(rho0, mu, K, Wk[0], bk, T);
         const double z = sound(rho0, mu, K, Wk[0]) / Wk[0];
         const double rk = 1.0 / g.cn[k];
         double M[Dm::NMS];
@@ -523,17 +543,18 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
     }
 }
 
-template <int D, bool LOOP, bool LIM>
+template <int D, bool LOOP, bool LIM, bool FAM>
 __global__ __launch_bounds__(256) void k_predict(StepArgs a, WorkList w) {
-    for_items<LOOP>(w, [&](int64_t c) { predict_cell<D, LIM>(a, c); });
+    for_items<LOOP>(w, [&](int64_t c) { predict_cell<D, LIM, FAM>(a, c); });
 }
 
 // list-driven variant: the cells just flagged, recomputed at first order
-template <int D, bool LIM>
+template <int D, bool LIM, bool FAM>
 __global__ __launch_bounds__(256) void k_predict_list(StepArgs a, const int32_t *__restrict__ list,
                                                       const unsigned *__restrict__ count) {
     const int64_t n = *count;
-    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) predict_cell<D, LIM>(a, list[i]);
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x)
+        predict_cell<D, LIM, FAM>(a, list[i]);
 }
 
 // ---------------------------------------------------------- node solve
@@ -1116,7 +1137,8 @@ __global__ __launch_bounds__(256) void k_diag(int64_t nc, const double *__restri
                                               const double *__restrict__ v, const double *__restrict__ e,
                                               const double *__restrict__ B, const double *__restrict__ rho0,
                                               const double *__restrict__ mu, const double *__restrict__ K,
-                                              const uint8_t *__restrict__ mask, double *__restrict__ part) {
+                                              const uint8_t *__restrict__ mask, double shear_a,
+                                              double *__restrict__ part) {
     __shared__ double sh[NDIAG][256];
     int64_t c = gtid();
     double q[NDIAG] = {};
@@ -1138,7 +1160,10 @@ __global__ __launch_bounds__(256) void k_diag(int64_t nc, const double *__restri
         double lj = log(J);
         double cJ = cbrt(J);
         double I1b = (b[0] + b[1] + b[2]) / (cJ * cJ);
-        double psi = K[c] / (4.0 * rho0[c]) * ((J - 1.0) * (J - 1.0) + lj * lj) + mu[c] / (2.0 * rho0[c]) * (I1b - 3.0);
+        double psi = shear_a == -1.0
+                         ? K[c] / (4.0 * rho0[c]) * ((J - 1.0) * (J - 1.0) + lj * lj) +
+                               mu[c] / (2.0 * rho0[c]) * (I1b - 3.0)
+                         : free_energy_family(rho0[c], mu[c], K[c], shear_a, tau[c], b);
         q[6] = mc * psi;
         q[7] = mask[c] >= 2 ? 1.0 : 0.0;   // first order
         q[8] = mask[c] == 1 ? 1.0 : 0.0;   // limited slopes
@@ -1193,12 +1218,15 @@ __global__ void k_soa_to_aos(int64_t n, int w, const double *__restrict__ in, do
 template <int D>
 __global__ void k_stress_query(int64_t nc, const double *__restrict__ tau, const double *__restrict__ B,
                                const double *__restrict__ rho0, const double *__restrict__ mu,
-                               const double *__restrict__ K, double *__restrict__ out) {
+                               const double *__restrict__ K, double shear_a, double *__restrict__ out) {
     int64_t c = gtid();
     if (c >= nc) return;
     double b[6], t[6];
     load_B6<D>(B, nc, c, b);
-    stress6(rho0[c], mu[c], K[c], tau[c], b, t);
+    if (shear_a == -1.0)
+        stress6(rho0[c], mu[c], K[c], tau[c], b, t);
+    else
+        stress6_family(rho0[c], mu[c], K[c], shear_a, tau[c], b, t);
     if (D == 3) {
         for (int s = 0; s < 6; ++s) out[c * 6 + s] = t[s];
     } else {
@@ -1231,17 +1259,20 @@ void launch_node_agg(const StepArgs &a, const Sched &k, hipStream_t s) {
 template <int D>
 void launch_predict(const StepArgs &a, const Sched &k, hipStream_t s) {
     if (!k.w.n_items) return;
-    if (a.limited == 2) {
-        if (k.loop)
-            k_predict<D, true, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+    const bool lim = a.limited == 2, fam = a.shear_a != -1.0;
+#define HL_PREDICT_LAUNCH(L, M, F) k_predict<D, L, M, F><<<k.grid, k.block, 0, s>>>(a, k.w)
+    if (k.loop) {
+        if (fam)
+            lim ? HL_PREDICT_LAUNCH(true, true, true) : HL_PREDICT_LAUNCH(true, false, true);
         else
-            k_predict<D, false, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+            lim ? HL_PREDICT_LAUNCH(true, true, false) : HL_PREDICT_LAUNCH(true, false, false);
     } else {
-        if (k.loop)
-            k_predict<D, true, false><<<k.grid, k.block, 0, s>>>(a, k.w);
+        if (fam)
+            lim ? HL_PREDICT_LAUNCH(false, true, true) : HL_PREDICT_LAUNCH(false, false, true);
         else
-            k_predict<D, false, false><<<k.grid, k.block, 0, s>>>(a, k.w);
+            lim ? HL_PREDICT_LAUNCH(false, true, false) : HL_PREDICT_LAUNCH(false, false, false);
     }
+#undef HL_PREDICT_LAUNCH
 }
 template <int D>
 void launch_node_solve(const StepArgs &a, const Sched &k, hipStream_t s) {
@@ -1267,10 +1298,13 @@ void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned 
     const int64_t nnodes = std::min<int64_t>(a.nn, (D + 1) * nflag);
     const int64_t ncells = std::min<int64_t>(a.nc, nnodes * max_deg);
     k_apply_list<<<grid(nflag), 256, 0, s>>>(const_cast<uint8_t *>(a.mask), flist, fcount, a.cascade);
+    const bool fam = a.shear_a != -1.0;
     if (a.limited)
-        k_predict_list<D, true><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+        fam ? k_predict_list<D, true, true><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
+            : k_predict_list<D, true, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
     else
-        k_predict_list<D, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+        fam ? k_predict_list<D, false, true><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
+            : k_predict_list<D, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
     k_mark_nodes<D><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
     k_node_solve_list<D><<<grid(nnodes), 256, 0, s>>>(a);
     k_mark_cells<D><<<grid(nnodes), 256, 0, s>>>(a);
@@ -1306,7 +1340,7 @@ template <int D>
 int64_t launch_diag(const StepArgs &a, const double *tau, const double *v, const double *e, const double *B,
                     double *part, double *out, hipStream_t s) {
     int64_t nb = nblk(a.nc);
-    if (a.nc) k_diag<D><<<nb, 256, 0, s>>>(a.nc, a.mass, tau, v, e, B, a.rho0, a.mu, a.K, a.mask, part);
+    if (a.nc) k_diag<D><<<nb, 256, 0, s>>>(a.nc, a.mass, tau, v, e, B, a.rho0, a.mu, a.K, a.mask, a.shear_a, part);
     k_diag_finalize<<<NDIAG, 256, 0, s>>>(a.nc ? nb : 0, part, out);
     return nb;
 }
@@ -1321,7 +1355,7 @@ void launch_soa_to_aos(int64_t n, int w, const double *in, double *out, hipStrea
 }
 template <int D>
 void launch_stress_query(const StepArgs &a, double *out, hipStream_t s) {
-    if (a.nc) k_stress_query<D><<<nblk(a.nc), 256, 0, s>>>(a.nc, a.tau, a.B, a.rho0, a.mu, a.K, out);
+    if (a.nc) k_stress_query<D><<<nblk(a.nc), 256, 0, s>>>(a.nc, a.tau, a.B, a.rho0, a.mu, a.K, a.shear_a, out);
 }
 
 template void launch_centroids<2>(const StepArgs &, const Sched &, hipStream_t);
