@@ -194,13 +194,15 @@ def batch_measure(steps=5, warmup=2, n_meshes=256, autotune=True):
             "speedup": ts / tb, "schedules": tuned}
 
 
-def cascade3_measure(ctx, w, steps, warmup, graph):
-    """The same workload from t = 0 with the three-level cascade P1 -> P1
-    with the Barth-Jespersen limiter -> P0 (Section 3.5)."""
+def variant_measure(ctx, w, steps, warmup, graph, name, **params):
+    """The same workload from t = 0 with other scheme parameters: the
+    three-level cascade P1 -> P1 with the Barth-Jespersen limiter -> P0
+    (Section 3.5), or another member of the shear energy family (eq.
+    familiy_energies)."""
     import torch
     from paper_2104_02139_amd import hyperlag as H
     ctx.init_state(w.rho0, w.mu, w.lam, w.v_cell, w.v_node,
-                   H.default_params(w.dim, c_cfl=w.c_cfl, cascade=3))
+                   H.default_params(w.dim, c_cfl=w.c_cfl, **params))
     ctx.use_graph(graph, 6)
     lim, p0, it = [], [], []
     for _ in range(warmup):
@@ -218,7 +220,7 @@ def cascade3_measure(ctx, w, steps, warmup, graph):
     lim.append(inf["n_limited"])
     p0.append(inf["n_p0"])
     it.append(inf["mood_iters"])
-    return {"cascade": "P1->P1+BJ->P0", "steps": steps, "ms_per_step": 1e3 * el / steps,
+    return {"variant": name, "steps": steps, "ms_per_step": 1e3 * el / steps,
             "cell_updates_per_s": w.n_cells * steps / el,
             "limited_frac_mean": sum(lim) / len(lim) / w.n_cells,
             "first_order_frac_mean": sum(p0) / len(p0) / w.n_cells,
@@ -268,8 +270,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the many-mesh batched-vs-sequential measurement")
-    ap.add_argument("--no-cascade3", action="store_true",
-                    help="skip the three-level-cascade measurement")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the three-level cascade and shear-energy variant measurements")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward time measurement")
     ap.add_argument("--eager", action="store_true",
@@ -392,9 +394,14 @@ def main():
         "schedules": schedules,
         "kernel_source_sha1": kernel_source_hash(),
     }
-    if not args.no_cascade3:
-        print("[bench] three-level cascade on the same workload", file=sys.stderr, flush=True)
-        out["cascade3"] = cascade3_measure(ctx, w, args.steps, args.warmup, not args.eager)
+    if not args.no_variants:
+        print("[bench] scheme variants on the same workload", file=sys.stderr, flush=True)
+        out["variants"] = [
+            variant_measure(ctx, w, args.steps, args.warmup, not args.eager,
+                            "cascade P1->P1+BJ->P0", cascade=3),
+            variant_measure(ctx, w, args.steps, args.warmup, not args.eager,
+                            "shear energy a=0", shear_a=0.0),
+        ]
     if not args.no_adjoint:
         print("[bench] adjoint vs forward on the identification cube", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_measure()
