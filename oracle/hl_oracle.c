@@ -44,6 +44,13 @@
  *      (eq. cst), I2 the principal invariant, Bbar^-1 the matrix inverse;
  *      a = -1 is neo-Hookean.  The sound speed of R5 is kept for every a
  *      (the family's small-strain shear modulus is mu).
+ *  R28 prescribed traction T^BC on a boundary face f: each node p of f gets
+ *      the additional right-hand side T^BC (|f|/d) n_f in the nodal solver
+ *      ((|f|/d) n_f = -C_ck for the face opposite node k of cell c).
+ *  R29 prescribed normal velocity v_n on boundary faces: with
+ *      d_p = sum_f (|f|/d) n_f and V = sum_f v_n |f|/d over the node's
+ *      loaded faces, v_p = M_p^-1 (r - pi d_p) with pi such that
+ *      v_p . d_p = V.  Wall and symmetry projections take precedence.
  *  R26 Barth-Jespersen: per reconstructed scalar, bounds = min / max over
  *      {c} and its reconstruction stencil at t^n, ratio evaluated at the
  *      d+1 vertices of c; the limited gradient replaces the unlimited one
@@ -88,6 +95,13 @@ typedef struct {
     int64_t *n2c;     /* corner id = c * nv + k                            */
     int *nallow;      /* number of allowed directions per node (d - walls) */
     double *allow;    /* [nn][3][3], column a = allowed unit direction a   */
+    /* boundary loads (Appendix B; R28, R29): face = (cell, local face k,
+     * the face opposite the cell's k-th node); kind 1 traction tensor,
+     * kind 2 normal velocity; value[6] (tensor in SYM3 order, or v_n) */
+    int64_t nload;
+    int32_t *ld_cell;
+    int *ld_face, *ld_kind;
+    double *ld_val;
 } orc_mesh;
 
 /* symmetric component ordering of B in the state arrays                 */
@@ -464,6 +478,10 @@ static int allowed_basis(int d, int nw, const double *normals, double P[3][3]) {
 
 void orc_mesh_free(orc_mesh *M) {
     if (!M) return;
+    free(M->ld_cell);
+    free(M->ld_face);
+    free(M->ld_kind);
+    free(M->ld_val);
     free(M->c2n);
     free(M->n2c_off);
     free(M->n2c);
@@ -508,6 +526,33 @@ orc_mesh *orc_mesh_new(int dim, int64_t nn, int64_t nc, const int32_t *c2n, cons
         memcpy(M->allow + p * 9, P, sizeof P);
     }
     return M;
+}
+
+/* Replace the boundary loads of the mesh (n = 0 clears them). */
+int orc_set_loads(orc_mesh *M, int64_t n, const int32_t *cell, const uint8_t *face, const uint8_t *kind,
+                  const double *value) {
+    free(M->ld_cell);
+    free(M->ld_face);
+    free(M->ld_kind);
+    free(M->ld_val);
+    M->ld_cell = NULL;
+    M->ld_face = M->ld_kind = NULL;
+    M->ld_val = NULL;
+    M->nload = 0;
+    if (n <= 0) return 0;
+    M->ld_cell = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    M->ld_face = (int *)malloc(sizeof(int) * (size_t)n);
+    M->ld_kind = (int *)malloc(sizeof(int) * (size_t)n);
+    M->ld_val = (double *)malloc(sizeof(double) * (size_t)n * 6);
+    for (int64_t l = 0; l < n; ++l) {
+        if (cell[l] < 0 || cell[l] >= M->nc || face[l] >= M->nv || (kind[l] != 1 && kind[l] != 2)) return -1;
+        M->ld_cell[l] = cell[l];
+        M->ld_face[l] = face[l];
+        M->ld_kind[l] = kind[l];
+        for (int q = 0; q < 6; ++q) M->ld_val[l * 6 + q] = value[l * 6 + q];
+    }
+    M->nload = n;
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -850,10 +895,53 @@ static void candidate(orc_work *w, const uint8_t *mask) {
                 r[a] += s;
             }
         }
+        /* boundary loads of the faces through p (readings R28, R29) */
+        double dv[3] = {0, 0, 0}, Vn = 0.0;
+        int has_v = 0;
+        for (int64_t l = 0; l < M->nload; ++l) {
+            int64_t c = M->ld_cell[l];
+            int k = M->ld_face[l], on = 0;
+            for (int j = 0; j < nv; ++j)
+                if (j != k && M->c2n[c * nv + j] == p) on = 1;
+            if (!on) continue;
+            double ln[3];
+            for (int a = 0; a < 3; ++a) ln[a] = -w->geo[c].C[k][a]; /* (|f|/d) n_f */
+            const double *val = M->ld_val + l * 6;
+            if (M->ld_kind[l] == 1) {
+                double T[3][3];
+                for (int q = 0; q < 6; ++q) {
+                    T[SYM3[q][0]][SYM3[q][1]] = val[q];
+                    T[SYM3[q][1]][SYM3[q][0]] = val[q];
+                }
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) r[a] += T[a][b] * ln[b];
+            } else {
+                has_v = 1;
+                for (int a = 0; a < 3; ++a) dv[a] += ln[a];
+                Vn += val[0] * norm3(ln);
+            }
+        }
         const double *P = M->allow + p * 9;
         int m = M->nallow[p];
         double vs[3] = {0, 0, 0};
-        if (m > 0) {
+        if (m == d && has_v && M->n2c_off[p + 1] > M->n2c_off[p]) {
+            /* v = M_p^-1 (r - pi d), v . d = V */
+            double A1[9], A2[9], y[3], z[3];
+            for (int a = 0; a < d; ++a) {
+                y[a] = r[a];
+                z[a] = dv[a];
+                for (int b = 0; b < d; ++b) A1[a * d + b] = A2[a * d + b] = Mp[a][b];
+            }
+            gepp(d, A1, y);
+            gepp(d, A2, z);
+            double yd = 0.0, zd = 0.0;
+            for (int a = 0; a < d; ++a) {
+                yd += y[a] * dv[a];
+                zd += z[a] * dv[a];
+            }
+            double pi = (yd - Vn) / zd;
+            for (int a = 0; a < d; ++a) vs[a] = y[a] - pi * z[a];
+        } else if (m > 0) {
             double Ar[9], br[3];
             for (int s = 0; s < m; ++s) {
                 br[s] = 0.0;

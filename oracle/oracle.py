@@ -78,6 +78,8 @@ def lib():
         L.orc_mesh_new.restype = C.c_void_p
         L.orc_mesh_new.argtypes = [C.c_int, C.c_int64, C.c_int64, _I32, _U8, _P]
         L.orc_mesh_free.argtypes = [C.c_void_p]
+        L.orc_set_loads.restype = C.c_int
+        L.orc_set_loads.argtypes = [C.c_void_p, C.c_int64, _I32, _U8, _U8, _P]
         L.orc_init_state.restype = C.c_int
         L.orc_init_state.argtypes = [C.c_void_p] + [_P] * 6 + [_P] * 7
         L.orc_step.restype = C.c_int
@@ -202,6 +204,18 @@ class Mesh:
         if not h:
             raise ValueError("invalid mesh")
         self.h = h
+
+    def set_loads(self, cell, face, kind, value):
+        """Boundary loads (Appendix B): face (cell, k) is the face opposite
+        the cell's k-th node; kind 1 traction tensor value[6] in (11, 22,
+        33, 12, 13, 23) order, kind 2 normal velocity value[0]."""
+        self._ld = (np.ascontiguousarray(cell, np.int32), np.ascontiguousarray(face, np.uint8),
+                    np.ascontiguousarray(kind, np.uint8), _f64(np.reshape(value, (-1, 6))))
+        rc = lib().orc_set_loads(self.h, len(self._ld[0]), self._ld[0].ctypes.data_as(_I32),
+                                 self._ld[1].ctypes.data_as(_U8), self._ld[2].ctypes.data_as(_U8),
+                                 _ptr(self._ld[3]))
+        if rc != 0:
+            raise ValueError("invalid boundary load")
 
     def __del__(self):
         h = getattr(self, "h", None)
