@@ -154,6 +154,30 @@ hl_status hl_state_init(hl_ctx *ctx, const double *rho0, const double *mu, const
 /* Replace the parameters used by the following steps. */
 hl_status hl_set_params(hl_ctx *ctx, const hl_params *p);
 
+/* Boundary loads on faces of the mesh (Section 3.8, Appendix B: boundary
+ * conditions; not part of the paper's test problems).  Load l acts on the
+ * face of cell cell[l] opposite its local node face[l] (0..dim), which the
+ * caller names as a boundary face; kind[l] is
+ *   1  prescribed traction: value[l] = the symmetric stress T^BC as
+ *      (11, 22, 33, 12, 13, 23) (2D uses 11, 22, 12); every node p of the
+ *      face gets T^BC (|f|/dim) n_f on the right-hand side of its nodal
+ *      system, n_f the outward unit normal and |f| the face measure at t^n
+ *      ((|f|/dim) n_f = -C_ck, k = face[l]);
+ *   2  prescribed outward normal velocity: value[l][0] = v_n (the other
+ *      entries are ignored); at a node of such faces with no wall
+ *      constraint, v*_p = M_p^-1 (r_p - pi d_p), d_p = sum over its loaded
+ *      faces of (|f|/dim) n_f, with the multiplier pi chosen so that
+ *      v*_p . d_p = sum of v_n |f|/dim over the same faces (for one flat
+ *      face: v*_p . n = v_n).  Nodes with wall constraints ignore it.
+ * Every node sums its loads in the order of l.  value: [n][6] doubles.
+ * n = 0 removes all loads.  Loads persist across steps until replaced or
+ * until a new mesh is uploaded; setting them drops captured graphs and any
+ * recorded adjoint tape, and hl_forward_record refuses a context that has
+ * loads (its adjoint omits them).  HL_E_INVALID for a cell out of range, a
+ * face > dim, a kind other than 1 or 2 or a value that is not finite. */
+hl_status hl_set_boundary_loads(hl_ctx *ctx, int64_t n, const int32_t *cell, const uint8_t *face,
+                                const uint8_t *kind, const double *value, int on_device);
+
 /* Acoustic time step C_CFL min_c L_c / a_c of the current state (eq. CFL2
  * at the first step).  It also becomes the dt used by hl_step(ctx, 0). */
 hl_status hl_compute_dt(hl_ctx *ctx, double *dt_out);
@@ -239,8 +263,9 @@ hl_status hl_autotune(hl_ctx *ctx, int reps, double *best_ms);
 /* Run nsteps CFL-controlled ADER-MOOD steps from the current state,
  * recording each step's dt and cascade mask and a state checkpoint every
  * ckpt_every steps (device memory owned by the context).  The adjoint
- * covers the two-level cascade and the neo-Hookean law: with cascade 3 or
- * shear_a != -1 this returns HL_E_INVALID. */
+ * covers the two-level cascade and the neo-Hookean law without boundary
+ * loads: with cascade 3, shear_a != -1 or loads set this returns
+ * HL_E_INVALID. */
 hl_status hl_forward_record(hl_ctx *ctx, int nsteps, int ckpt_every);
 
 /* Re-run the recorded steps from the current state with the recorded dt and

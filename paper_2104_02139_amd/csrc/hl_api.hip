@@ -100,6 +100,14 @@ struct hl_ctx {
     hl::Sched sk[HL_STAGE_COUNT] = {};
     bool sched_ready = false;
     std::map<std::pair<int, int>, DevList> wlists;  // (entity kind, tile) -> list
+    // boundary loads grouped by node (own allocations, freed with the mesh)
+    struct {
+        int64_t n = 0;  // loads set by the caller
+        int32_t *off = nullptr, *cell = nullptr;
+        uint8_t *fk = nullptr;
+        double *val = nullptr;
+        std::vector<void *> mem;
+    } ld;
     // adjoint tapes (own allocations, freed with the mesh)
     struct {
         int nsteps = 0, every = 0, nckpt = 0;
@@ -167,9 +175,19 @@ void free_tape(hl_ctx *c) {
     c->tape.cadj = c->tape.nadj = c->tape.cell = c->tape.agg = c->tape.xadj = c->tape.mu_bar = c->tape.out = nullptr;
 }
 
+void free_loads(hl_ctx *c) {
+    for (void *p : c->ld.mem) (void)hipFree(p);
+    c->ld.mem.clear();
+    c->ld.n = 0;
+    c->ld.off = c->ld.cell = nullptr;
+    c->ld.fk = nullptr;
+    c->ld.val = nullptr;
+}
+
 void free_all(hl_ctx *c) {
     drop_graphs(c);
     free_tape(c);
+    free_loads(c);
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->counters_host) (void)hipHostFree(c->counters_host);
@@ -412,6 +430,10 @@ hl::StepArgs make_args(hl_ctx *c, int src) {
     a.cascade = c->prm.cascade == 3 ? 3 : 2;
     a.shear_a = c->prm.shear_a;
     a.limited = a.cascade == 3 ? 1 : 0;
+    a.ld_off = c->ld.off;
+    a.ld_cell = c->ld.cell;
+    a.ld_fk = c->ld.fk;
+    a.ld_val = c->ld.val;
     return a;
 }
 
@@ -1232,6 +1254,80 @@ hl_status hl_set_params(hl_ctx *c, const hl_params *p) {
     return HL_OK;
 }
 
+hl_status hl_set_boundary_loads(hl_ctx *c, int64_t n, const int32_t *cell, const uint8_t *face, const uint8_t *kind,
+                                const double *value, int on_device) {
+    if (!c || n < 0) return HL_E_INVALID;
+    if (!c->have_mesh) return HL_E_STATE;
+    if (n > 0 && (!cell || !face || !kind || !value)) return HL_E_INVALID;
+    if (n >= (int64_t)INT32_MAX / 3) return HL_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    const int d = c->dim, nv = d + 1;
+    std::vector<int32_t> hc(n);
+    std::vector<uint8_t> hf(n), hk(n);
+    std::vector<double> hv(6 * n);
+    if (n > 0 && on_device) {
+        HIPCHK(hipMemcpy(hc.data(), cell, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(hf.data(), face, n, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(hk.data(), kind, n, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(hv.data(), value, sizeof(double) * 6 * n, hipMemcpyDeviceToHost));
+    } else if (n > 0) {
+        std::memcpy(hc.data(), cell, sizeof(int32_t) * n);
+        std::memcpy(hf.data(), face, n);
+        std::memcpy(hk.data(), kind, n);
+        std::memcpy(hv.data(), value, sizeof(double) * 6 * n);
+    }
+    for (int64_t l = 0; l < n; ++l) {
+        if (hc[l] < 0 || hc[l] >= c->nc || hf[l] > d || (hk[l] != 1 && hk[l] != 2)) return HL_E_INVALID;
+        for (int q = 0; q < 6; ++q)
+            if (!std::isfinite(hv[6 * l + q])) return HL_E_INVALID;
+    }
+    // entries grouped by node, each node's in the order of l
+    const int64_t nn = c->nn;
+    std::vector<int32_t> off(nn + 1, 0);
+    for (int64_t l = 0; l < n; ++l)
+        for (int j = 0; j < nv; ++j)
+            if (j != hf[l]) ++off[c->c2n_host[(size_t)hc[l] * nv + j] + 1];
+    for (int64_t p = 0; p < nn; ++p) off[p + 1] += off[p];
+    const int64_t ne = off[nn];
+    std::vector<int32_t> pos(off.begin(), off.end() - 1), ec(ne);
+    std::vector<uint8_t> efk(ne);
+    std::vector<double> ev(6 * ne);
+    for (int64_t l = 0; l < n; ++l)
+        for (int j = 0; j < nv; ++j) {
+            if (j == hf[l]) continue;
+            const int32_t q = pos[c->c2n_host[(size_t)hc[l] * nv + j]]++;
+            ec[q] = hc[l];
+            efk[q] = (uint8_t)(hf[l] | (hk[l] << 2));
+            for (int t = 0; t < 6; ++t) ev[6 * (size_t)q + t] = hv[6 * l + t];
+        }
+    drop_graphs(c);
+    free_tape(c);
+    free_loads(c);
+    if (n == 0) return HL_OK;
+    auto get = [&](void **p, size_t bytes) -> bool {
+        if (hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) return false;
+        c->ld.mem.push_back(*p);
+        return true;
+    };
+    if (!get((void **)&c->ld.off, sizeof(int32_t) * (nn + 1)) || !get((void **)&c->ld.cell, sizeof(int32_t) * ne) ||
+        !get((void **)&c->ld.fk, ne) || !get((void **)&c->ld.val, sizeof(double) * 6 * ne)) {
+        free_loads(c);
+        return HL_E_OOM;
+    }
+    hipStream_t s = c->stream;
+    hipError_t e = hipMemcpyAsync(c->ld.off, off.data(), sizeof(int32_t) * (nn + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->ld.cell, ec.data(), sizeof(int32_t) * ne, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->ld.fk, efk.data(), ne, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->ld.val, ev.data(), sizeof(double) * 6 * ne, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_loads(c);
+        return hip_fail(e, "boundary load upload", __LINE__);
+    }
+    c->ld.n = n;
+    return HL_OK;
+}
+
 hl_status hl_state_init(hl_ctx *c, const double *rho0, const double *mu, const double *lam, const double *v_cell,
                         const double *v_node, const hl_params *p, int on_device) {
     if (!c) return HL_E_INVALID;
@@ -1439,9 +1535,10 @@ hl_status hl_upload_field(hl_ctx *c, int field, const void *in, int64_t count, i
 hl_status hl_forward_record(hl_ctx *c, int nsteps, int ckpt_every) {
     if (!c || nsteps < 1 || ckpt_every < 1) return HL_E_INVALID;
     if (!c->have_state) return HL_E_STATE;
-    if (c->prm.cascade == 3 || c->prm.shear_a != -1.0) {
+    if (c->prm.cascade == 3 || c->prm.shear_a != -1.0 || c->ld.n > 0) {
         std::snprintf(g_last_error, sizeof g_last_error,
-                      "the adjoint covers the two-level cascade and the neo-Hookean law (cascade 2, shear_a -1)");
+                      "the adjoint covers the two-level cascade and the neo-Hookean law without boundary loads "
+                      "(cascade 2, shear_a -1, no loads)");
         return HL_E_INVALID;
     }
     if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;

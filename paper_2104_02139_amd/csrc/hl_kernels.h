@@ -42,6 +42,14 @@ struct StepArgs {
     int limited;   // 0: no limited cells; 1: they appear in the MOOD passes
                    // (node W bounds, limiter in the pass kernels); 2: also in
                    // the full-mesh pass (replayed levels)
+    // Boundary loads grouped by node (all null when there are none): the
+    // entries of node p are ld_off[p] .. ld_off[p+1]-1; entry q is the face
+    // opposite local node (ld_fk[q] & 3) of cell ld_cell[q], of kind
+    // ld_fk[q] >> 2 (1 traction, 2 normal velocity), with values
+    // ld_val[6q .. 6q+5].
+    const int32_t *ld_off, *ld_cell;
+    const uint8_t *ld_fk;
+    const double *ld_val;
 };
 
 enum { CNT_F0 = 0, CNT_F1 = 1, CNT_NODES = 2, CNT_CELLS = 3, CNT_BAD = 4, CNT_N = 8 };

@@ -560,14 +560,25 @@ __global__ __launch_bounds__(256) void k_predict_list(StepArgs a, const int32_t 
 // ---------------------------------------------------------- node solve
 // M_p v*_p = sum_c (M_cp v*_cp - T*_cp C_cp) (eq. nodal_solver^n, readings
 // R14, R15); slip walls by Galerkin projection onto the allowed directions
-// (Appendix B eq. sBC1, reading R22).  Then x^{n+1} = x^n + dt v*_p and
-// vhat^{n+1} = 2 v*_p - vhat^n (Section 3.4, reading R9).
-template <int D>
+// (Appendix B eq. sBC1, reading R22); boundary loads of the faces through
+// the node (Appendix B, readings R28, R29).  Then x^{n+1} = x^n + dt v*_p
+// and vhat^{n+1} = 2 v*_p - vhat^n (Section 3.4, reading R9).
+template <int D, bool LD>
 __device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64_t p, const bool any,
                                                   const double (&M)[Dims<D>::NMS], const double (&r)[D],
                                                   const int comp);
 
+// Symmetric tensor from its components (11, 22, 33, 12, 13, 23); the
+// leading D x D block.
 template <int D>
+__device__ __forceinline__ void sym6_unpack(const double *v, double (&T)[D][D]) {
+    constexpr int row[6] = {0, 1, 2, 0, 0, 1}, col[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        if (row[q] < D && col[q] < D) T[row[q]][col[q]] = T[col[q]][row[q]] = v[q];
+}
+
+template <int D, bool LD>
 __device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t p) {
     using Dm = Dims<D>;
     double M[Dm::NMS] = {}, r[D] = {};
@@ -579,14 +590,14 @@ __device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t 
 #pragma unroll
         for (int i = 0; i < D; ++i) r[i] += rec[Dm::NMS + i];
     }
-    node_solve_finish<D>(a, p, q1 > q0, M, r, -1);
+    node_solve_finish<D, LD>(a, p, q1 > q0, M, r, -1);
 }
 
 // Cooperative corner gather (as for the node aggregates): lane l of a group
 // of AGG_G sums value pair l of the node's corner records in CSR order, so a
 // wave-wide load brings whole records; the sums then meet in every lane of
 // the group, which all run the solve.  Lane i < D writes component i.
-template <int D>
+template <int D, bool LD>
 __device__ __forceinline__ void node_solve_group(const StepArgs &a, const int64_t p, const int l) {
     using Dm = Dims<D>;
     constexpr int NP = Dm::CW / 2;  // value pairs per corner record
@@ -621,18 +632,64 @@ __device__ __forceinline__ void node_solve_group(const StepArgs &a, const int64_
     for (int s = 0; s < Dm::NMS; ++s) M[s] = v[s];
 #pragma unroll
     for (int i = 0; i < D; ++i) r[i] = v[Dm::NMS + i];
-    node_solve_finish<D>(a, p, q1 > q0, M, r, l);
+    node_solve_finish<D, LD>(a, p, q1 > q0, M, r, l);
 }
 
 // v* from the summed corner matrices and right-hand sides; comp < 0 writes
-// every component, otherwise only component comp (if < D)
-template <int D>
+// every component, otherwise only component comp (if < D).  LD: the mesh
+// has boundary loads (a separate instantiation keeps the plain solve's
+// register budget).
+template <int D, bool LD>
 __device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64_t p, const bool any,
                                                   const double (&M)[Dims<D>::NMS], const double (&r)[D],
                                                   const int comp) {
     using Dm = Dims<D>;
     const int64_t nn = a.nn;
-    double vs[D] = {};
+    double vs[D] = {}, rl[D], dl[D] = {}, vn = 0.0;
+    bool has_v = false;
+#pragma unroll
+    for (int i = 0; i < D; ++i) rl[i] = r[i];
+    if (LD) {
+        // face vector (|f|/d) n_f = -C_k of the face opposite node k, from
+        // the positions at t^n: a traction adds T^BC (|f|/d) n_f to the
+        // right-hand side (R28); a normal velocity adds to d_p and to the
+        // target sum_f v_n |f|/d (R29)
+        const int32_t l0 = a.ld_off[p], l1 = a.ld_off[p + 1];
+        for (int32_t q = l0; q < l1; ++q) {
+            const int64_t c = a.ld_cell[q];
+            const int code = a.ld_fk[q], k = code & 3;
+            double X[D + 1][D];
+#pragma unroll
+            for (int j = 0; j <= D; ++j) {
+                const int64_t pj = a.c2n[c * (D + 1) + j];
+#pragma unroll
+                for (int i = 0; i < D; ++i) X[j][i] = a.x[i * nn + pj];
+            }
+            Geo<D> g;
+            geom<D>(X, g);
+            double Ck[D] = {}, ck = 0.0;  // row k by selects (no indexed registers)
+#pragma unroll
+            for (int j = 0; j <= D; ++j) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) Ck[i] = j == k ? g.C[j][i] : Ck[i];
+                ck = j == k ? g.cn[j] : ck;
+            }
+            const double *val = a.ld_val + 6 * (int64_t)q;
+            if ((code >> 2) == 1) {
+                double T[D][D];
+                sym6_unpack<D>(val, T);
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+#pragma unroll
+                    for (int j = 0; j < D; ++j) rl[i] -= T[i][j] * Ck[j];
+            } else {
+                has_v = true;
+#pragma unroll
+                for (int i = 0; i < D; ++i) dl[i] -= Ck[i];
+                vn += val[0] * ck;
+            }
+        }
+    }
     const int na = a.nallow[p];
     if (any && na == D) {
         double inv[Dm::NMS];
@@ -644,8 +701,24 @@ __device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64
         for (int i = 0; i < D; ++i) {
             double s = 0.0;
 #pragma unroll
-            for (int j = 0; j < D; ++j) s += inv[midx<D>(i, j)] * r[j];
+            for (int j = 0; j < D; ++j) s += inv[midx<D>(i, j)] * rl[j];
             vs[i] = s;
+        }
+        if (has_v) {
+            // v = M^-1 (r - pi d) with pi such that v . d = sum_f v_n |f|/d
+            double z[D], yd = 0.0, zd = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) s += inv[midx<D>(i, j)] * dl[j];
+                z[i] = s;
+                yd += vs[i] * dl[i];
+                zd += s * dl[i];
+            }
+            const double pi = (yd - vn) / zd;
+#pragma unroll
+            for (int i = 0; i < D; ++i) vs[i] -= pi * z[i];
         }
     } else if (any && na > 0) {
         // P: D x na orthonormal columns, P[i][t] = allow[p*D*D + i*D + t]
@@ -660,7 +733,7 @@ __device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64
         for (int s = 0; s < D; ++s) {
             double t = 0.0;
 #pragma unroll
-            for (int i = 0; i < D; ++i) t += P[i * D + s] * r[i];
+            for (int i = 0; i < D; ++i) t += P[i * D + s] * rl[i];
             br[s] = t;
 #pragma unroll
             for (int u = 0; u < D; ++u) {
@@ -698,7 +771,7 @@ __device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64
     }
 }
 
-template <int D, bool LOOP>
+template <int D, bool LOOP, bool LD>
 __global__ __launch_bounds__(256) void k_node_solve(StepArgs a, WorkList w) {
     const int l = threadIdx.x & (AGG_G - 1);
     const int g = threadIdx.x / AGG_G;
@@ -710,15 +783,15 @@ __global__ __launch_bounds__(256) void k_node_solve(StepArgs a, WorkList w) {
     for (int64_t it = i0 + (blockIdx.x >> 3); it < i1; it += nslot) {
         const int64_t s0 = w.start[it];
         const int len = w.len[it];
-        for (int base = g; base < len; base += per_pass) node_solve_group<D>(a, s0 + base, l);
+        for (int base = g; base < len; base += per_pass) node_solve_group<D, LD>(a, s0 + base, l);
         if (!LOOP) break;
     }
 }
 
-template <int D>
+template <int D, bool LD>
 __global__ __launch_bounds__(256) void k_node_solve_list(StepArgs a) {
     const int64_t n = a.counters[CNT_NODES];
-    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) node_solve_one<D>(a, a.nlist[i]);
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) node_solve_one<D, LD>(a, a.nlist[i]);
 }
 
 // -------------------------------------------------------- cell update
@@ -1277,10 +1350,13 @@ void launch_predict(const StepArgs &a, const Sched &k, hipStream_t s) {
 template <int D>
 void launch_node_solve(const StepArgs &a, const Sched &k, hipStream_t s) {
     if (!k.w.n_items) return;
+    const bool ld = a.ld_off != nullptr;
     if (k.loop)
-        k_node_solve<D, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+        ld ? k_node_solve<D, true, true><<<k.grid, k.block, 0, s>>>(a, k.w)
+           : k_node_solve<D, true, false><<<k.grid, k.block, 0, s>>>(a, k.w);
     else
-        k_node_solve<D, false><<<k.grid, k.block, 0, s>>>(a, k.w);
+        ld ? k_node_solve<D, false, true><<<k.grid, k.block, 0, s>>>(a, k.w)
+           : k_node_solve<D, false, false><<<k.grid, k.block, 0, s>>>(a, k.w);
 }
 template <int D>
 void launch_update(const StepArgs &a, const Sched &k, hipStream_t s) {
@@ -1306,7 +1382,10 @@ void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned 
         fam ? k_predict_list<D, false, true><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
             : k_predict_list<D, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
     k_mark_nodes<D><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
-    k_node_solve_list<D><<<grid(nnodes), 256, 0, s>>>(a);
+    if (a.ld_off)
+        k_node_solve_list<D, true><<<grid(nnodes), 256, 0, s>>>(a);
+    else
+        k_node_solve_list<D, false><<<grid(nnodes), 256, 0, s>>>(a);
     k_mark_cells<D><<<grid(nnodes), 256, 0, s>>>(a);
     k_update_list<D><<<grid(ncells), 256, 0, s>>>(a);
 }

@@ -26,7 +26,7 @@ EXPORTS = ["hl_create", "hl_destroy", "hl_mesh_upload", "hl_state_init", "hl_set
            "hl_profile_enable", "hl_profile_reset", "hl_profile_get", "hl_status_str",
            "hl_last_error", "hl_mesh_upload_batch", "hl_step_batch", "hl_query_dt", "hl_use_graph",
            "hl_forward_record", "hl_forward_replay", "hl_adjoint_run", "hl_tape_get",
-           "hl_set_schedule", "hl_get_schedule", "hl_autotune"]
+           "hl_set_schedule", "hl_get_schedule", "hl_autotune", "hl_set_boundary_loads"]
 
 # stages of the full-mesh part of a step (launch schedules)
 STAGES = ("pack", "node_agg", "predict", "node_solve", "update")
@@ -107,6 +107,7 @@ def load():
     L.hl_tape_get.argtypes = [vp, C.c_int, vp, vp]
     L.hl_state_init.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(Params), C.c_int]
     L.hl_set_params.argtypes = [vp, C.POINTER(Params)]
+    L.hl_set_boundary_loads.argtypes = [vp, i64, vp, vp, vp, vp, C.c_int]
     L.hl_compute_dt.argtypes = [vp, C.POINTER(dp)]
     L.hl_step.argtypes = [vp, dp, C.POINTER(StepInfo)]
     L.hl_step_replay.argtypes = [vp, dp, vp, C.c_int, C.POINTER(StepInfo)]
@@ -232,6 +233,26 @@ class Context:
     def set_params(self, params):
         self.params = params
         _check(load().hl_set_params(self._h, C.byref(params)), "hl_set_params")
+
+    def set_boundary_loads(self, cell=None, face=None, kind=None, value=None):
+        """Loads on boundary faces: face ``face[l]`` (opposite that local
+        node) of cell ``cell[l]``; ``kind`` 1 = traction with ``value[l]`` the
+        stress (11, 22, 33, 12, 13, 23), 2 = outward normal velocity
+        ``value[l][0]``.  No arguments remove every load."""
+        if cell is None or len(cell) == 0:
+            _check(load().hl_set_boundary_loads(self._h, 0, None, None, None, None, 0),
+                   "hl_set_boundary_loads")
+            return
+        n = len(cell)
+        pc, kc, dev = _arg(cell, np.int32)
+        pf, kf, df = _arg(face, np.uint8)
+        pk, kk, dk = _arg(kind, np.uint8)
+        pv, kv, dv = _arg(value, np.float64)
+        if len(face) != n or len(kind) != n or tuple(kv.shape) != (n, 6):
+            raise ValueError("cell, face, kind: [n]; value: [n][6]")
+        if not dev == df == dk == dv:
+            raise ValueError("boundary load arrays must all be on the host or all on the device")
+        _check(load().hl_set_boundary_loads(self._h, n, pc, pf, pk, pv, dev), "hl_set_boundary_loads")
 
     def compute_dt(self):
         dt = C.c_double()
