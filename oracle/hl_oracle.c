@@ -50,7 +50,11 @@
  *  R29 prescribed normal velocity v_n on boundary faces: with
  *      d_p = sum_f (|f|/d) n_f and V = sum_f v_n |f|/d over the node's
  *      loaded faces, v_p = M_p^-1 (r - pi d_p) with pi such that
- *      v_p . d_p = V.  Wall and symmetry projections take precedence.
+ *      v_p . d_p = V.  Wall and symmetry constraints come first (the
+ *      paper's hierarchy): at a constrained node the same multiplier acts
+ *      in the allowed directions, v = P a, (P^T M P) a = P^T (r - pi d_p),
+ *      a . P^T d_p = V; the load is dropped where P^T d_p vanishes
+ *      (|P^T d|^2 <= 1e-20 |d|^2).
  *  R26 Barth-Jespersen: per reconstructed scalar, bounds = min / max over
  *      {c} and its reconstruction stencil at t^n, ratio evaluated at the
  *      d+1 vertices of c; the limited gradient replaces the unlimited one
@@ -942,18 +946,38 @@ static void candidate(orc_work *w, const uint8_t *mask) {
             double pi = (yd - Vn) / zd;
             for (int a = 0; a < d; ++a) vs[a] = y[a] - pi * z[a];
         } else if (m > 0) {
-            double Ar[9], br[3];
+            /* Galerkin projection on the allowed directions (R22); a
+               velocity load is then met within them, unless they are
+               orthogonal to d (R29: walls and symmetry first) */
+            double Ar[9], br[3], A2[9], e[3], z[3];
+            double ee = 0.0, dd = 0.0;
             for (int s = 0; s < m; ++s) {
                 br[s] = 0.0;
+                e[s] = 0.0;
                 for (int i = 0; i < 3; ++i) br[s] += P[i * 3 + s] * r[i];
+                for (int i = 0; i < 3; ++i) e[s] += P[i * 3 + s] * dv[i];
+                ee += e[s] * e[s];
                 for (int t = 0; t < m; ++t) {
                     double a = 0.0;
                     for (int i = 0; i < 3; ++i)
                         for (int j = 0; j < 3; ++j) a += P[i * 3 + s] * Mp[i][j] * P[j * 3 + t];
                     Ar[s * m + t] = a;
+                    A2[s * m + t] = a;
                 }
             }
+            for (int a = 0; a < 3; ++a) dd += dv[a] * dv[a];
             gepp(m, Ar, br);
+            if (has_v && ee > 1e-20 * dd) {
+                for (int s = 0; s < m; ++s) z[s] = e[s];
+                gepp(m, A2, z);
+                double ye = 0.0, ze = 0.0;
+                for (int s = 0; s < m; ++s) {
+                    ye += br[s] * e[s];
+                    ze += z[s] * e[s];
+                }
+                double pi = (ye - Vn) / ze;
+                for (int s = 0; s < m; ++s) br[s] -= pi * z[s];
+            }
             for (int i = 0; i < 3; ++i)
                 for (int t = 0; t < m; ++t) vs[i] += P[i * 3 + t] * br[t];
         }

@@ -177,3 +177,32 @@ def test_wall_takes_precedence_over_a_velocity_load():
     s1, vs1, _, _ = Pw.step(dt)
     s2, vs2, _, _ = P2.step(dt)
     assert np.array_equal(vs1, vs2) and np.array_equal(s1.v, s2.v)
+
+
+def test_velocity_load_is_met_along_a_wall():
+    """Hierarchy: a node on a slip wall (z = 0) and on a piston face (x = 0)
+    keeps v_z = 0 and still meets the piston's normal velocity."""
+    U = 0.4
+    w = W.rotating_cube_3d(n=3, seed=7, omega=0.0)
+    x = w.x
+    bottom = np.abs(x[:, 2] - x[:, 2].min()) < 1e-12
+    w.nwall = bottom.astype(np.uint8)
+    w.normals = np.zeros((w.n_nodes, 3, 3))
+    w.normals[bottom, 0, 2] = 1.0
+    face = [(c, k) for c, k in boundary_faces(w.cells)
+            if np.all(np.abs(x[np.delete(w.cells[c], k), 0] - x[:, 0].min()) < 1e-12)]
+    on = np.zeros(w.n_nodes, bool)
+    for c, k in face:
+        on[np.delete(w.cells[c], k)] = True
+    edge = on & bottom
+    assert edge.sum() == 4
+    P = O.Problem(w, O.default_params(w.c_cfl, detect=False))
+    val = np.zeros((len(face), 6))
+    val[:, 0] = -U                      # outward normal -x: v_x = U
+    P.mesh.set_loads([f[0] for f in face], [f[1] for f in face], np.full(len(face), 2), val)
+    dt = P.initial_dt()
+    _, vs, _, _ = P.step(dt)
+    assert np.abs(vs[bottom, 2]).max() <= 1e-15 * U
+    assert np.abs(vs[on, 0] - U).max() <= 1e-12 * U
+    # the bending field moves the edge nodes along y: they are not held
+    assert np.abs(vs[edge, 1]).max() > 1e-6
