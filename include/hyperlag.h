@@ -164,11 +164,14 @@ hl_status hl_set_params(hl_ctx *ctx, const hl_params *p);
  *      system, n_f the outward unit normal and |f| the face measure at t^n
  *      ((|f|/dim) n_f = -C_ck, k = face[l]);
  *   2  prescribed outward normal velocity: value[l][0] = v_n (the other
- *      entries are ignored); at a node of such faces with no wall
- *      constraint, v*_p = M_p^-1 (r_p - pi d_p), d_p = sum over its loaded
- *      faces of (|f|/dim) n_f, with the multiplier pi chosen so that
+ *      entries are ignored); at a node of such faces,
+ *      v*_p = M_p^-1 (r_p - pi d_p), d_p = sum over its loaded faces of
+ *      (|f|/dim) n_f, with the multiplier pi chosen so that
  *      v*_p . d_p = sum of v_n |f|/dim over the same faces (for one flat
- *      face: v*_p . n = v_n).  Nodes with wall constraints ignore it.
+ *      face: v*_p . n = v_n).  Walls and symmetry constraints come first:
+ *      at a constrained node the multiplier acts within the allowed
+ *      directions P (v = P a, (P^T M_p P) a = P^T (r_p - pi d_p)), and the
+ *      load is dropped where P^T d_p vanishes (|P^T d|^2 <= 1e-20 |d|^2).
  * Every node sums its loads in the order of l.  value: [n][6] doubles.
  * n = 0 removes all loads.  Loads persist across steps until replaced or
  * until a new mesh is uploaded; setting them drops captured graphs and any

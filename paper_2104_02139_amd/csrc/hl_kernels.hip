@@ -746,12 +746,42 @@ __device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64
             }
         }
         double al[D] = {};
-        if (na == 1) {
-            al[0] = br[0] / Ar[0][0];
-        } else {  // na == 2 < D == 3
-            double det = Ar[0][0] * Ar[1][1] - Ar[0][1] * Ar[1][0];
-            al[0] = (Ar[1][1] * br[0] - Ar[0][1] * br[1]) / det;
-            al[1] = (Ar[0][0] * br[1] - Ar[1][0] * br[0]) / det;
+        const double det = na == 1 ? Ar[0][0] : Ar[0][0] * Ar[1][1] - Ar[0][1] * Ar[1][0];
+        auto solve = [&](const double (&b)[D], double (&x)[D]) {
+            if (na == 1) {
+                x[0] = b[0] / Ar[0][0];
+            } else {  // na == 2 < D == 3
+                x[0] = (Ar[1][1] * b[0] - Ar[0][1] * b[1]) / det;
+                x[1] = (Ar[0][0] * b[1] - Ar[1][0] * b[0]) / det;
+            }
+        };
+        solve(br, al);
+        if (LD && has_v) {
+            // the velocity load within the allowed directions: a = y - pi z,
+            // z = (P^T M P)^-1 P^T d, a . P^T d = sum_f v_n |f|/d; dropped
+            // where P^T d vanishes (walls and symmetry come first)
+            double e[D] = {}, z[D] = {}, ee = 0.0, dd = 0.0;
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                double u = 0.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i) u += P[i * D + t] * dl[i];
+                e[t] = t < na ? u : 0.0;
+                ee += e[t] * e[t];
+                dd += dl[t] * dl[t];
+            }
+            if (ee > 1e-20 * dd) {
+                solve(e, z);
+                double ye = 0.0, ze = 0.0;
+#pragma unroll
+                for (int t = 0; t < D; ++t) {
+                    ye += t < na ? al[t] * e[t] : 0.0;
+                    ze += t < na ? z[t] * e[t] : 0.0;
+                }
+                const double pi = (ye - vn) / ze;
+#pragma unroll
+                for (int t = 0; t < D; ++t) al[t] -= t < na ? pi * z[t] : 0.0;
+            }
         }
 #pragma unroll
         for (int i = 0; i < D; ++i) {

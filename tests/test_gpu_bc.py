@@ -171,6 +171,41 @@ def test_zero_normal_velocity_is_the_slip_wall():
         assert np.allclose(vl, vw, rtol=0, atol=1e-12 * np.abs(vw).max())
 
 
+def test_velocity_load_along_a_wall_parity():
+    """BC hierarchy: a piston face (x = 0) meets a slip floor (z = 0); the
+    edge nodes keep v_z = 0 and meet the piston velocity."""
+    U = 0.4
+    w = W.rotating_cube_3d(n=4, seed=7, omega=0.5)
+    bottom = np.abs(w.x[:, 2]) < 1e-12
+    w.nwall = bottom.astype(np.uint8)
+    w.normals = np.zeros((w.n_nodes, 3, 3))
+    w.normals[bottom, 0, 2] = 1.0
+    face = _faces_on(w, 0, 0.0)
+    on = np.zeros(w.n_nodes, bool)
+    for c, k in face:
+        on[np.delete(w.cells[c], k)] = True
+    val = np.zeros((len(face), 6))
+    val[:, 0] = -U
+    loads = (np.array([f[0] for f in face], np.int32), np.array([f[1] for f in face], np.uint8),
+             np.full(len(face), 2, np.uint8), val)
+    ctx, prob = _pair(w, loads)
+    dt = prob.initial_dt()
+    for n in range(10):
+        ctx.step(dt)
+        s1, vs, mk, oi = prob.step(dt)
+        assert np.array_equal(ctx.query("order"), mk)
+        g = ctx.query("vstar")
+        if n == 0:
+            e = compare_states(ctx, s1, vs)
+            assert max_err(e) <= ONE_STEP, fmt(e)
+        assert np.abs(g[bottom, 2]).max() <= 1e-15 * U
+        assert np.abs(g[on & bottom, 0] - U).max() <= 1e-12 * U
+        dt = oi.dt_next
+    e = compare_states(ctx, prob.state)
+    print(f"[bc wall+piston] 10 steps: {fmt(e)}", flush=True)
+    assert max_err(e) <= MANY, fmt(e)
+
+
 def _same(a, b):
     sa, sb = a.state(), b.state()
     for f in FIELDS:
