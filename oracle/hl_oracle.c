@@ -559,6 +559,16 @@ int orc_set_loads(orc_mesh *M, int64_t n, const int32_t *cell, const uint8_t *fa
     return 0;
 }
 
+/* Replace the wall normals of node p (nw rows of dim components), for
+ * boundary conditions that change type during a run (Section 3.8). */
+int orc_set_node_walls(orc_mesh *M, int64_t p, int nw, const double *normals) {
+    if (p < 0 || p >= M->nn || nw < 0 || nw > 3) return -1;
+    double P[3][3];
+    M->nallow[p] = allowed_basis(M->dim, nw, nw ? normals : NULL, P);
+    memcpy(M->allow + p * 9, P, sizeof P);
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* initial state (Section 4 preamble; reading R25)                    */
 /* ------------------------------------------------------------------ */

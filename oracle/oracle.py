@@ -80,6 +80,8 @@ def lib():
         L.orc_mesh_free.argtypes = [C.c_void_p]
         L.orc_set_loads.restype = C.c_int
         L.orc_set_loads.argtypes = [C.c_void_p, C.c_int64, _I32, _U8, _U8, _P]
+        L.orc_set_node_walls.restype = C.c_int
+        L.orc_set_node_walls.argtypes = [C.c_void_p, C.c_int64, C.c_int, _P]
         L.orc_init_state.restype = C.c_int
         L.orc_init_state.argtypes = [C.c_void_p] + [_P] * 6 + [_P] * 7
         L.orc_step.restype = C.c_int
@@ -328,3 +330,116 @@ class Problem:
                               _ptr(self.m), *[_ptr(a) for a in ins], C.byref(info),
                               float(self.params.shear_a))
         return info.as_dict()
+
+
+class Contact:
+    """Rigid-plane contact with boundary conditions that change type during
+    the run (Section 3.8, "Boundary condition treatments"; reading R30).
+
+    The plane passes through ``point`` with unit ``normal`` pointing from
+    the obstacle into the body.  Each candidate node is free (its own walls
+    only) until it would cross the plane, then a slip wall along the plane
+    (added to its own walls) until its free velocity points away from the
+    plane.  One step (``step``):
+
+    1. a trial step from t^n with the current dt and node conditions;
+    2. detachment: a node in contact whose free velocity -- the nodal
+       solution with its own walls only, from the same corner values --
+       has a positive normal component leaves the plane at t^n; the trial
+       is repeated with the same dt;
+    3. impact: a free node that ends below the plane (g1 < 0, gap
+       g = (x - x_T) . n) reaches it at the fraction s = g0 / (g0 - g1) of
+       the step (s = 0 if g0 <= 0).  If min s <= 1e-9 those nodes go into
+       contact at once and the trial is repeated; otherwise dt is cut to
+       s_min dt, the nodes with s <= s_min (1 + 1e-9) are held pending (and
+       left out of the check), and the trial is repeated;
+    4. otherwise the trial is accepted and pending nodes go into contact
+       from the next step on.  After at most 8 trials the last is accepted
+       and every node still below the plane goes into contact.
+
+    After a cut step the next dt is min(acoustic, volume, (1 + C_i) dt of
+    the uncut trial), so the growth bound does not restart from the cut.
+    """
+
+    S_EPS = 1e-9
+    TIE = 1e-9
+    MAX_TRIALS = 8
+
+    def __init__(self, problem, nodes, point, normal):
+        self.P = problem
+        d = problem.dim
+        self.nodes = np.asarray(nodes, dtype=np.int64)
+        self.xT = _f64(point)[:d].copy()
+        n = _f64(normal)[:d]
+        self.n = n / np.sqrt(np.sum(n * n))
+        self.contact = np.zeros(len(self.nodes), bool)
+        w = problem.w
+        self.own = [np.array(w.normals[p][:int(w.nwall[p])], dtype=np.float64).reshape(-1, d)
+                    for p in self.nodes]
+
+    def _set(self, i, on):
+        rows = self.own[i]
+        if on and rows.shape[0] < self.P.dim:
+            rows = np.vstack([rows, self.n[None, :]])
+        rows = np.ascontiguousarray(rows, dtype=np.float64)
+        rc = lib().orc_set_node_walls(self.P.mesh.h, int(self.nodes[i]), rows.shape[0],
+                                      _ptr(rows) if rows.size else None)
+        assert rc == 0
+
+    def _apply(self):
+        for i in range(len(self.nodes)):
+            self._set(i, bool(self.contact[i]))
+
+    def step(self, dt):
+        """Advance the held state; returns (state, vstar, mask, info,
+        report) with report = dict(dt, dt_next, trials, clipped)."""
+        P = self.P
+        s0 = P.state
+        dt_req = dt
+        pending = np.zeros(len(self.nodes), bool)
+        clipped = False
+        self._apply()
+        for trial in range(1, self.MAX_TRIALS + 1):
+            s1, vs, mk, info = P.step(dt, state=s0)
+            if trial == self.MAX_TRIALS:
+                break
+            idx = np.nonzero(self.contact)[0]
+            if len(idx):
+                for i in idx:
+                    self._set(i, False)
+                _, vfree, _, _ = P.step(dt, mask=mk, replay=True, state=s0)
+                for i in idx:
+                    self._set(i, True)
+                away = vfree[self.nodes[idx]] @ self.n > 0.0
+                if away.any():
+                    for i in idx[away]:
+                        self.contact[i] = False
+                        self._set(i, False)
+                    continue
+            g0 = (s0.x[self.nodes] - self.xT) @ self.n
+            g1 = (s1.x[self.nodes] - self.xT) @ self.n
+            hit = ~self.contact & ~pending & (g1 < 0.0)
+            if not hit.any():
+                break
+            frac = np.where(g0 > 0.0, g0 / np.where(hit, g0 - g1, 1.0), 0.0)
+            smin = frac[hit].min()
+            if smin <= self.S_EPS:
+                for i in np.nonzero(hit & (frac <= self.S_EPS))[0]:
+                    self.contact[i] = True
+                    self._set(i, True)
+                continue
+            pending |= hit & (frac <= smin * (1.0 + self.TIE))
+            dt = smin * dt
+            clipped = True
+        if trial == self.MAX_TRIALS:
+            g1 = (s1.x[self.nodes] - self.xT) @ self.n
+            pending |= ~self.contact & (g1 < 0.0)
+        P.state = s1
+        P.t += dt
+        P.dt_prev = dt
+        self.contact |= pending
+        self._apply()
+        dt_next = info.dt_next
+        if clipped:
+            dt_next = min(info.dt_acoustic, info.dt_volume, (1.0 + P.params.c_i) * dt_req)
+        return s1, vs, mk, info, dict(dt=dt, dt_next=dt_next, trials=trial, clipped=clipped)
