@@ -88,6 +88,9 @@ typedef struct {
     int32_t mood_iters;  /* candidate evaluations (1 = nothing flagged)     */
     int32_t status;      /* 1: some first-order cell is not admissible      */
     int64_t n_limited;   /* cells advanced with limited slopes (cascade 3)  */
+    int64_t n_contact;   /* contact candidates held by the plane afterwards */
+    int32_t trials;      /* step evaluations (> 1: a contact event redid it) */
+    int32_t clipped;     /* 1: dt was cut to a contact impact time          */
 } hl_step_info;
 
 /* Fields for hl_query / hl_upload_field. */
@@ -219,6 +222,38 @@ hl_status hl_step_replay(hl_ctx *ctx, double dt, const uint8_t *mask, int on_dev
  * max_mood_passes: 0..64. */
 hl_status hl_use_graph(hl_ctx *ctx, int on, int max_mood_passes);
 
+/* Rigid-plane contact, a boundary condition that changes type during the
+ * run (Section 3.8, "Boundary condition treatments"; single mesh only).
+ * The plane passes through point[dim] with normal[dim] pointing from the
+ * obstacle into the body (normalised here).  Each of the n candidate nodes
+ * (distinct, in range) is free -- its own walls only -- until it would
+ * cross the plane, then held on it as a slip wall (added to its own walls)
+ * until its free velocity points away.  hl_step then runs trial steps from
+ * t^n:
+ *   - a held node whose free velocity (the nodal solution with its own
+ *     walls only, from the same corner values) has a positive normal
+ *     component is released at t^n and the trial is repeated;
+ *   - a free node ending below the plane (gap g = (x - point) . normal,
+ *     g1 < 0) reaches it at the fraction s = g0 / (g0 - g1) of the step
+ *     (0 if g0 <= 0).  If min s <= 1e-9 those nodes are held at once and
+ *     the trial is repeated; otherwise dt is cut to s_min dt and the nodes
+ *     with s <= s_min (1 + 1e-9) are held from the next step on;
+ *   - after 8 trials the last is accepted and every free node below the
+ *     plane is held from the next step on.
+ * After a cut step the next dt is min(acoustic, volume, (1 + c_i) dt of
+ * the uncut trial).  hl_step_info reports trials, clipped and n_contact;
+ * hl_step_replay does not evolve the contact.  point / normal are host
+ * arrays; nodes is host or device (on_device).  n = 0 removes the contact
+ * and restores every candidate's own walls.  A new mesh drops it;
+ * hl_state_init releases every candidate; hl_forward_record refuses a
+ * context with contact. */
+hl_status hl_set_contact(hl_ctx *ctx, int64_t n, const int32_t *nodes, const double *point,
+                         const double *normal, int on_device);
+
+/* Contact state of the candidates in the order given: [n] uint8, 1 = held
+ * by the plane (n must match). */
+hl_status hl_get_contact(hl_ctx *ctx, uint8_t *state, int64_t n);
+
 /* Stages of the full-mesh part of a step, for launch schedules. */
 enum {
     HL_STAGE_PACK = 0,       /* per cell: gather record of the state */
@@ -267,8 +302,8 @@ hl_status hl_autotune(hl_ctx *ctx, int reps, double *best_ms);
  * recording each step's dt and cascade mask and a state checkpoint every
  * ckpt_every steps (device memory owned by the context).  The adjoint
  * covers the two-level cascade and the neo-Hookean law without boundary
- * loads: with cascade 3, shear_a != -1 or loads set this returns
- * HL_E_INVALID. */
+ * loads or contact: with cascade 3, shear_a != -1, loads or a contact set
+ * this returns HL_E_INVALID. */
 hl_status hl_forward_record(hl_ctx *ctx, int nsteps, int ckpt_every);
 
 /* Re-run the recorded steps from the current state with the recorded dt and

@@ -108,6 +108,22 @@ struct hl_ctx {
         double *val = nullptr;
         std::vector<void *> mem;
     } ld;
+    // rigid-plane contact (own allocations, freed with the mesh)
+    struct {
+        int64_t n = 0;
+        int32_t *node = nullptr;
+        uint8_t *state = nullptr;           // device copy of state_h
+        uint8_t *nal[2] = {nullptr, nullptr};
+        double *alw[2] = {nullptr, nullptr};
+        double *out = nullptr;              // [2n]: s, then vn
+        std::vector<uint8_t> state_h;
+        double xT[3] = {0, 0, 0}, nrm[3] = {0, 0, 0};
+        std::vector<void *> mem;
+    } ct;
+    // statistics of the last step's MOOD loop
+    int64_t last_first = 0;
+    int last_iters = 0;
+    unsigned last_inadm = 0;
     // adjoint tapes (own allocations, freed with the mesh)
     struct {
         int nsteps = 0, every = 0, nckpt = 0;
@@ -184,10 +200,23 @@ void free_loads(hl_ctx *c) {
     c->ld.val = nullptr;
 }
 
+void free_contact(hl_ctx *c) {
+    for (void *p : c->ct.mem) (void)hipFree(p);
+    c->ct.mem.clear();
+    c->ct.n = 0;
+    c->ct.node = nullptr;
+    c->ct.state = nullptr;
+    c->ct.nal[0] = c->ct.nal[1] = nullptr;
+    c->ct.alw[0] = c->ct.alw[1] = nullptr;
+    c->ct.out = nullptr;
+    c->ct.state_h.clear();
+}
+
 void free_all(hl_ctx *c) {
     drop_graphs(c);
     free_tape(c);
     free_loads(c);
+    free_contact(c);
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     if (c->counters_host) (void)hipHostFree(c->counters_host);
@@ -538,6 +567,9 @@ hl_status capture_step(hl_ctx *c, int src) {
 }
 
 template <int D>
+hl_status fill_info(hl_ctx *c, int src, hl_step_info *info);
+
+template <int D>
 hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on_device, hl_step_info *info) {
     hipStream_t s = c->stream;
     const int src = c->cur;
@@ -631,7 +663,24 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
         if ((st = read_counters(c, s)) != HL_OK) return st;
     }
     const unsigned inadm = c->counters_host[hl::CNT_BAD];
+    c->last_first = first;
+    c->last_iters = iters;
+    c->last_inadm = inadm;
+    c->cur = 1 - src;
     if (info) {
+        hl_status st = fill_info<D>(c, src, info);
+        if (st != HL_OK) return st;
+    }
+    return inadm ? HL_WARN_PARACHUTE_INADMISSIBLE : HL_OK;
+}
+
+// Step report of the step just taken from buffer src (statistics of its
+// MOOD loop from the context).
+template <int D>
+hl_status fill_info(hl_ctx *c, int src, hl_step_info *info) {
+    hipStream_t s = c->stream;
+    hl::StepArgs a = make_args(c, src);
+    {
         std::memset(info, 0, sizeof(*info));
         const int dst = 1 - src;
         hl::launch_diag<D>(a, c->tau[dst], c->v[dst], c->e[dst], c->B[dst], c->diag_part, c->diag_out, s);
@@ -654,12 +703,132 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
         info->elastic = d[6];
         info->n_p0 = (int64_t)llround(d[7]);
         info->n_limited = (int64_t)llround(d[8]);
-        info->n_flag_first = first;
-        info->mood_iters = iters;
-        info->status = inadm ? 1 : 0;
+        info->n_flag_first = c->last_first;
+        info->mood_iters = c->last_iters;
+        info->status = c->last_inadm ? 1 : 0;
+        info->trials = 1;
+        for (uint8_t v : c->ct.state_h) info->n_contact += v;
     }
-    c->cur = 1 - src;
-    return inadm ? HL_WARN_PARACHUTE_INADMISSIBLE : HL_OK;
+    return HL_OK;
+}
+
+hl::ContactArgs contact_args(hl_ctx *c) {
+    hl::ContactArgs k{};
+    k.n = c->ct.n;
+    k.node = c->ct.node;
+    k.state = c->ct.state;
+    k.nal[0] = c->ct.nal[0];
+    k.nal[1] = c->ct.nal[1];
+    k.alw[0] = c->ct.alw[0];
+    k.alw[1] = c->ct.alw[1];
+    k.nallow = c->nallow;
+    k.allow = c->allow;
+    for (int i = 0; i < 3; ++i) {
+        k.xT[i] = c->ct.xT[i];
+        k.nrm[i] = c->ct.nrm[i];
+    }
+    k.out_s = c->ct.out;
+    k.out_vn = c->ct.out + c->ct.n;
+    return k;
+}
+
+// upload the host contact states and set the candidates' constraints
+hl_status contact_apply(hl_ctx *c) {
+    hipStream_t s = c->stream;
+    HIPCHK(hipMemcpyAsync(c->ct.state, c->ct.state_h.data(), (size_t)c->ct.n, hipMemcpyHostToDevice, s));
+    hl::launch_contact_apply(contact_args(c), c->dim, s);
+    HIPCHK(hipStreamSynchronize(s));
+    return HL_OK;
+}
+
+// One step with rigid-plane contact (Section 3.8, reading R30): trial
+// steps from t^n until no candidate detaches or crosses the plane; the
+// step that reaches the plane is cut to the impact time.
+template <int D>
+hl_status contact_step(hl_ctx *c, double dt, hl_step_info *info) {
+    constexpr double S_EPS = 1e-9, TIE = 1e-9;
+    constexpr int MAX_TRIALS = 8;
+    hipStream_t s = c->stream;
+    const int src = c->cur;
+    const int64_t n = c->ct.n;
+    if (!(dt > 0.0)) {
+        HIPCHK(hipMemcpyAsync(&dt, c->dt_next, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    const double dt_req = dt;
+    std::vector<uint8_t> pending(n, 0);
+    std::vector<double> out(2 * n);
+    bool clipped = false;
+    hl_status st = contact_apply(c);
+    if (st != HL_OK) return st;
+    hl_status rs = HL_OK;
+    auto evaluate = [&]() -> hl_status {
+        hl::launch_contact_eval<D>(make_args(c, src), contact_args(c), s);
+        HIPCHK(hipMemcpyAsync(out.data(), c->ct.out, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return HL_OK;
+    };
+    int trial = 1;
+    for (;; ++trial) {
+        if (trial > 1) {
+            c->cur = src;
+            c->rec_valid = false;  // the gather records hold the trial's state
+        }
+        rs = run_step<D>(c, dt, nullptr, 0, nullptr);
+        if (rs < 0) return rs;
+        if (trial == MAX_TRIALS) break;
+        if ((st = evaluate()) != HL_OK) return st;
+        // detachment at t^n
+        bool away = false;
+        for (int64_t i = 0; i < n; ++i)
+            if (c->ct.state_h[i] && out[n + i] > 0.0) {
+                c->ct.state_h[i] = 0;
+                away = true;
+            }
+        if (away) {
+            if ((st = contact_apply(c)) != HL_OK) return st;
+            continue;
+        }
+        // impact
+        double smin = 2.0;
+        for (int64_t i = 0; i < n; ++i)
+            if (!c->ct.state_h[i] && !pending[i] && out[i] < 2.0) smin = std::min(smin, out[i]);
+        if (smin >= 2.0) break;
+        if (smin <= S_EPS) {
+            for (int64_t i = 0; i < n; ++i)
+                if (!c->ct.state_h[i] && !pending[i] && out[i] <= S_EPS) c->ct.state_h[i] = 1;
+            if ((st = contact_apply(c)) != HL_OK) return st;
+            continue;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            if (!c->ct.state_h[i] && !pending[i] && out[i] <= smin * (1.0 + TIE)) pending[i] = 1;
+        dt = smin * dt;
+        clipped = true;
+    }
+    if (trial == MAX_TRIALS) {
+        // accepted as is: every free node below the plane goes into contact
+        if ((st = evaluate()) != HL_OK) return st;
+        for (int64_t i = 0; i < n; ++i)
+            if (!c->ct.state_h[i] && out[i] < 2.0) pending[i] = 1;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (pending[i]) c->ct.state_h[i] = 1;
+    if ((st = contact_apply(c)) != HL_OK) return st;
+    if (clipped) {
+        // the growth bound continues from the uncut trial dt
+        double parts[2];
+        HIPCHK(hipMemcpyAsync(parts, c->dt_parts, sizeof parts, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double dn = std::min(std::min(parts[0], parts[1]), (1.0 + c->prm.c_i) * dt_req);
+        HIPCHK(hipMemcpyAsync(c->dt_next, &dn, sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    if (info) {
+        if ((st = fill_info<D>(c, src, info)) != HL_OK) return st;
+        info->trials = trial;
+        info->clipped = clipped ? 1 : 0;
+    }
+    return rs;
 }
 
 // ------------------------------------------------------------- adjoint
@@ -1328,11 +1497,149 @@ hl_status hl_set_boundary_loads(hl_ctx *c, int64_t n, const int32_t *cell, const
     return HL_OK;
 }
 
+hl_status hl_set_contact(hl_ctx *c, int64_t n, const int32_t *nodes, const double *point, const double *normal,
+                         int on_device) {
+    if (!c || n < 0) return HL_E_INVALID;
+    if (!c->have_mesh) return HL_E_STATE;
+    if (n > 0 && (!nodes || !point || !normal || c->n_mesh != 1)) return HL_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    const int d = c->dim, dd = d * d;
+    const int64_t nn = c->nn;
+    std::vector<int32_t> nd(n);
+    double xT[3] = {0, 0, 0}, nr[3] = {0, 0, 0};
+    if (n > 0) {
+        if (on_device)
+            HIPCHK(hipMemcpy(nd.data(), nodes, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+        else
+            std::memcpy(nd.data(), nodes, sizeof(int32_t) * n);
+        std::vector<char> seen(nn, 0);
+        for (int64_t i = 0; i < n; ++i) {
+            if (nd[i] < 0 || nd[i] >= nn || seen[nd[i]]) return HL_E_INVALID;
+            seen[nd[i]] = 1;
+        }
+        double l = 0.0;
+        for (int i = 0; i < d; ++i) {
+            xT[i] = point[i];
+            nr[i] = normal[i];
+            if (!std::isfinite(xT[i]) || !std::isfinite(nr[i])) return HL_E_INVALID;
+            l += nr[i] * nr[i];
+        }
+        l = std::sqrt(l);
+        if (!(l > 0.0)) return HL_E_INVALID;
+        for (int i = 0; i < d; ++i) nr[i] /= l;
+    }
+    // release the previous candidates to their own walls
+    if (c->ct.n > 0) {
+        std::fill(c->ct.state_h.begin(), c->ct.state_h.end(), 0);
+        hl_status st = contact_apply(c);
+        if (st != HL_OK) return st;
+    }
+    drop_graphs(c);
+    free_tape(c);
+    free_contact(c);
+    if (n == 0) return HL_OK;
+    // own allowed directions of each candidate, and those left when the
+    // plane's normal is added (Gram-Schmidt of the own basis against the
+    // normal's projection on it; a projection below 1e-8 adds nothing)
+    std::vector<uint8_t> nal_all(nn);
+    std::vector<double> alw_all((size_t)nn * dd);
+    HIPCHK(hipMemcpy(nal_all.data(), c->nallow, nn, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(alw_all.data(), c->allow, sizeof(double) * nn * dd, hipMemcpyDeviceToHost));
+    std::vector<uint8_t> nal0(n), nal1(n);
+    std::vector<double> alw0((size_t)n * dd), alw1((size_t)n * dd, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t p = nd[i];
+        const int na = nal_all[p];
+        const double *P = alw_all.data() + p * dd;
+        nal0[i] = (uint8_t)na;
+        std::copy(P, P + dd, alw0.begin() + i * dd);
+        double u[3] = {0, 0, 0}, lu = 0.0;
+        for (int t = 0; t < na; ++t) {
+            double s = 0.0;
+            for (int j = 0; j < d; ++j) s += P[j * d + t] * nr[j];
+            for (int j = 0; j < d; ++j) u[j] += s * P[j * d + t];
+        }
+        for (int j = 0; j < d; ++j) lu += u[j] * u[j];
+        lu = std::sqrt(lu);
+        if (lu < 1e-8) {
+            nal1[i] = (uint8_t)na;
+            std::copy(P, P + dd, alw1.begin() + i * dd);
+            continue;
+        }
+        for (int j = 0; j < d; ++j) u[j] /= lu;
+        double Q[3][3];
+        int nq = 0;
+        for (int t = 0; t < na && nq < na - 1; ++t) {
+            double w[3] = {0, 0, 0};
+            for (int j = 0; j < d; ++j) w[j] = P[j * d + t];
+            double s = 0.0;
+            for (int j = 0; j < d; ++j) s += w[j] * u[j];
+            for (int j = 0; j < d; ++j) w[j] -= s * u[j];
+            for (int q = 0; q < nq; ++q) {
+                double r = 0.0;
+                for (int j = 0; j < d; ++j) r += w[j] * Q[q][j];
+                for (int j = 0; j < d; ++j) w[j] -= r * Q[q][j];
+            }
+            double lw = 0.0;
+            for (int j = 0; j < d; ++j) lw += w[j] * w[j];
+            lw = std::sqrt(lw);
+            if (lw < 1e-8) continue;
+            for (int j = 0; j < d; ++j) Q[nq][j] = w[j] / lw;
+            ++nq;
+        }
+        nal1[i] = (uint8_t)nq;
+        for (int q = 0; q < nq; ++q)
+            for (int j = 0; j < d; ++j) alw1[i * dd + j * d + q] = Q[q][j];
+    }
+    auto get = [&](void **p, size_t bytes) -> bool {
+        if (hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess) return false;
+        c->ct.mem.push_back(*p);
+        return true;
+    };
+    auto &ct = c->ct;
+    if (!get((void **)&ct.node, sizeof(int32_t) * n) || !get((void **)&ct.state, n) ||
+        !get((void **)&ct.nal[0], n) || !get((void **)&ct.nal[1], n) ||
+        !get((void **)&ct.alw[0], sizeof(double) * n * dd) || !get((void **)&ct.alw[1], sizeof(double) * n * dd) ||
+        !get((void **)&ct.out, sizeof(double) * 2 * n)) {
+        free_contact(c);
+        return HL_E_OOM;
+    }
+    hipStream_t s = c->stream;
+    hipError_t e = hipMemcpyAsync(ct.node, nd.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ct.nal[0], nal0.data(), n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ct.nal[1], nal1.data(), n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ct.alw[0], alw0.data(), sizeof(double) * n * dd, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ct.alw[1], alw1.data(), sizeof(double) * n * dd, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_contact(c);
+        return hip_fail(e, "contact upload", __LINE__);
+    }
+    ct.n = n;
+    ct.state_h.assign(n, 0);
+    for (int i = 0; i < 3; ++i) {
+        ct.xT[i] = xT[i];
+        ct.nrm[i] = nr[i];
+    }
+    return contact_apply(c);
+}
+
+hl_status hl_get_contact(hl_ctx *c, uint8_t *state, int64_t n) {
+    if (!c || n != c->ct.n || (n > 0 && !state)) return HL_E_INVALID;
+    if (n > 0) std::memcpy(state, c->ct.state_h.data(), n);
+    return HL_OK;
+}
+
 hl_status hl_state_init(hl_ctx *c, const double *rho0, const double *mu, const double *lam, const double *v_cell,
                         const double *v_node, const hl_params *p, int on_device) {
     if (!c) return HL_E_INVALID;
     if (!c->have_mesh) return HL_E_STATE;
     if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    if (c->ct.n > 0) {  // a new state starts with every contact candidate free
+        std::fill(c->ct.state_h.begin(), c->ct.state_h.end(), 0);
+        hl_status st = contact_apply(c);
+        if (st != HL_OK) return st;
+    }
     const int d = c->dim, nv = d + 1, nB = d == 3 ? 6 : 3;
     const size_t nc = (size_t)c->nc, nn = (size_t)c->nn;
     std::vector<double> r, m_, l, vc, vn;
@@ -1433,7 +1740,11 @@ static hl_status step_common(hl_ctx *c, double dt, const uint8_t *mask, int on_d
     if (!c->have_state) return HL_E_STATE;
     if (!std::isfinite(dt)) return HL_E_INVALID;
     if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
-    hl_status st = c->dim == 3 ? run_step<3>(c, dt, mask, on_device, info) : run_step<2>(c, dt, mask, on_device, info);
+    hl_status st;
+    if (c->ct.n > 0 && !mask && c->nc > 0)
+        st = c->dim == 3 ? contact_step<3>(c, dt, info) : contact_step<2>(c, dt, info);
+    else
+        st = c->dim == 3 ? run_step<3>(c, dt, mask, on_device, info) : run_step<2>(c, dt, mask, on_device, info);
     if (c->prof.on) prof_collect(c);
     hipError_t le = hipGetLastError();
     if (le != hipSuccess) return hip_fail(le, "kernel launch", __LINE__);
@@ -1535,10 +1846,10 @@ hl_status hl_upload_field(hl_ctx *c, int field, const void *in, int64_t count, i
 hl_status hl_forward_record(hl_ctx *c, int nsteps, int ckpt_every) {
     if (!c || nsteps < 1 || ckpt_every < 1) return HL_E_INVALID;
     if (!c->have_state) return HL_E_STATE;
-    if (c->prm.cascade == 3 || c->prm.shear_a != -1.0 || c->ld.n > 0) {
+    if (c->prm.cascade == 3 || c->prm.shear_a != -1.0 || c->ld.n > 0 || c->ct.n > 0) {
         std::snprintf(g_last_error, sizeof g_last_error,
                       "the adjoint covers the two-level cascade and the neo-Hookean law without boundary loads "
-                      "(cascade 2, shear_a -1, no loads)");
+                      "or contact (cascade 2, shear_a -1)");
         return HL_E_INVALID;
     }
     if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;

@@ -134,6 +134,26 @@ struct Sched {
                            // each thread has at most one entity (no loop)
 };
 
+// Rigid-plane contact (evolving boundary condition): candidate i is node
+// node[i] in constraint set state[i] (0 its own walls, 1 its own walls and
+// the plane), whose allowed-direction counts and bases (D x D, row-major,
+// columns) are nal[set][i] and alw[set][i D D ..].  The evaluation writes
+// out_s (fraction of the step at which a free candidate reaches the plane,
+// 2 if it does not) and out_vn (free normal velocity of a held candidate).
+struct ContactArgs {
+    int64_t n;
+    const int32_t *node;
+    const uint8_t *state;
+    const uint8_t *nal[2];
+    const double *alw[2];
+    uint8_t *nallow;   // the mesh's per-node constraint arrays (apply)
+    double *allow;
+    double xT[3], nrm[3];
+    double *out_s, *out_vn;
+};
+void launch_contact_apply(const ContactArgs &k, int dim, hipStream_t s);
+template <int D> void launch_contact_eval(const StepArgs &a, const ContactArgs &k, hipStream_t s);
+
 template <int D> void launch_centroids(const StepArgs &a, const Sched &k, hipStream_t s);
 template <int D> void launch_node_agg(const StepArgs &a, const Sched &k, hipStream_t s);
 template <int D> void launch_predict(const StepArgs &a, const Sched &k, hipStream_t s);

@@ -578,10 +578,16 @@ __device__ __forceinline__ void sym6_unpack(const double *v, double (&T)[D][D]) 
         if (row[q] < D && col[q] < D) T[row[q]][col[q]] = T[col[q]][row[q]] = v[q];
 }
 
-template <int D, bool LD>
-__device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t p) {
+// M_p and the corner part of r_p, summed over the node's corners in CSR
+// order by one thread; returns whether the node has corners
+template <int D>
+__device__ __forceinline__ bool node_gather(const StepArgs &a, const int64_t p, double (&M)[Dims<D>::NMS],
+                                            double (&r)[D]) {
     using Dm = Dims<D>;
-    double M[Dm::NMS] = {}, r[D] = {};
+#pragma unroll
+    for (int s = 0; s < Dm::NMS; ++s) M[s] = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) r[i] = 0.0;
     const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
     for (int32_t q = q0; q < q1; ++q) {
         const double *rec = a.corner + corner_slot_of<D>(a.n2c[q]) * Dm::CW;
@@ -590,7 +596,14 @@ __device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t 
 #pragma unroll
         for (int i = 0; i < D; ++i) r[i] += rec[Dm::NMS + i];
     }
-    node_solve_finish<D, LD>(a, p, q1 > q0, M, r, -1);
+    return q1 > q0;
+}
+
+template <int D, bool LD>
+__device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t p) {
+    double M[Dims<D>::NMS], r[D];
+    const bool any = node_gather<D>(a, p, M, r);
+    node_solve_finish<D, LD>(a, p, any, M, r, -1);
 }
 
 // Cooperative corner gather (as for the node aggregates): lane l of a group
@@ -635,17 +648,18 @@ __device__ __forceinline__ void node_solve_group(const StepArgs &a, const int64_
     node_solve_finish<D, LD>(a, p, q1 > q0, M, r, l);
 }
 
-// v* from the summed corner matrices and right-hand sides; comp < 0 writes
-// every component, otherwise only component comp (if < D).  LD: the mesh
-// has boundary loads (a separate instantiation keeps the plain solve's
-// register budget).
+// Node velocity from the summed corner matrices and right-hand sides, with
+// na allowed directions P (na == D: free).  LD: the mesh has boundary loads
+// (a separate instantiation keeps the plain solve's register budget).
 template <int D, bool LD>
-__device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64_t p, const bool any,
-                                                  const double (&M)[Dims<D>::NMS], const double (&r)[D],
-                                                  const int comp) {
+__device__ __forceinline__ void node_velocity(const StepArgs &a, const int64_t p, const bool any,
+                                              const double (&M)[Dims<D>::NMS], const double (&r)[D], const int na,
+                                              const double *P, double (&vs)[D]) {
     using Dm = Dims<D>;
     const int64_t nn = a.nn;
-    double vs[D] = {}, rl[D], dl[D] = {}, vn = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) vs[i] = 0.0;
+    double rl[D], dl[D] = {}, vn = 0.0;
     bool has_v = false;
 #pragma unroll
     for (int i = 0; i < D; ++i) rl[i] = r[i];
@@ -690,7 +704,6 @@ __device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64
             }
         }
     }
-    const int na = a.nallow[p];
     if (any && na == D) {
         double inv[Dm::NMS];
         if (D == 3)
@@ -721,8 +734,7 @@ __device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64
             for (int i = 0; i < D; ++i) vs[i] -= pi * z[i];
         }
     } else if (any && na > 0) {
-        // P: D x na orthonormal columns, P[i][t] = allow[p*D*D + i*D + t]
-        const double *P = a.allow + p * D * D;
+        // P: D x na orthonormal columns, P[i][t] = P[i*D + t]
         double Mf[D][D];
 #pragma unroll
         for (int i = 0; i < D; ++i)
@@ -791,6 +803,17 @@ __device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64
             vs[i] = s;
         }
     }
+}
+
+// v* of node p under its current constraints, then x^{n+1} and vhat^{n+1};
+// comp < 0 writes every component, otherwise only component comp (if < D)
+template <int D, bool LD>
+__device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64_t p, const bool any,
+                                                  const double (&M)[Dims<D>::NMS], const double (&r)[D],
+                                                  const int comp) {
+    const int64_t nn = a.nn;
+    double vs[D];
+    node_velocity<D, LD>(a, p, any, M, r, a.nallow[p], a.allow + p * D * D, vs);
     const double dt = mesh_dt(a.dt, a.node_mesh, p);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -822,6 +845,50 @@ template <int D, bool LD>
 __global__ __launch_bounds__(256) void k_node_solve_list(StepArgs a) {
     const int64_t n = a.counters[CNT_NODES];
     for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) node_solve_one<D, LD>(a, a.nlist[i]);
+}
+
+// ------------------------------------------------------------ contact
+// Candidate i of a rigid-plane contact takes constraint set state[i]: 0 its
+// own walls, 1 its own walls and the plane (Section 3.8, reading R30).
+__global__ void k_contact_apply(ContactArgs k, int dd) {
+    const int64_t i = gtid();
+    if (i >= k.n) return;
+    const int s = k.state[i] ? 1 : 0;
+    const int64_t p = k.node[i];
+    k.nallow[p] = k.nal[s][i];
+    for (int j = 0; j < dd; ++j) k.allow[p * dd + j] = k.alw[s][i * dd + j];
+}
+
+// After a trial step: for a free candidate the fraction of the step at
+// which it reaches the plane, s = g0 / (g0 - g1) with the gaps
+// g = (x - x_T) . n at t^n and at the trial's t^{n+1} (0 if g0 <= 0; 2 when
+// it stays above the plane); for a candidate in contact the normal
+// component of its free velocity (its own walls only, same corner values).
+template <int D, bool LD>
+__global__ __launch_bounds__(256) void k_contact_eval(StepArgs a, ContactArgs k) {
+    const int64_t i = gtid();
+    if (i >= k.n) return;
+    const int64_t p = k.node[i];
+    const int64_t nn = a.nn;
+    if (k.state[i]) {
+        double M[Dims<D>::NMS], r[D], vs[D];
+        const bool any = node_gather<D>(a, p, M, r);
+        node_velocity<D, LD>(a, p, any, M, r, k.nal[0][i], k.alw[0] + i * D * D, vs);
+        double vn = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) vn += vs[j] * k.nrm[j];
+        k.out_s[i] = 2.0;
+        k.out_vn[i] = vn;
+    } else {
+        double g0 = 0.0, g1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            g0 += (a.x[j * nn + p] - k.xT[j]) * k.nrm[j];
+            g1 += (a.x1[j * nn + p] - k.xT[j]) * k.nrm[j];
+        }
+        k.out_s[i] = g1 < 0.0 ? (g0 > 0.0 ? g0 / (g0 - g1) : 0.0) : 2.0;
+        k.out_vn[i] = 0.0;
+    }
 }
 
 // -------------------------------------------------------- cell update
@@ -1388,6 +1455,17 @@ void launch_node_solve(const StepArgs &a, const Sched &k, hipStream_t s) {
         ld ? k_node_solve<D, false, true><<<k.grid, k.block, 0, s>>>(a, k.w)
            : k_node_solve<D, false, false><<<k.grid, k.block, 0, s>>>(a, k.w);
 }
+void launch_contact_apply(const ContactArgs &k, int dim, hipStream_t s) {
+    if (k.n) k_contact_apply<<<nblk(k.n), 256, 0, s>>>(k, dim * dim);
+}
+template <int D>
+void launch_contact_eval(const StepArgs &a, const ContactArgs &k, hipStream_t s) {
+    if (!k.n) return;
+    if (a.ld_off)
+        k_contact_eval<D, true><<<nblk(k.n), 256, 0, s>>>(a, k);
+    else
+        k_contact_eval<D, false><<<nblk(k.n), 256, 0, s>>>(a, k);
+}
 template <int D>
 void launch_update(const StepArgs &a, const Sched &k, hipStream_t s) {
     if (!k.w.n_items) return;
@@ -1473,6 +1551,8 @@ template void launch_node_agg<2>(const StepArgs &, const Sched &, hipStream_t);
 template void launch_node_agg<3>(const StepArgs &, const Sched &, hipStream_t);
 template void launch_predict<2>(const StepArgs &, const Sched &, hipStream_t);
 template void launch_predict<3>(const StepArgs &, const Sched &, hipStream_t);
+template void launch_contact_eval<2>(const StepArgs &, const ContactArgs &, hipStream_t);
+template void launch_contact_eval<3>(const StepArgs &, const ContactArgs &, hipStream_t);
 template void launch_node_solve<2>(const StepArgs &, const Sched &, hipStream_t);
 template void launch_node_solve<3>(const StepArgs &, const Sched &, hipStream_t);
 template void launch_update<2>(const StepArgs &, const Sched &, hipStream_t);

@@ -26,7 +26,8 @@ EXPORTS = ["hl_create", "hl_destroy", "hl_mesh_upload", "hl_state_init", "hl_set
            "hl_profile_enable", "hl_profile_reset", "hl_profile_get", "hl_status_str",
            "hl_last_error", "hl_mesh_upload_batch", "hl_step_batch", "hl_query_dt", "hl_use_graph",
            "hl_forward_record", "hl_forward_replay", "hl_adjoint_run", "hl_tape_get",
-           "hl_set_schedule", "hl_get_schedule", "hl_autotune", "hl_set_boundary_loads"]
+           "hl_set_schedule", "hl_get_schedule", "hl_autotune", "hl_set_boundary_loads",
+           "hl_set_contact", "hl_get_contact"]
 
 # stages of the full-mesh part of a step (launch schedules)
 STAGES = ("pack", "node_agg", "predict", "node_solve", "update")
@@ -51,14 +52,16 @@ class StepInfo(C.Structure):
                 ("dt_volume", C.c_double), ("mass", C.c_double), ("mom", C.c_double * 3),
                 ("energy", C.c_double), ("kinetic", C.c_double), ("elastic", C.c_double),
                 ("n_p0", C.c_int64), ("n_flag_first", C.c_int64), ("mood_iters", C.c_int32),
-                ("status", C.c_int32), ("n_limited", C.c_int64)]
+                ("status", C.c_int32), ("n_limited", C.c_int64), ("n_contact", C.c_int64),
+                ("trials", C.c_int32), ("clipped", C.c_int32)]
 
     def as_dict(self):
         return dict(dt_used=self.dt_used, dt_next=self.dt_next, dt_acoustic=self.dt_acoustic,
                     dt_volume=self.dt_volume, mass=self.mass, mom=list(self.mom),
                     energy=self.energy, kinetic=self.kinetic, elastic=self.elastic,
                     n_p0=self.n_p0, n_flag_first=self.n_flag_first,
-                    mood_iters=self.mood_iters, status=self.status, n_limited=self.n_limited)
+                    mood_iters=self.mood_iters, status=self.status, n_limited=self.n_limited,
+                    n_contact=self.n_contact, trials=self.trials, clipped=self.clipped)
 
 
 class Schedule(C.Structure):
@@ -108,6 +111,8 @@ def load():
     L.hl_state_init.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(Params), C.c_int]
     L.hl_set_params.argtypes = [vp, C.POINTER(Params)]
     L.hl_set_boundary_loads.argtypes = [vp, i64, vp, vp, vp, vp, C.c_int]
+    L.hl_set_contact.argtypes = [vp, i64, vp, vp, vp, C.c_int]
+    L.hl_get_contact.argtypes = [vp, vp, i64]
     L.hl_compute_dt.argtypes = [vp, C.POINTER(dp)]
     L.hl_step.argtypes = [vp, dp, C.POINTER(StepInfo)]
     L.hl_step_replay.argtypes = [vp, dp, vp, C.c_int, C.POINTER(StepInfo)]
@@ -187,6 +192,7 @@ class Context:
         nc = int(cells.shape[0])
         _check(load().hl_mesh_upload(self._h, int(dim), nn, px, nc, pc, pw, pn, dev),
                "hl_mesh_upload")
+        self._n_contact = 0
         self.dim, self.n_nodes, self.n_cells = int(dim), nn, nc
 
     def upload_mesh_batch(self, dim, node_offsets, cell_offsets, x, cells, nwall=None, normals=None):
@@ -253,6 +259,30 @@ class Context:
         if not dev == df == dk == dv:
             raise ValueError("boundary load arrays must all be on the host or all on the device")
         _check(load().hl_set_boundary_loads(self._h, n, pc, pf, pk, pv, dev), "hl_set_boundary_loads")
+
+    def set_contact(self, nodes=None, point=None, normal=None):
+        """Rigid-plane contact for the candidate ``nodes`` (plane through
+        ``point``, ``normal`` pointing into the body).  No arguments remove
+        it."""
+        if nodes is None or len(nodes) == 0:
+            _check(load().hl_set_contact(self._h, 0, None, None, None, 0), "hl_set_contact")
+            self._n_contact = 0
+            return
+        pn, kn, dev = _arg(nodes, np.int32)
+        pt = np.ascontiguousarray(point, dtype=np.float64)
+        nr = np.ascontiguousarray(normal, dtype=np.float64)
+        if pt.size < self.dim or nr.size < self.dim:
+            raise ValueError("point and normal need dim components")
+        _check(load().hl_set_contact(self._h, len(nodes), pn, pt.ctypes.data_as(C.c_void_p),
+                                     nr.ctypes.data_as(C.c_void_p), dev), "hl_set_contact")
+        self._n_contact = len(nodes)
+
+    def contact_state(self):
+        n = getattr(self, "_n_contact", 0)
+        out = np.zeros(n, np.uint8)
+        _check(load().hl_get_contact(self._h, out.ctypes.data_as(C.c_void_p) if n else None, n),
+               "hl_get_contact")
+        return out.astype(bool)
 
     def compute_dt(self):
         dt = C.c_double()
