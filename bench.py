@@ -194,22 +194,28 @@ def batch_measure(steps=5, warmup=2, n_meshes=256, autotune=True):
             "speedup": ts / tb, "schedules": tuned}
 
 
-def variant_measure(ctx, w, steps, warmup, graph, name, **params):
-    """The same workload from t = 0 with other scheme parameters: the
+def variant_measure(ctx, w, steps, warmup, graph, name, setup=None, **params):
+    """The same workload from t = 0 with other scheme parameters -- the
     three-level cascade P1 -> P1 with the Barth-Jespersen limiter -> P0
-    (Section 3.5), or another member of the shear energy family (eq.
-    familiy_energies)."""
+    (Section 3.5), another member of the shear energy family (eq.
+    familiy_energies) -- or with boundary conditions added by ``setup(ctx)``
+    (Section 3.8: loads, contact), which must undo them when called with
+    ``None``."""
     import torch
     from paper_2104_02139_amd import hyperlag as H
     ctx.init_state(w.rho0, w.mu, w.lam, w.v_cell, w.v_node,
                    H.default_params(w.dim, c_cfl=w.c_cfl, **params))
+    if setup:
+        setup(ctx)
     ctx.use_graph(graph, 6)
-    lim, p0, it = [], [], []
+    lim, p0, it, tr, clip = [], [], [], [], 0
     for _ in range(warmup):
         inf = ctx.step(0.0, info=True)
         lim.append(inf["n_limited"])
         p0.append(inf["n_p0"])
         it.append(inf["mood_iters"])
+        tr.append(inf["trials"])
+        clip += inf["clipped"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -220,11 +226,58 @@ def variant_measure(ctx, w, steps, warmup, graph, name, **params):
     lim.append(inf["n_limited"])
     p0.append(inf["n_p0"])
     it.append(inf["mood_iters"])
-    return {"variant": name, "steps": steps, "ms_per_step": 1e3 * el / steps,
-            "cell_updates_per_s": w.n_cells * steps / el,
-            "limited_frac_mean": sum(lim) / len(lim) / w.n_cells,
-            "first_order_frac_mean": sum(p0) / len(p0) / w.n_cells,
-            "mood_iters_mean": sum(it) / len(it)}
+    out = {"variant": name, "steps": steps, "ms_per_step": 1e3 * el / steps,
+           "cell_updates_per_s": w.n_cells * steps / el,
+           "limited_frac_mean": sum(lim) / len(lim) / w.n_cells,
+           "first_order_frac_mean": sum(p0) / len(p0) / w.n_cells,
+           "mood_iters_mean": sum(it) / len(it)}
+    if setup:
+        out["untimed_steps_trials_mean"] = sum(tr) / max(len(tr), 1)
+        out["untimed_steps_clipped"] = clip
+        out["n_contact_after"] = inf["n_contact"]
+        setup(None)
+    return out
+
+
+def bar_loads(w):
+    """Boundary loads on the impact bar: the far end (x = 4) pushed at the
+    impact speed (outward normal velocity -150 m/s) and a shear traction
+    T13 = 10 MPa on the top face (z = 1)."""
+    import numpy as np
+    from paper_2104_02139_amd import workloads as W
+    ce, fe = W.plane_faces(w, 0, 4.0)
+    ct, ft = W.plane_faces(w, 2, 1.0)
+    val = np.zeros((len(ce) + len(ct), 6))
+    val[:len(ce), 0] = -150.0
+    val[len(ce):, 4] = 1e7
+    kind = np.concatenate([np.full(len(ce), 2), np.full(len(ct), 1)]).astype(np.uint8)
+    loads = (np.concatenate([ce, ct]), np.concatenate([fe, ft]), kind, val)
+    holder = {}
+
+    def setup(ctx):
+        if ctx is None:
+            holder["ctx"].set_boundary_loads()
+            return
+        ctx.set_boundary_loads(*loads)
+        holder["ctx"] = ctx
+    return setup
+
+
+def bar_lid(w, gap=2e-5):
+    """Rigid lid above the bar: the plane z = 1 + gap (normal -z) with the
+    top-face nodes as contact candidates; the bulge of the impact end
+    reaches it within the first steps."""
+    import numpy as np
+    nodes = np.nonzero(np.abs(w.x[:, 2] - 1.0) < 1e-12)[0].astype(np.int32)
+    holder = {}
+
+    def setup(ctx):
+        if ctx is None:
+            holder["ctx"].set_contact()
+            return
+        ctx.set_contact(nodes, [0.0, 0.0, 1.0 + gap], [0.0, 0.0, -1.0])
+        holder["ctx"] = ctx
+    return setup
 
 
 def adjoint_measure(n=32, steps=200, every=20):
@@ -402,6 +455,13 @@ def main():
             variant_measure(ctx, w, args.steps, args.warmup, not args.eager,
                             "shear energy a=0", shear_a=0.0),
         ]
+        if w.dim == 3 and name.startswith("impact_bar"):
+            out["variants"] += [
+                variant_measure(ctx, w, args.steps, args.warmup, not args.eager,
+                                "boundary loads (far-end velocity, top traction)", setup=bar_loads(w)),
+                variant_measure(ctx, w, args.steps, args.warmup, not args.eager,
+                                "contact lid over the top face", setup=bar_lid(w)),
+            ]
     if not args.no_adjoint:
         print("[bench] adjoint vs forward on the identification cube", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_measure()

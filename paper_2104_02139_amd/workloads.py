@@ -326,6 +326,21 @@ def plane_wave_3d(n=8, jitter=0.15, amp=1e-6, seed=0):
                     v_cell, v_node, 0.25, 0, meta=dict(amp=amp, n=n, c=2.0))
 
 
+def plane_faces(w, axis, value, tol=1e-12):
+    """Faces of ``w`` whose nodes all have coordinate ``axis`` equal to
+    ``value`` (a planar side of a box mesh): (cells int32, local face
+    uint8), face k being the one opposite the cell's k-th node."""
+    on = np.abs(w.x[:, axis] - value) < tol
+    onc = on[w.cells]
+    cells, faces = [], []
+    for k in range(w.dim + 1):
+        m = np.all(np.delete(onc, k, axis=1), axis=1)
+        idx = np.nonzero(m)[0]
+        cells.append(idx)
+        faces.append(np.full(len(idx), k))
+    return np.concatenate(cells).astype(np.int32), np.concatenate(faces).astype(np.uint8)
+
+
 def shear_modulus_field(nc, mu0=8.2e5, sigma=0.2, seed=1):
     """Per-cell shear modulus mu0 * clip(exp(sigma g), 0.5, 2), g ~ N(0,1)."""
     rng = np.random.Generator(np.random.PCG64(seed))
