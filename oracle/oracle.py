@@ -443,3 +443,113 @@ class Contact:
         if clipped:
             dt_next = min(info.dt_acoustic, info.dt_volume, (1.0 + P.params.c_i) * dt_req)
         return s1, vs, mk, info, dict(dt=dt, dt_next=dt_next, trials=trial, clipped=clipped)
+
+
+def refine(dim, x, cells, nwall, normals, levels=1):
+    """Conforming red refinement, ``levels`` times (Section 3.9: the local
+    1 -> 8 split of every tetrahedron; 1 -> 4 for triangles), in plain
+    Python over the cells.  Conventions (they fix the numbering):
+
+    - edges are numbered in increasing (min node, max node) order; the
+      midpoint of edge e is node nn + e, at 0.5 (x_p + x_q);
+    - a midpoint keeps the wall normals of its first end node (the smaller
+      number) that the other end node also has (unit normals with dot
+      product >= 1 - 1e-12), at most dim of them;
+    - the children of cell c are 8c .. 8c+7: the corner tetrahedra at v0,
+      v1, v2, v3, each made of its vertex and the midpoints of its three
+      edges in the parent's vertex order, then the four tetrahedra around
+      the shortest diagonal of the inner octahedron -- diagonal
+      (m01, m23), (m02, m13) or (m03, m12), the first if lengths tie --
+      each made of the diagonal and two consecutive midpoints of the cycle
+      of the other four: the cycle starts at the first of them in edge
+      order (01, 02, 03, 12, 13, 23) and each next one is the first
+      remaining whose edge shares a vertex of the parent with the last;
+    - in 2D the children are 4c .. 4c+3: (v0, m01, m02), (m01, v1, m12),
+      (m02, m12, v2), (m01, m12, m02);
+    - a child of negative measure has its last two nodes swapped.
+    """
+    x = np.array(x, dtype=np.float64)
+    cells = np.array(cells, dtype=np.int64)
+    nwall = np.array(nwall, dtype=np.uint8)
+    normals = np.array(normals, dtype=np.float64).reshape(len(x), dim, dim)
+    for _ in range(levels):
+        x, cells, nwall, normals = _refine_once(dim, x, cells, nwall, normals)
+    return x, cells.astype(np.int32), nwall, normals
+
+
+def _measure(dim, P):
+    e = [[P[k + 1][j] - P[0][j] for j in range(dim)] for k in range(dim)]
+    if dim == 2:
+        return e[0][0] * e[1][1] - e[0][1] * e[1][0]
+    return (e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) - e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0])
+            + e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]))
+
+
+def _refine_once(dim, x, cells, nwall, normals):
+    nn = len(x)
+    nv = dim + 1
+    keys = set()
+    for c in cells:
+        for a in range(nv):
+            for b in range(a + 1, nv):
+                p, q = int(c[a]), int(c[b])
+                keys.add((min(p, q), max(p, q)))
+    order = sorted(keys)
+    eid = {k: i for i, k in enumerate(order)}
+    ne = len(order)
+    xo = np.zeros((nn + ne, dim))
+    xo[:nn] = x
+    nw = np.zeros(nn + ne, np.uint8)
+    nr = np.zeros((nn + ne, dim, dim))
+    nw[:nn] = nwall
+    nr[:nn] = normals
+    for (p, q), e in eid.items():
+        for j in range(dim):
+            xo[nn + e, j] = 0.5 * (x[p, j] + x[q, j])
+        cnt = 0
+        for r in range(int(nwall[p])):
+            n_p = normals[p, r]
+            if any(float(np.dot(n_p, normals[q, t])) >= 1.0 - 1e-12 for t in range(int(nwall[q]))) and cnt < dim:
+                nr[nn + e, cnt] = n_p
+                cnt += 1
+        nw[nn + e] = cnt
+
+    def mid(c, a, b):
+        p, q = int(c[a]), int(c[b])
+        return nn + eid[(min(p, q), max(p, q))]
+
+    def put(out, nodes):
+        nodes = list(nodes)
+        if _measure(dim, [xo[k] for k in nodes]) < 0.0:
+            nodes[-2], nodes[-1] = nodes[-1], nodes[-2]
+        out.append(nodes)
+
+    out = []
+    for c in cells:
+        v = [int(k) for k in c]
+        if dim == 2:
+            m01, m02, m12 = mid(c, 0, 1), mid(c, 0, 2), mid(c, 1, 2)
+            for t in ((v[0], m01, m02), (m01, v[1], m12), (m02, m12, v[2]), (m01, m12, m02)):
+                put(out, t)
+            continue
+        m = {(a, b): mid(c, a, b) for a in range(4) for b in range(a + 1, 4)}
+        for k in range(4):
+            put(out, [v[k] if j == k else m[(min(j, k), max(j, k))] for j in range(4)])
+        diags = [((0, 1), (2, 3)), ((0, 2), (1, 3)), ((0, 3), (1, 2))]
+
+        def sq(a, b):
+            d = [xo[m[a]][j] - xo[m[b]][j] for j in range(3)]
+            return d[0] * d[0] + d[1] * d[1] + d[2] * d[2]
+
+        lens = [sq(a, b) for a, b in diags]
+        i = min(range(3), key=lambda t: (lens[t], t))
+        da, db = diags[i]
+        rest = [e for e in m if e not in (da, db)]
+        # cycle of the other four: consecutive midpoints share a parent vertex
+        cyc = [rest[0]]
+        while len(cyc) < 4:
+            nxt = [e for e in rest if e not in cyc and set(e) & set(cyc[-1])]
+            cyc.append(nxt[0])
+        for j in range(4):
+            put(out, [m[da], m[db], m[cyc[j]], m[cyc[(j + 1) % 4]]])
+    return xo, np.array(out, dtype=np.int64), nw, nr
