@@ -144,6 +144,30 @@ hl_status hl_mesh_upload(hl_ctx *ctx, int dim, int64_t n_nodes, const double *x0
                          int64_t n_cells, const int32_t *cells, const uint8_t *nwall,
                          const double *normals, int on_device);
 
+/* Conforming red refinement of the uploaded mesh, `levels` times (0..4),
+ * computed on the GPU (edge numbering by a device radix sort).  This is the
+ * local 1 -> 8 refinement the paper applies to the partitions of a coarse
+ * mesh (Section 3.9, "Implementation considerations").  Each tetrahedron
+ * becomes 4 corner tetrahedra and 4 tetrahedra of its inner octahedron,
+ * split along the octahedron's shortest diagonal (squared length without
+ * fused operations, ties to the first of (m01,m23), (m02,m13), (m03,m12));
+ * each triangle becomes 4.  Children of cell c are cells 8c .. 8c+7
+ * (4c .. 4c+3 in 2D); the midpoint of an edge is a new node numbered after
+ * the old ones in the order of the edges' (min node, max node) keys, at
+ * 0.5 (x_p + x_q), with the wall normals its two end nodes share.  Every
+ * child is positively oriented (the last two nodes are swapped where
+ * needed).  Replaces the mesh and discards the state (per-cell inputs of
+ * hl_state_init then follow the child order).  Single-mesh contexts. */
+hl_status hl_mesh_refine(hl_ctx *ctx, int levels);
+
+/* Dimension and sizes of the held mesh (any pointer may be NULL). */
+hl_status hl_mesh_info(hl_ctx *ctx, int *dim, int64_t *n_nodes, int64_t *n_cells);
+
+/* Copy out the held mesh in its reference configuration: x [n_nodes][dim],
+ * cells [n_cells][dim+1], nwall [n_nodes], normals [n_nodes][dim][dim];
+ * any pointer may be NULL; on_device: the destinations are device memory. */
+hl_status hl_mesh_get(hl_ctx *ctx, double *x, int32_t *cells, uint8_t *nwall, double *normals, int on_device);
+
 /* Initial state (Section 4 preamble): tau = 1/rho0, B = I, v_c = v_cell,
  * e = |v_c|^2 / 2, m_c = rho0 V_c, carried node velocity = v_node projected
  * on the directions its walls allow.  Material per cell: rho0, shear

@@ -58,8 +58,9 @@ struct hl_ctx {
     int32_t *c2n = nullptr, *n2c_off = nullptr, *n2c = nullptr;
     uint8_t *nallow = nullptr;
     double *allow = nullptr;
-    std::vector<double> x0_host;
+    std::vector<double> x0_host, nrm_host;
     std::vector<int32_t> c2n_host;
+    std::vector<uint8_t> nw_host;
     std::vector<int64_t> cell_off_host, node_off_host;
     int32_t *cell_mesh = nullptr, *node_mesh = nullptr;
     // material
@@ -1368,6 +1369,8 @@ hl_status upload_impl(hl_ctx *c, int dim, int n_mesh, const std::vector<int64_t>
     c->stamp_host = 0;
     c->x0_host.swap(xh);
     c->c2n_host.swap(ch);
+    c->nw_host.swap(nw);
+    c->nrm_host.swap(nrm);
     c->cur = 0;
     c->prm = default_params(dim);
     c->have_mesh = true;
@@ -1414,6 +1417,90 @@ hl_status hl_mesh_upload_batch(hl_ctx *c, int dim, int n_meshes, const int64_t *
             h.cells[q] = (int32_t)g;
         }
     return upload_impl(c, dim, n_meshes, no, co, h);
+}
+
+hl_status hl_mesh_refine(hl_ctx *c, int levels) {
+    if (!c || levels < 0 || levels > 4) return HL_E_INVALID;
+    if (!c->have_mesh) return HL_E_STATE;
+    if (c->n_mesh != 1) return HL_E_INVALID;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    const int d = c->dim, nv = d + 1, dd = d * d;
+    HostMesh h;
+    h.x = c->x0_host;
+    h.cells = c->c2n_host;
+    h.nw = c->nw_host;
+    h.nrm = c->nrm_host;
+    for (int l = 0; l < levels; ++l) {
+        const int64_t nn = (int64_t)h.nw.size(), nc = (int64_t)h.cells.size() / nv;
+        std::vector<double> xo;
+        std::vector<int32_t> co;
+        std::vector<uint64_t> ed;
+        hipError_t e = d == 3 ? hl::refine_once<3>(nn, nc, h.x.data(), h.cells.data(), c->stream, xo, co, ed)
+                              : hl::refine_once<2>(nn, nc, h.x.data(), h.cells.data(), c->stream, xo, co, ed);
+        if (e != hipSuccess) return hip_fail(e, "mesh refinement", __LINE__);
+        // a midpoint keeps the wall normals its two end nodes share
+        const int64_t ne = (int64_t)ed.size();
+        std::vector<uint8_t> nw((size_t)(nn + ne), 0);
+        std::vector<double> nrm((size_t)(nn + ne) * dd, 0.0);
+        std::copy(h.nw.begin(), h.nw.end(), nw.begin());
+        std::copy(h.nrm.begin(), h.nrm.end(), nrm.begin());
+        for (int64_t k = 0; k < ne; ++k) {
+            const int64_t p = (int64_t)(ed[k] >> 32), q = (int64_t)(ed[k] & 0xffffffffu);
+            int cnt = 0;
+            for (int r = 0; r < h.nw[p]; ++r) {
+                const double *np_ = h.nrm.data() + p * dd + r * d;
+                bool shared = false;
+                for (int t = 0; t < h.nw[q] && !shared; ++t) {
+                    const double *nq = h.nrm.data() + q * dd + t * d;
+                    double dot = 0.0;
+                    for (int i = 0; i < d; ++i) dot += np_[i] * nq[i];
+                    shared = dot >= 1.0 - 1e-12;
+                }
+                if (shared && cnt < d) {
+                    for (int i = 0; i < d; ++i) nrm[(nn + k) * dd + cnt * d + i] = np_[i];
+                    ++cnt;
+                }
+            }
+            nw[nn + k] = (uint8_t)cnt;
+        }
+        h.x.swap(xo);
+        h.cells.swap(co);
+        h.nw.swap(nw);
+        h.nrm.swap(nrm);
+    }
+    const int64_t nn = (int64_t)h.nw.size(), nc = (int64_t)h.cells.size() / nv;
+    std::vector<int64_t> no = {0, nn}, cof = {0, nc};
+    return upload_impl(c, d, 1, no, cof, h);
+}
+
+hl_status hl_mesh_info(hl_ctx *c, int *dim, int64_t *n_nodes, int64_t *n_cells) {
+    if (!c) return HL_E_INVALID;
+    if (!c->have_mesh) return HL_E_STATE;
+    if (dim) *dim = c->dim;
+    if (n_nodes) *n_nodes = c->nn;
+    if (n_cells) *n_cells = c->nc;
+    return HL_OK;
+}
+
+hl_status hl_mesh_get(hl_ctx *c, double *x, int32_t *cells, uint8_t *nwall, double *normals, int on_device) {
+    if (!c) return HL_E_INVALID;
+    if (!c->have_mesh) return HL_E_STATE;
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    const hipMemcpyKind k = on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+    auto put = [&](void *dst, const void *src, size_t bytes) -> hl_status {
+        if (!dst || !bytes) return HL_OK;
+        if (on_device) {
+            HIPCHK(hipMemcpy(dst, src, bytes, k));
+        } else {
+            std::memcpy(dst, src, bytes);
+        }
+        return HL_OK;
+    };
+    hl_status st;
+    if ((st = put(x, c->x0_host.data(), sizeof(double) * c->x0_host.size())) != HL_OK) return st;
+    if ((st = put(cells, c->c2n_host.data(), sizeof(int32_t) * c->c2n_host.size())) != HL_OK) return st;
+    if ((st = put(nwall, c->nw_host.data(), c->nw_host.size())) != HL_OK) return st;
+    return put(normals, c->nrm_host.data(), sizeof(double) * c->nrm_host.size());
 }
 
 hl_status hl_set_params(hl_ctx *c, const hl_params *p) {

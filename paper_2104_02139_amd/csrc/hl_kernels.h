@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "hyperlag.h"
 
 namespace hl {
@@ -153,6 +155,14 @@ struct ContactArgs {
 };
 void launch_contact_apply(const ContactArgs &k, int dim, hipStream_t s);
 template <int D> void launch_contact_eval(const StepArgs &a, const ContactArgs &k, hipStream_t s);
+
+// One level of conforming red refinement on the device (hl_refine.hip):
+// positions [nn][D] and cells [nc][D+1] from the host, the refined mesh and
+// the node pair (min << 32 | max) of every new edge-midpoint node back.
+template <int D>
+hipError_t refine_once(int64_t nn, int64_t nc, const double *x_host, const int32_t *cells_host, hipStream_t s,
+                       std::vector<double> &x_out, std::vector<int32_t> &cells_out,
+                       std::vector<uint64_t> &edges_out);
 
 template <int D> void launch_centroids(const StepArgs &a, const Sched &k, hipStream_t s);
 template <int D> void launch_node_agg(const StepArgs &a, const Sched &k, hipStream_t s);

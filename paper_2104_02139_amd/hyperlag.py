@@ -27,7 +27,7 @@ EXPORTS = ["hl_create", "hl_destroy", "hl_mesh_upload", "hl_state_init", "hl_set
            "hl_last_error", "hl_mesh_upload_batch", "hl_step_batch", "hl_query_dt", "hl_use_graph",
            "hl_forward_record", "hl_forward_replay", "hl_adjoint_run", "hl_tape_get",
            "hl_set_schedule", "hl_get_schedule", "hl_autotune", "hl_set_boundary_loads",
-           "hl_set_contact", "hl_get_contact"]
+           "hl_set_contact", "hl_get_contact", "hl_mesh_refine", "hl_mesh_info", "hl_mesh_get"]
 
 # stages of the full-mesh part of a step (launch schedules)
 STAGES = ("pack", "node_agg", "predict", "node_solve", "update")
@@ -112,6 +112,9 @@ def load():
     L.hl_set_params.argtypes = [vp, C.POINTER(Params)]
     L.hl_set_boundary_loads.argtypes = [vp, i64, vp, vp, vp, vp, C.c_int]
     L.hl_set_contact.argtypes = [vp, i64, vp, vp, vp, C.c_int]
+    L.hl_mesh_refine.argtypes = [vp, C.c_int]
+    L.hl_mesh_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(i64), C.POINTER(i64)]
+    L.hl_mesh_get.argtypes = [vp, vp, vp, vp, vp, C.c_int]
     L.hl_get_contact.argtypes = [vp, vp, i64]
     L.hl_compute_dt.argtypes = [vp, C.POINTER(dp)]
     L.hl_step.argtypes = [vp, dp, C.POINTER(StepInfo)]
@@ -194,6 +197,26 @@ class Context:
                "hl_mesh_upload")
         self._n_contact = 0
         self.dim, self.n_nodes, self.n_cells = int(dim), nn, nc
+
+    def refine(self, levels=1):
+        """Conforming red refinement of the held mesh on the GPU; the state
+        is discarded (children of cell c are 8c..8c+7, 4c..4c+3 in 2D)."""
+        _check(load().hl_mesh_refine(self._h, int(levels)), "hl_mesh_refine")
+        d, nn, nc = C.c_int(), C.c_int64(), C.c_int64()
+        _check(load().hl_mesh_info(self._h, C.byref(d), C.byref(nn), C.byref(nc)), "hl_mesh_info")
+        self.dim, self.n_nodes, self.n_cells = d.value, nn.value, nc.value
+
+    def mesh(self):
+        """The held mesh in its reference configuration: x, cells, nwall,
+        normals."""
+        d, nn, nc = self.dim, self.n_nodes, self.n_cells
+        x = np.zeros((nn, d))
+        cells = np.zeros((nc, d + 1), np.int32)
+        nwall = np.zeros(nn, np.uint8)
+        normals = np.zeros((nn, d, d))
+        _check(load().hl_mesh_get(self._h, *(a.ctypes.data_as(C.c_void_p) for a in (x, cells, nwall, normals)), 0),
+               "hl_mesh_get")
+        return dict(x=x, cells=cells, nwall=nwall, normals=normals)
 
     def upload_mesh_batch(self, dim, node_offsets, cell_offsets, x, cells, nwall=None, normals=None):
         """Concatenated meshes; ``cells`` in mesh-local node numbers."""
