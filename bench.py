@@ -280,6 +280,44 @@ def bar_lid(w, gap=2e-5):
     return setup
 
 
+def refined_measure(w, steps, warmup, graph):
+    """The paper's route to large meshes (Section 3.9): the workload's mesh
+    refined once on the GPU (1 -> 8 tetrahedra, 1 -> 4 triangles), its
+    cells inheriting their parent's material and velocity, then stepped
+    like the main measurement.  Needs a uniform initial node velocity."""
+    import numpy as np
+    import torch
+    from paper_2104_02139_amd import hyperlag as H
+    if not np.all(w.v_node == w.v_node[:1]):
+        return None
+    ctx = H.Context(stream=torch.cuda.current_stream())
+    ctx.upload_mesh(w.dim, w.x, w.cells, w.nwall, w.normals)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.refine(1)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t0
+    k = 8 if w.dim == 3 else 4
+    rep = lambda a: np.repeat(a, k, axis=0)
+    ctx.init_state(rep(w.rho0), rep(w.mu), rep(w.lam), rep(w.v_cell), np.tile(w.v_node[:1], (ctx.n_nodes, 1)),
+                   H.default_params(w.dim, c_cfl=w.c_cfl))
+    ctx.use_graph(graph, 6)
+    it = []
+    for _ in range(warmup):
+        it.append(ctx.step(0.0, info=True)["mood_iters"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(0.0, info=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {"n_cells": ctx.n_cells, "n_nodes": ctx.n_nodes, "refine_s_incl_upload": t_ref, "steps": steps,
+           "ms_per_step": 1e3 * el / steps, "cell_updates_per_s": ctx.n_cells * steps / el,
+           "mood_iters_mean": sum(it) / max(len(it), 1)}
+    ctx.close()
+    return out
+
+
 def adjoint_measure(n=32, steps=200, every=20):
     """Shear-modulus identification cube (32^3 Kuhn cells, lognormal mu):
     time of the checkpointed forward record, of the same steps without
@@ -323,6 +361,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the many-mesh batched-vs-sequential measurement")
+    ap.add_argument("--no-refined", action="store_true",
+                    help="skip the step on the once-refined workload")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the three-level cascade and shear-energy variant measurements")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -462,6 +502,9 @@ def main():
                 variant_measure(ctx, w, args.steps, args.warmup, not args.eager,
                                 "contact lid over the top face", setup=bar_lid(w)),
             ]
+    if not args.no_refined:
+        print("[bench] the workload refined once on the GPU, stepped", file=sys.stderr, flush=True)
+        out["refined_x8"] = refined_measure(w, args.steps, args.warmup, not args.eager)
     if not args.no_adjoint:
         print("[bench] adjoint vs forward on the identification cube", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_measure()
