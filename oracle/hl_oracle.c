@@ -79,6 +79,10 @@ typedef struct {
     int detect;             /* 0: accept the unlimited candidate          */
     int cascade;            /* 2: P1 -> P0; 3: P1 -> P1+BJ -> P0 (R18)    */
     double shear_a;         /* shear energy family parameter (R27)        */
+    int eos;                /* 0: volumetric energy of eq. EOS_neoHook;
+                               1: stiffened gas (eq. EOS_stiffened_gas, R31) */
+    int pad_;
+    double sg_gamma, sg_pinf; /* stiffened-gas gamma and p_inf              */
 } orc_params;
 
 typedef struct {
@@ -263,6 +267,8 @@ static void corner_matrix_shape(int d, const orc_geo *g, int p, double N[3][3]) 
 typedef struct {
     double rho0, mu, K;
     double a; /* shear energy family (eq. familiy_energies); -1: neo-Hookean */
+    int eos;  /* 1: stiffened gas (R31): p from the internal energy           */
+    double gam, pinf;
 } orc_mat;
 
 /* p = -(K/2)(J - 1 + ln J / J) */
@@ -292,12 +298,56 @@ static double inv2(const double A[3][3]) {
     return 0.5 * (tr * tr - tr2);
 }
 
+/* Shear part of the specific free energy (eq. familiy_energies):
+ *   Psi_s = mu/(4 rho0) [-2a (I1b - 3) + (1+a)/3 (I2b^2 - 9)],
+ * Bbar = J^{-2/3} B, I1b = tr Bbar, I2b its second invariant. */
+static double shear_energy(const orc_mat *m, double tau, const double B[3][3]) {
+    double J = m->rho0 * tau;
+    double s = pow(J, -2.0 / 3.0);
+    double Bb[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Bb[i][j] = s * B[i][j];
+    double I1b = Bb[0][0] + Bb[1][1] + Bb[2][2];
+    double I2b = inv2(Bb);
+    return m->mu / (4.0 * m->rho0) * (-2.0 * m->a * (I1b - 3.0) + (1.0 + m->a) / 3.0 * (I2b * I2b - 9.0));
+}
+
+/* Derivative of Psi_s along (dtau, dB):
+ *   dPsi_s = mu/(4 rho0) [-2a dI1b + (2/3)(1+a) I2b dI2b],
+ *   dBbar = J^{-2/3} dB - (2/3)(dJ/J) Bbar, dI1b = tr dBbar,
+ *   dI2b = tr Bbar tr dBbar - tr(Bbar dBbar). */
+static double shear_energy_direction(const orc_mat *m, double tau, const double B[3][3], double dtau,
+                                     const double dB[3][3]) {
+    double J = m->rho0 * tau, dJ = m->rho0 * dtau;
+    double s = pow(J, -2.0 / 3.0);
+    double Bb[3][3], dBb[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            Bb[i][j] = s * B[i][j];
+            dBb[i][j] = s * dB[i][j] - (2.0 / 3.0) * (dJ / J) * s * B[i][j];
+        }
+    double tr = Bb[0][0] + Bb[1][1] + Bb[2][2], dtr = dBb[0][0] + dBb[1][1] + dBb[2][2];
+    double BdB = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) BdB += Bb[i][k] * dBb[k][i];
+    double I2b = inv2(Bb), dI2b = tr * dtr - BdB;
+    return m->mu / (4.0 * m->rho0) * (-2.0 * m->a * dtr + (2.0 / 3.0) * (1.0 + m->a) * I2b * dI2b);
+}
+
+/* Stiffened gas (eq. EOS_stiffened_gas; reading R31): the volumetric part
+ * of the specific internal energy is eps_v = eps - Psi_s, and
+ * eps_v = (p + gamma p_inf) / ((gamma - 1) rho) gives
+ *   p = (gamma - 1) (eps - Psi_s) / tau - gamma p_inf. */
+static double sg_pressure(const orc_mat *m, double tau, const double B[3][3], double eps) {
+    return (m->gam - 1.0) * (eps - shear_energy(m, tau, B)) / tau - m->gam * m->pinf;
+}
+
 /* T = -p I + (mu / J) [-a dev(Bbar) - ((1+a)/3) I2(Bbar) dev(Bbar^-1)],
  * Bbar = J^{-2/3} B (eqs. cst, familiy_energies; R27).  For a = -1 this is
  * (mu / J) dev(Bbar) - p I (eq. cstnh). */
-static void stress(const orc_mat *m, double tau, const double B[3][3], double T[3][3]) {
+static void stress(const orc_mat *m, double tau, const double B[3][3], double eps, double T[3][3]) {
     double J = m->rho0 * tau;
-    double p = pressure(m, J);
+    double p = m->eos ? sg_pressure(m, tau, B, eps) : pressure(m, J);
     double s = pow(J, -2.0 / 3.0);
     double Bb[3][3];
     for (int i = 0; i < 3; ++i)
@@ -319,16 +369,19 @@ static void stress(const orc_mat *m, double tau, const double B[3][3], double T[
         }
 }
 
-/* sound speed a = sqrt(tau (K_t + 4 mu / 3)), K_t = -J dp/dJ (R5) */
-static double sound_speed(const orc_mat *m, double tau) {
+/* sound speed a = sqrt(tau (K_t + 4 mu / 3)), K_t = -J dp/dJ (R5); for the
+ * stiffened gas K_t = gamma (p + p_inf), the isentropic bulk modulus (R31) */
+static double sound_speed(const orc_mat *m, double tau, const double B[3][3], double eps) {
+    if (m->eos) return sqrt(tau * (m->gam * (sg_pressure(m, tau, B, eps) + m->pinf) + 4.0 * m->mu / 3.0));
     double J = m->rho0 * tau;
     double Kt = 0.5 * m->K * (J + (1.0 - log(J)) / J);
     return sqrt(tau * (Kt + 4.0 * m->mu / 3.0));
 }
 
 /* Specific free energy Psi_v + Psi_s (Section 2.2.4, eq. familiy_energies),
- * used by the energy diagnostics only. */
+ * used by the energy diagnostics only; the stiffened gas reports Psi_s. */
 static double free_energy(const orc_mat *m, double tau, const double B[3][3]) {
+    if (m->eos) return shear_energy(m, tau, B);
     double J = m->rho0 * tau;
     double lj = log(J);
     double s = pow(J, -2.0 / 3.0);
@@ -348,14 +401,16 @@ static double free_energy(const orc_mat *m, double tau, const double B[3][3]) {
  *     dT = rho0 [ -p'(J) I - (5/3) mu J^{-8/3} dev(B) ] dtau + mu J^{-5/3} dev(dB)
  *   family (R27), with dJ = rho0 dtau, dBbar = J^{-2/3} dB - (2/3)(dJ/J) Bbar,
  *   d(Bbar^-1) = -Bbar^-1 dBbar Bbar^-1, dI2 = tr(Bbar) tr(dBbar) - tr(Bbar dBbar):
- *     dT = -p'(J) dJ I - (dJ/J) T_0 + (mu/J) [-a dev(dBbar)
- *          - c (dI2 dev(Bbar^-1) + I2 dev(d(Bbar^-1)))],  c = (1+a)/3. */
-static void stress_direction(const orc_mat *m, double tau, const double B[3][3], double dtau,
-                             const double dB[3][3], double dT[3][3]) {
+ *     dT = -dp I - (dJ/J) T_0 + (mu/J) [-a dev(dBbar)
+ *          - c (dI2 dev(Bbar^-1) + I2 dev(d(Bbar^-1)))],  c = (1+a)/3,
+ *   with dp = p'(J) dJ, or for the stiffened gas (R31) the derivative of
+ *   p(tau, eps, B) along (dtau, deps, dB). */
+static void stress_direction(const orc_mat *m, double tau, const double B[3][3], double eps, double dtau,
+                             const double dB[3][3], double deps, double dT[3][3]) {
     double J = m->rho0 * tau;
     double lj = log(J);
     double dpdJ = -0.5 * m->K * (1.0 + (1.0 - lj) / (J * J));
-    if (m->a == -1.0) {
+    if (m->a == -1.0 && !m->eos) {
         double J53 = pow(J, -5.0 / 3.0);
         double J83 = pow(J, -8.0 / 3.0);
         double trB = B[0][0] + B[1][1] + B[2][2];
@@ -397,13 +452,19 @@ static void stress_direction(const orc_mat *m, double tau, const double B[3][3],
         for (int k = 0; k < 3; ++k) BdB += Bb[i][k] * dBb[k][i];
     double dI2 = trBb * trdBb - BdB;
     double trBi = Bi[0][0] + Bi[1][1] + Bi[2][2], trdBi = dBi[0][0] + dBi[1][1] + dBi[2][2];
+    /* dp: -p'(J) dJ, or for the stiffened gas (R31)
+     * (gamma - 1) [(deps - dPsi_s) / tau - (eps - Psi_s) dtau / tau^2] */
+    double dpv = dpdJ * dJ;
+    if (m->eos)
+        dpv = (m->gam - 1.0) * ((deps - shear_energy_direction(m, tau, B, dtau, dB)) / tau -
+                                (eps - shear_energy(m, tau, B)) * dtau / (tau * tau));
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             double e = (i == j) ? 1.0 : 0.0;
             double T0 = (m->mu / J) * (-m->a * (Bb[i][j] - e * trBb / 3.0) - c * I2 * (Bi[i][j] - e * trBi / 3.0));
             double dsh = -m->a * (dBb[i][j] - e * trdBb / 3.0) -
                          c * (dI2 * (Bi[i][j] - e * trBi / 3.0) + I2 * (dBi[i][j] - e * trdBi / 3.0));
-            dT[i][j] = -dpdJ * dJ * e - (dJ / J) * T0 + (m->mu / J) * dsh;
+            dT[i][j] = -dpv * e - (dJ / J) * T0 + (m->mu / J) * dsh;
         }
 }
 
@@ -619,13 +680,20 @@ int orc_init_state(const orc_mesh *M, const double *x, const double *rho0, const
 /* ------------------------------------------------------------------ */
 /* least-squares gradients (reading R8)                                */
 /* ------------------------------------------------------------------ */
-/* W = (tau, v_1..v_d, B components in state order) */
-static void cell_W(const orc_mesh *M, const double *tau, const double *v, const double *B, int64_t c,
-                   double *W) {
+/* W = (tau, v_1..v_d, B components in state order, eps = e - |v|^2 / 2);
+ * eps (index nW) is reconstructed for the stiffened gas (R31) and is 0
+ * when e is NULL */
+static void cell_W(const orc_mesh *M, const double *tau, const double *v, const double *B, const double *e,
+                   int64_t c, double *W) {
     int d = M->dim;
     W[0] = tau[c];
-    for (int i = 0; i < d; ++i) W[1 + i] = v[c * d + i];
+    double k2 = 0.0;
+    for (int i = 0; i < d; ++i) {
+        W[1 + i] = v[c * d + i];
+        k2 += v[c * d + i] * v[c * d + i];
+    }
     for (int s = 0; s < M->nB; ++s) W[1 + d + s] = B[c * M->nB + s];
+    W[M->nW] = e ? e[c] - 0.5 * k2 : 0.0;
 }
 
 /* grad[c][w][j] = d W_w / d x_j from an unweighted least-squares fit over
@@ -633,14 +701,14 @@ static void cell_W(const orc_mesh *M, const double *tau, const double *v, const 
  * stencil with fewer than d visits, or whose normal matrix is singular
  * (det A <= 1e-12 (tr A / d)^d), gives a zero gradient. */
 static void lsq_gradients(const orc_mesh *M, const double *xc, const double *tau, const double *v,
-                          const double *B, double *grad) {
-    int d = M->dim, nW = M->nW, nv = M->nv;
+                          const double *B, const double *e, double *grad) {
+    int d = M->dim, nW = M->nW + 1, nv = M->nv;
     for (int64_t c = 0; c < M->nc; ++c) {
         double A[3][3] = {{0}};
-        double b[10][3] = {{0}};
-        double Wc[10], Wk[10];
+        double b[11][3] = {{0}};
+        double Wc[11], Wk[11];
         int visits = 0;
-        cell_W(M, tau, v, B, c, Wc);
+        cell_W(M, tau, v, B, e, c, Wc);
         for (int k = 0; k < nv; ++k) {
             int64_t p = M->c2n[c * nv + k];
             for (int64_t q = M->n2c_off[p]; q < M->n2c_off[p + 1]; ++q) {
@@ -649,7 +717,7 @@ static void lsq_gradients(const orc_mesh *M, const double *xc, const double *tau
                 ++visits;
                 double dx[3] = {0, 0, 0};
                 for (int i = 0; i < d; ++i) dx[i] = xc[j * 3 + i] - xc[c * 3 + i];
-                cell_W(M, tau, v, B, j, Wk);
+                cell_W(M, tau, v, B, e, j, Wk);
                 for (int a = 0; a < d; ++a)
                     for (int bb = 0; bb < d; ++bb) A[a][bb] += dx[a] * dx[bb];
                 for (int w = 0; w < nW; ++w)
@@ -664,7 +732,7 @@ static void lsq_gradients(const orc_mesh *M, const double *xc, const double *tau
             detA = A[0][0] * A[1][1] - A[0][1] * A[1][0];
         double scale = pow(trA / d, d);
         double *g = grad + c * nW * 3;
-        memset(g, 0, sizeof(double) * nW * 3);
+        memset(g, 0, sizeof(double) * nW * 3);  /* nW includes eps here */
         if (visits < d || !(trA > 0.0) || !(detA > 1e-12 * scale)) continue;
         for (int w = 0; w < nW; ++w) {
             double Am[9], rhs[3];
@@ -688,23 +756,24 @@ static void lsq_gradients(const orc_mesh *M, const double *xc, const double *tau
  * and the limited gradient is phi grad W_w. */
 static void bj_limit(const orc_mesh *M, const double *x, const double *xc, const double *tau,
                      const double *v, const double *B, const double *grad, double *glim) {
-    int d = M->dim, nW = M->nW, nv = M->nv;
+    int d = M->dim, nW = M->nW, nv = M->nv, st = M->nW + 1;
     for (int64_t c = 0; c < M->nc; ++c) {
-        double Wc[10], Wk[10], lo[10], hi[10];
-        cell_W(M, tau, v, B, c, Wc);
+        double Wc[11], Wk[11], lo[11], hi[11];
+        cell_W(M, tau, v, B, NULL, c, Wc);
         for (int w = 0; w < nW; ++w) lo[w] = hi[w] = Wc[w];
         for (int k = 0; k < nv; ++k) {
             int64_t p = M->c2n[c * nv + k];
             for (int64_t q = M->n2c_off[p]; q < M->n2c_off[p + 1]; ++q) {
-                cell_W(M, tau, v, B, M->n2c[q] / nv, Wk);
+                cell_W(M, tau, v, B, NULL, M->n2c[q] / nv, Wk);
                 for (int w = 0; w < nW; ++w) {
                     lo[w] = fmin(lo[w], Wk[w]);
                     hi[w] = fmax(hi[w], Wk[w]);
                 }
             }
         }
-        const double *g = grad + c * nW * 3;
-        double *o = glim + c * nW * 3;
+        const double *g = grad + c * st * 3;
+        double *o = glim + c * st * 3;
+        for (int i = 0; i < 3; ++i) o[nW * 3 + i] = g[nW * 3 + i]; /* eps: not limited */
         for (int w = 0; w < nW; ++w) {
             double phi = 1.0;
             for (int k = 0; k < nv; ++k) {
@@ -728,6 +797,7 @@ static void bj_limit(const orc_mesh *M, const double *x, const double *xc, const
 /* ------------------------------------------------------------------ */
 typedef struct {
     double tau, v[3], B[3][3]; /* predicted state at the corner */
+    double eps;                /* predicted specific internal energy (R31) */
     double T[3][3];            /* stress of the predicted state */
     double z;                  /* swept mass flux a / tau (R5)  */
 } orc_corner;
@@ -738,11 +808,12 @@ typedef struct {
  *   dtau/dt = tau tr G,  dv/dt = tau div T,  dB/dt = G B + B G^T,
  *   G = grad v, div T by the chain rule through T(tau, B). */
 static void predict_corner(const orc_mesh *M, const orc_mat *mat, const orc_geo *g, const double *X,
-                           double tau, const double *vc, const double Bc[3][3], const double *grad,
+                           double tau, const double *vc, const double Bc[3][3], double eps, const double *grad,
                            int p1, double dt, orc_corner *out) {
     int d = M->dim;
     memset(out, 0, sizeof(*out));
     out->tau = tau;
+    out->eps = eps;
     for (int i = 0; i < d; ++i) out->v[i] = vc[i];
     memcpy(out->B, Bc, sizeof(out->B));
     if (p1) {
@@ -768,17 +839,27 @@ static void predict_corner(const orc_mesh *M, const orc_mat *mat, const orc_geo 
                 for (int k = 0; k < 3; ++k) s += G[i][k] * Bc[k][j] + Bc[i][k] * G[j][k];
                 dB[i][j] = s;
             }
+        double ge[3] = {0, 0, 0};
+        for (int j = 0; j < d; ++j) ge[j] = grad[M->nW * 3 + j];
         double divT[3] = {0, 0, 0};
         for (int j = 0; j < d; ++j) {
             double dTj[3][3];
-            stress_direction(mat, tau, Bc, gt[j], gB[j], dTj);
+            stress_direction(mat, tau, Bc, eps, gt[j], gB[j], ge[j], dTj);
             for (int i = 0; i < 3; ++i) divT[i] += dTj[i][j];
         }
+        /* internal energy (R31): d eps / dt = tau T : grad v */
+        double Tc[3][3], TG = 0.0;
+        stress(mat, tau, Bc, eps, Tc);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) TG += Tc[i][j] * G[i][j];
         double delta[3] = {0, 0, 0};
         for (int i = 0; i < d; ++i) delta[i] = X[i] - g->xc[i];
         double s = 0.0;
         for (int j = 0; j < d; ++j) s += gt[j] * delta[j];
         out->tau = tau + s + h * dtau;
+        double se = 0.0;
+        for (int j = 0; j < d; ++j) se += ge[j] * delta[j];
+        out->eps = eps + se + h * tau * TG;
         for (int i = 0; i < d; ++i) {
             double a = 0.0;
             for (int j = 0; j < d; ++j) a += G[i][j] * delta[j];
@@ -792,8 +873,8 @@ static void predict_corner(const orc_mesh *M, const orc_mat *mat, const orc_geo 
             }
         if (d == 2) out->B[2][2] = 1.0;
     }
-    stress(mat, out->tau, out->B, out->T);
-    out->z = sound_speed(mat, out->tau) / out->tau;
+    stress(mat, out->tau, out->B, out->eps, out->T);
+    out->z = sound_speed(mat, out->tau, out->B, out->eps) / out->tau;
 }
 
 /* ------------------------------------------------------------------ */
@@ -857,6 +938,8 @@ typedef struct {
     const double *x, *vhat, *tau, *v, *e, *B;
     double dt;
     double a;        /* shear energy family parameter (R27) */
+    int eos;         /* stiffened gas (R31) and its parameters */
+    double gam, pinf;
     /* derived at t^n */
     orc_geo *geo;
     double *xc;      /* [nc][3] */
@@ -870,7 +953,7 @@ typedef struct {
 } orc_work;
 
 static orc_mat mat_of(const orc_work *w, int64_t c) {
-    orc_mat m = {w->rho0[c], w->mu[c], w->K[c], w->a};
+    orc_mat m = {w->rho0[c], w->mu[c], w->K[c], w->a, w->eos, w->gam, w->pinf};
     return m;
 }
 
@@ -886,9 +969,11 @@ static void candidate(orc_work *w, const uint8_t *mask) {
             int64_t p = M->c2n[c * nv + k];
             double X[3] = {0, 0, 0};
             for (int i = 0; i < d; ++i) X[i] = w->x[p * d + i];
-            const double *gc = (mask[c] == 1 ? w->glim : w->grad) + c * M->nW * 3;
-            predict_corner(M, &mat, &w->geo[c], X, w->tau[c], w->v + c * d, Bc, gc, mask[c] < 2,
-                           w->dt, &w->cor[c * nv + k]);
+            const double *gc = (mask[c] == 1 ? w->glim : w->grad) + c * (M->nW + 1) * 3;
+            double k2 = 0.0;
+            for (int i = 0; i < d; ++i) k2 += w->v[c * d + i] * w->v[c * d + i];
+            predict_corner(M, &mat, &w->geo[c], X, w->tau[c], w->v + c * d, Bc, w->e[c] - 0.5 * k2, gc,
+                           mask[c] < 2, w->dt, &w->cor[c * nv + k]);
         }
     }
     /* nodal solver (eq. nodal_solver^n, readings R14, R15, R22) */
@@ -1070,6 +1155,11 @@ static int inadmissible(const orc_work *w, const orc_params *prm, int64_t c) {
     for (int i = 0; i < d; ++i) k2 += w->v1[c * d + i] * w->v1[c * d + i];
     double eps = w->e1[c] - 0.5 * k2;
     if (eps < -prm->eps_tol * (fabs(w->e1[c]) + 0.5 * k2)) return 1;
+    if (prm->eos) {
+        /* stiffened gas (R31): hyperbolic only while p + p_inf > 0 */
+        orc_mat mat = mat_of(w, c);
+        if (!(sg_pressure(&mat, w->tau1[c], B1, eps) + prm->sg_pinf > 0.0)) return 1;
+    }
     return 0;
 }
 
@@ -1084,13 +1174,13 @@ static int troubled(const orc_work *w, const orc_params *prm, int64_t c) {
 }
 
 static void diagnostics(const orc_mesh *M, const double *rho0, const double *mu, const double *K,
-                        double a, const double *m, const double *tau, const double *v, const double *e,
-                        const double *B, orc_info *info) {
+                        const orc_params *prm, const double *m, const double *tau, const double *v,
+                        const double *e, const double *B, orc_info *info) {
     int d = M->dim;
     info->mass = info->energy = info->kinetic = info->elastic = 0.0;
     info->mom[0] = info->mom[1] = info->mom[2] = 0.0;
     for (int64_t c = 0; c < M->nc; ++c) {
-        orc_mat mat = {rho0[c], mu[c], K[c], a};
+        orc_mat mat = {rho0[c], mu[c], K[c], prm->shear_a, prm->eos, prm->sg_gamma, prm->sg_pinf};
         double Bc[3][3];
         unpack_B(d, B + c * M->nB, Bc);
         double k2 = 0.0;
@@ -1108,8 +1198,9 @@ static void diagnostics(const orc_mesh *M, const double *rho0, const double *mu,
 /* Time step (eqs. CFL, CFL2; readings R20, R21).  dt_prev <= 0 requests the
  * acoustic bound only (first step). */
 static void time_step(const orc_mesh *M, const double *rho0, const double *mu, const double *K,
-                      const double *x1, const double *tau1, const double *m, const double *V0,
-                      double dt_prev, const orc_params *prm, orc_info *info) {
+                      const double *x1, const double *tau1, const double *v1, const double *e1,
+                      const double *B1, const double *m, const double *V0, double dt_prev,
+                      const orc_params *prm, orc_info *info) {
     int d = M->dim;
     double ac = INFINITY, vol = INFINITY;
     for (int64_t c = 0; c < M->nc; ++c) {
@@ -1117,8 +1208,11 @@ static void time_step(const orc_mesh *M, const double *rho0, const double *mu, c
         orc_geo g;
         cell_nodes(M, x1, c, X);
         geometry(d, X, &g);
-        orc_mat mat = {rho0[c], mu[c], K[c], prm->shear_a};
-        double a = sound_speed(&mat, tau1[c]);
+        orc_mat mat = {rho0[c], mu[c], K[c], prm->shear_a, prm->eos, prm->sg_gamma, prm->sg_pinf};
+        double Bc[3][3], k2 = 0.0;
+        unpack_B(d, B1 + c * M->nB, Bc);
+        for (int i = 0; i < d; ++i) k2 += v1[c * d + i] * v1[c * d + i];
+        double a = sound_speed(&mat, tau1[c], Bc, e1[c] - 0.5 * k2);
         ac = fmin(ac, g.Lc / a);
         if (V0) {
             double V1 = m[c] * tau1[c];
@@ -1137,10 +1231,11 @@ static void time_step(const orc_mesh *M, const double *rho0, const double *mu, c
 }
 
 double orc_initial_dt(const orc_mesh *M, const double *rho0, const double *mu, const double *K,
-                      const double *x, const double *tau, const double *m, const orc_params *prm) {
+                      const double *x, const double *tau, const double *v, const double *e, const double *B,
+                      const double *m, const orc_params *prm) {
     orc_info info;
     memset(&info, 0, sizeof info);
-    time_step(M, rho0, mu, K, x, tau, m, NULL, 0.0, prm, &info);
+    time_step(M, rho0, mu, K, x, tau, v, e, B, m, NULL, 0.0, prm, &info);
     return info.dt_next;
 }
 
@@ -1168,6 +1263,9 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
     w.B = B;
     w.dt = dt;
     w.a = prm->shear_a;
+    w.eos = prm->eos;
+    w.gam = prm->sg_gamma;
+    w.pinf = prm->sg_pinf;
     w.x1 = x1;
     w.vhat1 = vhat1;
     w.tau1 = tau1;
@@ -1176,8 +1274,8 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
     w.B1 = B1;
     w.geo = (orc_geo *)malloc(sizeof(orc_geo) * (size_t)(M->nc + 1));
     w.xc = (double *)malloc(sizeof(double) * (size_t)(M->nc * 3 + 1));
-    w.grad = (double *)malloc(sizeof(double) * (size_t)(M->nc * M->nW * 3 + 1));
-    w.glim = (double *)malloc(sizeof(double) * (size_t)(M->nc * M->nW * 3 + 1));
+    w.grad = (double *)malloc(sizeof(double) * (size_t)(M->nc * (M->nW + 1) * 3 + 1));
+    w.glim = (double *)malloc(sizeof(double) * (size_t)(M->nc * (M->nW + 1) * 3 + 1));
     w.rmin = (double *)malloc(sizeof(double) * (size_t)(M->nc + 1));
     w.rmax = (double *)malloc(sizeof(double) * (size_t)(M->nc + 1));
     w.cor = (orc_corner *)malloc(sizeof(orc_corner) * (size_t)(M->nc * nv + 1));
@@ -1192,7 +1290,7 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
         for (int i = 0; i < 3; ++i) w.xc[c * 3 + i] = w.geo[c].xc[i];
         V0[c] = m[c] * tau[c];
     }
-    lsq_gradients(M, w.xc, tau, v, B, w.grad);
+    lsq_gradients(M, w.xc, tau, v, B, e, w.grad);
     bj_limit(M, x, w.xc, tau, v, B, w.grad, w.glim);
     /* relaxed-DMP bounds of rho^n over {c} and its reconstruction stencil */
     for (int64_t c = 0; c < M->nc; ++c) {
@@ -1242,8 +1340,8 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
     if (vstar_out)
         for (int64_t p = 0; p < M->nn; ++p)
             for (int i = 0; i < d; ++i) vstar_out[p * d + i] = w.vstar[p * 3 + i];
-    time_step(M, rho0, mu, K, x1, tau1, m, V0, dt, prm, info);
-    diagnostics(M, rho0, mu, K, prm->shear_a, m, tau1, v1, e1, B1, info);
+    time_step(M, rho0, mu, K, x1, tau1, v1, e1, B1, m, V0, dt, prm, info);
+    diagnostics(M, rho0, mu, K, prm, m, tau1, v1, e1, B1, info);
 
     free(w.geo);
     free(w.xc);
@@ -1294,23 +1392,47 @@ void orc_corner_shape(int d, const double *Xin, int p, double *N) {
 /* full 3x3 B in, full 3x3 T out, plus p, a, Psi */
 void orc_point_stress(double rho0, double mu, double K, double tau, const double *B, double *T,
                       double *p, double *a, double *psi, double shear_a) {
-    orc_mat m = {rho0, mu, K, shear_a};
+    orc_mat m = {rho0, mu, K, shear_a, 0, 0.0, 0.0};
     double Bm[3][3], Tm[3][3];
     memcpy(Bm, B, sizeof Bm);
-    stress(&m, tau, Bm, Tm);
+    stress(&m, tau, Bm, 0.0, Tm);
     memcpy(T, Tm, sizeof Tm);
     *p = pressure(&m, rho0 * tau);
-    *a = sound_speed(&m, tau);
+    *a = sound_speed(&m, tau, Bm, 0.0);
     *psi = free_energy(&m, tau, Bm);
 }
 
 void orc_point_stress_direction(double rho0, double mu, double K, double tau, const double *B,
                                 double dtau, const double *dB, double *dT, double shear_a) {
-    orc_mat m = {rho0, mu, K, shear_a};
+    orc_mat m = {rho0, mu, K, shear_a, 0, 0.0, 0.0};
     double Bm[3][3], dBm[3][3], dTm[3][3];
     memcpy(Bm, B, sizeof Bm);
     memcpy(dBm, dB, sizeof dBm);
-    stress_direction(&m, tau, Bm, dtau, dBm, dTm);
+    stress_direction(&m, tau, Bm, 0.0, dtau, dBm, 0.0, dTm);
+    memcpy(dT, dTm, sizeof dTm);
+}
+
+/* stiffened gas with the shear family (R31): T, p, a, Psi_s at (tau, B, eps) */
+void orc_point_stress_sg(double rho0, double mu, double shear_a, double gam, double pinf, double tau,
+                         const double *B, double eps, double *T, double *p, double *a, double *psi_s) {
+    orc_mat m = {rho0, mu, 0.0, shear_a, 1, gam, pinf};
+    double Bm[3][3], Tm[3][3];
+    memcpy(Bm, B, sizeof Bm);
+    stress(&m, tau, Bm, eps, Tm);
+    memcpy(T, Tm, sizeof Tm);
+    *p = sg_pressure(&m, tau, Bm, eps);
+    *a = sound_speed(&m, tau, Bm, eps);
+    *psi_s = shear_energy(&m, tau, Bm);
+}
+
+void orc_point_stress_direction_sg(double rho0, double mu, double shear_a, double gam, double pinf, double tau,
+                                   const double *B, double eps, double dtau, const double *dB, double deps,
+                                   double *dT) {
+    orc_mat m = {rho0, mu, 0.0, shear_a, 1, gam, pinf};
+    double Bm[3][3], dBm[3][3], dTm[3][3];
+    memcpy(Bm, B, sizeof Bm);
+    memcpy(dBm, dB, sizeof dBm);
+    stress_direction(&m, tau, Bm, eps, dtau, dBm, deps, dTm);
     memcpy(dT, dTm, sizeof dTm);
 }
 
@@ -1330,6 +1452,7 @@ int orc_point_cn(int d, const double *Bn, const double *Ln, const double *L1, do
 void orc_lsq(const orc_mesh *M, const double *x, const double *tau, const double *v,
              const double *B, double *grad) {
     double *xc = (double *)malloc(sizeof(double) * (size_t)(M->nc * 3 + 1));
+    double *gw = (double *)malloc(sizeof(double) * (size_t)(M->nc * (M->nW + 1) * 3 + 1));
     for (int64_t c = 0; c < M->nc; ++c) {
         double X[4][3];
         orc_geo g;
@@ -1337,15 +1460,20 @@ void orc_lsq(const orc_mesh *M, const double *x, const double *tau, const double
         geometry(M->dim, X, &g);
         for (int i = 0; i < 3; ++i) xc[c * 3 + i] = g.xc[i];
     }
-    lsq_gradients(M, xc, tau, v, B, grad);
+    lsq_gradients(M, xc, tau, v, B, NULL, gw);
+    for (int64_t c = 0; c < M->nc; ++c)
+        memcpy(grad + c * M->nW * 3, gw + c * (M->nW + 1) * 3, sizeof(double) * M->nW * 3);
+    free(gw);
     free(xc);
 }
 
 /* Barth-Jespersen limited gradients of all cells: glim [nc][nW][3] */
 void orc_bj(const orc_mesh *M, const double *x, const double *tau, const double *v,
             const double *B, double *glim) {
+    const int st = M->nW + 1;
     double *xc = (double *)malloc(sizeof(double) * (size_t)(M->nc * 3 + 1));
-    double *grad = (double *)malloc(sizeof(double) * (size_t)(M->nc * M->nW * 3 + 1));
+    double *grad = (double *)malloc(sizeof(double) * (size_t)(M->nc * st * 3 + 1));
+    double *gl = (double *)malloc(sizeof(double) * (size_t)(M->nc * st * 3 + 1));
     for (int64_t c = 0; c < M->nc; ++c) {
         double X[4][3];
         orc_geo g;
@@ -1353,8 +1481,11 @@ void orc_bj(const orc_mesh *M, const double *x, const double *tau, const double 
         geometry(M->dim, X, &g);
         for (int i = 0; i < 3; ++i) xc[c * 3 + i] = g.xc[i];
     }
-    lsq_gradients(M, xc, tau, v, B, grad);
-    bj_limit(M, x, xc, tau, v, B, grad, glim);
+    lsq_gradients(M, xc, tau, v, B, NULL, grad);
+    bj_limit(M, x, xc, tau, v, B, grad, gl);
+    for (int64_t c = 0; c < M->nc; ++c)
+        memcpy(glim + c * M->nW * 3, gl + c * st * 3, sizeof(double) * M->nW * 3);
+    free(gl);
     free(grad);
     free(xc);
 }
@@ -1366,23 +1497,32 @@ void orc_predict(const orc_mesh *M, const double *rho0, const double *mu, const 
                  const double *x, const double *tau, const double *v, const double *B, double dt,
                  double shear_a, const uint8_t *mask, double *tau_s, double *v_s, double *B_s, double *T_s,
                  double *z_s) {
-    int d = M->dim, nv = M->nv;
-    double *grad = (double *)malloc(sizeof(double) * (size_t)(M->nc * M->nW * 3 + 1));
-    double *glim = (double *)malloc(sizeof(double) * (size_t)(M->nc * M->nW * 3 + 1));
-    orc_lsq(M, x, tau, v, B, grad);
-    orc_bj(M, x, tau, v, B, glim);
+    int d = M->dim, nv = M->nv, st = M->nW + 1;
+    double *grad = (double *)malloc(sizeof(double) * (size_t)(M->nc * st * 3 + 1));
+    double *glim = (double *)malloc(sizeof(double) * (size_t)(M->nc * st * 3 + 1));
+    double *xc = (double *)malloc(sizeof(double) * (size_t)(M->nc * 3 + 1));
     for (int64_t c = 0; c < M->nc; ++c) {
         double X[4][3];
         orc_geo g;
         cell_nodes(M, x, c, X);
         geometry(d, X, &g);
-        orc_mat mat = {rho0[c], mu[c], K[c], shear_a};
+        for (int i = 0; i < 3; ++i) xc[c * 3 + i] = g.xc[i];
+    }
+    lsq_gradients(M, xc, tau, v, B, NULL, grad);
+    bj_limit(M, x, xc, tau, v, B, grad, glim);
+    free(xc);
+    for (int64_t c = 0; c < M->nc; ++c) {
+        double X[4][3];
+        orc_geo g;
+        cell_nodes(M, x, c, X);
+        geometry(d, X, &g);
+        orc_mat mat = {rho0[c], mu[c], K[c], shear_a, 0, 0.0, 0.0};
         double Bc[3][3];
         unpack_B(d, B + c * M->nB, Bc);
         for (int k = 0; k < nv; ++k) {
             orc_corner cr;
-            predict_corner(M, &mat, &g, X[k], tau[c], v + c * d, Bc,
-                           (mask[c] == 1 ? glim : grad) + c * M->nW * 3, mask[c] < 2, dt, &cr);
+            predict_corner(M, &mat, &g, X[k], tau[c], v + c * d, Bc, 0.0,
+                           (mask[c] == 1 ? glim : grad) + c * st * 3, mask[c] < 2, dt, &cr);
             int64_t q = c * nv + k;
             tau_s[q] = cr.tau;
             for (int i = 0; i < 3; ++i) v_s[q * 3 + i] = cr.v[i];
@@ -1395,11 +1535,56 @@ void orc_predict(const orc_mesh *M, const double *rho0, const double *mu, const 
     free(glim);
 }
 
+/* predicted corner states with the equation of state of prm (the
+ * stiffened gas needs e): tau*[nc*nv], eps*[nc*nv], T*[nc*nv][9],
+ * z*[nc*nv]; mask as for orc_predict */
+void orc_predict_eos(const orc_mesh *M, const double *rho0, const double *mu, const double *K,
+                     const double *x, const double *tau, const double *v, const double *e, const double *B,
+                     double dt, const orc_params *prm, const uint8_t *mask, double *tau_s, double *eps_s,
+                     double *T_s, double *z_s) {
+    int d = M->dim, nv = M->nv, st = M->nW + 1;
+    double *grad = (double *)malloc(sizeof(double) * (size_t)(M->nc * st * 3 + 1));
+    double *glim = (double *)malloc(sizeof(double) * (size_t)(M->nc * st * 3 + 1));
+    double *xc = (double *)malloc(sizeof(double) * (size_t)(M->nc * 3 + 1));
+    for (int64_t c = 0; c < M->nc; ++c) {
+        double X[4][3];
+        orc_geo g;
+        cell_nodes(M, x, c, X);
+        geometry(d, X, &g);
+        for (int i = 0; i < 3; ++i) xc[c * 3 + i] = g.xc[i];
+    }
+    lsq_gradients(M, xc, tau, v, B, e, grad);
+    bj_limit(M, x, xc, tau, v, B, grad, glim);
+    free(xc);
+    for (int64_t c = 0; c < M->nc; ++c) {
+        double X[4][3];
+        orc_geo g;
+        cell_nodes(M, x, c, X);
+        geometry(d, X, &g);
+        orc_mat mat = {rho0[c], mu[c], K[c], prm->shear_a, prm->eos, prm->sg_gamma, prm->sg_pinf};
+        double Bc[3][3], k2 = 0.0;
+        unpack_B(d, B + c * M->nB, Bc);
+        for (int i = 0; i < d; ++i) k2 += v[c * d + i] * v[c * d + i];
+        for (int k = 0; k < nv; ++k) {
+            orc_corner cr;
+            predict_corner(M, &mat, &g, X[k], tau[c], v + c * d, Bc, e[c] - 0.5 * k2,
+                           (mask[c] == 1 ? glim : grad) + c * st * 3, mask[c] < 2, dt, &cr);
+            int64_t q = c * nv + k;
+            tau_s[q] = cr.tau;
+            eps_s[q] = cr.eps;
+            memcpy(T_s + q * 9, cr.T, sizeof cr.T);
+            z_s[q] = cr.z;
+        }
+    }
+    free(grad);
+    free(glim);
+}
+
 void orc_diagnostics(const orc_mesh *M, const double *rho0, const double *mu, const double *K,
                      const double *m, const double *tau, const double *v, const double *e,
-                     const double *B, orc_info *info, double shear_a) {
+                     const double *B, orc_info *info, const orc_params *prm) {
     memset(info, 0, sizeof(*info));
-    diagnostics(M, rho0, mu, K, shear_a, m, tau, v, e, B, info);
+    diagnostics(M, rho0, mu, K, prm, m, tau, v, e, B, info);
 }
 
 int orc_info_size(void) { return (int)sizeof(orc_info); }

@@ -37,7 +37,8 @@ def build(force: bool = True) -> str:
 class Params(C.Structure):
     _fields_ = [("c_cfl", C.c_double), ("c_v", C.c_double), ("c_i", C.c_double),
                 ("delta0", C.c_double), ("delta1", C.c_double), ("eps_tol", C.c_double),
-                ("detect", C.c_int), ("cascade", C.c_int), ("shear_a", C.c_double)]
+                ("detect", C.c_int), ("cascade", C.c_int), ("shear_a", C.c_double),
+                ("eos", C.c_int), ("pad_", C.c_int), ("sg_gamma", C.c_double), ("sg_pinf", C.c_double)]
 
 
 class Info(C.Structure):
@@ -55,12 +56,16 @@ class Info(C.Structure):
                     mood_iters=self.mood_iters, status=self.status, n_lim=self.n_lim)
 
 
-def default_params(c_cfl=0.25, detect=True, cascade=2, shear_a=-1.0):
+def default_params(c_cfl=0.25, detect=True, cascade=2, shear_a=-1.0, eos=0, sg_gamma=2.2, sg_pinf=1e6):
     """Paper values: C_v = 0.2, C_i = 0.1, delta0 = 1e-4, delta1 = 1e-3
     (Sections 3.5 and 3.6).  cascade 2: P1 -> P0; 3: P1 -> P1 with the
     Barth-Jespersen limiter -> P0 (Section 3.5).  shear_a: parameter of the
-    shear energy family (eq. familiy_energies); -1 is neo-Hookean."""
-    return Params(c_cfl, 0.2, 0.1, 1e-4, 1e-3, 1e-12, 1 if detect else 0, int(cascade), float(shear_a))
+    shear energy family (eq. familiy_energies); -1 is neo-Hookean.  eos 1:
+    the stiffened gas (eq. EOS_stiffened_gas) with gamma and p_inf (the
+    droplet test's 2.2 and 1e6 by default) in place of the volumetric
+    energy of eq. EOS_neoHook."""
+    return Params(c_cfl, 0.2, 0.1, 1e-4, 1e-3, 1e-12, 1 if detect else 0, int(cascade), float(shear_a),
+                  int(eos), 0, float(sg_gamma), float(sg_pinf))
 
 
 _lib = None
@@ -88,7 +93,7 @@ def lib():
         L.orc_step.argtypes = ([C.c_void_p] + [_P] * 4 + [_P] * 6 + [C.c_double, C.POINTER(Params),
                                _U8, C.c_int] + [_P] * 7 + [C.POINTER(Info)])
         L.orc_initial_dt.restype = C.c_double
-        L.orc_initial_dt.argtypes = [C.c_void_p] + [_P] * 6 + [C.POINTER(Params)]
+        L.orc_initial_dt.argtypes = [C.c_void_p] + [_P] * 9 + [C.POINTER(Params)]
         L.orc_cell_geometry.argtypes = [C.c_int, _P, _P, _P, _P, _P, _P]
         L.orc_corner_shape.argtypes = [C.c_int, _P, C.c_int, _P]
         L.orc_point_stress.argtypes = [C.c_double] * 4 + [_P, _P, _P, _P, _P, C.c_double]
@@ -98,7 +103,11 @@ def lib():
         L.orc_lsq.argtypes = [C.c_void_p] + [_P] * 5
         L.orc_bj.argtypes = [C.c_void_p] + [_P] * 5
         L.orc_predict.argtypes = ([C.c_void_p] + [_P] * 7 + [C.c_double, C.c_double, _U8] + [_P] * 5)
-        L.orc_diagnostics.argtypes = [C.c_void_p] + [_P] * 8 + [C.POINTER(Info), C.c_double]
+        L.orc_diagnostics.argtypes = [C.c_void_p] + [_P] * 8 + [C.POINTER(Info), C.POINTER(Params)]
+        L.orc_predict_eos.argtypes = ([C.c_void_p] + [_P] * 8 + [C.c_double, C.POINTER(Params), _U8] + [_P] * 4)
+        L.orc_point_stress_sg.argtypes = [C.c_double] * 6 + [_P, C.c_double, _P, _P, _P, _P]
+        L.orc_point_stress_direction_sg.argtypes = ([C.c_double] * 6 + [_P, C.c_double, C.c_double, _P,
+                                                    C.c_double, _P])
         L.orc_info_size.restype = C.c_int
         L.orc_params_size.restype = C.c_int
         assert L.orc_info_size() == C.sizeof(Info)
@@ -152,6 +161,23 @@ def point_stress(rho0, mu, K, tau, B, shear_a=-1.0):
     psi = np.zeros(1)
     lib().orc_point_stress(rho0, mu, K, tau, _ptr(B), _ptr(T), _ptr(p), _ptr(a), _ptr(psi), float(shear_a))
     return T, p[0], a[0], psi[0]
+
+
+def point_stress_sg(rho0, mu, tau, B, eps, shear_a=-1.0, gamma=2.2, p_inf=1e6):
+    """Stiffened gas with the shear family (eq. EOS_stiffened_gas; R31):
+    (T, p, a, Psi_s) at (tau, B, eps), eps the specific internal energy."""
+    T = np.zeros(9)
+    p, a, psi = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_point_stress_sg(rho0, mu, shear_a, gamma, p_inf, tau, _ptr(_f64(np.reshape(B, 9))), eps,
+                              _ptr(T), C.byref(p), C.byref(a), C.byref(psi))
+    return T.reshape(3, 3), p.value, a.value, psi.value
+
+
+def point_stress_direction_sg(rho0, mu, tau, B, eps, dtau, dB, deps, shear_a=-1.0, gamma=2.2, p_inf=1e6):
+    dT = np.zeros(9)
+    lib().orc_point_stress_direction_sg(rho0, mu, shear_a, gamma, p_inf, tau, _ptr(_f64(np.reshape(B, 9))), eps,
+                                        dtau, _ptr(_f64(np.reshape(dB, 9))), deps, _ptr(dT))
+    return dT.reshape(3, 3)
 
 
 def point_stress_direction(rho0, mu, K, tau, B, dtau, dB, shear_a=-1.0):
@@ -248,16 +274,21 @@ class Problem:
                                   _ptr(st.vhat))
         if rc != 0:
             raise ValueError("degenerate cell in the initial mesh")
-        self.state = st
         self.params = params if params is not None else default_params(w.c_cfl)
+        if self.params.eos == 1:
+            # stiffened gas at rest pressure p = 0 (reading R31):
+            # e = |v|^2 / 2 + gamma p_inf tau / (gamma - 1), Psi_s(B = I) = 0
+            g, pinf = self.params.sg_gamma, self.params.sg_pinf
+            st.e = st.e + g * pinf * st.tau / (g - 1.0)
+        self.state = st
         self.dt_prev = 0.0
         self.t = 0.0
 
     def initial_dt(self):
         s = self.state
+        ins = [_f64(a) for a in (s.x, s.tau, s.v, s.e, s.B)]
         return lib().orc_initial_dt(self.mesh.h, _ptr(self.rho0), _ptr(self.mu), _ptr(self.K),
-                                    _ptr(s.x), _ptr(s.tau), _ptr(self.m),
-                                    C.byref(self.params))
+                                    *[_ptr(a) for a in ins], _ptr(self.m), C.byref(self.params))
 
     def step(self, dt, mask=None, replay=False, state=None):
         """Advance ``state`` (default: the held state) by ``dt``.  Returns
@@ -322,13 +353,26 @@ class Problem:
                           _ptr(tau_s), _ptr(v_s), _ptr(B_s), _ptr(T_s), _ptr(z_s))
         return dict(tau=tau_s, v=v_s, B=B_s, T=T_s, z=z_s)
 
+    def predict_eos(self, dt, mask=None, state=None):
+        """Corner states with this problem's equation of state: (tau*,
+        eps*, T* [.., 3, 3], z*), each [n_cells, nv, ...]."""
+        s = self.state if state is None else state
+        nc, nv = self.mesh.nc, self.dim + 1
+        mk = np.zeros(nc, np.uint8) if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+        ts, es, zs = np.zeros(nc * nv), np.zeros(nc * nv), np.zeros(nc * nv)
+        Ts = np.zeros(nc * nv * 9)
+        ins = [_f64(a) for a in (s.x, s.tau, s.v, s.e, s.B)]
+        lib().orc_predict_eos(self.mesh.h, _ptr(self.rho0), _ptr(self.mu), _ptr(self.K), *[_ptr(a) for a in ins],
+                              float(dt), C.byref(self.params), mk.ctypes.data_as(_U8), _ptr(ts), _ptr(es),
+                              _ptr(Ts), _ptr(zs))
+        return ts.reshape(nc, nv), es.reshape(nc, nv), Ts.reshape(nc, nv, 3, 3), zs.reshape(nc, nv)
+
     def diagnostics(self, state=None):
         s = self.state if state is None else state
         info = Info()
         ins = [_f64(a) for a in (s.tau, s.v, s.e, s.B)]
         lib().orc_diagnostics(self.mesh.h, _ptr(self.rho0), _ptr(self.mu), _ptr(self.K),
-                              _ptr(self.m), *[_ptr(a) for a in ins], C.byref(info),
-                              float(self.params.shear_a))
+                              _ptr(self.m), *[_ptr(a) for a in ins], C.byref(info), C.byref(self.params))
         return info.as_dict()
 
 
