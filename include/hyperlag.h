@@ -74,6 +74,19 @@ typedef struct {
     double shear_a; /* shear energy family (eq. familiy_energies), in
                        [-1, 1/2] (the hyperbolic range): -1 neo-Hookean
                        (the default), 0 the paper's non-linear law          */
+    int32_t eos;    /* volumetric part: 0 the energy of eq. EOS_neoHook with
+                       K = lambda + 2 mu / 3 (default); 1 the stiffened gas
+                       (eq. EOS_stiffened_gas): p = (gamma - 1)(eps - Psi_s)
+                       / tau - gamma p_inf with eps = e - |v|^2 / 2 and Psi_s
+                       the shear energy, sound speed a^2 = tau (gamma (p +
+                       p_inf) + 4 mu / 3), eps reconstructed and advanced by
+                       d eps/dt = tau T : grad v in the predictor, a state
+                       with p + p_inf <= 0 troubled, hl_state_init at p = 0
+                       (e += gamma p_inf tau / (gamma - 1)).  eos 1 needs
+                       cascade 0 or 2, gamma > 1, p_inf >= 0               */
+    int32_t reserved;
+    double sg_gamma;/* stiffened-gas gamma (default 2.2, the droplet test)  */
+    double sg_pinf; /* stiffened-gas p_inf (default 1e6)                    */
 } hl_params;
 
 /* Per-step report.  Filled by hl_step / hl_step_replay when non-NULL. */

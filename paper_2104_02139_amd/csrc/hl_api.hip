@@ -165,12 +165,18 @@ hl_params default_params(int dim) {
     p.detect = 1;
     p.cascade = 2;
     p.shear_a = -1.0;
+    p.eos = 0;
+    p.reserved = 0;
+    p.sg_gamma = 2.2;
+    p.sg_pinf = 1e6;
     return p;
 }
 
 bool params_valid(const hl_params &p) {
+    const bool sg_ok = p.eos == 0 || (p.eos == 1 && p.sg_gamma > 1.0 && std::isfinite(p.sg_gamma) &&
+                                      p.sg_pinf >= 0.0 && std::isfinite(p.sg_pinf) && p.cascade != 3);
     return p.c_cfl > 0 && p.c_v > 0 && p.c_i >= 0 && p.delta0 >= 0 && p.delta1 >= 0 && p.eps_tol >= 0 &&
-           (p.cascade == 0 || p.cascade == 2 || p.cascade == 3) && p.shear_a >= -1.0 && p.shear_a <= 0.5;
+           (p.cascade == 0 || p.cascade == 2 || p.cascade == 3) && p.shear_a >= -1.0 && p.shear_a <= 0.5 && sg_ok;
 }
 
 void drop_graphs(hl_ctx *c) {
@@ -459,6 +465,9 @@ hl::StepArgs make_args(hl_ctx *c, int src) {
     a.detect = c->prm.detect;
     a.cascade = c->prm.cascade == 3 ? 3 : 2;
     a.shear_a = c->prm.shear_a;
+    a.eos = c->prm.eos;
+    a.sg_gamma = c->prm.sg_gamma;
+    a.sg_pinf = c->prm.sg_pinf;
     a.limited = a.cascade == 3 ? 1 : 0;
     a.ld_off = c->ld.off;
     a.ld_cell = c->ld.cell;
@@ -1755,6 +1764,8 @@ hl_status hl_state_init(hl_ctx *c, const double *rho0, const double *mu, const d
             k2 += vc[cc * d + i] * vc[cc * d + i];
         }
         e[cc] = 0.5 * k2;
+        // stiffened gas at rest pressure p = 0: eps = gamma p_inf tau / (gamma - 1)
+        if (prm.eos == 1) e[cc] += prm.sg_gamma * prm.sg_pinf * tau[cc] / (prm.sg_gamma - 1.0);
         for (int s = 0; s < d; ++s) Bs[s * nc + cc] = 1.0;  // diagonal comps first
     }
     // carried node velocity projected on the allowed directions
@@ -1933,10 +1944,10 @@ hl_status hl_upload_field(hl_ctx *c, int field, const void *in, int64_t count, i
 hl_status hl_forward_record(hl_ctx *c, int nsteps, int ckpt_every) {
     if (!c || nsteps < 1 || ckpt_every < 1) return HL_E_INVALID;
     if (!c->have_state) return HL_E_STATE;
-    if (c->prm.cascade == 3 || c->prm.shear_a != -1.0 || c->ld.n > 0 || c->ct.n > 0) {
+    if (c->prm.cascade == 3 || c->prm.shear_a != -1.0 || c->prm.eos != 0 || c->ld.n > 0 || c->ct.n > 0) {
         std::snprintf(g_last_error, sizeof g_last_error,
                       "the adjoint covers the two-level cascade and the neo-Hookean law without boundary loads "
-                      "or contact (cascade 2, shear_a -1)");
+                      "or contact (cascade 2, shear_a -1, eos 0)");
         return HL_E_INVALID;
     }
     if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;

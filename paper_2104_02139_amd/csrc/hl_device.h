@@ -35,7 +35,15 @@ struct Dims {
     static constexpr int O_WMIN = NA_BASE;
     static constexpr int O_WMAX = O_WMIN + NW;
     static constexpr int NA = O_WMAX + NW;           // 72 (3D) / 38 (2D)
-    static constexpr int GR = D == 3 ? 16 : 10;      // gather record: W, centroid, pad
+    static constexpr int GR = D == 3 ? 16 : 10;      // gather record: W, centroid, eps, pad
+    // the stiffened gas (R31) also reconstructs eps = e - |v|^2 / 2: slot
+    // G_EPS of the gather record; sum eps and sum y eps in the aggregates
+    // after the base record (the W bounds of the limited level are not
+    // used with it)
+    static constexpr int G_EPS = NW + D;
+    static constexpr int O_SE = NA_BASE;
+    static constexpr int O_SYE = NA_BASE + 1;
+    static constexpr int NA_SG = NA_BASE + 1 + D + (D == 3 ? 0 : 1);  // whole pairs
 };
 
 // index of the symmetric entry (i, j) in the 6-vector
@@ -238,6 +246,66 @@ HL_HD double free_energy_family(double rho0, double mu, double K, double a, doub
 }
 
 // a = sqrt(tau (K_t + 4 mu / 3)), K_t = (K/2)(J + (1 - ln J)/J) = -J dp/dJ
+// ------------------------------------------------- stiffened gas (R31)
+// The stiffened gas (eq. EOS_stiffened_gas) in place of the volumetric
+// energy: with Psi_s the shear energy of the family (the family's energy
+// with K = 0) and eps the specific internal energy,
+//   p = (gamma - 1) (eps - Psi_s) / tau - gamma p_inf,
+//   T = T_s - p I (T_s the family's stress with K = 0),
+//   a^2 = tau (gamma (p + p_inf) + 4 mu / 3).
+HL_HD double shear_energy6(double rho0, double mu, double a, double tau, const double b[6]) {
+    return free_energy_family(rho0, mu, 0.0, a, tau, b);
+}
+
+// derivative of Psi_s along (dtau, db): mu/(4 rho0) [-2a dI1b + (2/3)(1+a) I2b dI2b]
+HL_HD double shear_energy_dir6(double rho0, double mu, double a, double tau, const double b[6], double dtau,
+                               const double db[6]) {
+    const double J = rho0 * tau, dJ = rho0 * dtau;
+    const double cJ = cbrt(J);
+    const double s = 1.0 / (cJ * cJ);
+    double bb[6], dbb[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        bb[q] = s * b[q];
+        dbb[q] = s * db[q] - (2.0 / 3.0) * (dJ / J) * bb[q];
+    }
+    const double trB = bb[0] + bb[1] + bb[2], trdB = dbb[0] + dbb[1] + dbb[2];
+    const double BdB = bb[0] * dbb[0] + bb[1] * dbb[1] + bb[2] * dbb[2] +
+                       2.0 * (bb[3] * dbb[3] + bb[4] * dbb[4] + bb[5] * dbb[5]);
+    const double I2 = inv2_6(bb);
+    return mu / (4.0 * rho0) * (-2.0 * a * trdB + (2.0 / 3.0) * (1.0 + a) * I2 * (trB * trdB - BdB));
+}
+
+HL_HD double sg_pressure6(double rho0, double mu, double a, double gam, double pinf, double tau, const double b[6],
+                          double eps) {
+    return (gam - 1.0) * (eps - shear_energy6(rho0, mu, a, tau, b)) / tau - gam * pinf;
+}
+
+HL_HD void stress6_sg(double rho0, double mu, double a, double gam, double pinf, double tau, const double b[6],
+                      double eps, double t[6]) {
+    stress6_family(rho0, mu, 0.0, a, tau, b, t);
+    const double p = sg_pressure6(rho0, mu, a, gam, pinf, tau, b, eps);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) t[q] -= p;
+}
+
+HL_HD double sound_sg(double rho0, double mu, double a, double gam, double pinf, double tau, const double b[6],
+                      double eps) {
+    return sqrt(tau * (gam * (sg_pressure6(rho0, mu, a, gam, pinf, tau, b, eps) + pinf) + (4.0 / 3.0) * mu));
+}
+
+// derivative of stress6_sg along (dtau, db, deps):
+//   dT = dT_s - dp I, dp = (gamma - 1) [(deps - dPsi_s) / tau - (eps - Psi_s) dtau / tau^2]
+HL_HD void stress6_dir_sg(double rho0, double mu, double a, double gam, double pinf, double tau, const double b[6],
+                          double eps, double dtau, const double db[6], double deps, double dt[6]) {
+    stress6_dir_family(rho0, mu, 0.0, a, tau, b, dtau, db, dt);
+    const double psi = shear_energy6(rho0, mu, a, tau, b);
+    const double dpsi = shear_energy_dir6(rho0, mu, a, tau, b, dtau, db);
+    const double dp = (gam - 1.0) * ((deps - dpsi) / tau - (eps - psi) * dtau / (tau * tau));
+#pragma unroll
+    for (int q = 0; q < 3; ++q) dt[q] -= dp;
+}
+
 HL_HD double sound(double rho0, double mu, double K, double tau) {
     double J = rho0 * tau;
     double Kt = 0.5 * K * (J + (1.0 - log(J)) / J);

@@ -41,6 +41,8 @@ struct StepArgs {
     int detect;
     int cascade;   // 2: a flagged cell goes to first order; 3: to limited first
     double shear_a;  // shear energy family parameter; -1: neo-Hookean
+    int eos;       // 1: stiffened gas (gamma, p_inf) for the volumetric part
+    double sg_gamma, sg_pinf;
     int limited;   // 0: no limited cells; 1: they appear in the MOOD passes
                    // (node W bounds, limiter in the pass kernels); 2: also in
                    // the full-mesh pass (replayed levels)

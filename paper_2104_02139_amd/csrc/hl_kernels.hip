@@ -82,14 +82,19 @@ __device__ __forceinline__ void pack_cell(const StepArgs &a, const int64_t c) {
     }
     double r[Dm::GR];
     r[0] = a.tau[c];
+    double k2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < D; ++i) r[1 + i] = a.v[i * nc + c];
+    for (int i = 0; i < D; ++i) {
+        r[1 + i] = a.v[i * nc + c];
+        k2 += r[1 + i] * r[1 + i];
+    }
 #pragma unroll
     for (int q = 0; q < Dm::NB; ++q) r[1 + D + q] = a.B[q * nc + c];
 #pragma unroll
     for (int i = 0; i < D; ++i) r[Dm::NW + i] = s[i] * (1.0 / (D + 1));
 #pragma unroll
     for (int q = Dm::NW + D; q < Dm::GR; ++q) r[q] = 0.0;
+    if (a.eos) r[Dm::G_EPS] = a.e[c] - 0.5 * k2;
     double2 *o = reinterpret_cast<double2 *>(a.xc + c * Dm::GR);
 #pragma unroll
     for (int q = 0; q < Dm::GR / 2; ++q) o[q] = make_double2(r[2 * q], r[2 * q + 1]);
@@ -193,6 +198,10 @@ __device__ __forceinline__ void node_agg_group(const StepArgs &a, const int64_t 
 #pragma unroll
             for (int i = 0; i < D; ++i)
                 if (i <= k) o[Dm::O_SYY + midx<D>(i, k)] = Sy[i];
+        } else if (v == Dm::G_EPS && a.eos) {
+            o[Dm::O_SE] = S;
+#pragma unroll
+            for (int i = 0; i < D; ++i) o[Dm::O_SYE + i] = Sy[i];
         }
     };
     put(v0, Sa, Sya);
@@ -211,6 +220,7 @@ __device__ __forceinline__ void node_agg_group(const StepArgs &a, const int64_t 
         o[0] = n;
         o[Dm::O_RMM] = rmin;
         o[Dm::O_RMM + 1] = rmax;
+        if (a.eos && Dm::NA_SG > Dm::O_SYE + D) o[Dm::NA_SG - 1] = 0.0;  // pad to a whole pair
     }
 }
 
@@ -237,7 +247,7 @@ __global__ __launch_bounds__(256) void k_node_agg(StepArgs a, WorkList w) {
             __syncthreads();
             if (act) {
                 double2 *b = reinterpret_cast<double2 *>(a.agg) + p;
-                const int np = (a.limited ? Dm::NA : Dm::NA_BASE) / 2;
+                const int np = (a.limited ? Dm::NA : (a.eos ? Dm::NA_SG : Dm::NA_BASE)) / 2;
                 for (int j = l; j < np; j += AGG_G)
                     b[(int64_t)j * nn] = make_double2(sh[g][2 * j], sh[g][2 * j + 1]);
             }
@@ -284,8 +294,10 @@ __device__ __forceinline__ constexpr int bslot(int s) {
 // ------------------------------------------ predictor + corner records
 // Reconstruction (R8), ADER midpoint predictor (Section 3.4, reading R7),
 // corner stress and impedance (R5), corner matrix M_cp (eq. Mcp, R4) and
-// r_cp = M_cp v*_cp - T*_cp C_cp (eq. nodal_solver^n).
-template <int D, bool LIM, bool FAM>
+// r_cp = M_cp v*_cp - T*_cp C_cp (eq. nodal_solver^n).  SG: the stiffened
+// gas (R31) also reconstructs eps = e - |v|^2 / 2, advances it with
+// d eps/dt = tau T : grad v and carries it through div T.
+template <int D, bool LIM, bool FAM, bool SG>
 __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c) {
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
@@ -332,11 +344,21 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
     for (int w = 0; w < Dm::NW; ++w)
 #pragma unroll
         for (int i = 0; i < D; ++i) grad[w][i] = 0.0;
+    // stiffened gas: eps at the centroid (advanced by dt/2 below) and its slope
+    double eps0 = 0.0, geps[D] = {};
+    if (SG) {
+        double k2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) k2 += W0[1 + i] * W0[1 + i];
+        eps0 = a.e[c] - 0.5 * k2;
+    }
+    double eps_mid = eps0;
 
     if (p1) {
         // ---- least-squares normal equations from the node aggregates (R8)
         double A[Dm::NMS] = {};
         double rhs[Dm::NW][D] = {};
+        double rhs_e[D] = {};
         double visits = 0.0;  // neighbour visits: sum over nodes of (n - 1)
 #pragma unroll 1
         for (int k = 0; k < NV; ++k) {
@@ -362,6 +384,12 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
                 for (int j = 0; j < D; ++j)
                     rhs[w][j] += ag[Dm::O_SYW + w * D + j] - u[j] * sw - Sy[j] * W0[w] + n * u[j] * W0[w];
             }
+            if (SG) {
+                const double se = ag[Dm::O_SE];
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    rhs_e[j] += ag[Dm::O_SYE + j] - u[j] * se - Sy[j] * eps0 + n * u[j] * eps0;
+            }
         }
         double inv[Dm::NMS];
         double det, tr = 0.0;
@@ -383,6 +411,15 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
                 for (int j = 0; j < D; ++j) s += inv[midx<D>(i, j)] * rhs[w][j];
                 grad[w][i] = ok ? s : 0.0;
             }
+        if (SG) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) s += inv[midx<D>(i, j)] * rhs_e[j];
+                geps[i] = ok ? s : 0.0;
+            }
+        }
 
         // ---- Barth-Jespersen limiter (the cascade's second scheme, Section
         // 3.5; reading R26): per scalar, bounds over {c} and its stencil from
@@ -441,8 +478,30 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
             for (int k = 0; k < 3; ++k) y += G[i][k] * B3[k][j] + B3[i][k] * G[j][k];
             W0[1 + D + q] += h * y;
         }
-        // div T by the chain rule through T(tau, B)
-        if (FAM) {
+        // div T by the chain rule through T(tau, B) (and eps for the gas)
+        if (SG) {
+            double divT[D] = {}, Tc[6];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                double db[6], dT[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) db[q] = gB(q, j);
+                stress6_dir_sg(rho0, mu, a.shear_a, a.sg_gamma, a.sg_pinf, tau, b, eps0, grad[0][j], db, geps[j],
+                               dT);
+#pragma unroll
+                for (int i = 0; i < D; ++i) divT[i] += dT[sidx(i, j)];
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i) W0[1 + i] += h * tau * divT[i];
+            // d eps / dt = tau T : G
+            stress6_sg(rho0, mu, a.shear_a, a.sg_gamma, a.sg_pinf, tau, b, eps0, Tc);
+            double TG = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) TG += Tc[sidx(i, j)] * G[i][j];
+            eps_mid = eps0 + h * tau * TG;
+        } else if (FAM) {
             // shear energy family: column j of grad T from the derivative of
             // T along (d tau / d x_j, d B / d x_j)
             double divT[D] = {};
@@ -517,12 +576,20 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
             bk[4] = 0.0;
             bk[5] = 0.0;
         }
-        double T[6];
-        if (FAM)
-            stress6_family(rho0, mu, K, a.shear_a, Wk[0], bk, T);
-        else
-            stress6(rho0, mu, K, Wk[0], bk, T);
-        const double z = sound(rho0, mu, K, Wk[0]) / Wk[0];
+        double T[6], z;
+        if (SG) {
+            double ek = eps_mid;
+#pragma unroll
+            for (int j = 0; j < D; ++j) ek += geps[j] * X[k][j];
+            stress6_sg(rho0, mu, a.shear_a, a.sg_gamma, a.sg_pinf, Wk[0], bk, ek, T);
+            z = sound_sg(rho0, mu, a.shear_a, a.sg_gamma, a.sg_pinf, Wk[0], bk, ek) / Wk[0];
+        } else {
+            if (FAM)
+                stress6_family(rho0, mu, K, a.shear_a, Wk[0], bk, T);
+            else
+                stress6(rho0, mu, K, Wk[0], bk, T);
+            z = sound(rho0, mu, K, Wk[0]) / Wk[0];
+        }
         const double rk = 1.0 / g.cn[k];
         double M[Dm::NMS];
 #pragma unroll
@@ -543,18 +610,18 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
     }
 }
 
-template <int D, bool LOOP, bool LIM, bool FAM>
+template <int D, bool LOOP, bool LIM, bool FAM, bool SG>
 __global__ __launch_bounds__(256) void k_predict(StepArgs a, WorkList w) {
-    for_items<LOOP>(w, [&](int64_t c) { predict_cell<D, LIM, FAM>(a, c); });
+    for_items<LOOP>(w, [&](int64_t c) { predict_cell<D, LIM, FAM, SG>(a, c); });
 }
 
 // list-driven variant: the cells just flagged, recomputed at first order
-template <int D, bool LIM, bool FAM>
+template <int D, bool LIM, bool FAM, bool SG>
 __global__ __launch_bounds__(256) void k_predict_list(StepArgs a, const int32_t *__restrict__ list,
                                                       const unsigned *__restrict__ count) {
     const int64_t n = *count;
     for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x)
-        predict_cell<D, LIM, FAM>(a, list[i]);
+        predict_cell<D, LIM, FAM, SG>(a, list[i]);
 }
 
 // ---------------------------------------------------------- node solve
@@ -896,7 +963,9 @@ __global__ __launch_bounds__(256) void k_contact_eval(StepArgs a, ContactArgs k)
 // total energy (eqs. v_c^n, e_c^n), tau = V(x^{n+1}) / m (reading R12), B by
 // Crank-Nicolson (P1) or Euler (P0) (eqs. CN_B, firstB; R10, R11), then
 // detection (eqs. PAD, RDMP; R16, R17) and the per-cell time-step bounds.
-template <int D>
+// SG: the stiffened gas (R31) -- eps in the gather record, p + p_inf > 0 in
+// the admissibility test, its sound speed in the time-step bound.
+template <int D, bool SG>
 __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) {
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
@@ -1038,6 +1107,12 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
         for (int i = 0; i < D; ++i) r[Dm::NW + i] = xc1[i];
 #pragma unroll
         for (int q = Dm::NW + D; q < Dm::GR; ++q) r[q] = 0.0;
+        if (SG) {
+            double kk = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) kk += v1[i] * v1[i];
+            r[Dm::G_EPS] = e1 - 0.5 * kk;
+        }
         double2 *o = reinterpret_cast<double2 *>(a.xc + c * Dm::GR);
 #pragma unroll
         for (int q = 0; q < Dm::GR / 2; ++q) o[q] = make_double2(r[2 * q], r[2 * q + 1]);
@@ -1053,8 +1128,12 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
 #pragma unroll
     for (int i = 0; i < D; ++i) k2 += v1[i] * v1[i];
     const double eps = e1 - 0.5 * k2;
-    const bool pad_bad = !fin || !(tau1 > 0.0) || !(det6(b1) > 0.0) ||
-                         (eps < -a.eps_tol * (fabs(e1) + 0.5 * k2));
+    bool pad_bad = !fin || !(tau1 > 0.0) || !(det6(b1) > 0.0) || (eps < -a.eps_tol * (fabs(e1) + 0.5 * k2));
+    double p_sg = 0.0;
+    if (SG) {
+        p_sg = sg_pressure6(a.rho0[c], a.mu[c], a.shear_a, a.sg_gamma, a.sg_pinf, tau1, b1, eps);
+        pad_bad = pad_bad || !(p_sg + a.sg_pinf > 0.0);
+    }
     if (p1 && a.detect) {
         double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
 #pragma unroll
@@ -1072,22 +1151,23 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
     a.pstat[c] = (!p1 && pad_bad) ? 1 : 0;
 
     // ---- time-step bounds at t^{n+1} (eq. CFL2; R20, R21)
-    const double ac = sound(a.rho0[c], a.mu[c], a.K[c], tau1);
+    const double ac = SG ? sqrt(tau1 * (a.sg_gamma * (p_sg + a.sg_pinf) + (4.0 / 3.0) * a.mu[c]))
+                         : sound(a.rho0[c], a.mu[c], a.K[c], tau1);
     const double V0 = m * a.tau[c], V1 = m * tau1;
     const double dV = fabs(V1 - V0);
     a.dtc[c] = Lc / ac;
     a.dtc[nc + c] = dV > 0.0 ? V1 / dV : __builtin_huge_val();
 }
 
-template <int D, bool LOOP>
+template <int D, bool LOOP, bool SG>
 __global__ __launch_bounds__(256) void k_update(StepArgs a, WorkList w) {
-    for_items<LOOP>(w, [&](int64_t c) { update_cell<D>(a, c); });
+    for_items<LOOP>(w, [&](int64_t c) { update_cell<D, SG>(a, c); });
 }
 
-template <int D>
+template <int D, bool SG>
 __global__ __launch_bounds__(256) void k_update_list(StepArgs a) {
     const int64_t n = a.counters[CNT_CELLS];
-    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) update_cell<D>(a, a.clist[i]);
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) update_cell<D, SG>(a, a.clist[i]);
 }
 
 // ------------------------------------------------------ MOOD bookkeeping
@@ -1274,11 +1354,12 @@ __global__ void k_dt_finalize(int n_mesh, const double *__restrict__ red, const 
 
 // acoustic bound of the current state (initial time step)
 template <int D>
-__global__ __launch_bounds__(256) void k_acoustic(int64_t nc, int64_t nn, const int32_t *__restrict__ c2n,
-                                                  const double *__restrict__ x, const double *__restrict__ tau,
-                                                  const double *__restrict__ rho0, const double *__restrict__ mu,
-                                                  const double *__restrict__ K, double *__restrict__ dtc) {
+__global__ __launch_bounds__(256) void k_acoustic(StepArgs a) {
     constexpr int NV = D + 1;
+    const int64_t nc = a.nc, nn = a.nn;
+    const int32_t *__restrict__ c2n = a.c2n;
+    const double *__restrict__ x = a.x;
+    double *__restrict__ dtc = a.dtc;
     int64_t c = gtid();
     if (c >= nc) return;
     double X[NV][D];
@@ -1293,7 +1374,17 @@ __global__ __launch_bounds__(256) void k_acoustic(int64_t nc, int64_t nn, const 
     double S = 0.0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) S += g.cn[k];
-    dtc[c] = 2.0 * g.V / S / sound(rho0[c], mu[c], K[c], tau[c]);
+    double ac;
+    if (a.eos) {
+        double b[6], k2 = 0.0;
+        load_B6<D>(a.B, nc, c, b);
+#pragma unroll
+        for (int i = 0; i < D; ++i) k2 += a.v[i * nc + c] * a.v[i * nc + c];
+        ac = sound_sg(a.rho0[c], a.mu[c], a.shear_a, a.sg_gamma, a.sg_pinf, a.tau[c], b, a.e[c] - 0.5 * k2);
+    } else {
+        ac = sound(a.rho0[c], a.mu[c], a.K[c], a.tau[c]);
+    }
+    dtc[c] = 2.0 * g.V / S / ac;
     dtc[nc + c] = __builtin_huge_val();
 }
 
@@ -1307,7 +1398,7 @@ __global__ __launch_bounds__(256) void k_diag(int64_t nc, const double *__restri
                                               const double *__restrict__ v, const double *__restrict__ e,
                                               const double *__restrict__ B, const double *__restrict__ rho0,
                                               const double *__restrict__ mu, const double *__restrict__ K,
-                                              const uint8_t *__restrict__ mask, double shear_a,
+                                              const uint8_t *__restrict__ mask, double shear_a, int eos,
                                               double *__restrict__ part) {
     __shared__ double sh[NDIAG][256];
     int64_t c = gtid();
@@ -1330,7 +1421,8 @@ __global__ __launch_bounds__(256) void k_diag(int64_t nc, const double *__restri
         double lj = log(J);
         double cJ = cbrt(J);
         double I1b = (b[0] + b[1] + b[2]) / (cJ * cJ);
-        double psi = shear_a == -1.0
+        double psi = eos ? shear_energy6(rho0[c], mu[c], shear_a, tau[c], b)   // stiffened gas: Psi_s
+                     : shear_a == -1.0
                          ? K[c] / (4.0 * rho0[c]) * ((J - 1.0) * (J - 1.0) + lj * lj) +
                                mu[c] / (2.0 * rho0[c]) * (I1b - 3.0)
                          : free_energy_family(rho0[c], mu[c], K[c], shear_a, tau[c], b);
@@ -1386,14 +1478,21 @@ __global__ void k_soa_to_aos(int64_t n, int w, const double *__restrict__ in, do
 // stress of the current state for queries: 3D (11,22,33,12,13,23),
 // 2D (11,22,12,33), AoS
 template <int D>
-__global__ void k_stress_query(int64_t nc, const double *__restrict__ tau, const double *__restrict__ B,
-                               const double *__restrict__ rho0, const double *__restrict__ mu,
-                               const double *__restrict__ K, double shear_a, double *__restrict__ out) {
+__global__ void k_stress_query(StepArgs a, double *__restrict__ out) {
+    const int64_t nc = a.nc;
+    const double *__restrict__ tau = a.tau, *__restrict__ rho0 = a.rho0, *__restrict__ mu = a.mu,
+                                *__restrict__ K = a.K;
+    const double shear_a = a.shear_a;
     int64_t c = gtid();
     if (c >= nc) return;
     double b[6], t[6];
-    load_B6<D>(B, nc, c, b);
-    if (shear_a == -1.0)
+    load_B6<D>(a.B, nc, c, b);
+    if (a.eos) {
+        double k2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) k2 += a.v[i * nc + c] * a.v[i * nc + c];
+        stress6_sg(rho0[c], mu[c], shear_a, a.sg_gamma, a.sg_pinf, tau[c], b, a.e[c] - 0.5 * k2, t);
+    } else if (shear_a == -1.0)
         stress6(rho0[c], mu[c], K[c], tau[c], b, t);
     else
         stress6_family(rho0[c], mu[c], K[c], shear_a, tau[c], b, t);
@@ -1430,8 +1529,13 @@ template <int D>
 void launch_predict(const StepArgs &a, const Sched &k, hipStream_t s) {
     if (!k.w.n_items) return;
     const bool lim = a.limited == 2, fam = a.shear_a != -1.0;
-#define HL_PREDICT_LAUNCH(L, M, F) k_predict<D, L, M, F><<<k.grid, k.block, 0, s>>>(a, k.w)
-    if (k.loop) {
+#define HL_PREDICT_LAUNCH(L, M, F) k_predict<D, L, M, F, false><<<k.grid, k.block, 0, s>>>(a, k.w)
+    if (a.eos) {  // stiffened gas: never with the limited level
+        if (k.loop)
+            k_predict<D, true, false, false, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+        else
+            k_predict<D, false, false, false, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+    } else if (k.loop) {
         if (fam)
             lim ? HL_PREDICT_LAUNCH(true, true, true) : HL_PREDICT_LAUNCH(true, false, true);
         else
@@ -1470,9 +1574,11 @@ template <int D>
 void launch_update(const StepArgs &a, const Sched &k, hipStream_t s) {
     if (!k.w.n_items) return;
     if (k.loop)
-        k_update<D, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+        a.eos ? k_update<D, true, true><<<k.grid, k.block, 0, s>>>(a, k.w)
+              : k_update<D, true, false><<<k.grid, k.block, 0, s>>>(a, k.w);
     else
-        k_update<D, false><<<k.grid, k.block, 0, s>>>(a, k.w);
+        a.eos ? k_update<D, false, true><<<k.grid, k.block, 0, s>>>(a, k.w)
+              : k_update<D, false, false><<<k.grid, k.block, 0, s>>>(a, k.w);
 }
 template <int D>
 void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned *fcount, int64_t nflag,
@@ -1483,19 +1589,24 @@ void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned 
     const int64_t ncells = std::min<int64_t>(a.nc, nnodes * max_deg);
     k_apply_list<<<grid(nflag), 256, 0, s>>>(const_cast<uint8_t *>(a.mask), flist, fcount, a.cascade);
     const bool fam = a.shear_a != -1.0;
-    if (a.limited)
-        fam ? k_predict_list<D, true, true><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
-            : k_predict_list<D, true, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+    if (a.eos)
+        k_predict_list<D, false, false, true><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+    else if (a.limited)
+        fam ? k_predict_list<D, true, true, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
+            : k_predict_list<D, true, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
     else
-        fam ? k_predict_list<D, false, true><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
-            : k_predict_list<D, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+        fam ? k_predict_list<D, false, true, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
+            : k_predict_list<D, false, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
     k_mark_nodes<D><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
     if (a.ld_off)
         k_node_solve_list<D, true><<<grid(nnodes), 256, 0, s>>>(a);
     else
         k_node_solve_list<D, false><<<grid(nnodes), 256, 0, s>>>(a);
     k_mark_cells<D><<<grid(nnodes), 256, 0, s>>>(a);
-    k_update_list<D><<<grid(ncells), 256, 0, s>>>(a);
+    if (a.eos)
+        k_update_list<D, true><<<grid(ncells), 256, 0, s>>>(a);
+    else
+        k_update_list<D, false><<<grid(ncells), 256, 0, s>>>(a);
 }
 void launch_step_begin(unsigned *counters, double *dt_cur, const double *dt_next, int n_mesh, int copy_dt,
                        hipStream_t s) {
@@ -1521,13 +1632,14 @@ void launch_dt_finalize(int n_mesh, const double *red, const double *dt, const h
 }
 template <int D>
 void launch_acoustic(const StepArgs &a, hipStream_t s) {
-    if (a.nc) k_acoustic<D><<<nblk(a.nc), 256, 0, s>>>(a.nc, a.nn, a.c2n, a.x, a.tau, a.rho0, a.mu, a.K, a.dtc);
+    if (a.nc) k_acoustic<D><<<nblk(a.nc), 256, 0, s>>>(a);
 }
 template <int D>
 int64_t launch_diag(const StepArgs &a, const double *tau, const double *v, const double *e, const double *B,
                     double *part, double *out, hipStream_t s) {
     int64_t nb = nblk(a.nc);
-    if (a.nc) k_diag<D><<<nb, 256, 0, s>>>(a.nc, a.mass, tau, v, e, B, a.rho0, a.mu, a.K, a.mask, a.shear_a, part);
+    if (a.nc)
+        k_diag<D><<<nb, 256, 0, s>>>(a.nc, a.mass, tau, v, e, B, a.rho0, a.mu, a.K, a.mask, a.shear_a, a.eos, part);
     k_diag_finalize<<<NDIAG, 256, 0, s>>>(a.nc ? nb : 0, part, out);
     return nb;
 }
@@ -1542,7 +1654,7 @@ void launch_soa_to_aos(int64_t n, int w, const double *in, double *out, hipStrea
 }
 template <int D>
 void launch_stress_query(const StepArgs &a, double *out, hipStream_t s) {
-    if (a.nc) k_stress_query<D><<<nblk(a.nc), 256, 0, s>>>(a.nc, a.tau, a.B, a.rho0, a.mu, a.K, a.shear_a, out);
+    if (a.nc) k_stress_query<D><<<nblk(a.nc), 256, 0, s>>>(a, out);
 }
 
 template void launch_centroids<2>(const StepArgs &, const Sched &, hipStream_t);

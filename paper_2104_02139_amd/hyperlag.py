@@ -36,15 +36,18 @@ STAGES = ("pack", "node_agg", "predict", "node_solve", "update")
 class Params(C.Structure):
     _fields_ = [("c_cfl", C.c_double), ("c_v", C.c_double), ("c_i", C.c_double),
                 ("delta0", C.c_double), ("delta1", C.c_double), ("eps_tol", C.c_double),
-                ("detect", C.c_int32), ("cascade", C.c_int32), ("shear_a", C.c_double)]
+                ("detect", C.c_int32), ("cascade", C.c_int32), ("shear_a", C.c_double),
+                ("eos", C.c_int32), ("reserved", C.c_int32), ("sg_gamma", C.c_double), ("sg_pinf", C.c_double)]
 
 
-def default_params(dim=3, detect=True, c_cfl=None, cascade=2, shear_a=-1.0):
+def default_params(dim=3, detect=True, c_cfl=None, cascade=2, shear_a=-1.0, eos=0, sg_gamma=2.2, sg_pinf=1e6):
     """Paper values (Sections 3.5, 3.6); cascade 2: P1 -> P0, 3: P1 -> P1
     with the Barth-Jespersen limiter -> P0; shear_a: shear energy family
-    (-1 neo-Hookean, 0 the paper's non-linear law)."""
+    (-1 neo-Hookean, 0 the paper's non-linear law); eos 1: the stiffened
+    gas with sg_gamma and sg_pinf."""
     return Params(c_cfl if c_cfl is not None else (0.4 if dim == 2 else 0.25),
-                  0.2, 0.1, 1e-4, 1e-3, 1e-12, 1 if detect else 0, int(cascade), float(shear_a))
+                  0.2, 0.1, 1e-4, 1e-3, 1e-12, 1 if detect else 0, int(cascade), float(shear_a),
+                  int(eos), 0, float(sg_gamma), float(sg_pinf))
 
 
 class StepInfo(C.Structure):
