@@ -615,15 +615,6 @@ __global__ __launch_bounds__(256) void k_predict(StepArgs a, WorkList w) {
     for_items<LOOP>(w, [&](int64_t c) { predict_cell<D, LIM, FAM, SG>(a, c); });
 }
 
-// list-driven variant: the cells just flagged, recomputed at first order
-template <int D, bool LIM, bool FAM, bool SG>
-__global__ __launch_bounds__(256) void k_predict_list(StepArgs a, const int32_t *__restrict__ list,
-                                                      const unsigned *__restrict__ count) {
-    const int64_t n = *count;
-    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x)
-        predict_cell<D, LIM, FAM, SG>(a, list[i]);
-}
-
 // ---------------------------------------------------------- node solve
 // M_p v*_p = sum_c (M_cp v*_cp - T*_cp C_cp) (eq. nodal_solver^n, readings
 // R14, R15); slip walls by Galerkin projection onto the allowed directions
@@ -908,11 +899,6 @@ __global__ __launch_bounds__(256) void k_node_solve(StepArgs a, WorkList w) {
     }
 }
 
-template <int D, bool LD>
-__global__ __launch_bounds__(256) void k_node_solve_list(StepArgs a) {
-    const int64_t n = a.counters[CNT_NODES];
-    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) node_solve_one<D, LD>(a, a.nlist[i]);
-}
 
 // ------------------------------------------------------------ contact
 // Candidate i of a rigid-plane contact takes constraint set state[i]: 0 its
@@ -1171,44 +1157,41 @@ __global__ __launch_bounds__(256) void k_update_list(StepArgs a) {
 }
 
 // ------------------------------------------------------ MOOD bookkeeping
-// Cells flagged in the last candidate drop to the next scheme of the cascade.
-__global__ __launch_bounds__(256) void k_apply_list(uint8_t *__restrict__ mask, const int32_t *__restrict__ list,
-                                                    const unsigned *__restrict__ count, int cascade) {
-    const int64_t n = *count;
-    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = list[i];
-        mask[c] = (cascade == 3 && mask[c] == 0) ? 1 : 2;  // next scheme of the cascade
-    }
-}
-
-// Nodes of the flagged cells, each listed once (stamp = this iteration).
-template <int D>
-__global__ __launch_bounds__(256) void k_mark_nodes(StepArgs a, const int32_t *__restrict__ list,
+// A sparse MOOD pass (Section 3.7) in three launches after k_pass_begin:
+// the flagged cells, the nodes they touch, the cells around those nodes.
+// First: every flagged cell drops to the next scheme of the cascade, its
+// corner records are recomputed at that level, and its nodes are listed
+// once (stamp = this pass).
+template <int D, bool LIM, bool FAM, bool SG>
+__global__ __launch_bounds__(256) void k_pass_cells(StepArgs a, const int32_t *__restrict__ list,
                                                     const unsigned *__restrict__ count) {
     const int64_t n = *count;
     const int32_t st = *a.stamp;
+    uint8_t *mask = const_cast<uint8_t *>(a.mask);
     for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = list[i];
+        const int32_t c = list[i];
+        mask[c] = (a.cascade == 3 && mask[c] == 0) ? 1 : 2;
+        predict_cell<D, LIM, FAM, SG>(a, c);
 #pragma unroll
         for (int k = 0; k <= D; ++k) {
-            const int32_t p = a.c2n[c * (D + 1) + k];
-            if (atomicExch(&a.nstamp[p], st) != st)
-                a.nlist[atomicAdd(&a.counters[CNT_NODES], 1u)] = p;
+            const int32_t p = a.c2n[(int64_t)c * (D + 1) + k];
+            if (atomicExch(&a.nstamp[p], st) != st) a.nlist[atomicAdd(&a.counters[CNT_NODES], 1u)] = p;
         }
     }
 }
 
-// Cells around the re-solved nodes, each listed once.
-template <int D>
-__global__ __launch_bounds__(256) void k_mark_cells(StepArgs a) {
+// Second: every listed node is solved again, and the cells around it are
+// listed once.
+template <int D, bool LD>
+__global__ __launch_bounds__(256) void k_pass_nodes(StepArgs a) {
     const int64_t n = a.counters[CNT_NODES];
     const int32_t st = *a.stamp;
     for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t p = a.nlist[i];
+        node_solve_one<D, LD>(a, p);
         for (int32_t q = a.n2c_off[p]; q < a.n2c_off[p + 1]; ++q) {
             const int32_t j = a.n2c[q] / (D + 1);
-            if (atomicExch(&a.cstamp[j], st) != st)
-                a.clist[atomicAdd(&a.counters[CNT_CELLS], 1u)] = j;
+            if (atomicExch(&a.cstamp[j], st) != st) a.clist[atomicAdd(&a.counters[CNT_CELLS], 1u)] = j;
         }
     }
 }
@@ -1587,22 +1570,19 @@ void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned 
     if (fixed_grid) nflag = std::min<int64_t>(a.nc, 256 * 1024);
     const int64_t nnodes = std::min<int64_t>(a.nn, (D + 1) * nflag);
     const int64_t ncells = std::min<int64_t>(a.nc, nnodes * max_deg);
-    k_apply_list<<<grid(nflag), 256, 0, s>>>(const_cast<uint8_t *>(a.mask), flist, fcount, a.cascade);
     const bool fam = a.shear_a != -1.0;
     if (a.eos)
-        k_predict_list<D, false, false, true><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+        k_pass_cells<D, false, false, true><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
     else if (a.limited)
-        fam ? k_predict_list<D, true, true, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
-            : k_predict_list<D, true, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+        fam ? k_pass_cells<D, true, true, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
+            : k_pass_cells<D, true, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
     else
-        fam ? k_predict_list<D, false, true, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
-            : k_predict_list<D, false, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
-    k_mark_nodes<D><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+        fam ? k_pass_cells<D, false, true, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
+            : k_pass_cells<D, false, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
     if (a.ld_off)
-        k_node_solve_list<D, true><<<grid(nnodes), 256, 0, s>>>(a);
+        k_pass_nodes<D, true><<<grid(nnodes), 256, 0, s>>>(a);
     else
-        k_node_solve_list<D, false><<<grid(nnodes), 256, 0, s>>>(a);
-    k_mark_cells<D><<<grid(nnodes), 256, 0, s>>>(a);
+        k_pass_nodes<D, false><<<grid(nnodes), 256, 0, s>>>(a);
     if (a.eos)
         k_update_list<D, true><<<grid(ncells), 256, 0, s>>>(a);
     else
