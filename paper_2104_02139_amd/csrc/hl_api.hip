@@ -82,6 +82,10 @@ struct hl_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // continuation: CONT_PASSES more sparse MOOD passes, per buffer parity
+    // and parity of the input flag list
+    hipGraph_t gcont_g[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t gcont[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     int64_t *mesh_cell_off = nullptr;
     double *dt_part = nullptr;
     unsigned *counters = nullptr;
@@ -182,6 +186,12 @@ bool params_valid(const hl_params &p) {
 void drop_graphs(hl_ctx *c) {
     for (int b = 0; b < 2; ++b) {
         if (c->gexec[b]) (void)hipGraphExecDestroy(c->gexec[b]);
+        for (int f = 0; f < 2; ++f) {
+            if (c->gcont[b][f]) (void)hipGraphExecDestroy(c->gcont[b][f]);
+            if (c->gcont_g[b][f]) (void)hipGraphDestroy(c->gcont_g[b][f]);
+            c->gcont[b][f] = nullptr;
+            c->gcont_g[b][f] = nullptr;
+        }
         if (c->graph[b]) (void)hipGraphDestroy(c->graph[b]);
         c->gexec[b] = nullptr;
         c->graph[b] = nullptr;
@@ -536,10 +546,10 @@ void enqueue_first(hl_ctx *c, hl::StepArgs &a, bool copy_dt, bool clear_mask, hi
 // MOOD pass reading flag list fb: the flagged cells drop to first order and
 // only their corners, their nodes and the cells around those nodes change.
 template <int D>
-void enqueue_pass(hl_ctx *c, hl::StepArgs a, int fb, int pass, int64_t nflag, bool fixed, hipStream_t s) {
+void enqueue_pass(hl_ctx *c, hl::StepArgs a, int fb, int log_index, int64_t nflag, bool fixed, hipStream_t s) {
     const int nb = 1 - fb;
-    hl::launch_pass_begin(c->counters, fb, c->stamp_dev, pass < 64 ? c->pass_log : nullptr, pass < 64 ? pass : 0,
-                          s);
+    hl::launch_pass_begin(c->counters, fb, c->stamp_dev, log_index >= 0 ? c->pass_log : nullptr,
+                          log_index >= 0 ? log_index : 0, s);
     a.flist_out = c->flist[nb];
     a.fcount_out = c->counters + hl::CNT_F0 + nb;
     PROF(c, PK_MOOD,
@@ -578,6 +588,23 @@ hl_status capture_step(hl_ctx *c, int src) {
 
 template <int D>
 hl_status fill_info(hl_ctx *c, int src, hl_step_info *info);
+
+// Passes per continuation graph (even, so the input list parity returns).
+constexpr int CONT_PASSES = 8;
+
+template <int D>
+hl_status capture_cont(hl_ctx *c, int src, int fb) {
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = c->cap_stream;
+    hl::StepArgs a = make_args(c, src);
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int p = 0; p < CONT_PASSES; ++p) enqueue_pass<D>(c, a, fb ^ (p & 1), 64 + p, 0, true, cs);
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamEndCapture(cs, &g));
+    c->gcont_g[src][fb] = g;
+    HIPCHK(hipGraphInstantiate(&c->gcont[src][fb], g, nullptr, nullptr, 0));
+    return HL_OK;
+}
 
 template <int D>
 hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on_device, hl_step_info *info) {
@@ -640,14 +667,25 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
         first = np ? log[0] : nflag;
         for (int p = 0; p < np; ++p) iters += log[p] > 0;
         if (a.detect && nflag > 0) {
-            // the captured passes did not reach the fixpoint: finish eagerly
+            // the captured passes did not reach the fixpoint: one more pass
+            // eagerly, then captured blocks of CONT_PASSES passes (a pass
+            // with no input exits at once) until no cell is flagged
+            enqueue_pass<D>(c, a, fb, -1, nflag, false, s);
+            c->stamp_host++;
+            ++iters;
+            ++pass;
+            if ((st = read_counters(c, s)) != HL_OK) return st;
+            fb = 1 - fb;
+            nflag = c->counters_host[hl::CNT_F0 + fb];
             while (nflag > 0) {
-                enqueue_pass<D>(c, a, fb, pass, nflag, false, s);
-                c->stamp_host++;
-                ++iters;
-                ++pass;
+                if (!c->gcont[src][fb] && (st = capture_cont<D>(c, src, fb)) != HL_OK) return st;
+                HIPCHK(hipGraphLaunch(c->gcont[src][fb], s));
+                c->stamp_host += CONT_PASSES;
+                unsigned clog[CONT_PASSES];
+                HIPCHK(hipMemcpyAsync(clog, c->pass_log + 64, sizeof clog, hipMemcpyDeviceToHost, s));
                 if ((st = read_counters(c, s)) != HL_OK) return st;
-                fb = 1 - fb;
+                for (int p = 0; p < CONT_PASSES; ++p) iters += clog[p] > 0;
+                pass += CONT_PASSES;
                 nflag = c->counters_host[hl::CNT_F0 + fb];
             }
             enqueue_reduce(c, s);
@@ -661,7 +699,7 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
         nflag = c->counters_host[hl::CNT_F0];
         first = nflag;
         while (a.detect && nflag > 0) {
-            enqueue_pass<D>(c, a, fb, pass, nflag, false, s);
+            enqueue_pass<D>(c, a, fb, -1, nflag, false, s);
             c->stamp_host++;
             ++iters;
             ++pass;
@@ -1327,7 +1365,7 @@ hl_status upload_impl(hl_ctx *c, int dim, int n_mesh, const std::vector<int64_t>
     A_(c->dt_part, 2 * (ncl / 256 + 2));
     A_(c->counters, hl::CNT_N);
     A_(c->stamp_dev, 1);
-    A_(c->pass_log, 64);
+    A_(c->pass_log, 128);  // [0, 64): captured step; [64, 128): continuation
     A_(c->dt_cur, (size_t)n_mesh);
     A_(c->dt_next, (size_t)n_mesh);
     A_(c->dt_red, 2 * (size_t)n_mesh);

@@ -1566,7 +1566,10 @@ void launch_update(const StepArgs &a, const Sched &k, hipStream_t s) {
 template <int D>
 void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned *fcount, int64_t nflag,
                         int64_t max_deg, bool fixed_grid, hipStream_t s) {
-    auto grid = [](int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384)); };
+    // fixed grids (graph capture) are capped at 1024 blocks: the kernels
+    // stride over their lists, and an empty pass then launches few blocks
+    const int64_t gmax = fixed_grid ? 1024 : 16384;
+    auto grid = [gmax](int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, gmax)); };
     if (fixed_grid) nflag = std::min<int64_t>(a.nc, 256 * 1024);
     const int64_t nnodes = std::min<int64_t>(a.nn, (D + 1) * nflag);
     const int64_t ncells = std::min<int64_t>(a.nc, nnodes * max_deg);
