@@ -1472,6 +1472,15 @@ hl_status hl_mesh_refine(hl_ctx *c, int levels) {
     if (c->n_mesh != 1) return HL_E_INVALID;
     if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
     const int d = c->dim, nv = d + 1, dd = d * d;
+    {
+        // every level multiplies the cells by 2^d; node and corner ids stay int32
+        double ncl = (double)c->nc;
+        for (int l = 0; l < levels; ++l) ncl *= (d == 3 ? 8.0 : 4.0);
+        if (ncl * (nv > 3 ? 6 : 3) >= (double)INT32_MAX) {
+            std::snprintf(g_last_error, sizeof g_last_error, "refined mesh too large for 32-bit ids");
+            return HL_E_INVALID;
+        }
+    }
     HostMesh h;
     h.x = c->x0_host;
     h.cells = c->c2n_host;
