@@ -391,8 +391,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1",
+        print("bench.py measures one GPU: the step has no multi-GPU path; run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

@@ -1,5 +1,5 @@
 """Rigid-plane contact (hl_set_contact; Section 3.8, reading R30) through
-the C-ABI against the oracle's contact driver: an elastic block falls onto
+the C-ABI against the oracle's contact stepper: an elastic block falls onto
 the plane, is held, rebounds and detaches (3D, oblique, and a 2D square),
 with the same trial sequence, cut steps, contact states and cascade masks
 at every step; graph capture; the argument checks."""

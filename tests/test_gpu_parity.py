@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
 
-Bar (the benchmark spec's tolerances): normwise relative error <= 1e-12 after one
+Bar: normwise relative error <= 1e-12 after one
 step from identical input, <= 1e-9 after 100 steps, identical MOOD masks,
 time steps to 1e-12.  Full-size meshes are checked on sampled cells: the
 oracle recomputes a patch of two node-rings around each sample with the GPU's

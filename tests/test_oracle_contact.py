@@ -2,7 +2,7 @@
 "Boundary condition treatments"; reading R30): an elastic block falls onto
 a rigid slip plane, is held by it, rebounds and detaches.
 
-Fixed by kinematics and mechanics, not by the driver's own formulas: the
+Fixed by kinematics and mechanics, not by the contact stepper's own formulas: the
 step that reaches the plane is cut to the exact impact time gap / U of the
 free flight; every node of the flat bottom face lands at once, on the
 plane; a slip wall does no work and exerts no tangential force, so total
