@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 
 METRIC = "FP64 cell-updates/s per Lagrangian step; adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector peak
 PROFILED = ("pack", "node_agg", "predict", "node_solve", "update", "mood_sparse", "reduce")
 
 
@@ -97,6 +97,25 @@ def read_traffic(kernel, workload):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def read_valu(kernel, workload):
+    """FP64 flop of one launch of `kernel` from the committed rocprofv3
+    VALU counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha1") != kernel_source_hash():
+        return None
+    try:
+        return float(vals[f"fp64_flop_per_launch_{kernel}"])
     except (KeyError, ValueError):
         return None
 
@@ -468,6 +487,7 @@ def main():
     avg_ms, launches = kern[dom]
     achieved = kb[dom] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     traffic = read_traffic(dom, name)
+    flop = read_valu(dom, name)
     step_bytes = step_alg_bytes(w.dim, w.n_cells, w.n_nodes)
 
     out = {
@@ -490,6 +510,12 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "alg_bytes_per_launch": kb[dom],
                      "avg_launch_ms": avg_ms, "launches": launches},
+        # the same launch against the FP64 vector peak, from the committed
+        # VALU counter summary (null when taken on another kernel source)
+        "fp64_valu": None if flop is None or avg_ms <= 0 else {
+            "kernel": dom, "achieved": flop / (avg_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": flop / (avg_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "flop_per_launch": flop},
         "step_roofline": {"alg_bytes_per_step": step_bytes,
                           "hbm_frac": (step_bytes / (HBM_PEAK_GBS * 1e9)) / (ms_per_step * 1e-3)},
         "kernel_avg_ms": {k: kern[k][0] for k in kern},
