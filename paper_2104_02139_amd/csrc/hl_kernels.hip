@@ -27,6 +27,22 @@ __device__ __forceinline__ int64_t gtid() {
     return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 }
 
+// Append `val` to `list` where `want`, one counter atomic per wave: the
+// lowest active lane reserves the wave's slots, each lane takes the slot of
+// its rank among the wanting lanes.  Callable with a partial wave active.
+__device__ __forceinline__ void wave_append(int32_t *__restrict__ list, unsigned *__restrict__ counter, bool want,
+                                            int32_t val) {
+    const unsigned long long act = __ballot(1);
+    const unsigned long long m = __ballot(want);
+    if (!m) return;
+    const int lane = (int)__lane_id();
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(counter, (unsigned)__popcll(m));
+    base = __shfl(base, leader, 64);
+    if (want) list[base + __popcll(m & ((1ull << lane) - 1ull))] = val;
+}
+
 // Walk the items of a work list (see WorkList); f(entity) for each entity.
 template <class F>
 __device__ __forceinline__ void walk_items(const WorkList &w, F f) {
@@ -657,13 +673,6 @@ __device__ __forceinline__ bool node_gather(const StepArgs &a, const int64_t p, 
     return q1 > q0;
 }
 
-template <int D, bool LD>
-__device__ __forceinline__ void node_solve_one(const StepArgs &a, const int64_t p) {
-    double M[Dims<D>::NMS], r[D];
-    const bool any = node_gather<D>(a, p, M, r);
-    node_solve_finish<D, LD>(a, p, any, M, r, -1);
-}
-
 // Cooperative corner gather (as for the node aggregates): lane l of a group
 // of AGG_G sums value pair l of the node's corner records in CSR order, so a
 // wave-wide load brings whole records; the sums then meet in every lane of
@@ -1172,26 +1181,31 @@ __global__ __launch_bounds__(256) void k_pass_cells(StepArgs a, const int32_t *_
         const int32_t c = list[i];
         mask[c] = (a.cascade == 3 && mask[c] == 0) ? 1 : 2;
         predict_cell<D, LIM, FAM, SG>(a, c);
+        bool fresh[D + 1];
 #pragma unroll
-        for (int k = 0; k <= D; ++k) {
-            const int32_t p = a.c2n[(int64_t)c * (D + 1) + k];
-            if (atomicExch(&a.nstamp[p], st) != st) a.nlist[atomicAdd(&a.counters[CNT_NODES], 1u)] = p;
-        }
+        for (int k = 0; k <= D; ++k) fresh[k] = atomicExch(&a.nstamp[a.c2n[(int64_t)c * (D + 1) + k]], st) != st;
+#pragma unroll
+        for (int k = 0; k <= D; ++k)
+            wave_append(a.nlist, &a.counters[CNT_NODES], fresh[k], a.c2n[(int64_t)c * (D + 1) + k]);
     }
 }
 
-// Second: every listed node is solved again, and the cells around it are
-// listed once.
+// Second: every listed node is solved again by a group of AGG_G lanes (the
+// cooperative gather of the full node solve, same sums), and the group
+// lists the cells around it once.
 template <int D, bool LD>
 __global__ __launch_bounds__(256) void k_pass_nodes(StepArgs a) {
     const int64_t n = a.counters[CNT_NODES];
     const int32_t st = *a.stamp;
-    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int l = threadIdx.x & (AGG_G - 1);
+    const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / AGG_G);
+    for (int64_t i = gtid() / AGG_G; i < n; i += ngroups) {
         const int32_t p = a.nlist[i];
-        node_solve_one<D, LD>(a, p);
-        for (int32_t q = a.n2c_off[p]; q < a.n2c_off[p + 1]; ++q) {
+        node_solve_group<D, LD>(a, p, l);
+        const int32_t q1 = a.n2c_off[p + 1];
+        for (int32_t q = a.n2c_off[p] + l; q < q1; q += AGG_G) {
             const int32_t j = a.n2c[q] / (D + 1);
-            if (atomicExch(&a.cstamp[j], st) != st) a.clist[atomicAdd(&a.counters[CNT_CELLS], 1u)] = j;
+            wave_append(a.clist, &a.counters[CNT_CELLS], atomicExch(&a.cstamp[j], st) != st, j);
         }
     }
 }
@@ -1583,9 +1597,9 @@ void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned 
         fam ? k_pass_cells<D, false, true, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
             : k_pass_cells<D, false, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
     if (a.ld_off)
-        k_pass_nodes<D, true><<<grid(nnodes), 256, 0, s>>>(a);
+        k_pass_nodes<D, true><<<grid(AGG_G * nnodes), 256, 0, s>>>(a);
     else
-        k_pass_nodes<D, false><<<grid(nnodes), 256, 0, s>>>(a);
+        k_pass_nodes<D, false><<<grid(AGG_G * nnodes), 256, 0, s>>>(a);
     if (a.eos)
         k_update_list<D, true><<<grid(ncells), 256, 0, s>>>(a);
     else
