@@ -316,12 +316,15 @@ typedef struct {
 } hl_schedule;
 
 /* Set / get the schedule of stage `stage` (HL_STAGE_*).  The default is
- * {256, 256, 0}.  Setting one drops captured graphs. */
+ * {256, 256, 0} for the cell stages and {32, 256, 0} for the node stages
+ * (8 lanes per node: one pass of 32 nodes per block).  Setting one drops
+ * captured graphs. */
 hl_status hl_set_schedule(hl_ctx *ctx, int stage, const hl_schedule *sched);
 hl_status hl_get_schedule(hl_ctx *ctx, int stage, hl_schedule *sched);
 
 /* Autotuner: times each stage on the current mesh and state under every
- * candidate schedule (block 64/128/256, tile 1/2/4 blocks, 0/2/4/8 blocks
+ * candidate schedule (block 64/128/256, tile 1/2/4 blocks and, for the node
+ * stages, also 1/8 and 1/4 of a block, 0/2/4/8 blocks
  * per compute unit; `reps` timed launches each, HIP events on the context's
  * stream) and keeps the fastest per stage.  The state is not changed; the
  * next step rebuilds its work buffers.  best_ms: NULL or [HL_STAGE_COUNT],

@@ -101,7 +101,11 @@ struct hl_ctx {
     Prof prof;
     // stage schedules and their work lists (device memory in allocs)
     int n_cu = 0;
-    StageCfg cfg[HL_STAGE_COUNT];
+    // default schedules: a cell stage one 256-cell item per block; a node
+    // stage (AGG_G lanes per node) one pass of 32 nodes per block, which
+    // keeps each XCD's nodes in flight, and the cell records they share, in
+    // its L2
+    StageCfg cfg[HL_STAGE_COUNT] = {{256, 256, 0}, {32, 256, 0}, {256, 256, 0}, {32, 256, 0}, {256, 256, 0}};
     hl::Sched sk[HL_STAGE_COUNT] = {};
     bool sched_ready = false;
     std::map<std::pair<int, int>, DevList> wlists;  // (entity kind, tile) -> list
@@ -1104,14 +1108,17 @@ hl_status autotune(hl_ctx *c, int reps, double *best_ms) {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     static const int kBlock[] = {64, 128, 256};
-    static const int kMult[] = {1, 2, 4};
+    // tile in eighths of a block: node stages run AGG_G lanes per node, so
+    // their one-pass items (block / AGG_G nodes) are candidates too
+    static const int kTile8[] = {1, 2, 8, 16, 32};
     static const int kPerCu[] = {0, 2, 4, 8};
     auto sweep = [&](int stage, StageCfg *keep, double *best) -> hl_status {
         for (int b : kBlock)
-            for (int m : kMult)
+            for (int m8 : kTile8)
                 for (int q : kPerCu) {
+                    if (m8 < 8 && kStageKind[stage] == 0) continue;
                     StageCfg g;
-                    g.tile = b * m;
+                    g.tile = b * m8 / 8;
                     g.block = b;
                     g.blocks_per_cu = q;
                     hl::Sched k;

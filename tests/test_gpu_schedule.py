@@ -18,6 +18,7 @@ SCHEDULES = [
     dict(tile=512, block=128, blocks_per_cu=2),    # persistent, several items per block
     dict(tile=100, block=192, blocks_per_cu=0),    # ragged items, idle lanes
     dict(tile=1024, block=256, blocks_per_cu=8),
+    dict(tile=8, block=64, blocks_per_cu=0),       # one pass of 8 nodes per block
 ]
 
 
@@ -51,6 +52,14 @@ def _family():
           W.rotating_cube_3d(n=5, seed=3), W.rotating_cube_3d(n=1, seed=4)]
     ws[2].mu = ws[2].mu * 1.7
     return ws
+
+
+def test_default_schedules():
+    ctx = H.from_workload(_bar())
+    for stage in H.STAGES:
+        want = (dict(tile=32, block=256, blocks_per_cu=0) if stage in ("node_agg", "node_solve")
+                else dict(tile=256, block=256, blocks_per_cu=0))
+        assert ctx.get_schedule(stage) == want, stage
 
 
 @pytest.mark.parametrize("sched", range(len(SCHEDULES)))
@@ -90,7 +99,11 @@ def test_autotune_keeps_state_and_results():
     for f in FIELDS:
         assert np.array_equal(before[f], after[f]), f
     for stage, (sch, ms) in picked.items():
-        assert sch["block"] in (64, 128, 256) and sch["tile"] % sch["block"] == 0
+        # node stages (8 lanes per node) may also take 1/8 or 1/4 of a block
+        tiles = [m * sch["block"] for m in (1, 2, 4)]
+        if stage in ("node_agg", "node_solve"):
+            tiles += [sch["block"] // 8, sch["block"] // 4]
+        assert sch["block"] in (64, 128, 256) and sch["tile"] in tiles, (stage, sch)
         assert ms > 0.0
     _same(ref, _run(ctx, steps, False))
 
