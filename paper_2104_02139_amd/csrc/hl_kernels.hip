@@ -313,8 +313,11 @@ __device__ __forceinline__ constexpr int bslot(int s) {
 // r_cp = M_cp v*_cp - T*_cp C_cp (eq. nodal_solver^n).  SG: the stiffened
 // gas (R31) also reconstructs eps = e - |v|^2 / 2, advances it with
 // d eps/dt = tau T : grad v and carries it through div T.
-template <int D, bool LIM, bool FAM, bool SG>
-__device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c) {
+// STAGE: the corner records go to LDS, record k at lrec + k * lstride (NMS +
+// D values), for the block to copy out (k_predict_staged).
+template <int D, bool LIM, bool FAM, bool SG, bool STAGE = false>
+__device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c, double *lrec = nullptr,
+                                             const int lstride = 0) {
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
     const int64_t nc = a.nc, nn = a.nn;
@@ -613,7 +616,7 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
 #pragma unroll
             for (int j = i; j < D; ++j)
                 M[midx<D>(i, j)] = z * (S[midx<D>(i, j)] - g.C[k][i] * g.C[k][j] * rk);
-        double *o = a.corner + corner_slot<D>(c, k) * Dm::CW;
+        double *o = STAGE ? lrec + k * lstride : a.corner + corner_slot<D>(c, k) * Dm::CW;
 #pragma unroll
         for (int q = 0; q < Dm::NMS; ++q) o[q] = M[q];
 #pragma unroll
@@ -629,6 +632,40 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c)
 template <int D, bool LOOP, bool LIM, bool FAM, bool SG>
 __global__ __launch_bounds__(256) void k_predict(StepArgs a, WorkList w) {
     for_items<LOOP>(w, [&](int64_t c) { predict_cell<D, LIM, FAM, SG>(a, c); });
+}
+
+// One block per item (the one_item mapping), corner records staged in LDS
+// ([corner][cell][NMS + D], dynamic, NV * blockDim * (NMS + D) doubles):
+// after a barrier the block copies them out in 16-byte chunks in address
+// order, so each wave store covers 1 KB of consecutive bytes instead of 64
+// records 80 bytes apart.  Same values as k_predict (the pad of each
+// record is written as 0).
+template <int D, bool LIM, bool FAM, bool SG>
+__global__ __launch_bounds__(256) void k_predict_staged(StepArgs a, WorkList w) {
+    using Dm = Dims<D>;
+    constexpr int NV = D + 1, RW = Dm::NMS + D, NP = Dm::CW / 2;
+    extern __shared__ double cs[];
+    const int64_t per = (w.n_items + 7) >> 3;
+    const int64_t slot = blockIdx.x >> 3;
+    const int64_t it = (int64_t)(blockIdx.x & 7u) * per + slot;
+    if (slot >= per || it >= w.n_items) return;  // the whole block
+    const int64_t s0 = w.start[it];
+    const int len = w.len[it];
+    const int bs = blockDim.x;
+    if ((int)threadIdx.x < len)
+        predict_cell<D, LIM, FAM, SG, true>(a, s0 + threadIdx.x, cs + threadIdx.x * RW, bs * RW);
+    __syncthreads();
+    double2 *out = reinterpret_cast<double2 *>(a.corner);
+    const int tot = len * NP;
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+        for (int r = threadIdx.x; r < tot; r += bs) {
+            const int ci = r / NP, j = r - ci * NP;
+            const double *src = cs + (k * bs + ci) * RW + 2 * j;
+            const double x = src[0];
+            const double y = 2 * j + 1 < RW ? src[1] : 0.0;
+            out[corner_slot<D>(s0 + ci, k) * NP + j] = make_double2(x, y);
+        }
 }
 
 // ---------------------------------------------------------- node solve
@@ -1531,17 +1568,23 @@ void launch_predict(const StepArgs &a, const Sched &k, hipStream_t s) {
         if (k.loop)
             k_predict<D, true, false, false, true><<<k.grid, k.block, 0, s>>>(a, k.w);
         else
-            k_predict<D, false, false, false, true><<<k.grid, k.block, 0, s>>>(a, k.w);
+            k_predict_staged<D, false, false, true>
+                <<<k.grid, k.block, sizeof(double) * (size_t)(D + 1) * k.block * (Dims<D>::NMS + D), s>>>(a, k.w);
     } else if (k.loop) {
         if (fam)
             lim ? HL_PREDICT_LAUNCH(true, true, true) : HL_PREDICT_LAUNCH(true, false, true);
         else
             lim ? HL_PREDICT_LAUNCH(true, true, false) : HL_PREDICT_LAUNCH(true, false, false);
     } else {
+        // one block per item: corner records staged through LDS (not for the
+        // shear family, whose staged body no longer fits two waves per SIMD)
+        const size_t lds = sizeof(double) * (size_t)(D + 1) * k.block * (Dims<D>::NMS + D);
         if (fam)
             lim ? HL_PREDICT_LAUNCH(false, true, true) : HL_PREDICT_LAUNCH(false, false, true);
+        else if (lim)
+            k_predict_staged<D, true, false, false><<<k.grid, k.block, lds, s>>>(a, k.w);
         else
-            lim ? HL_PREDICT_LAUNCH(false, true, false) : HL_PREDICT_LAUNCH(false, false, false);
+            k_predict_staged<D, false, false, false><<<k.grid, k.block, lds, s>>>(a, k.w);
     }
 #undef HL_PREDICT_LAUNCH
 }
