@@ -997,8 +997,10 @@ __global__ __launch_bounds__(256) void k_contact_eval(StepArgs a, ContactArgs k)
 // detection (eqs. PAD, RDMP; R16, R17) and the per-cell time-step bounds.
 // SG: the stiffened gas (R31) -- eps in the gather record, p + p_inf > 0 in
 // the admissibility test, its sound speed in the time-step bound.
-template <int D, bool SG>
-__device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) {
+// STAGE: the gather record goes to LDS at lrec (16-byte aligned) for the
+// block to copy out (k_update_staged).
+template <int D, bool SG, bool STAGE = false>
+__device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, double *lrec = nullptr) {
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
     const int64_t nc = a.nc, nn = a.nn;
@@ -1145,7 +1147,7 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
             for (int i = 0; i < D; ++i) kk += v1[i] * v1[i];
             r[Dm::G_EPS] = e1 - 0.5 * kk;
         }
-        double2 *o = reinterpret_cast<double2 *>(a.xc + c * Dm::GR);
+        double2 *o = reinterpret_cast<double2 *>(STAGE ? lrec : a.xc + c * Dm::GR);
 #pragma unroll
         for (int q = 0; q < Dm::GR / 2; ++q) o[q] = make_double2(r[2 * q], r[2 * q + 1]);
     }
@@ -1194,6 +1196,37 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c) 
 template <int D, bool LOOP, bool SG>
 __global__ __launch_bounds__(256) void k_update(StepArgs a, WorkList w) {
     for_items<LOOP>(w, [&](int64_t c) { update_cell<D, SG>(a, c); });
+}
+
+// LDS stride of a staged gather record: 18 doubles in 3D, so that the
+// 16-byte LDS writes of 8 consecutive lanes fall in distinct banks
+template <int D>
+constexpr int staged_gr() {
+    return Dims<D>::GR + (D == 3 ? 2 : 0);
+}
+
+// One block per item, gather records staged in LDS (dynamic, blockDim *
+// staged_gr doubles): the item's records are one contiguous run, copied
+// out after a barrier in 16-byte chunks in address order.
+template <int D, bool SG>
+__global__ __launch_bounds__(256) void k_update_staged(StepArgs a, WorkList w) {
+    using Dm = Dims<D>;
+    constexpr int LS = staged_gr<D>(), NPR = Dm::GR / 2;
+    extern __shared__ double cs[];
+    const int64_t per = (w.n_items + 7) >> 3;
+    const int64_t slot = blockIdx.x >> 3;
+    const int64_t it = (int64_t)(blockIdx.x & 7u) * per + slot;
+    if (slot >= per || it >= w.n_items) return;  // the whole block
+    const int64_t s0 = w.start[it];
+    const int len = w.len[it];
+    if ((int)threadIdx.x < len) update_cell<D, SG, true>(a, s0 + threadIdx.x, cs + threadIdx.x * LS);
+    __syncthreads();
+    const double2 *src = reinterpret_cast<const double2 *>(cs);
+    double2 *out = reinterpret_cast<double2 *>(a.xc + s0 * Dm::GR);
+    for (int q = threadIdx.x; q < len * NPR; q += blockDim.x) {
+        const int ci = q / NPR, j = q - ci * NPR;
+        out[q] = src[ci * (LS / 2) + j];
+    }
 }
 
 template <int D, bool SG>
@@ -1616,9 +1649,11 @@ void launch_update(const StepArgs &a, const Sched &k, hipStream_t s) {
     if (k.loop)
         a.eos ? k_update<D, true, true><<<k.grid, k.block, 0, s>>>(a, k.w)
               : k_update<D, true, false><<<k.grid, k.block, 0, s>>>(a, k.w);
-    else
-        a.eos ? k_update<D, false, true><<<k.grid, k.block, 0, s>>>(a, k.w)
-              : k_update<D, false, false><<<k.grid, k.block, 0, s>>>(a, k.w);
+    else {
+        const size_t lds = sizeof(double) * (size_t)k.block * staged_gr<D>();
+        a.eos ? k_update_staged<D, true><<<k.grid, k.block, lds, s>>>(a, k.w)
+              : k_update_staged<D, false><<<k.grid, k.block, lds, s>>>(a, k.w);
+    }
 }
 template <int D>
 void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned *fcount, int64_t nflag,
