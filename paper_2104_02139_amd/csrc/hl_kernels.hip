@@ -1319,58 +1319,109 @@ __device__ __forceinline__ double wave_min(double v) {
     return v;
 }
 
-// Stage 1: per-block minimum of the two time-step bounds (blocks inside
-// one mesh), or per-cell atomics for a block that straddles meshes; count
-// of inadmissible first-order cells.
+// Per-mesh minima of the two time-step bounds and the count of inadmissible
+// first-order cells, stage 1.  A block covers DT_TILES tiles of 256 cells
+// (one load of each per thread in flight).  A block inside one mesh writes
+// its minima to part[block]; otherwise a tile that straddles meshes takes
+// per-cell atomics, the other tiles one atomic per mesh, and part[block]
+// is +inf.  The minimum runs on the ordered bit patterns of non-negative
+// doubles: order independent, hence deterministic.
+constexpr int DT_TILES = 8;
 __global__ __launch_bounds__(256) void k_dt_reduce(int64_t nc, const double *__restrict__ dtc,
                                                    const int32_t *__restrict__ cell_mesh,
                                                    const uint8_t *__restrict__ pstat,
                                                    double *__restrict__ red /* [n_mesh][2] */,
                                                    double *__restrict__ part /* [nblocks][2] */,
                                                    unsigned *__restrict__ bad_count) {
-    __shared__ double sa[4], sv[4];
-    __shared__ int sbad[4];
-    const int64_t c = gtid();
-    const int64_t first = (int64_t)blockIdx.x * blockDim.x;
-    const int64_t last = min(first + (int64_t)blockDim.x, nc) - 1;
-    double ac = __builtin_huge_val(), vol = __builtin_huge_val();
-    int bad = 0;
-    if (c < nc) {
-        ac = dtc[c];
-        vol = dtc[nc + c];
-        bad = pstat[c];
-    }
-    if (!(ac >= 0.0)) ac = __builtin_huge_val();
-    if (!(vol >= 0.0)) vol = __builtin_huge_val();
-    const bool straddle = cell_mesh && cell_mesh[first] != cell_mesh[last];
-    if (straddle) {
-        if (c < nc) {
-            atomic_min_pos(&red[2 * cell_mesh[c]], ac);
-            atomic_min_pos(&red[2 * cell_mesh[c] + 1], vol);
-        }
-        ac = vol = __builtin_huge_val();
-    }
-    ac = wave_min(ac);
-    vol = wave_min(vol);
-    unsigned long long bb = __ballot(bad != 0);
+    __shared__ double sa[DT_TILES][4], sv[DT_TILES][4];
+    __shared__ int sbad[DT_TILES][4];
+    __shared__ int smesh[DT_TILES];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) {
-        sa[w] = ac;
-        sv[w] = vol;
-        sbad[w] = __popcll(bb);
+    double ac[DT_TILES], vol[DT_TILES];
+    int bad[DT_TILES];
+#pragma unroll
+    for (int g = 0; g < DT_TILES; ++g) {
+        const int64_t c = ((int64_t)blockIdx.x * DT_TILES + g) * 256 + threadIdx.x;
+        ac[g] = vol[g] = __builtin_huge_val();
+        bad[g] = 0;
+        if (c < nc) {
+            ac[g] = dtc[c];
+            vol[g] = dtc[nc + c];
+            bad[g] = pstat[c];
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < DT_TILES; ++g) {
+        const int64_t first = ((int64_t)blockIdx.x * DT_TILES + g) * 256;
+        const int64_t c = first + threadIdx.x;
+        double a = ac[g], v = vol[g];
+        if (!(a >= 0.0)) a = __builtin_huge_val();
+        if (!(v >= 0.0)) v = __builtin_huge_val();
+        int mesh = -1;  // -1: empty tile or straddling tile (done here)
+        if (first < nc) {
+            const int64_t last = min(first + 255, nc - 1);
+            mesh = cell_mesh ? cell_mesh[first] : 0;
+            if (cell_mesh && cell_mesh[last] != mesh) {
+                if (c < nc) {
+                    atomic_min_pos(&red[2 * cell_mesh[c]], a);
+                    atomic_min_pos(&red[2 * cell_mesh[c] + 1], v);
+                }
+                a = v = __builtin_huge_val();
+                mesh = -1;
+            }
+        }
+        a = wave_min(a);
+        v = wave_min(v);
+        const unsigned long long bb = __ballot(bad[g] != 0);
+        if (lane == 0) {
+            sa[g][w] = a;
+            sv[g][w] = v;
+            sbad[g][w] = __popcll(bb);
+        }
+        if (threadIdx.x == 0) smesh[g] = mesh;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a0 = fmin(fmin(sa[0], sa[1]), fmin(sa[2], sa[3]));
-        double v0 = fmin(fmin(sv[0], sv[1]), fmin(sv[2], sv[3]));
-        part[2 * blockIdx.x] = a0;
-        part[2 * blockIdx.x + 1] = v0;
-        int nb = sbad[0] + sbad[1] + sbad[2] + sbad[3];
+        const int64_t c0 = (int64_t)blockIdx.x * DT_TILES * 256;
+        const int64_t c1 = min(c0 + DT_TILES * 256, nc) - 1;
+        const bool one_mesh = !cell_mesh || cell_mesh[c0] == cell_mesh[c1];
+        int nb = 0;
+        int cur = -1;
+        double am = __builtin_huge_val(), vm = __builtin_huge_val(), ab = am, vb = vm;
+        for (int g = 0; g < DT_TILES; ++g) {
+            nb += sbad[g][0] + sbad[g][1] + sbad[g][2] + sbad[g][3];
+            const int m = smesh[g];
+            if (m < 0) continue;
+            const double at = fmin(fmin(sa[g][0], sa[g][1]), fmin(sa[g][2], sa[g][3]));
+            const double vt = fmin(fmin(sv[g][0], sv[g][1]), fmin(sv[g][2], sv[g][3]));
+            if (one_mesh) {
+                ab = fmin(ab, at);
+                vb = fmin(vb, vt);
+                continue;
+            }
+            if (m != cur) {
+                if (cur >= 0) {
+                    atomic_min_pos(&red[2 * cur], am);
+                    atomic_min_pos(&red[2 * cur + 1], vm);
+                }
+                cur = m;
+                am = vm = __builtin_huge_val();
+            }
+            am = fmin(am, at);
+            vm = fmin(vm, vt);
+        }
+        if (cur >= 0) {
+            atomic_min_pos(&red[2 * cur], am);
+            atomic_min_pos(&red[2 * cur + 1], vm);
+        }
+        part[2 * blockIdx.x] = ab;
+        part[2 * blockIdx.x + 1] = vb;
         if (nb) atomicAdd(bad_count, (unsigned)nb);
     }
 }
 
-// Stage 2: one block per mesh reduces the partials of its blocks.
+// Stage 2: one block per mesh reduces the partials of the stage-1 blocks
+// that hold its cells (blocks shared with another mesh left +inf).
 __global__ __launch_bounds__(256) void k_dt_reduce2(int n_mesh, const int64_t *__restrict__ mesh_cell_off,
                                                     const double *__restrict__ part, double *__restrict__ red) {
     __shared__ double sa[4], sv[4];
@@ -1379,7 +1430,9 @@ __global__ __launch_bounds__(256) void k_dt_reduce2(int n_mesh, const int64_t *_
     const int64_t c0 = mesh_cell_off[m], c1 = mesh_cell_off[m + 1];
     double ac = __builtin_huge_val(), vol = __builtin_huge_val();
     if (c1 > c0) {
-        const int64_t b0 = c0 / 256, b1 = (c1 - 1) / 256;
+        constexpr int64_t CH = 256 * DT_TILES;
+        const int64_t b0 = c0 / CH, b1 = (c1 - 1) / CH;
+#pragma unroll 4
         for (int64_t b = b0 + threadIdx.x; b <= b1; b += blockDim.x) {
             ac = fmin(ac, part[2 * b]);
             vol = fmin(vol, part[2 * b + 1]);
@@ -1697,7 +1750,8 @@ void launch_dt_reduce(int64_t nc, const double *dtc, const int32_t *cell_mesh, c
                       double *part, const int64_t *mesh_cell_off, int n_mesh, unsigned *bad_count, hipStream_t s) {
     k_fill<<<nblk(2 * n_mesh), 256, 0, s>>>(red, 2 * n_mesh, __builtin_huge_val());
     if (nc) {
-        k_dt_reduce<<<nblk(nc), 256, 0, s>>>(nc, dtc, cell_mesh, pstat, red, part, bad_count);
+        const int64_t nb = (nc + 256 * DT_TILES - 1) / (256 * DT_TILES);
+        k_dt_reduce<<<(unsigned)nb, 256, 0, s>>>(nc, dtc, cell_mesh, pstat, red, part, bad_count);
         k_dt_reduce2<<<n_mesh, 256, 0, s>>>(n_mesh, mesh_cell_off, part, red);
     }
 }
