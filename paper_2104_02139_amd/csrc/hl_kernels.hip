@@ -27,6 +27,29 @@ __device__ __forceinline__ int64_t gtid() {
     return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 }
 
+// Append `val` to `list` where `want`, one counter atomic per block of 256
+// threads; every thread of the block calls it the same number of times.
+// sh: 5 words of LDS.
+__device__ __forceinline__ void block_append(int32_t *__restrict__ list, unsigned *__restrict__ counter, bool want,
+                                             int32_t val, unsigned *sh) {
+    const int lane = (int)__lane_id(), w = (int)(threadIdx.x >> 6);
+    const unsigned long long m = __ballot(want);
+    if (lane == 0) sh[w] = (unsigned)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned tot = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            const unsigned t = sh[i];
+            sh[i] = tot;
+            tot += t;
+        }
+        sh[4] = tot ? atomicAdd(counter, tot) : 0u;
+    }
+    __syncthreads();
+    if (want) list[sh[4] + sh[w] + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = val;
+    __syncthreads();
+}
+
 // Append `val` to `list` where `want`, one counter atomic per wave: the
 // lowest active lane reserves the wave's slots, each lane takes the slot of
 // its rank among the wanting lanes.  Callable with a partial wave active.
@@ -1180,7 +1203,7 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
         const double rho1 = 1.0 / tau1;
         const double delta = fmax(a.delta0, a.delta1 * (hi - lo));
         const bool bad = pad_bad || rho1 < lo - delta || rho1 > hi + delta;
-        if (bad) a.flist_out[atomicAdd(a.fcount_out, 1u)] = (int32_t)c;
+        wave_append(a.flist_out, a.fcount_out, bad, (int32_t)c);
     }
     a.pstat[c] = (!p1 && pad_bad) ? 1 : 0;
 
@@ -1265,17 +1288,29 @@ __global__ __launch_bounds__(256) void k_pass_cells(StepArgs a, const int32_t *_
 // lists the cells around it once.
 template <int D, bool LD>
 __global__ __launch_bounds__(256) void k_pass_nodes(StepArgs a) {
+    __shared__ unsigned sh[5];
     const int64_t n = a.counters[CNT_NODES];
     const int32_t st = *a.stamp;
     const int l = threadIdx.x & (AGG_G - 1);
-    const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / AGG_G);
-    for (int64_t i = gtid() / AGG_G; i < n; i += ngroups) {
-        const int32_t p = a.nlist[i];
-        node_solve_group<D, LD>(a, p, l);
-        const int32_t q1 = a.n2c_off[p + 1];
-        for (int32_t q = a.n2c_off[p] + l; q < q1; q += AGG_G) {
-            const int32_t j = a.n2c[q] / (D + 1);
-            wave_append(a.clist, &a.counters[CNT_CELLS], atomicExch(&a.cstamp[j], st) != st, j);
+    const int per_block = blockDim.x / AGG_G;
+    // block-uniform loops (block_append synchronises the block)
+    for (int64_t b0 = (int64_t)blockIdx.x * per_block; b0 < n; b0 += (int64_t)gridDim.x * per_block) {
+        const int64_t i = b0 + threadIdx.x / AGG_G;
+        int32_t q0 = 0, q1 = 0;
+        if (i < n) {
+            const int32_t p = a.nlist[i];
+            node_solve_group<D, LD>(a, p, l);
+            q0 = a.n2c_off[p];
+            q1 = a.n2c_off[p + 1];
+        }
+        for (int32_t q = q0 + l; __syncthreads_or(q < q1); q += AGG_G) {
+            bool fresh = false;
+            int32_t j = 0;
+            if (q < q1) {
+                j = a.n2c[q] / (D + 1);
+                fresh = atomicExch(&a.cstamp[j], st) != st;
+            }
+            block_append(a.clist, &a.counters[CNT_CELLS], fresh, j, sh);
         }
     }
 }
@@ -1350,6 +1385,34 @@ __global__ __launch_bounds__(256) void k_dt_reduce(int64_t nc, const double *__r
             bad[g] = pstat[c];
         }
     }
+    const int64_t cb0 = (int64_t)blockIdx.x * DT_TILES * 256;
+    const int64_t cb1 = min(cb0 + DT_TILES * 256, nc) - 1;
+    if (!cell_mesh || cell_mesh[cb0] == cell_mesh[cb1]) {
+        // the block lies in one mesh: one minimum over all its cells
+        double a = __builtin_huge_val(), v = __builtin_huge_val();
+        int nbad = 0;
+#pragma unroll
+        for (int g = 0; g < DT_TILES; ++g) {
+            a = fmin(a, ac[g] >= 0.0 ? ac[g] : __builtin_huge_val());
+            v = fmin(v, vol[g] >= 0.0 ? vol[g] : __builtin_huge_val());
+            nbad += __popcll(__ballot(bad[g] != 0));
+        }
+        a = wave_min(a);
+        v = wave_min(v);
+        if (lane == 0) {
+            sa[0][w] = a;
+            sv[0][w] = v;
+            sbad[0][w] = nbad;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            part[2 * blockIdx.x] = fmin(fmin(sa[0][0], sa[0][1]), fmin(sa[0][2], sa[0][3]));
+            part[2 * blockIdx.x + 1] = fmin(fmin(sv[0][0], sv[0][1]), fmin(sv[0][2], sv[0][3]));
+            const int nb = sbad[0][0] + sbad[0][1] + sbad[0][2] + sbad[0][3];
+            if (nb) atomicAdd(bad_count, (unsigned)nb);
+        }
+        return;
+    }
 #pragma unroll
     for (int g = 0; g < DT_TILES; ++g) {
         const int64_t first = ((int64_t)blockIdx.x * DT_TILES + g) * 256;
@@ -1382,23 +1445,16 @@ __global__ __launch_bounds__(256) void k_dt_reduce(int64_t nc, const double *__r
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int64_t c0 = (int64_t)blockIdx.x * DT_TILES * 256;
-        const int64_t c1 = min(c0 + DT_TILES * 256, nc) - 1;
-        const bool one_mesh = !cell_mesh || cell_mesh[c0] == cell_mesh[c1];
+        // the block spans meshes: one atomic per run of tiles of one mesh
         int nb = 0;
         int cur = -1;
-        double am = __builtin_huge_val(), vm = __builtin_huge_val(), ab = am, vb = vm;
+        double am = __builtin_huge_val(), vm = __builtin_huge_val();
         for (int g = 0; g < DT_TILES; ++g) {
             nb += sbad[g][0] + sbad[g][1] + sbad[g][2] + sbad[g][3];
             const int m = smesh[g];
             if (m < 0) continue;
             const double at = fmin(fmin(sa[g][0], sa[g][1]), fmin(sa[g][2], sa[g][3]));
             const double vt = fmin(fmin(sv[g][0], sv[g][1]), fmin(sv[g][2], sv[g][3]));
-            if (one_mesh) {
-                ab = fmin(ab, at);
-                vb = fmin(vb, vt);
-                continue;
-            }
             if (m != cur) {
                 if (cur >= 0) {
                     atomic_min_pos(&red[2 * cur], am);
@@ -1414,8 +1470,8 @@ __global__ __launch_bounds__(256) void k_dt_reduce(int64_t nc, const double *__r
             atomic_min_pos(&red[2 * cur], am);
             atomic_min_pos(&red[2 * cur + 1], vm);
         }
-        part[2 * blockIdx.x] = ab;
-        part[2 * blockIdx.x + 1] = vb;
+        part[2 * blockIdx.x] = __builtin_huge_val();
+        part[2 * blockIdx.x + 1] = __builtin_huge_val();
         if (nb) atomicAdd(bad_count, (unsigned)nb);
     }
 }
