@@ -24,6 +24,18 @@ namespace {
 
 __device__ __forceinline__ int64_t tid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
+// Node gathers run AG lanes per node: lane l sums the corners l, l + AG, ...
+// of the node in CSR order, then a butterfly over the group gives every
+// lane the same total (each partial sum pairs with its commuted twin).
+constexpr int AG = 8;
+template <int N>
+__device__ __forceinline__ void group_sum(double (&v)[N]) {
+#pragma unroll
+    for (int o = 1; o < AG; o <<= 1)
+#pragma unroll
+        for (int n = 0; n < N; ++n) v[n] += __shfl_xor(v[n], o, AG);
+}
+
 __device__ __forceinline__ double dtof(const double *dtm, const int32_t *mesh_id, int64_t i) {
     return dtm[mesh_id ? mesh_id[i] : 0];
 }
@@ -222,50 +234,57 @@ template <int D>
 __global__ __launch_bounds__(256) void k_adj_node1(StepArgs a, AdjArgs j) {
     using Dm = Dims<D>;
     constexpr int NMS = Dm::NMS;
-    const int64_t p = tid();
+    const int64_t p = tid() / AG;  // the group's lanes share p: they exit together
+    const int l = (int)(threadIdx.x & (AG - 1));
     if (p >= a.nn) return;
     const int64_t nn = a.nn;
     const double dt = dtof(a.dt, a.node_mesh, p);
-    double x1b[D], vh1b[D], vsb[D], x0b[D], vh0b[D], M[NMS] = {};
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-        x1b[i] = j.lx_in[i * nn + p];
-        vh1b[i] = j.lvh_in[i * nn + p];
-        vsb[i] = 0.0;
-        x0b[i] = 0.0;
-        vh0b[i] = 0.0;
-    }
+    // corner sums: x1b, vh1b, v*b, x0b, vh0b (D each), then M
+    double acc[5 * D + NMS] = {};
     const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
-    for (int32_t q = q0; q < q1; ++q) {
+    for (int32_t q = q0 + l; q < q1; q += AG) {
         const int64_t cid = a.n2c[q];
         const double *r = j.cadj + cid * AdjArgs::CA;
         const double *cr = a.corner + corner_slot_of<D>(cid) * Dm::CW;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            x1b[i] += r[AdjArgs::O_X1 + i];
-            vh1b[i] += r[AdjArgs::O_VH1 + i];
-            vsb[i] += r[AdjArgs::O_VS + i];
-            x0b[i] += r[AdjArgs::O_X0 + i];
-            vh0b[i] += r[AdjArgs::O_VH0 + i];
+            acc[i] += r[AdjArgs::O_X1 + i];
+            acc[D + i] += r[AdjArgs::O_VH1 + i];
+            acc[2 * D + i] += r[AdjArgs::O_VS + i];
+            acc[3 * D + i] += r[AdjArgs::O_X0 + i];
+            acc[4 * D + i] += r[AdjArgs::O_VH0 + i];
         }
 #pragma unroll
-        for (int s = 0; s < NMS; ++s) M[s] += cr[s];
+        for (int s = 0; s < NMS; ++s) acc[5 * D + s] += cr[s];
     }
+    group_sum(acc);
+    double x1b[D], vh1b[D], M[NMS];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        x1b[i] = j.lx_in[i * nn + p] + acc[i];
+        vh1b[i] = j.lvh_in[i * nn + p] + acc[D + i];
+    }
+#pragma unroll
+    for (int s = 0; s < NMS; ++s) M[s] = acc[5 * D + s];
     double v[D], vb[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         v[i] = a.vstar[i * nn + p];
-        vb[i] = dt * x1b[i] + 2.0 * vh1b[i] + vsb[i];
-        j.lx_out[i * nn + p] = x1b[i] + x0b[i];
-        j.lvh_out[i * nn + p] = -vh1b[i] + vh0b[i];
+        vb[i] = dt * x1b[i] + 2.0 * vh1b[i] + acc[2 * D + i];
+        if (l == i) {
+            j.lx_out[i * nn + p] = x1b[i] + acc[3 * D + i];
+            j.lvh_out[i * nn + p] = -vh1b[i] + acc[4 * D + i];
+        }
     }
     double rb[D] = {}, Mb[NMS] = {};
     if (q1 > q0) node_solve_vjp<D>(M, a.allow + p * D * D, a.nallow[p], v, vb, rb, Mb);
     double *o = j.nadj + p * AdjArgs::NAD;
+    if (l == 0) {
 #pragma unroll
-    for (int i = 0; i < D; ++i) o[i] = rb[i];
+        for (int i = 0; i < D; ++i) o[i] = rb[i];
 #pragma unroll
-    for (int s = 0; s < NMS; ++s) o[D + s] = Mb[s];
+        for (int s = 0; s < NMS; ++s) o[D + s] = Mb[s];
+    }
 }
 
 // ------------------------------------------------------------------ A3
@@ -619,15 +638,19 @@ __global__ __launch_bounds__(256) void k_adj_agg(StepArgs a, AdjArgs j) {
     constexpr int NV = D + 1;
     constexpr int NMS = Dm::NMS;
     constexpr int NW = Dm::NW;
-    const int64_t p = tid();
+    const int64_t p = tid() / AG;  // the group's lanes share p: they exit together
+    const int l = (int)(threadIdx.x & (AG - 1));
     if (p >= a.nn) return;
     const int64_t nn = a.nn, nc = a.nc;
     double xp[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) xp[i] = a.x[i * nn + p];
-    double SB[NW][D] = {}, SYB[NW] = {}, SBW[D] = {}, SA[NMS] = {}, SAY[D] = {};
+    // SB[NW][D], SYB[NW], SBW[D], SA[NMS], SAY[D] in one array
+    constexpr int OB = 0, OYB = NW * D, OBW = OYB + NW, OA = OBW + D, OAY = OA + NMS, NS = OAY + D;
+    static_assert(NS == AdjArgs::NAA || D == 2, "aggregate adjoint record");
+    double S[NS] = {};
     const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
-    for (int32_t q = q0; q < q1; ++q) {
+    for (int32_t q = q0 + l; q < q1; q += AG) {
         const int64_t c = a.n2c[q] / NV;
         double y[D];
 #pragma unroll
@@ -650,35 +673,29 @@ __global__ __launch_bounds__(256) void k_adj_agg(StepArgs a, AdjArgs j) {
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const double bw = cl[AdjArgs::O_BB + w * D + i];
-                SB[w][i] += bw;
+                S[OB + w * D + i] += bw;
                 yb += y[i] * bw;
-                SBW[i] += W[w] * bw;
+                S[OBW + i] += W[w] * bw;
             }
-            SYB[w] += yb;
+            S[OYB + w] += yb;
         }
         double Ah[NMS], Ay[D];
 #pragma unroll
         for (int s = 0; s < NMS; ++s) {
             Ah[s] = cl[AdjArgs::O_AH + s];
-            SA[s] += Ah[s];
+            S[OA + s] += Ah[s];
         }
         sym_mul<D>(Ah, y, Ay);
 #pragma unroll
-        for (int i = 0; i < D; ++i) SAY[i] += Ay[i];
+        for (int i = 0; i < D; ++i) S[OAY + i] += Ay[i];
     }
+    group_sum(S);
+    // same record order as before: SB, SYB, SBW, SA, SAY; lane l writes
+    // the values l, l + AG, ...
     double *o = j.agg + p * AdjArgs::NAA;
 #pragma unroll
-    for (int w = 0; w < NW; ++w)
-#pragma unroll
-        for (int i = 0; i < D; ++i) o[w * D + i] = SB[w][i];
-#pragma unroll
-    for (int w = 0; w < NW; ++w) o[NW * D + w] = SYB[w];
-#pragma unroll
-    for (int i = 0; i < D; ++i) o[NW * D + NW + i] = SBW[i];
-#pragma unroll
-    for (int s = 0; s < NMS; ++s) o[NW * D + NW + D + s] = SA[s];
-#pragma unroll
-    for (int i = 0; i < D; ++i) o[NW * D + NW + D + NMS + i] = SAY[i];
+    for (int t = 0; t < NS; ++t)
+        if ((t & (AG - 1)) == l) o[t] = S[t];
 }
 
 // ------------------------------------------------------------------ A5
@@ -783,18 +800,21 @@ __global__ __launch_bounds__(256) void k_adj_lsq(StepArgs a, AdjArgs j) {
 // ------------------------------------------------------------------ A6
 template <int D>
 __global__ __launch_bounds__(256) void k_adj_node2(StepArgs a, AdjArgs j) {
-    const int64_t p = tid();
+    const int64_t p = tid() / AG;  // the group's lanes share p: they exit together
+    const int l = (int)(threadIdx.x & (AG - 1));
     if (p >= a.nn) return;
     const int64_t nn = a.nn;
     double s[D] = {};
     const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
-    for (int32_t q = q0; q < q1; ++q) {
+    for (int32_t q = q0 + l; q < q1; q += AG) {
         const double *xo = j.xadj + (int64_t)a.n2c[q] * D;
 #pragma unroll
         for (int i = 0; i < D; ++i) s[i] += xo[i];
     }
+    group_sum(s);
 #pragma unroll
-    for (int i = 0; i < D; ++i) j.lx_out[i * nn + p] += s[i];
+    for (int i = 0; i < D; ++i)
+        if (l == i) j.lx_out[i * nn + p] += s[i];
 }
 
 // initial-state adjoint of the node velocity: projection on allowed directions
@@ -821,11 +841,11 @@ static inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
 template <int D>
 void launch_adjoint_step(const StepArgs &a, const AdjArgs &j, hipStream_t s) {
     if (a.nc) k_adj_update<D><<<nb(a.nc), 256, 0, s>>>(a, j);
-    if (a.nn) k_adj_node1<D><<<nb(a.nn), 256, 0, s>>>(a, j);
+    if (a.nn) k_adj_node1<D><<<nb(AG * a.nn), 256, 0, s>>>(a, j);
     if (a.nc) k_adj_predict<D><<<nb(a.nc), 256, 0, s>>>(a, j);
-    if (a.nn) k_adj_agg<D><<<nb(a.nn), 256, 0, s>>>(a, j);
+    if (a.nn) k_adj_agg<D><<<nb(AG * a.nn), 256, 0, s>>>(a, j);
     if (a.nc) k_adj_lsq<D><<<nb(a.nc), 256, 0, s>>>(a, j);
-    if (a.nn) k_adj_node2<D><<<nb(a.nn), 256, 0, s>>>(a, j);
+    if (a.nn) k_adj_node2<D><<<nb(AG * a.nn), 256, 0, s>>>(a, j);
 }
 
 template <int D>
