@@ -22,7 +22,7 @@ struct Dims {
     static constexpr int NB = D == 3 ? 6 : 3;        // stored B components
     static constexpr int NW = 1 + D + NB;            // reconstructed scalars
     static constexpr int NMS = D == 3 ? 6 : 3;       // symmetric DxD entries
-    static constexpr int CW = D == 3 ? 10 : 6;       // corner record (padded)
+    static constexpr int CW = D == 3 ? 9 : 5;        // corner record: M_cp, r_cp
     // node aggregate record: n, Sy, Syy, SW, SyW, rho min, rho max, W min,
     // W max
     static constexpr int O_SY = 1;

@@ -659,14 +659,14 @@ __global__ __launch_bounds__(256) void k_predict(StepArgs a, WorkList w) {
 
 // One block per item (the one_item mapping), corner records staged in LDS
 // ([corner][cell][NMS + D], dynamic, NV * blockDim * (NMS + D) doubles):
-// after a barrier the block copies them out in 16-byte chunks in address
-// order, so each wave store covers 1 KB of consecutive bytes instead of 64
-// records 80 bytes apart.  Same values as k_predict (the pad of each
-// record is written as 0).
+// after a barrier the block copies them out in address order, so each wave
+// store covers 512 consecutive bytes instead of 64 records 72 bytes apart.
+// Same values as k_predict.
 template <int D, bool LIM, bool FAM, bool SG>
 __global__ __launch_bounds__(256) void k_predict_staged(StepArgs a, WorkList w) {
     using Dm = Dims<D>;
-    constexpr int NV = D + 1, RW = Dm::NMS + D, NP = Dm::CW / 2;
+    constexpr int NV = D + 1, RW = Dm::CW;
+    static_assert(Dm::CW == Dm::NMS + D, "corner records hold M_cp and r_cp only");
     extern __shared__ double cs[];
     const int64_t per = (w.n_items + 7) >> 3;
     const int64_t slot = blockIdx.x >> 3;
@@ -678,16 +678,14 @@ __global__ __launch_bounds__(256) void k_predict_staged(StepArgs a, WorkList w) 
     if ((int)threadIdx.x < len)
         predict_cell<D, LIM, FAM, SG, true>(a, s0 + threadIdx.x, cs + threadIdx.x * RW, bs * RW);
     __syncthreads();
-    double2 *out = reinterpret_cast<double2 *>(a.corner);
-    const int tot = len * NP;
+    // the item's records of corner k are one run within a tile (two runs
+    // if the item crosses a tile boundary)
+    const int tot = len * RW;
 #pragma unroll
     for (int k = 0; k < NV; ++k)
         for (int r = threadIdx.x; r < tot; r += bs) {
-            const int ci = r / NP, j = r - ci * NP;
-            const double *src = cs + (k * bs + ci) * RW + 2 * j;
-            const double x = src[0];
-            const double y = 2 * j + 1 < RW ? src[1] : 0.0;
-            out[corner_slot<D>(s0 + ci, k) * NP + j] = make_double2(x, y);
+            const int ci = r / RW, j = r - ci * RW;
+            a.corner[corner_slot<D>(s0 + ci, k) * RW + j] = cs[k * bs * RW + r];
         }
 }
 
@@ -734,39 +732,40 @@ __device__ __forceinline__ bool node_gather(const StepArgs &a, const int64_t p, 
 }
 
 // Cooperative corner gather (as for the node aggregates): lane l of a group
-// of AGG_G sums value pair l of the node's corner records in CSR order, so a
-// wave-wide load brings whole records; the sums then meet in every lane of
-// the group, which all run the solve.  Lane i < D writes component i.
+// of AGG_G sums value l of the node's corner records in CSR order (lane
+// 0 also value AGG_G of the 9-value 3D record), so a wave-wide load brings
+// whole records; the sums then meet in every lane of the group, which all
+// run the solve.  Lane i < D writes component i.
 template <int D, bool LD>
 __device__ __forceinline__ void node_solve_group(const StepArgs &a, const int64_t p, const int l) {
     using Dm = Dims<D>;
-    constexpr int NP = Dm::CW / 2;  // value pairs per corner record
-    const bool has = l < NP;
-    const double2 *rec = reinterpret_cast<const double2 *>(a.corner);
-    double Sa = 0.0, Sb = 0.0;
+    constexpr int CW = Dm::CW;  // values per corner record
+    static_assert(CW < 2 * AGG_G, "a lane sums at most two values of a record");
+    const bool has = l < CW, has2 = l + AGG_G < CW;
+    double S = 0.0, S2 = 0.0;
     const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
     for (int32_t qb = q0; qb < q1; qb += AGG_G) {
         const int32_t ql = qb + l;
         const int kl = ql < q1 ? a.n2c[ql] : 0;
-        double2 t[AGG_G];
+        double t[AGG_G], t2[AGG_G];
 #pragma unroll
         for (int m = 0; m < AGG_G; ++m) {
             const int km = __shfl(kl, m, AGG_G);
-            t[m] = (has && qb + m < q1) ? rec[corner_slot_of<D>(km) * NP + l] : make_double2(0.0, 0.0);
+            const double *rec = a.corner + corner_slot_of<D>(km) * CW;
+            const bool in = qb + m < q1;
+            t[m] = (has && in) ? rec[l] : 0.0;
+            t2[m] = (has2 && in) ? rec[l + AGG_G] : 0.0;
         }
 #pragma unroll
         for (int m = 0; m < AGG_G; ++m) {
             if (qb + m >= q1) break;
-            Sa += t[m].x;
-            Sb += t[m].y;
+            S += t[m];
+            S2 += t2[m];
         }
     }
-    double v[2 * NP];
+    double v[CW];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        v[2 * j] = __shfl(Sa, j, AGG_G);
-        v[2 * j + 1] = __shfl(Sb, j, AGG_G);
-    }
+    for (int j = 0; j < CW; ++j) v[j] = j < AGG_G ? __shfl(S, j, AGG_G) : __shfl(S2, j - AGG_G, AGG_G);
     double M[Dm::NMS], r[D];
 #pragma unroll
     for (int s = 0; s < Dm::NMS; ++s) M[s] = v[s];
