@@ -39,10 +39,7 @@ HL_HD void stress6_vjp(double rho0, double mu, double K, double tau, const doubl
 }
 
 // z = a / tau = sqrt((K_t + 4 mu / 3) / tau), K_t = (K/2)(J + (1 - ln J)/J)
-HL_HD double impedance(double rho0, double mu, double K, double tau) {
-    return sound(rho0, mu, K, tau) / tau;
-}
-
+// (impedance() itself is with the stress in hl_device.h)
 HL_HD void impedance_vjp(double rho0, double mu, double K, double tau, double zb, double &taub, double &mub,
                          double &Kb) {
     const double J = rho0 * tau;

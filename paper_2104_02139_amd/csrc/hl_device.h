@@ -121,11 +121,13 @@ HL_HD void geom<2>(const double X[3][2], Geo<2> &g) { geom2(X, g); }
 // dev(B), J = rho0 tau.
 HL_HD void stress6(double rho0, double mu, double K, double tau,
                                         const double b[6], double t[6]) {
+    // one reciprocal of J: ln J / J and J^{-5/3} = J^{1/3} (1/J)^2
     double J = rho0 * tau;
+    double rJ = 1.0 / J;
     double lj = log(J);
-    double p = -0.5 * K * (J - 1.0 + lj / J);
+    double p = -0.5 * K * (J - 1.0 + lj * rJ);
     double c = cbrt(J);
-    double s = mu / (J * c * c);
+    double s = mu * c * rJ * rJ;
     double tr3 = (b[0] + b[1] + b[2]) * (1.0 / 3.0);
     t[0] = s * (b[0] - tr3) - p;
     t[1] = s * (b[1] - tr3) - p;
@@ -308,8 +310,14 @@ HL_HD void stress6_dir_sg(double rho0, double mu, double a, double gam, double p
 
 HL_HD double sound(double rho0, double mu, double K, double tau) {
     double J = rho0 * tau;
-    double Kt = 0.5 * K * (J + (1.0 - log(J)) / J);
+    double Kt = 0.5 * K * (J + (1.0 - log(J)) * (1.0 / J));
     return sqrt(tau * (Kt + (4.0 / 3.0) * mu));
+}
+
+// acoustic impedance per unit volume, z = a / tau = a rho0 / J
+HL_HD double impedance(double rho0, double mu, double K, double tau) {
+    const double rJ = 1.0 / (rho0 * tau);
+    return sound(rho0, mu, K, tau) * (rho0 * rJ);
 }
 
 HL_HD double det6(const double b[6]) {
@@ -346,6 +354,7 @@ HL_HD double sym_inv2(const double a[3], double inv[3]) {
 // Dense n x n solve with partial pivoting, fully unrolled; A row-major.
 template <int N>
 HL_HD void gepp(double A[N][N], double b[N]) {
+    double rp[N];  // reciprocals of the pivots, reused by the back substitution
 #pragma unroll
     for (int col = 0; col < N; ++col) {
         // pivot search
@@ -373,7 +382,8 @@ HL_HD void gepp(double A[N][N], double b[N]) {
             b[col] = sw ? t : u;
             b[r] = sw ? u : t;
         }
-        double inv = 1.0 / A[col][col];
+        const double inv = 1.0 / A[col][col];
+        rp[col] = inv;
 #pragma unroll
         for (int r = col + 1; r < N; ++r) {
             double f = A[r][col] * inv;
@@ -387,7 +397,7 @@ HL_HD void gepp(double A[N][N], double b[N]) {
         double s = b[r];
 #pragma unroll
         for (int k = r + 1; k < N; ++k) s -= A[r][k] * b[k];
-        b[r] = s / A[r][r];
+        b[r] = s * rp[r];
     }
 }
 

@@ -560,11 +560,12 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c,
             for (int i = 0; i < D; ++i) W0[1 + i] += h * tau * divT[i];
         } else {
             const double J = rho0 * tau;
+            const double rJ = 1.0 / J;
             const double lj = log(J);
             const double cJ = cbrt(J);
-            const double J53 = 1.0 / (J * cJ * cJ);   // J^{-5/3}
-            const double J83 = J53 / J;               // J^{-8/3}
-            const double mdpdJ = 0.5 * K * (1.0 + (1.0 - lj) / (J * J));  // -dp/dJ
+            const double J53 = cJ * rJ * rJ;          // J^{-5/3}
+            const double J83 = J53 * rJ;              // J^{-8/3}
+            const double mdpdJ = 0.5 * K * (1.0 + (1.0 - lj) * rJ * rJ);  // -dp/dJ
             const double trB3 = (b[0] + b[1] + b[2]) * (1.0 / 3.0);
 #pragma unroll
             for (int i = 0; i < D; ++i) {
@@ -630,7 +631,7 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c,
                 stress6_family(rho0, mu, K, a.shear_a, Wk[0], bk, T);
             else
                 stress6(rho0, mu, K, Wk[0], bk, T);
-            z = sound(rho0, mu, K, Wk[0]) / Wk[0];
+            z = impedance(rho0, mu, K, Wk[0]);
         }
         const double rk = 1.0 / g.cn[k];
         double M[Dm::NMS];
