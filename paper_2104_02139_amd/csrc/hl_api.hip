@@ -610,8 +610,11 @@ hl_status capture_cont(hl_ctx *c, int src, int fb) {
     return HL_OK;
 }
 
+// quick: a replay for the reverse sweep (no MOOD, no report): the step is
+// enqueued without waiting for its counters.
 template <int D>
-hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on_device, hl_step_info *info) {
+hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on_device, hl_step_info *info,
+                   bool quick = false) {
     hipStream_t s = c->stream;
     const int src = c->cur;
     hl::StepArgs a = make_args(c, src);
@@ -695,6 +698,15 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
             enqueue_reduce(c, s);
             if ((st = read_counters(c, s)) != HL_OK) return st;
         }
+    } else if (quick && replay_mask && !info) {
+        if (dt > 0.0) hl::launch_fill(c->dt_cur, c->n_mesh, dt, s);
+        enqueue_first<D>(c, a, !(dt > 0.0), false, s);
+        enqueue_reduce(c, s);
+        c->last_first = 0;
+        c->last_iters = 1;
+        c->last_inadm = 0;
+        c->cur = 1 - src;
+        return HL_OK;
     } else {
         if (dt > 0.0) hl::launch_fill(c->dt_cur, c->n_mesh, dt, s);
         enqueue_first<D>(c, a, !(dt > 0.0), !replay_mask, s);
@@ -903,16 +915,15 @@ hl_status copy_state(hl_ctx *c, int buf, double *dst, bool to_snapshot) {
     const size_t d = c->dim, nn = c->nn, nc = c->nc, nB = d == 3 ? 6 : 3;
     double *parts[6] = {c->x[buf], c->vhat[buf], c->tau[buf], c->v[buf], c->e[buf], c->B[buf]};
     const size_t sz[6] = {d * nn, d * nn, nc, d * nc, nc, nB * nc};
+    hl::CopyFields f{};
     size_t off = 0;
     for (int k = 0; k < 6; ++k) {
-        if (sz[k]) {
-            if (to_snapshot)
-                HIPCHK(hipMemcpyAsync(dst + off, parts[k], sizeof(double) * sz[k], hipMemcpyDeviceToDevice, c->stream));
-            else
-                HIPCHK(hipMemcpyAsync(parts[k], dst + off, sizeof(double) * sz[k], hipMemcpyDeviceToDevice, c->stream));
-        }
+        f.src[k] = to_snapshot ? parts[k] : dst + off;
+        f.dst[k] = to_snapshot ? dst + off : parts[k];
+        f.n[k] = (int64_t)sz[k];
         off += sz[k];
     }
+    hl::launch_copy_fields(f, c->stream);  // one launch for the six fields
     return HL_OK;
 }
 
@@ -922,7 +933,7 @@ hl_status replay_recorded(hl_ctx *c, int n) {
     hipStream_t s = c->stream;
     HIPCHK(hipMemcpyAsync(c->dt_next, c->tape.dts + (size_t)n * c->n_mesh, sizeof(double) * c->n_mesh,
                           hipMemcpyDeviceToDevice, s));
-    return run_step<D>(c, 0.0, c->tape.masks + (size_t)n * c->nc, 1, nullptr) < 0 ? HL_E_HIP : HL_OK;
+    return run_step<D>(c, 0.0, c->tape.masks + (size_t)n * c->nc, 1, nullptr, true) < 0 ? HL_E_HIP : HL_OK;
 }
 
 // forward intermediates of step n for the reverse sweep: state n in buffer 0

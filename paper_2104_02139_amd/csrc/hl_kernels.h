@@ -192,6 +192,13 @@ void launch_dt_finalize(int n_mesh, const double *red, const double *dt, const h
                         double *dt_next, double *parts, hipStream_t s);
 void launch_fill(double *p, int64_t n, double v, hipStream_t s);
 void launch_aos_to_soa(int64_t n, int w, const double *in, double *out, hipStream_t s);
+// up to six device-to-device copies of doubles in one launch
+struct CopyFields {
+    const double *src[6];
+    double *dst[6];
+    int64_t n[6];
+};
+void launch_copy_fields(const CopyFields &f, hipStream_t s);
 void launch_soa_to_aos(int64_t n, int w, const double *in, double *out, hipStream_t s);
 
 }  // namespace hl

@@ -184,12 +184,13 @@ __device__ __forceinline__ void node_agg_group(const StepArgs &a, const int64_t 
     double lo1 = lo0, hi1 = hi0;
     const double2 *rec = reinterpret_cast<const double2 *>(a.xc);
     const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
-    // corners in chunks of AGG_G: lane l reads the cell of corner qb + l,
-    // then all AGG_G record loads are issued before the sums, which run in
-    // CSR order
+    // corners in chunks of AGG_G: lane l reads the cell of corner qb + l
+    // (the next chunk's while this one is summed), then all AGG_G record
+    // loads are issued before the sums, which run in CSR order
+    int jl = q0 + l < q1 ? a.n2c[q0 + l] / (D + 1) : 0;
     for (int32_t qb = q0; qb < q1; qb += AGG_G) {
-        const int32_t ql = qb + l;
-        const int jl = ql < q1 ? a.n2c[ql] / (D + 1) : 0;
+        const int32_t qn = qb + AGG_G + l;
+        const int jn = qn < q1 ? a.n2c[qn] / (D + 1) : 0;
         double2 t[AGG_G];
 #pragma unroll
         for (int m = 0; m < AGG_G; ++m) {
@@ -221,6 +222,7 @@ __device__ __forceinline__ void node_agg_group(const StepArgs &a, const int64_t 
             lo1 = fmin(lo1, vb);
             hi1 = fmax(hi1, vb);
         }
+        jl = jn;
     }
     // rho = 1/tau: a correctly rounded reciprocal is monotone on tau > 0, so
     // these equal the min / max of the cells' 1/tau bitwise
@@ -1336,6 +1338,16 @@ __global__ void k_pass_begin(unsigned *__restrict__ counters, int in_list, int32
     if (log) log[pass] = counters[CNT_F0 + in_list];
 }
 
+// blockIdx.y picks the field; blocks stride over its elements
+__global__ __launch_bounds__(256) void k_copy_fields(CopyFields f) {
+    const int k = blockIdx.y;
+    const int64_t n = f.n[k];
+    const double *__restrict__ src = f.src[k];
+    double *__restrict__ dst = f.dst[k];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 __global__ void k_fill_u8(uint8_t *__restrict__ p, int64_t n, uint8_t v) {
     for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -1798,6 +1810,11 @@ void launch_step_begin(unsigned *counters, double *dt_cur, const double *dt_next
 }
 void launch_pass_begin(unsigned *counters, int in_list, int32_t *stamp, unsigned *log, int pass, hipStream_t s) {
     k_pass_begin<<<1, 64, 0, s>>>(counters, in_list, stamp, log, pass);
+}
+void launch_copy_fields(const CopyFields &f, hipStream_t s) {
+    int64_t m = 0;
+    for (int k = 0; k < 6; ++k) m = std::max<int64_t>(m, f.n[k]);
+    if (m) k_copy_fields<<<dim3((unsigned)std::min<int64_t>((m + 255) / 256, 2048), 6), 256, 0, s>>>(f);
 }
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s) {
     if (n) k_fill_u8<<<std::min<unsigned>(nblk(n), 4096), 256, 0, s>>>(p, n, v);
