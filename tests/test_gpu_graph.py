@@ -56,3 +56,28 @@ def test_graph_equals_eager_batch():
         graph.step_batch(None)
         assert _same(eager, graph) is None, k
         assert np.array_equal(eager.next_dt(), graph.next_dt())
+
+
+def test_graph_equals_eager_when_a_pass_lists_more_cells_than_the_head():
+    """A captured MOOD pass recomputes its first 262,144 listed cells in a
+    loop-free head kernel and the rest in a strided tail; the eager pass
+    covers them all in its head.  A rough velocity field on 384,000 tets
+    sends nearly every cell to first order in the first pass."""
+    w = W.rotating_cube_3d(n=40, seed=5)
+    rng = np.random.default_rng(0)
+    w.v_cell = 40.0 * rng.standard_normal(w.v_cell.shape)
+    eager = H.from_workload(w)
+    graph = H.from_workload(w)
+    graph.use_graph(True, 6)
+    eager.compute_dt()
+    graph.compute_dt()
+    first = []
+    for k in range(2):
+        ie = eager.step(0.0)
+        ig = graph.step(0.0)
+        print(f"[graph] step {k}: first pass flags {ie['n_flag_first']} of {w.n_cells}", flush=True)
+        first.append(ie["n_flag_first"])
+        assert ie["n_flag_first"] == ig["n_flag_first"]
+        assert _same(eager, graph) is None, k
+    # the cells around the flagged cells' nodes outnumber the head
+    assert first[0] > 262144 // 2
