@@ -101,6 +101,29 @@ def read_traffic(kernel, workload):
         return None
 
 
+def read_stage_traffic(workload):
+    """Measured HBM bytes (read + written) of one launch of each stage
+    kernel of the step, from the same committed counter summary, if it was
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_predict_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha1") != kernel_source_hash():
+        return None
+    try:
+        out = {"predict": float(vals["hbm_bytes_per_launch"])}
+        for k in ("node_agg", "node_solve", "update"):
+            out[k] = float(vals[f"hbm_bytes_per_launch_{k}"])
+        return out
+    except (KeyError, ValueError):
+        return None
+
+
 def read_valu(kernel, workload):
     """FP64 flop of one launch of `kernel` from the committed rocprofv3
     VALU counter summary, if it was taken on the current kernel source."""
@@ -489,6 +512,7 @@ def main():
     traffic = read_traffic(dom, name)
     flop = read_valu(dom, name)
     step_bytes = step_alg_bytes(w.dim, w.n_cells, w.n_nodes)
+    stage_traffic = read_stage_traffic(name)
 
     out = {
         "metric": METRIC,
@@ -516,8 +540,17 @@ def main():
             "kernel": dom, "achieved": flop / (avg_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": flop / (avg_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
             "flop_per_launch": flop},
+        # alg_bytes: compulsory bytes of the whole step (state in and out,
+        # constants, connectivity, node data, each once); measured: the
+        # rocprofv3 HBM traffic of the four stage kernels (one launch each,
+        # MOOD passes and the CFL reduction not included), null unless
+        # taken on the current kernel source
         "step_roofline": {"alg_bytes_per_step": step_bytes,
-                          "hbm_frac": (step_bytes / (HBM_PEAK_GBS * 1e9)) / (ms_per_step * 1e-3)},
+                          "hbm_frac": (step_bytes / (HBM_PEAK_GBS * 1e9)) / (ms_per_step * 1e-3),
+                          "measured_stage_bytes_per_step": None if stage_traffic is None
+                          else sum(stage_traffic.values()),
+                          "measured_hbm_frac": None if stage_traffic is None
+                          else sum(stage_traffic.values()) / (HBM_PEAK_GBS * 1e9) / (ms_per_step * 1e-3)},
         "kernel_avg_ms": {k: kern[k][0] for k in kern},
         "kernel_launches": {k: kern[k][1] for k in kern},
         "mood": {"iters_mean": sum(iters) / len(iters), "first_order_frac_mean":
