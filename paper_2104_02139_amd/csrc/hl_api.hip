@@ -274,7 +274,12 @@ hl_status dalloc(hl_ctx *c, T **p, size_t n) {
 }
 
 // Work list of entity kind `kind` cut into items of at most `tile`
-// entities, items of the largest mesh first (ties in mesh order).
+// entities, items of the largest mesh first (ties in mesh order).  Node
+// items of a mesh go in the order of the first cell that uses their first
+// node: the node numbering of a generated grid already follows its cells,
+// while after a refinement the edge midpoints (numbered after the old
+// nodes) are interleaved with the old nodes around them, so the cells
+// both gather are fetched once.
 hl_status work_list(hl_ctx *c, int kind, int tile, DevList *out) {
     const auto key = std::make_pair(kind, tile);
     auto it = c->wlists.find(key);
@@ -287,13 +292,29 @@ hl_status work_list(hl_ctx *c, int kind, int tile, DevList *out) {
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
+    std::vector<int64_t> first_use;
+    if (kind == 1) {
+        const int nv = c->dim + 1;
+        first_use.assign((size_t)c->nn, INT64_MAX);
+        for (int64_t q = 0; q < c->nc * nv; ++q) {
+            int64_t &f = first_use[(size_t)c->c2n_host[(size_t)q]];
+            f = std::min<int64_t>(f, q / nv);
+        }
+    }
     std::vector<int64_t> st;
     std::vector<int32_t> ln;
-    for (int m : order)
-        for (int64_t b = off[m]; b < off[m + 1]; b += tile) {
-            st.push_back(b);
-            ln.push_back((int32_t)std::min<int64_t>(tile, off[m + 1] - b));
+    std::vector<std::pair<int64_t, int64_t>> items;  // (key, start)
+    for (int m : order) {
+        items.clear();
+        for (int64_t b = off[m]; b < off[m + 1]; b += tile) items.emplace_back(kind == 1 ? first_use[b] : b, b);
+        if (kind == 1) std::stable_sort(items.begin(), items.end(), [](const auto &x, const auto &y) {
+            return x.first < y.first;
+        });
+        for (const auto &t : items) {
+            st.push_back(t.second);
+            ln.push_back((int32_t)std::min<int64_t>(tile, off[m + 1] - t.second));
         }
+    }
     DevList d;
     d.n = (int64_t)st.size();
     hl_status r;
