@@ -1254,18 +1254,14 @@ __global__ __launch_bounds__(256) void k_update_staged(StepArgs a, WorkList w) {
     }
 }
 
-// The cells of a MOOD pass's list: a loop-free head (one cell per thread,
-// the body's own register budget) over the first gridDim * blockDim
-// entries, and a strided tail from `from` on for longer lists.
-template <int D, bool SG, bool TAIL>
-__global__ __launch_bounds__(256) void k_update_list(StepArgs a, int64_t from) {
+// The cells of a MOOD pass's list, strided over the grid.  (A loop-free
+// head for the first gridDim * blockDim entries runs at three waves per
+// SIMD instead of two, but the tail launch it needs costs every captured
+// pass more than the head saves.)
+template <int D, bool SG>
+__global__ __launch_bounds__(256) void k_update_list(StepArgs a) {
     const int64_t n = a.counters[CNT_CELLS];
-    if (TAIL) {
-        for (int64_t i = from + gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) update_cell<D, SG>(a, a.clist[i]);
-    } else {
-        const int64_t i = gtid();
-        if (i < n) update_cell<D, SG>(a, a.clist[i]);
-    }
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) update_cell<D, SG>(a, a.clist[i]);
 }
 
 // ------------------------------------------------------ MOOD bookkeeping
@@ -1807,15 +1803,10 @@ void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned 
         k_pass_nodes<D, true><<<grid(AGG_G * nnodes), 256, 0, s>>>(a);
     else
         k_pass_nodes<D, false><<<grid(AGG_G * nnodes), 256, 0, s>>>(a);
-    const unsigned gu = grid(ncells);
-    const int64_t head = (int64_t)gu * 256;
-    if (a.eos) {
-        k_update_list<D, true, false><<<gu, 256, 0, s>>>(a, 0);
-        if (ncells > head) k_update_list<D, true, true><<<gu, 256, 0, s>>>(a, head);
-    } else {
-        k_update_list<D, false, false><<<gu, 256, 0, s>>>(a, 0);
-        if (ncells > head) k_update_list<D, false, true><<<gu, 256, 0, s>>>(a, head);
-    }
+    if (a.eos)
+        k_update_list<D, true><<<grid(ncells), 256, 0, s>>>(a);
+    else
+        k_update_list<D, false><<<grid(ncells), 256, 0, s>>>(a);
 }
 void launch_step_begin(unsigned *counters, double *dt_cur, const double *dt_next, int n_mesh, int copy_dt,
                        hipStream_t s) {

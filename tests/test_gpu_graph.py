@@ -58,11 +58,11 @@ def test_graph_equals_eager_batch():
         assert np.array_equal(eager.next_dt(), graph.next_dt())
 
 
-def test_graph_equals_eager_when_a_pass_lists_more_cells_than_the_head():
-    """A captured MOOD pass recomputes its first 262,144 listed cells in a
-    loop-free head kernel and the rest in a strided tail; the eager pass
-    covers them all in its head.  A rough velocity field on 384,000 tets
-    sends nearly every cell to first order in the first pass."""
+def test_graph_equals_eager_when_a_pass_lists_more_cells_than_the_grid():
+    """A captured MOOD pass has a fixed grid of 262,144 threads and strides
+    over longer lists; the eager pass sizes its grid to the list.  A rough
+    velocity field on 384,000 tets sends nearly every cell to first order
+    in the first pass."""
     w = W.rotating_cube_3d(n=40, seed=5)
     rng = np.random.default_rng(0)
     w.v_cell = 40.0 * rng.standard_normal(w.v_cell.shape)
@@ -79,5 +79,5 @@ def test_graph_equals_eager_when_a_pass_lists_more_cells_than_the_head():
         first.append(ie["n_flag_first"])
         assert ie["n_flag_first"] == ig["n_flag_first"]
         assert _same(eager, graph) is None, k
-    # the cells around the flagged cells' nodes outnumber the head
+    # the cells around the flagged cells' nodes outnumber the captured grid
     assert first[0] > 262144 // 2
