@@ -573,12 +573,11 @@ void enqueue_first(hl_ctx *c, hl::StepArgs &a, bool copy_dt, bool clear_mask, hi
 template <int D>
 void enqueue_pass(hl_ctx *c, hl::StepArgs a, int fb, int log_index, int64_t nflag, bool fixed, hipStream_t s) {
     const int nb = 1 - fb;
-    hl::launch_pass_begin(c->counters, fb, c->stamp_dev, log_index >= 0 ? c->pass_log : nullptr,
-                          log_index >= 0 ? log_index : 0, s);
     a.flist_out = c->flist[nb];
     a.fcount_out = c->counters + hl::CNT_F0 + nb;
     PROF(c, PK_MOOD,
-         hl::launch_mood_sparse<D>(a, c->flist[fb], c->counters + hl::CNT_F0 + fb, nflag, c->max_deg, fixed, s));
+         hl::launch_mood_sparse<D>(a, c->flist[fb], c->counters + hl::CNT_F0 + fb, nflag, c->max_deg, fixed,
+                                   log_index >= 0 ? c->pass_log : nullptr, log_index >= 0 ? log_index : 0, s));
 }
 
 void enqueue_reduce(hl_ctx *c, hipStream_t s) {

@@ -35,7 +35,7 @@ struct StepArgs {
     unsigned *fcount_out;
     int32_t *nlist, *clist;
     int32_t *nstamp, *cstamp;
-    int32_t *stamp;            // device: stamp of the current MOOD pass
+    int32_t *stamp;            // device: stamp of the last MOOD pass; a pass stamps with *stamp + 1
     unsigned int *counters;    // [CNT_NODES], [CNT_CELLS], [CNT_BAD]
     double delta0, delta1, eps_tol;
     int detect;
@@ -179,12 +179,13 @@ template <int D> void launch_stress_query(const StepArgs &a, double *out, hipStr
 // One sparse MOOD pass: flagged list `fb` in, newly flagged list written to
 // a.flist_out.  fixed_grid: launch shapes independent of the flag count
 // (for graph capture); kernels then read every count from device memory.
+// The pass clears its own lists and advances a.stamp; log (may be null):
+// log[log_idx] = the input flag count.
 template <int D>
 void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned *fcount, int64_t nflag,
-                        int64_t max_deg, bool fixed_grid, hipStream_t s);
+                        int64_t max_deg, bool fixed_grid, unsigned *log, int log_idx, hipStream_t s);
 void launch_step_begin(unsigned *counters, double *dt_cur, const double *dt_next, int n_mesh, int copy_dt,
                        hipStream_t s);
-void launch_pass_begin(unsigned *counters, int in_list, int32_t *stamp, unsigned *log, int pass, hipStream_t s);
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 void launch_dt_reduce(int64_t nc, const double *dtc, const int32_t *cell_mesh, const uint8_t *pstat, double *red,
                       double *part, const int64_t *mesh_cell_off, int n_mesh, unsigned *bad_count, hipStream_t s);

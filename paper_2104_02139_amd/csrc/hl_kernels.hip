@@ -29,9 +29,10 @@ __device__ __forceinline__ int64_t gtid() {
 
 // Append `val` to `list` where `want`, one counter atomic per block of 256
 // threads; every thread of the block calls it the same number of times.
-// sh: 5 words of LDS.
+// sh: 5 words of LDS.  Slots at or beyond `cap` (the list's length) are
+// counted but not written.
 __device__ __forceinline__ void block_append(int32_t *__restrict__ list, unsigned *__restrict__ counter, bool want,
-                                             int32_t val, unsigned *sh) {
+                                             int32_t val, unsigned cap, unsigned *sh) {
     const int lane = (int)__lane_id(), w = (int)(threadIdx.x >> 6);
     const unsigned long long m = __ballot(want);
     if (lane == 0) sh[w] = (unsigned)__popcll(m);
@@ -46,15 +47,17 @@ __device__ __forceinline__ void block_append(int32_t *__restrict__ list, unsigne
         sh[4] = tot ? atomicAdd(counter, tot) : 0u;
     }
     __syncthreads();
-    if (want) list[sh[4] + sh[w] + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = val;
+    const unsigned slot = sh[4] + sh[w] + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+    if (want && slot < cap) list[slot] = val;
     __syncthreads();
 }
 
 // Append `val` to `list` where `want`, one counter atomic per wave: the
 // lowest active lane reserves the wave's slots, each lane takes the slot of
 // its rank among the wanting lanes.  Callable with a partial wave active.
+// Slots at or beyond `cap` are counted but not written.
 __device__ __forceinline__ void wave_append(int32_t *__restrict__ list, unsigned *__restrict__ counter, bool want,
-                                            int32_t val) {
+                                            int32_t val, unsigned cap) {
     const unsigned long long act = __ballot(1);
     const unsigned long long m = __ballot(want);
     if (!m) return;
@@ -63,7 +66,8 @@ __device__ __forceinline__ void wave_append(int32_t *__restrict__ list, unsigned
     unsigned base = 0;
     if (lane == leader) base = atomicAdd(counter, (unsigned)__popcll(m));
     base = __shfl(base, leader, 64);
-    if (want) list[base + __popcll(m & ((1ull << lane) - 1ull))] = val;
+    const unsigned slot = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+    if (want && slot < cap) list[slot] = val;
 }
 
 // Walk the items of a work list (see WorkList); f(entity) for each entity.
@@ -1205,7 +1209,7 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
         const double rho1 = 1.0 / tau1;
         const double delta = fmax(a.delta0, a.delta1 * (hi - lo));
         const bool bad = pad_bad || rho1 < lo - delta || rho1 > hi + delta;
-        wave_append(a.flist_out, a.fcount_out, bad, (int32_t)c);
+        wave_append(a.flist_out, a.fcount_out, bad, (int32_t)c, (unsigned)a.nc);
     }
     a.pstat[c] = (!p1 && pad_bad) ? 1 : 0;
 
@@ -1258,23 +1262,40 @@ __global__ __launch_bounds__(256) void k_update_staged(StepArgs a, WorkList w) {
 // head for the first gridDim * blockDim entries runs at three waves per
 // SIMD instead of two, but the tail launch it needs costs every captured
 // pass more than the head saves.)
+//
+// The pass's bookkeeping rides on its kernels, each step after the last
+// reader of what it changes: the first thread of k_pass_cells clears the
+// output flag count and the cell list, and logs the input count; the first
+// thread of k_update_list clears the node list and advances the stamp for
+// the next pass.  k_step_begin clears every count before the first pass.
 template <int D, bool SG>
 __global__ __launch_bounds__(256) void k_update_list(StepArgs a) {
-    const int64_t n = a.counters[CNT_CELLS];
+    const int64_t n = min((int64_t)a.counters[CNT_CELLS], a.nc);
+    if (gtid() == 0) {
+        a.counters[CNT_NODES] = 0u;
+        *a.stamp = *a.stamp + 1;
+    }
     for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) update_cell<D, SG>(a, a.clist[i]);
 }
 
 // ------------------------------------------------------ MOOD bookkeeping
-// A sparse MOOD pass (Section 3.7) in three launches after k_pass_begin:
-// the flagged cells, the nodes they touch, the cells around those nodes.
+// A sparse MOOD pass (Section 3.7) in three launches: the flagged cells,
+// the nodes they touch, the cells around those nodes.  The pass's stamp is
+// the device stamp + 1 (k_update_list advances it at the pass's end).
 // First: every flagged cell drops to the next scheme of the cascade, its
 // corner records are recomputed at that level, and its nodes are listed
-// once (stamp = this pass).
+// once.  log (may be null): log[log_idx] = the input count.
 template <int D, bool LIM, bool FAM, bool SG>
 __global__ __launch_bounds__(256) void k_pass_cells(StepArgs a, const int32_t *__restrict__ list,
-                                                    const unsigned *__restrict__ count) {
-    const int64_t n = *count;
-    const int32_t st = *a.stamp;
+                                                    const unsigned *__restrict__ count, unsigned *__restrict__ log,
+                                                    int log_idx) {
+    const int64_t n = min((int64_t)*count, a.nc);
+    const int32_t st = *a.stamp + 1;
+    if (gtid() == 0) {
+        *a.fcount_out = 0u;
+        a.counters[CNT_CELLS] = 0u;
+        if (log) log[log_idx] = (unsigned)n;
+    }
     uint8_t *mask = const_cast<uint8_t *>(a.mask);
     for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = list[i];
@@ -1285,7 +1306,7 @@ __global__ __launch_bounds__(256) void k_pass_cells(StepArgs a, const int32_t *_
         for (int k = 0; k <= D; ++k) fresh[k] = atomicExch(&a.nstamp[a.c2n[(int64_t)c * (D + 1) + k]], st) != st;
 #pragma unroll
         for (int k = 0; k <= D; ++k)
-            wave_append(a.nlist, &a.counters[CNT_NODES], fresh[k], a.c2n[(int64_t)c * (D + 1) + k]);
+            wave_append(a.nlist, &a.counters[CNT_NODES], fresh[k], a.c2n[(int64_t)c * (D + 1) + k], (unsigned)a.nn);
     }
 }
 
@@ -1295,8 +1316,8 @@ __global__ __launch_bounds__(256) void k_pass_cells(StepArgs a, const int32_t *_
 template <int D, bool LD>
 __global__ __launch_bounds__(256) void k_pass_nodes(StepArgs a) {
     __shared__ unsigned sh[5];
-    const int64_t n = a.counters[CNT_NODES];
-    const int32_t st = *a.stamp;
+    const int64_t n = min((int64_t)a.counters[CNT_NODES], a.nn);
+    const int32_t st = *a.stamp + 1;
     const int l = threadIdx.x & (AGG_G - 1);
     const int per_block = blockDim.x / AGG_G;
     // block-uniform loops (block_append synchronises the block)
@@ -1316,7 +1337,7 @@ __global__ __launch_bounds__(256) void k_pass_nodes(StepArgs a) {
                 j = a.n2c[q] / (D + 1);
                 fresh = atomicExch(&a.cstamp[j], st) != st;
             }
-            block_append(a.clist, &a.counters[CNT_CELLS], fresh, j, sh);
+            block_append(a.clist, &a.counters[CNT_CELLS], fresh, j, (unsigned)a.nc, sh);
         }
     }
 }
@@ -1328,18 +1349,6 @@ __global__ void k_step_begin(unsigned *__restrict__ counters, double *__restrict
     if (i < CNT_N) counters[i] = 0u;
     if (copy_dt)
         for (int64_t m = i; m < n_mesh; m += (int64_t)gridDim.x * blockDim.x) dt_cur[m] = dt_next[m];
-}
-
-// Start of a sparse MOOD pass reading flag list `in_list`: clear the output
-// list and the node/cell lists, advance the stamp, log the input count.
-__global__ void k_pass_begin(unsigned *__restrict__ counters, int in_list, int32_t *__restrict__ stamp,
-                             unsigned *__restrict__ log, int pass) {
-    if (gtid() != 0) return;
-    counters[CNT_F0 + (1 - in_list)] = 0u;
-    counters[CNT_NODES] = 0u;
-    counters[CNT_CELLS] = 0u;
-    *stamp = *stamp + 1;
-    if (log) log[pass] = counters[CNT_F0 + in_list];
 }
 
 // blockIdx.y picks the field; blocks stride over its elements
@@ -1782,7 +1791,7 @@ void launch_update(const StepArgs &a, const Sched &k, hipStream_t s) {
 }
 template <int D>
 void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned *fcount, int64_t nflag,
-                        int64_t max_deg, bool fixed_grid, hipStream_t s) {
+                        int64_t max_deg, bool fixed_grid, unsigned *log, int log_idx, hipStream_t s) {
     // fixed grids (graph capture) are capped at 1024 blocks: the kernels
     // stride over their lists, and an empty pass then launches few blocks
     const int64_t gmax = fixed_grid ? 1024 : 16384;
@@ -1792,13 +1801,13 @@ void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned 
     const int64_t ncells = std::min<int64_t>(a.nc, nnodes * max_deg);
     const bool fam = a.shear_a != -1.0;
     if (a.eos)
-        k_pass_cells<D, false, false, true><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+        k_pass_cells<D, false, false, true><<<grid(nflag), 256, 0, s>>>(a, flist, fcount, log, log_idx);
     else if (a.limited)
-        fam ? k_pass_cells<D, true, true, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
-            : k_pass_cells<D, true, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+        fam ? k_pass_cells<D, true, true, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount, log, log_idx)
+            : k_pass_cells<D, true, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount, log, log_idx);
     else
-        fam ? k_pass_cells<D, false, true, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount)
-            : k_pass_cells<D, false, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount);
+        fam ? k_pass_cells<D, false, true, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount, log, log_idx)
+            : k_pass_cells<D, false, false, false><<<grid(nflag), 256, 0, s>>>(a, flist, fcount, log, log_idx);
     if (a.ld_off)
         k_pass_nodes<D, true><<<grid(AGG_G * nnodes), 256, 0, s>>>(a);
     else
@@ -1811,9 +1820,6 @@ void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned 
 void launch_step_begin(unsigned *counters, double *dt_cur, const double *dt_next, int n_mesh, int copy_dt,
                        hipStream_t s) {
     k_step_begin<<<std::max(1, (n_mesh + 255) / 256), 256, 0, s>>>(counters, dt_cur, dt_next, n_mesh, copy_dt);
-}
-void launch_pass_begin(unsigned *counters, int in_list, int32_t *stamp, unsigned *log, int pass, hipStream_t s) {
-    k_pass_begin<<<1, 64, 0, s>>>(counters, in_list, stamp, log, pass);
 }
 void launch_copy_fields(const CopyFields &f, hipStream_t s) {
     int64_t m = 0;
@@ -1876,9 +1882,9 @@ template void launch_node_solve<3>(const StepArgs &, const Sched &, hipStream_t)
 template void launch_update<2>(const StepArgs &, const Sched &, hipStream_t);
 template void launch_update<3>(const StepArgs &, const Sched &, hipStream_t);
 template void launch_mood_sparse<2>(const StepArgs &, const int32_t *, const unsigned *, int64_t, int64_t, bool,
-                                    hipStream_t);
+                                    unsigned *, int, hipStream_t);
 template void launch_mood_sparse<3>(const StepArgs &, const int32_t *, const unsigned *, int64_t, int64_t, bool,
-                                    hipStream_t);
+                                    unsigned *, int, hipStream_t);
 template void launch_acoustic<2>(const StepArgs &, hipStream_t);
 template void launch_acoustic<3>(const StepArgs &, hipStream_t);
 template int64_t launch_diag<2>(const StepArgs &, const double *, const double *, const double *, const double *,
