@@ -27,6 +27,17 @@ __device__ __forceinline__ int64_t gtid() {
     return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 }
 
+// Streamed stores: data that the next kernels read only after gigabytes of
+// other traffic (corner records, gather records, the new cell state) are
+// written with the nontemporal hint, so they do not push reused data (node
+// aggregates, node positions) out of the caches.
+__device__ __forceinline__ void store_stream(double *p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_stream(double2 *p, double2 v) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<d2 *>(p));
+}
+
 // Append `val` to `list` where `want`, one counter atomic per block of 256
 // threads; every thread of the block calls it the same number of times.
 // sh: 5 words of LDS.  Slots at or beyond `cap` (the list's length) are
@@ -322,11 +333,11 @@ template <int D>
 __device__ __forceinline__ void store_B6(double *__restrict__ B, int64_t nc, int64_t c, const double b[6]) {
     if (D == 3) {
 #pragma unroll
-        for (int s = 0; s < 6; ++s) B[s * nc + c] = b[s];
+        for (int s = 0; s < 6; ++s) store_stream(&B[s * nc + c], b[s]);
     } else {
-        B[c] = b[0];
-        B[nc + c] = b[1];
-        B[2 * nc + c] = b[3];
+        store_stream(&B[c], b[0]);
+        store_stream(&B[nc + c], b[1]);
+        store_stream(&B[2 * nc + c], b[3]);
     }
 }
 
@@ -692,7 +703,7 @@ __global__ __launch_bounds__(256) void k_predict_staged(StepArgs a, WorkList w) 
     for (int k = 0; k < NV; ++k)
         for (int r = threadIdx.x; r < tot; r += bs) {
             const int ci = r / RW, j = r - ci * RW;
-            a.corner[corner_slot<D>(s0 + ci, k) * RW + j] = cs[k * bs * RW + r];
+            store_stream(&a.corner[corner_slot<D>(s0 + ci, k) * RW + j], cs[k * bs * RW + r]);
         }
 }
 
@@ -1059,10 +1070,10 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         v1[i] = a.v[i * nc + c] + dtm * F[i];
-        a.v1[i * nc + c] = v1[i];
+        store_stream(&a.v1[i * nc + c], v1[i]);
     }
     const double e1 = a.e[c] + dtm * Wk;
-    a.e1[c] = e1;
+    store_stream(&a.e1[c], e1);
 
     // ---- geometry at t^n and t^{n+1}; velocity gradients
     const bool p1 = a.mask[c] < 2;   // unlimited or limited second order
@@ -1127,7 +1138,7 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
                 L1[i][j] *= r1;
             }
     }
-    a.tau1[c] = tau1;
+    store_stream(&a.tau1[c], tau1);
 
     // ---- B: Crank-Nicolson (P1) or Euler (P0)
     double b[6], b1[6];
@@ -1254,7 +1265,7 @@ __global__ __launch_bounds__(256) void k_update_staged(StepArgs a, WorkList w) {
     double2 *out = reinterpret_cast<double2 *>(a.xc + s0 * Dm::GR);
     for (int q = threadIdx.x; q < len * NPR; q += blockDim.x) {
         const int ci = q / NPR, j = q - ci * NPR;
-        out[q] = src[ci * (LS / 2) + j];
+        store_stream(&out[q], src[ci * (LS / 2) + j]);
     }
 }
 
