@@ -37,13 +37,6 @@ __device__ __forceinline__ void store_stream(double2 *p, double2 v) {
     const d2 t = {v.x, v.y};
     __builtin_nontemporal_store(t, reinterpret_cast<d2 *>(p));
 }
-// a record value: an ordinary store into LDS staging, else a streamed one
-template <bool LDS, class T> __device__ __forceinline__ void put_record(T *p, T v) {
-    if constexpr (LDS)
-        *p = v;
-    else
-        store_stream(p, v);
-}
 
 // Append `val` to `list` where `want`, one counter atomic per block of 256
 // threads; every thread of the block calls it the same number of times.
@@ -666,13 +659,13 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c,
                 M[midx<D>(i, j)] = z * (S[midx<D>(i, j)] - g.C[k][i] * g.C[k][j] * rk);
         double *o = STAGE ? lrec + k * lstride : a.corner + corner_slot<D>(c, k) * Dm::CW;
 #pragma unroll
-        for (int q = 0; q < Dm::NMS; ++q) put_record<STAGE>(&o[q], M[q]);
+        for (int q = 0; q < Dm::NMS; ++q) o[q] = M[q];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             double s = 0.0;
 #pragma unroll
             for (int j = 0; j < D; ++j) s += M[midx<D>(i, j)] * Wk[1 + j] - T[sidx(i, j)] * g.C[k][j];
-            put_record<STAGE>(&o[Dm::NMS + i], s);
+            o[Dm::NMS + i] = s;
         }
     }
 }
@@ -1196,7 +1189,7 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
         }
         double2 *o = reinterpret_cast<double2 *>(STAGE ? lrec : a.xc + c * Dm::GR);
 #pragma unroll
-        for (int q = 0; q < Dm::GR / 2; ++q) put_record<STAGE>(&o[q], make_double2(r[2 * q], r[2 * q + 1]));
+        for (int q = 0; q < Dm::GR / 2; ++q) o[q] = make_double2(r[2 * q], r[2 * q + 1]);
     }
 
     // ---- detection (eqs. PAD, RDMP; R16, R17)
