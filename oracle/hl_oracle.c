@@ -93,6 +93,15 @@ typedef struct {
     int32_t mood_iters;    /* number of candidate evaluations              */
     int32_t status;        /* 0 ok, 1 a parachute cell is not admissible   */
     int64_t n_lim;         /* cells computed with the limited slopes       */
+    int64_t n_recomp;      /* cell updates redone by the MOOD loop: per
+                              iteration, the cells that share a node with a
+                              newly flagged cell (R18)                      */
+    double gcl_defect;     /* max_c |V(x^{n+1}) - V(x^n) - dt sum_p Cbar_cp .
+                              v*_p| / V(x^n), Cbar the Simpson average of
+                              the corner vectors over the step (eq. GCL)    */
+    double detB_defect;    /* max_c |sqrt(det B^{n+1}) - rho0 tau^{n+1}|
+                              (eq. test_detB_rho, reading R19)             */
+    int64_t n_detB;        /* cells where that difference is >= L_c^3      */
 } orc_info;
 
 typedef struct {
@@ -1163,14 +1172,74 @@ static int inadmissible(const orc_work *w, const orc_params *prm, int64_t c) {
     return 0;
 }
 
-/* detection (eqs. PAD and RDMP; readings R16, R17): 1 = troubled */
+/* detection (eqs. PAD and RDMP; readings R16, R17): 0 = accepted,
+ * 1 = not physically admissible, 2 = outside the relaxed DMP bounds */
 static int troubled(const orc_work *w, const orc_params *prm, int64_t c) {
     if (inadmissible(w, prm, c)) return 1;
     double rho1 = 1.0 / w->tau1[c];
     double lo = w->rmin[c], hi = w->rmax[c];
     double delta = fmax(prm->delta0, prm->delta1 * (hi - lo));
-    if (rho1 < lo - delta || rho1 > hi + delta) return 1;
+    if (rho1 < lo - delta || rho1 > hi + delta) return 2;
     return 0;
+}
+
+/* Relaxed-DMP bounds (eq. RDMP, reading R17): min and max of rho^n = 1/tau^n
+ * over {c} and its reconstruction stencil, the cells sharing a node with c. */
+static void rdmp_bounds(const orc_mesh *M, const double *tau, double *rmin, double *rmax) {
+    int nv = M->nv;
+    for (int64_t c = 0; c < M->nc; ++c) {
+        double lo = 1.0 / tau[c], hi = lo;
+        for (int k = 0; k < nv; ++k) {
+            int64_t p = M->c2n[c * nv + k];
+            for (int64_t q = M->n2c_off[p]; q < M->n2c_off[p + 1]; ++q) {
+                double r = 1.0 / tau[M->n2c[q] / nv];
+                lo = fmin(lo, r);
+                hi = fmax(hi, r);
+            }
+        }
+        rmin[c] = lo;
+        rmax[c] = hi;
+    }
+}
+
+/* Involution monitors of the step just taken (Section 3.5): the discrete
+ * GCL (eq. GCL) with the corner vectors averaged over the step by Simpson's
+ * rule, which is exact for straight node paths (V is a cubic in time, its
+ * rate sum_p C_cp(t) . v*_p a quadratic), and |sqrt(det B) - J| against
+ * L_c^3 (eq. test_detB_rho, reading R19). */
+static void involutions(const orc_mesh *M, const double *rho0, const double *x, const double *vstar3, double dt,
+                        const double *x1, const double *tau1, const double *B1, orc_info *info) {
+    int d = M->dim, nv = M->nv;
+    info->gcl_defect = 0.0;
+    info->detB_defect = 0.0;
+    info->n_detB = 0;
+    double *xh = (double *)malloc(sizeof(double) * (size_t)(M->nn * d + 1));
+    for (int64_t p = 0; p < M->nn; ++p)
+        for (int i = 0; i < d; ++i) xh[p * d + i] = x[p * d + i] + 0.5 * dt * vstar3[p * 3 + i];
+    for (int64_t c = 0; c < M->nc; ++c) {
+        double X0[4][3], Xh[4][3], X1[4][3];
+        orc_geo g0, gh, g1;
+        cell_nodes(M, x, c, X0);
+        cell_nodes(M, xh, c, Xh);
+        cell_nodes(M, x1, c, X1);
+        geometry(d, X0, &g0);
+        geometry(d, Xh, &gh);
+        geometry(d, X1, &g1);
+        double flux = 0.0;
+        for (int k = 0; k < nv; ++k) {
+            int64_t p = M->c2n[c * nv + k];
+            for (int i = 0; i < d; ++i)
+                flux += (g0.C[k][i] + 4.0 * gh.C[k][i] + g1.C[k][i]) / 6.0 * vstar3[p * 3 + i];
+        }
+        double gcl = fabs(g1.V - g0.V - dt * flux) / g0.V;
+        if (gcl > info->gcl_defect) info->gcl_defect = gcl;
+        double Bc[3][3];
+        unpack_B(d, B1 + c * M->nB, Bc);
+        double dB = fabs(sqrt(det33(Bc)) - rho0[c] * tau1[c]);
+        if (dB > info->detB_defect) info->detB_defect = dB;
+        if (dB >= g1.Lc * g1.Lc * g1.Lc) info->n_detB++;
+    }
+    free(xh);
 }
 
 static void diagnostics(const orc_mesh *M, const double *rho0, const double *mu, const double *K,
@@ -1292,23 +1361,11 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
     }
     lsq_gradients(M, w.xc, tau, v, B, e, w.grad);
     bj_limit(M, x, w.xc, tau, v, B, w.grad, w.glim);
-    /* relaxed-DMP bounds of rho^n over {c} and its reconstruction stencil */
-    for (int64_t c = 0; c < M->nc; ++c) {
-        double lo = 1.0 / tau[c], hi = lo;
-        for (int k = 0; k < nv; ++k) {
-            int64_t p = M->c2n[c * nv + k];
-            for (int64_t q = M->n2c_off[p]; q < M->n2c_off[p + 1]; ++q) {
-                double r = 1.0 / tau[M->n2c[q] / nv];
-                lo = fmin(lo, r);
-                hi = fmax(hi, r);
-            }
-        }
-        w.rmin[c] = lo;
-        w.rmax[c] = hi;
-    }
+    rdmp_bounds(M, tau, w.rmin, w.rmax);
 
     int iters = 0;
-    int64_t first = -1;
+    int64_t first = -1, recomp = 0;
+    uint8_t *touch = (uint8_t *)calloc((size_t)M->nn + 1, 1);
     for (;;) {
         candidate(&w, mask);
         ++iters;
@@ -1325,9 +1382,22 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
         if (nflag == 0) break;
         for (int64_t c = 0; c < M->nc; ++c)
             if (flag[c]) mask[c] = (prm->cascade == 3 && mask[c] == 0) ? 1 : 2;
+        /* the next evaluation changes only the cells that share a node with
+           a flagged cell (R18): count them */
+        memset(touch, 0, (size_t)M->nn);
+        for (int64_t c = 0; c < M->nc; ++c)
+            if (flag[c])
+                for (int k = 0; k < nv; ++k) touch[M->c2n[c * nv + k]] = 1;
+        for (int64_t c = 0; c < M->nc; ++c) {
+            int hit = 0;
+            for (int k = 0; k < nv; ++k) hit |= touch[M->c2n[c * nv + k]];
+            recomp += hit;
+        }
     }
+    free(touch);
 
     memset(info, 0, sizeof(*info));
+    info->n_recomp = recomp;
     info->mood_iters = iters;
     info->n_flag_first = first < 0 ? 0 : first;
     for (int64_t c = 0; c < M->nc; ++c) {
@@ -1342,6 +1412,7 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
             for (int i = 0; i < d; ++i) vstar_out[p * d + i] = w.vstar[p * 3 + i];
     time_step(M, rho0, mu, K, x1, tau1, v1, e1, B1, m, V0, dt, prm, info);
     diagnostics(M, rho0, mu, K, prm, m, tau1, v1, e1, B1, info);
+    involutions(M, rho0, x, w.vstar, dt, x1, tau1, B1, info);
 
     free(w.geo);
     free(w.xc);
@@ -1359,6 +1430,43 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
 /* ------------------------------------------------------------------ */
 /* unit-level entry points used by the pin tests                       */
 /* ------------------------------------------------------------------ */
+/* Detection of a given candidate state (eqs. PAD, RDMP; readings R16, R17)
+ * with the relaxed-DMP bounds of the state tau0 at t^n: code[c] = 0
+ * accepted, 1 not physically admissible, 2 outside the relaxed DMP bounds.
+ * Cells at first order (mask >= 2) are accepted as the parachute. */
+void orc_detect(const orc_mesh *M, const double *rho0, const double *mu, const double *K, const double *tau0,
+                const double *tau1, const double *v1, const double *e1, const double *B1, const uint8_t *mask,
+                const orc_params *prm, uint8_t *code) {
+    orc_work w;
+    memset(&w, 0, sizeof w);
+    w.M = M;
+    w.rho0 = rho0;
+    w.mu = mu;
+    w.K = K;
+    w.a = prm->shear_a;
+    w.eos = prm->eos;
+    w.gam = prm->sg_gamma;
+    w.pinf = prm->sg_pinf;
+    w.tau1 = (double *)tau1;
+    w.v1 = (double *)v1;
+    w.e1 = (double *)e1;
+    w.B1 = (double *)B1;
+    w.rmin = (double *)malloc(sizeof(double) * (size_t)(M->nc + 1));
+    w.rmax = (double *)malloc(sizeof(double) * (size_t)(M->nc + 1));
+    rdmp_bounds(M, tau0, w.rmin, w.rmax);
+    for (int64_t c = 0; c < M->nc; ++c) code[c] = (uint8_t)((mask && mask[c] >= 2) ? 0 : troubled(&w, prm, c));
+    free(w.rmin);
+    free(w.rmax);
+}
+
+/* Time-step control of a given end-of-step state (eqs. CFL, CFL2; R20, R21):
+ * V0 (may be NULL: first step) holds V^n per cell, dt_prev the step's dt. */
+void orc_time_step(const orc_mesh *M, const double *rho0, const double *mu, const double *K, const double *x1,
+                   const double *tau1, const double *v1, const double *e1, const double *B1, const double *m,
+                   const double *V0, double dt_prev, const orc_params *prm, orc_info *info) {
+    memset(info, 0, sizeof(*info));
+    time_step(M, rho0, mu, K, x1, tau1, v1, e1, B1, m, V0, dt_prev, prm, info);
+}
 /* X: [(d+1)][d] -> V, xc[3], C[(d+1)][3], A[(d+1)][3], Lc */
 void orc_cell_geometry(int d, const double *Xin, double *V, double *xc, double *C, double *A,
                        double *Lc) {

@@ -46,14 +46,17 @@ class Info(C.Structure):
                 ("dt_volume", C.c_double), ("mass", C.c_double), ("mom", C.c_double * 3),
                 ("energy", C.c_double), ("kinetic", C.c_double), ("elastic", C.c_double),
                 ("n_p0", C.c_int64), ("n_flag_first", C.c_int64), ("mood_iters", C.c_int32),
-                ("status", C.c_int32), ("n_lim", C.c_int64)]
+                ("status", C.c_int32), ("n_lim", C.c_int64), ("n_recomp", C.c_int64),
+                ("gcl_defect", C.c_double), ("detB_defect", C.c_double), ("n_detB", C.c_int64)]
 
     def as_dict(self):
         return dict(dt_next=self.dt_next, dt_acoustic=self.dt_acoustic,
                     dt_volume=self.dt_volume, mass=self.mass, mom=list(self.mom),
                     energy=self.energy, kinetic=self.kinetic, elastic=self.elastic,
                     n_p0=self.n_p0, n_flag_first=self.n_flag_first,
-                    mood_iters=self.mood_iters, status=self.status, n_lim=self.n_lim)
+                    mood_iters=self.mood_iters, status=self.status, n_lim=self.n_lim,
+                    n_recomp=self.n_recomp, gcl_defect=self.gcl_defect,
+                    detB_defect=self.detB_defect, n_detB=self.n_detB)
 
 
 def default_params(c_cfl=0.25, detect=True, cascade=2, shear_a=-1.0, eos=0, sg_gamma=2.2, sg_pinf=1e6):
@@ -108,6 +111,9 @@ def lib():
         L.orc_point_stress_sg.argtypes = [C.c_double] * 6 + [_P, C.c_double, _P, _P, _P, _P]
         L.orc_point_stress_direction_sg.argtypes = ([C.c_double] * 6 + [_P, C.c_double, C.c_double, _P,
                                                     C.c_double, _P])
+        L.orc_detect.argtypes = [C.c_void_p] + [_P] * 8 + [_U8, C.POINTER(Params), _U8]
+        L.orc_time_step.argtypes = ([C.c_void_p] + [_P] * 10 + [C.c_double, C.POINTER(Params),
+                                    C.POINTER(Info)])
         L.orc_info_size.restype = C.c_int
         L.orc_params_size.restype = C.c_int
         assert L.orc_info_size() == C.sizeof(Info)
@@ -366,6 +372,33 @@ class Problem:
                               float(dt), C.byref(self.params), mk.ctypes.data_as(_U8), _ptr(ts), _ptr(es),
                               _ptr(Ts), _ptr(zs))
         return ts.reshape(nc, nv), es.reshape(nc, nv), Ts.reshape(nc, nv, 3, 3), zs.reshape(nc, nv)
+
+    def detect(self, cand, state=None, mask=None):
+        """Detection (eqs. PAD and RDMP) of the candidate state ``cand``
+        against the relaxed-DMP bounds of ``state`` (default: the held
+        state): per cell 0 accepted, 1 not physically admissible, 2 outside
+        the relaxed DMP bounds (cells with mask >= 2 are accepted)."""
+        s = self.state if state is None else state
+        nc = self.mesh.nc
+        code = np.zeros(nc, np.uint8)
+        mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+        ins = [_f64(a) for a in (s.tau, cand.tau, cand.v, cand.e, cand.B)]
+        lib().orc_detect(self.mesh.h, _ptr(self.rho0), _ptr(self.mu), _ptr(self.K), *[_ptr(a) for a in ins],
+                         mk.ctypes.data_as(_U8) if mk is not None else None, C.byref(self.params),
+                         code.ctypes.data_as(_U8))
+        return code
+
+    def time_step(self, cand, dt_prev, V0=None):
+        """Time-step control (eqs. CFL, CFL2) of the end-of-step state
+        ``cand`` after a step of ``dt_prev`` from cell volumes ``V0`` (None:
+        the first step, acoustic bound only).  Returns the Info."""
+        info = Info()
+        ins = [_f64(a) for a in (cand.x, cand.tau, cand.v, cand.e, cand.B)]
+        v0 = None if V0 is None else _f64(V0)
+        lib().orc_time_step(self.mesh.h, _ptr(self.rho0), _ptr(self.mu), _ptr(self.K), *[_ptr(a) for a in ins],
+                            _ptr(self.m), _ptr(v0) if v0 is not None else None, float(dt_prev),
+                            C.byref(self.params), C.byref(info))
+        return info
 
     def diagnostics(self, state=None):
         s = self.state if state is None else state
