@@ -54,6 +54,7 @@ typedef enum {
     HL_WARN_PARACHUTE_INADMISSIBLE = 1, /* a first-order cell is not admissible */
     HL_E_INVALID = -1,                  /* bad argument                          */
     HL_E_DEGENERATE_CELL = -2,          /* a cell with V <= 0 at upload           */
+    HL_E_NONCONFORMING = -3,            /* the cells do not form a conforming mesh */
     HL_E_OOM = -4,                      /* device allocation failed              */
     HL_E_HIP = -5,                      /* a HIP runtime call failed             */
     HL_E_STATE = -6                     /* call order (no mesh / no state yet)   */
@@ -104,6 +105,20 @@ typedef struct {
     int64_t n_contact;   /* contact candidates held by the plane afterwards */
     int32_t trials;      /* step evaluations (> 1: a contact event redid it) */
     int32_t clipped;     /* 1: dt was cut to a contact impact time          */
+    int64_t n_recomputed;/* cell updates redone by the MOOD passes: per pass,
+                            the cells sharing a node with a newly flagged
+                            cell (Section 3.5: troubled cells go back with
+                            their neighbours)                              */
+    double gcl_defect;   /* involution monitor of the geometric
+                            conservation law (eq. GCL): max over cells of
+                            |V(x^{n+1}) - V(x^n) - dt sum_p Cbar_cp . v*_p|
+                            / V(x^n), Cbar_cp the Simpson average of the
+                            corner vectors over the step (zero up to
+                            roundoff for this scheme)                      */
+    double detB_defect;  /* max over cells of |sqrt(det B^{n+1}) - J^{n+1}|,
+                            J = rho0 tau (eq. test_detB_rho)               */
+    int64_t n_detB;      /* cells where that difference is >= L_c^3, L_c the
+                            in-sphere diameter at t^{n+1} (eq. test_detB_rho) */
 } hl_step_info;
 
 /* Fields for hl_query / hl_upload_field. */
@@ -145,17 +160,47 @@ hl_status hl_mesh_upload_batch(hl_ctx *ctx, int dim, int n_meshes, const int64_t
  *   dim           2 (triangles) or 3 (tetrahedra)
  *   x0            [n_nodes][dim] initial node positions
  *   cells         [n_cells][dim+1] node indices, every cell positively
- *                 oriented (V > 0), else HL_E_DEGENERATE_CELL
+ *                 oriented (V > 0), else HL_E_DEGENERATE_CELL; the cells
+ *                 must form a conforming mesh, else HL_E_NONCONFORMING
+ *                 (the checks of hl_mesh_check)
  *   nwall         [n_nodes] number of slip-wall constraints at the node
  *                 (0 = free, dim = node held fixed), or NULL for none
  *   normals       [n_nodes][dim][dim]: the first nwall[p] rows are the unit
  *                 wall normals of node p (Appendix B symmetry/wall BC), or
  *                 NULL when nwall is NULL
- * Builds the node->corner lists (cells ascending, then local node order).
- * Replaces any previous mesh and discards the state.  n_cells may be 0. */
+ * Builds the node->corner lists (cells ascending in the internal numbering,
+ * see hl_set_numbering, then local node order).  Replaces any previous mesh
+ * and discards the state.  n_cells may be 0. */
 hl_status hl_mesh_upload(hl_ctx *ctx, int dim, int64_t n_nodes, const double *x0,
                          int64_t n_cells, const int32_t *cells, const uint8_t *nwall,
                          const double *normals, int on_device);
+
+/* Internal numbering of the meshes uploaded from now on (Section 3.9,
+ * "Meshing and parallelization": the cells of a partition are numbered for
+ * locality).  HL_NUMBERING_SPATIAL (the default) renumbers, within each
+ * mesh, the cells along a Hilbert curve through their centroids (J.
+ * Skilling's transpose method, 21 bits per axis in 3D, 31 in 2D, one scale
+ * for all axes; ties in the caller's order) and the nodes in the order those
+ * cells first use them, so that the gathers of the step touch neighbouring
+ * memory whatever order the caller's mesh comes in.  HL_NUMBERING_KEEP
+ * keeps the caller's numbering.  Either way every array at this interface
+ * stays in the caller's numbering; only sums over a node's cells (taken in
+ * the internal cell order) change at the level of rounding. */
+enum { HL_NUMBERING_KEEP = 0, HL_NUMBERING_SPATIAL = 1 };
+hl_status hl_set_numbering(hl_ctx *ctx, int numbering);
+
+/* Check a simplicial mesh on the host, with no context and no GPU (host
+ * arrays; the same checks hl_mesh_upload runs, Section 3.1 "Mesh and
+ * notation": cells of positive measure that meet face to face):
+ *   HL_E_INVALID          node id out of range, non-finite position;
+ *   HL_E_DEGENERATE_CELL  a cell with V <= 0 (not positively oriented);
+ *   HL_E_NONCONFORMING    a face shared by more than two cells, two cells
+ *                         on the same side of a shared face, (3D) a boundary
+ *                         edge on an odd number of boundary faces, or a
+ *                         node lying on a boundary face (2D: edge) it is not
+ *                         a vertex of (a hanging node), within 1e-9 of the
+ *                         face's size. */
+hl_status hl_mesh_check(int dim, int64_t n_nodes, const double *x0, int64_t n_cells, const int32_t *cells);
 
 /* Conforming red refinement of the uploaded mesh, `levels` times (0..4),
  * computed on the GPU (edge numbering by a device radix sort).  This is the
@@ -190,6 +235,23 @@ hl_status hl_mesh_get(hl_ctx *ctx, double *x, int32_t *cells, uint8_t *nwall, do
 hl_status hl_state_init(hl_ctx *ctx, const double *rho0, const double *mu, const double *lam,
                         const double *v_cell, const double *v_node, const hl_params *p,
                         int on_device);
+
+/* Snapshot of the held state in host memory: positions, carried node
+ * velocities, cell state (tau, v, e, B), material, the next dt, the
+ * cascade levels of the last step, the contact states and the parameters.
+ * blob NULL: *bytes receives the size needed.  Otherwise *bytes is the
+ * blob's capacity: HL_E_INVALID (and *bytes set to the size needed) if it
+ * is too small.  The blob's layout is internal; it restores only into a
+ * context holding the same mesh. */
+hl_status hl_state_save(hl_ctx *ctx, void *blob, int64_t *bytes);
+
+/* Restore a snapshot of hl_state_save: the state, material, next dt,
+ * cascade levels, contact states and parameters come back, so the next
+ * steps repeat bitwise.  HL_E_INVALID if the blob is not a snapshot of the
+ * held mesh (size, counts, dimension, connectivity check word); the held
+ * state is then unchanged.  Captured graphs are kept when the parameters
+ * are the same, else dropped; a recorded adjoint tape is kept. */
+hl_status hl_state_restore(hl_ctx *ctx, const void *blob, int64_t bytes);
 
 /* Replace the parameters used by the following steps. */
 hl_status hl_set_params(hl_ctx *ctx, const hl_params *p);

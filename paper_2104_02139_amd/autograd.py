@@ -28,10 +28,16 @@ class LagrangianRun(torch.autograd.Function):
         x = torch.empty((w.n_nodes, w.dim), dtype=torch.float64, device=dev)
         hctx.query("x", out=x)
         actx.hctx = hctx
+        actx.generation = hctx.record_generation
         return x
 
     @staticmethod
     def backward(actx, grad_x):
+        # the context holds one recorded run: a later forward on the same
+        # context replaced the tape this backward would need
+        if actx.hctx.record_generation != actx.generation:
+            raise RuntimeError("the context recorded another forward run since this one; give each "
+                               "differentiated run its own context")
         gmu, gvc, gvn = actx.hctx.adjoint_run(grad_x.contiguous())
         return gmu, gvc, gvn, None, None, None, None
 

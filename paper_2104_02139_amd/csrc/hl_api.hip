@@ -16,6 +16,7 @@
 
 #include "hl_device.h"
 #include "hl_kernels.h"
+#include "hl_mesh.h"
 #include "hyperlag.h"
 
 namespace {
@@ -63,6 +64,16 @@ struct hl_ctx {
     std::vector<uint8_t> nw_host;
     std::vector<int64_t> cell_off_host, node_off_host;
     int32_t *cell_mesh = nullptr, *node_mesh = nullptr;
+    // Internal numbering: the host mesh arrays above and every device array
+    // use it; everything at the boundary uses the caller's.  x_i2u[i] is the
+    // caller's id of internal entity i, x_u2i the inverse (empty and null
+    // when the two numberings coincide).
+    int numbering = HL_NUMBERING_SPATIAL;  // for the next upload
+    bool permuted = false;
+    std::vector<int32_t> c_i2u, c_u2i, n_i2u, n_u2i;
+    int32_t *d_c_i2u = nullptr, *d_c_u2i = nullptr, *d_n_u2i = nullptr;
+    uint8_t *mask_in = nullptr;  // a replayed cascade choice, internal order
+    uint64_t mesh_hash = 0;      // identifies the held mesh in state snapshots
     // material
     double *mass = nullptr, *rho0 = nullptr, *mu = nullptr, *K = nullptr;
     // state, double buffered
@@ -133,6 +144,7 @@ struct hl_ctx {
     int64_t last_first = 0;
     int last_iters = 0;
     unsigned last_inadm = 0;
+    int64_t last_recomp = 0;
     // adjoint tapes (own allocations, freed with the mesh)
     struct {
         int nsteps = 0, every = 0, nckpt = 0;
@@ -142,6 +154,7 @@ struct hl_ctx {
         double *lam[2] = {nullptr, nullptr};
         double *cadj = nullptr, *nadj = nullptr, *cell = nullptr, *agg = nullptr, *xadj = nullptr;
         double *mu_bar = nullptr, *out = nullptr;
+        double *dtn = nullptr;  // dt_next after the last recorded step [n_mesh]
         std::vector<void *> mem;
     } tape;
 };
@@ -210,6 +223,7 @@ void free_tape(hl_ctx *c) {
     c->tape.masks = nullptr;
     c->tape.lam[0] = c->tape.lam[1] = nullptr;
     c->tape.cadj = c->tape.nadj = c->tape.cell = c->tape.agg = c->tape.xadj = c->tape.mu_bar = c->tape.out = nullptr;
+    c->tape.dtn = nullptr;
 }
 
 void free_loads(hl_ctx *c) {
@@ -251,6 +265,14 @@ void free_all(hl_ctx *c) {
     c->flist[0] = c->flist[1] = c->nlist = c->clist = c->nstamp = c->cstamp = nullptr;
     c->mesh_cell_off = nullptr;
     c->cell_mesh = c->node_mesh = nullptr;
+    c->permuted = false;
+    c->c_i2u.clear();
+    c->c_u2i.clear();
+    c->n_i2u.clear();
+    c->n_u2i.clear();
+    c->d_c_i2u = c->d_c_u2i = c->d_n_u2i = nullptr;
+    c->mask_in = nullptr;
+    c->mesh_hash = 0;
     c->dt_part = nullptr;
     c->stamp_dev = nullptr;
     c->pass_log = nullptr;
@@ -725,6 +747,7 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
         c->last_first = 0;
         c->last_iters = 1;
         c->last_inadm = 0;
+        c->last_recomp = 0;
         c->cur = 1 - src;
         return HL_OK;
     } else {
@@ -750,6 +773,7 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
     c->last_first = first;
     c->last_iters = iters;
     c->last_inadm = inadm;
+    c->last_recomp = c->counters_host[hl::CNT_RECOMP];
     c->cur = 1 - src;
     if (info) {
         hl_status st = fill_info<D>(c, src, info);
@@ -766,9 +790,8 @@ hl_status fill_info(hl_ctx *c, int src, hl_step_info *info) {
     hl::StepArgs a = make_args(c, src);
     {
         std::memset(info, 0, sizeof(*info));
-        const int dst = 1 - src;
-        hl::launch_diag<D>(a, c->tau[dst], c->v[dst], c->e[dst], c->B[dst], c->diag_part, c->diag_out, s);
-        double d[9], dts[4];
+        hl::launch_diag<D>(a, c->diag_part, c->diag_out, s);
+        double d[hl::DIAG_N], dts[4];
         HIPCHK(hipMemcpyAsync(d, c->diag_out, sizeof d, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(&dts[0], c->dt_cur, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(&dts[1], c->dt_next, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -787,6 +810,10 @@ hl_status fill_info(hl_ctx *c, int src, hl_step_info *info) {
         info->elastic = d[6];
         info->n_p0 = (int64_t)llround(d[7]);
         info->n_limited = (int64_t)llround(d[8]);
+        info->gcl_defect = d[9];
+        info->detB_defect = d[10];
+        info->n_detB = (int64_t)llround(d[11]);
+        info->n_recomputed = c->last_recomp;
         info->n_flag_first = c->last_first;
         info->mood_iters = c->last_iters;
         info->status = c->last_inadm ? 1 : 0;
@@ -1020,6 +1047,7 @@ hl_status forward_record(hl_ctx *c, int nsteps, int every) {
     if ((st = talloc(c, &t.xadj, ncor * 3)) != HL_OK) return st;
     if ((st = talloc(c, &t.mu_bar, nc)) != HL_OK) return st;
     if ((st = talloc(c, &t.out, std::max(nn, nc) * 3)) != HL_OK) return st;
+    if ((st = talloc(c, &t.dtn, (size_t)c->n_mesh)) != HL_OK) return st;
     for (int n = 0; n < nsteps; ++n) {
         if (n % every == 0) {
             if ((st = copy_state(c, c->cur, t.ckpt + (size_t)(n / every) * t.state_sz, true)) != HL_OK) return st;
@@ -1031,6 +1059,7 @@ hl_status forward_record(hl_ctx *c, int nsteps, int every) {
                               hipMemcpyDeviceToDevice, c->stream));
     }
     if ((st = copy_state(c, c->cur, t.ckpt + (size_t)(t.nckpt - 1) * t.state_sz, true)) != HL_OK) return st;
+    HIPCHK(hipMemcpyAsync(t.dtn, c->dt_next, sizeof(double) * c->n_mesh, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return HL_OK;
 }
@@ -1061,7 +1090,7 @@ hl_status adjoint_run(hl_ctx *c, const double *dLdx, double *dLdmu, double *dLdv
     HIPCHK(hipMemsetAsync(t.mu_bar, 0, sizeof(double) * nc, s));
     if (nn) {
         HIPCHK(hipMemcpyAsync(t.out, dLdx, sizeof(double) * nn * D, kin, s));
-        hl::launch_aos_to_soa(nn, D, t.out, t.lam[0], s);
+        hl::launch_aos_to_soa(nn, D, t.out, t.lam[0], s, c->permuted ? c->d_n_u2i : nullptr);
     }
     int in = 0;
     const int nseg = (t.nsteps + t.every - 1) / t.every;
@@ -1085,19 +1114,34 @@ hl_status adjoint_run(hl_ctx *c, const double *dLdx, double *dLdmu, double *dLdv
     }
     // lambda at t = 0 -> gradients of the inputs
     const double *lam = t.lam[in];
+    const int32_t *cidx = c->permuted ? c->d_c_u2i : nullptr, *nidx = c->permuted ? c->d_n_u2i : nullptr;
     if (nc) {
-        HIPCHK(hipMemcpyAsync(dLdmu, t.mu_bar, sizeof(double) * nc, kout, s));
-        hl::launch_soa_to_aos(nc, D, lam + 2 * D * nn + nc, t.out, s);
+        if (cidx) {
+            hl::launch_soa_to_aos(nc, 1, t.mu_bar, t.out, s, cidx);
+            HIPCHK(hipMemcpyAsync(dLdmu, t.out, sizeof(double) * nc, kout, s));
+        } else {
+            HIPCHK(hipMemcpyAsync(dLdmu, t.mu_bar, sizeof(double) * nc, kout, s));
+        }
+        hl::launch_soa_to_aos(nc, D, lam + 2 * D * nn + nc, t.out, s, cidx);
         HIPCHK(hipMemcpyAsync(dLdvc, t.out, sizeof(double) * nc * D, kout, s));
     }
     if (nn) {
         hl::launch_adj_project<D>(nn, c->nallow, c->allow, lam + D * nn, t.out, s);
-        HIPCHK(hipMemcpyAsync(dLdvn, t.out, sizeof(double) * nn * D, kout, s));
+        if (nidx) {
+            hl::launch_gather_rows(nn, D, t.out, nidx, c->scratch, s);
+            HIPCHK(hipMemcpyAsync(dLdvn, c->scratch, sizeof(double) * nn * D, kout, s));
+        } else {
+            HIPCHK(hipMemcpyAsync(dLdvn, t.out, sizeof(double) * nn * D, kout, s));
+        }
     }
-    // leave the context at the final forward state
+    // leave the context at the final forward state, with the next dt and
+    // the cascade levels of the last recorded step
     c->cur = 0;
     hl_status st = copy_state(c, 0, t.ckpt + (size_t)(t.nckpt - 1) * t.state_sz, false);
     if (st != HL_OK) return st;
+    HIPCHK(hipMemcpyAsync(c->dt_next, t.dtn, sizeof(double) * c->n_mesh, hipMemcpyDeviceToDevice, s));
+    if (nc)
+        HIPCHK(hipMemcpyAsync(c->mask, t.masks + (size_t)(t.nsteps - 1) * nc, nc, hipMemcpyDeviceToDevice, s));
     c->rec_valid = false;
     HIPCHK(hipStreamSynchronize(s));
     hipError_t le = hipGetLastError();
@@ -1250,6 +1294,7 @@ const char *hl_status_str(hl_status s) {
         case HL_E_OOM: return "device allocation failed";
         case HL_E_HIP: return "HIP runtime error";
         case HL_E_STATE: return "call out of order (mesh or state missing)";
+        case HL_E_NONCONFORMING: return "the cells do not form a conforming mesh";
         default: return "unknown status";
     }
 }
@@ -1310,11 +1355,38 @@ hl_status gather_mesh(int dim, int64_t n_nodes, const double *x0, int64_t n_cell
     return HL_OK;
 }
 
+// The held mesh in the caller's numbering.
+void user_mesh(const hl_ctx *c, HostMesh &h) {
+    if (!c->permuted) {
+        h.x = c->x0_host;
+        h.cells = c->c2n_host;
+        h.nw = c->nw_host;
+        h.nrm = c->nrm_host;
+        return;
+    }
+    const int d = c->dim, nv = d + 1, dd = d * d;
+    const size_t nn = (size_t)c->nn, nc = (size_t)c->nc;
+    h.x.resize(nn * d);
+    h.nrm.resize(nn * dd);
+    h.nw.resize(nn);
+    h.cells.resize(nc * nv);
+    for (size_t u = 0; u < nn; ++u) {
+        const size_t i = (size_t)c->n_u2i[u];
+        for (int j = 0; j < d; ++j) h.x[u * d + j] = c->x0_host[i * d + j];
+        for (int j = 0; j < dd; ++j) h.nrm[u * dd + j] = c->nrm_host[i * dd + j];
+        h.nw[u] = c->nw_host[i];
+    }
+    for (size_t u = 0; u < nc; ++u) {
+        const size_t i = (size_t)c->c_u2i[u];
+        for (int k = 0; k < nv; ++k) h.cells[u * nv + k] = c->n_i2u[(size_t)c->c2n_host[i * nv + k]];
+    }
+}
+
 // Validate, build the node -> corner lists and wall bases, allocate the
 // device buffers and upload.  node_off / cell_off delimit the meshes of a
 // batch (n_mesh >= 1); cells already use global node numbers.
 hl_status upload_impl(hl_ctx *c, int dim, int n_mesh, const std::vector<int64_t> &node_off,
-                      const std::vector<int64_t> &cell_off, HostMesh &h) {
+                      const std::vector<int64_t> &cell_off, HostMesh &h, bool check_conformity) {
     const int nv = dim + 1;
     const int64_t n_nodes = node_off[n_mesh], n_cells = cell_off[n_mesh];
     std::vector<double> &xh = h.x, &nrm = h.nrm;
@@ -1334,6 +1406,45 @@ hl_status upload_impl(hl_ctx *c, int dim, int n_mesh, const std::vector<int64_t>
         for (int k = 0; k < nv; ++k)
             for (int i = 0; i < dim; ++i) X[k * dim + i] = xh[(size_t)ch[cc * nv + k] * dim + i];
         if (!(host_volume(dim, X) > 0.0)) return HL_E_DEGENERATE_CELL;
+    }
+    if (check_conformity)
+        for (int m = 0; m < n_mesh; ++m)
+            if ((st = hl::check_conforming(dim, xh.data(), ch.data(), node_off[m], node_off[m + 1], cell_off[m],
+                                           cell_off[m + 1])) != HL_OK)
+                return st;
+    // internal numbering: cells along a Hilbert curve, nodes by first use
+    std::vector<int32_t> ci2u, ni2u, cu2i, nu2i;
+    bool perm = c->numbering == HL_NUMBERING_SPATIAL && n_cells > 0;
+    if (perm) {
+        hl::spatial_numbering(dim, xh.data(), ch.data(), node_off, cell_off, ci2u, ni2u);
+        bool ident = true;
+        for (int64_t i = 0; i < n_cells && ident; ++i) ident = ci2u[i] == i;
+        for (int64_t i = 0; i < n_nodes && ident; ++i) ident = ni2u[i] == i;
+        perm = !ident;
+    }
+    if (perm) {
+        cu2i.resize((size_t)n_cells);
+        nu2i.resize((size_t)n_nodes);
+        for (int64_t i = 0; i < n_cells; ++i) cu2i[ci2u[i]] = (int32_t)i;
+        for (int64_t i = 0; i < n_nodes; ++i) nu2i[ni2u[i]] = (int32_t)i;
+        std::vector<double> x2((size_t)(n_nodes * dim)), n2((size_t)(n_nodes * dim * dim));
+        std::vector<uint8_t> w2((size_t)n_nodes);
+        std::vector<int32_t> c2((size_t)(n_cells * nv));
+        for (int64_t i = 0; i < n_nodes; ++i) {
+            const int64_t u = ni2u[i];
+            for (int j = 0; j < dim; ++j) x2[i * dim + j] = xh[u * dim + j];
+            for (int j = 0; j < dim * dim; ++j) n2[i * dim * dim + j] = nrm[u * dim * dim + j];
+            w2[i] = nw[u];
+        }
+        for (int64_t i = 0; i < n_cells; ++i)
+            for (int k = 0; k < nv; ++k) c2[i * nv + k] = nu2i[ch[(size_t)ci2u[i] * nv + k]];
+        xh.swap(x2);
+        nrm.swap(n2);
+        nw.swap(w2);
+        ch.swap(c2);
+    } else {
+        ci2u.clear();
+        ni2u.clear();
     }
     // node -> corner lists in (cell, local node) order
     std::vector<int32_t> off((size_t)n_nodes + 1, 0), lst((size_t)(n_cells * nv));
@@ -1408,10 +1519,16 @@ hl_status upload_impl(hl_ctx *c, int dim, int n_mesh, const std::vector<int64_t>
     A_(c->dt_next, (size_t)n_mesh);
     A_(c->dt_red, 2 * (size_t)n_mesh);
     A_(c->dt_parts, 2 * (size_t)n_mesh);
-    A_(c->diag_part, 9 * (ncl / 256 + 2));
+    A_(c->diag_part, hl::DIAG_N * (ncl / 256 + 2));
     A_(c->diag_out, 16);
     c->scratch_bytes = std::max<size_t>(sizeof(double) * std::max(nn * dim, ncl * 6), 256);
     A_(c->scratch, c->scratch_bytes / sizeof(double));
+    A_(c->mask_in, ncl);
+    if (perm) {
+        A_(c->d_c_i2u, ncl);
+        A_(c->d_c_u2i, ncl);
+        A_(c->d_n_u2i, nn);
+    }
 #undef A_
     if (hipHostMalloc((void **)&c->counters_host, hl::CNT_N * sizeof(unsigned), hipHostMallocDefault) != hipSuccess) {
         free_all(c);
@@ -1433,6 +1550,11 @@ hl_status upload_impl(hl_ctx *c, int dim, int n_mesh, const std::vector<int64_t>
     if (ncl) HIPCHK(hipMemsetAsync(c->pstat, 0, ncl, s));
     HIPCHK(hipMemcpyAsync(c->mesh_cell_off, cell_off.data(), sizeof(int64_t) * (n_mesh + 1), hipMemcpyHostToDevice,
                           s));
+    if (perm) {
+        HIPCHK(hipMemcpyAsync(c->d_c_i2u, ci2u.data(), sizeof(int32_t) * ncl, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(c->d_c_u2i, cu2i.data(), sizeof(int32_t) * ncl, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(c->d_n_u2i, nu2i.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, s));
+    }
     std::vector<int32_t> cm, nm;
     if (n_mesh > 1) {
         cm.resize(ncl);
@@ -1456,6 +1578,27 @@ hl_status upload_impl(hl_ctx *c, int dim, int n_mesh, const std::vector<int64_t>
     c->c2n_host.swap(ch);
     c->nw_host.swap(nw);
     c->nrm_host.swap(nrm);
+    c->permuted = perm;
+    c->c_i2u.swap(ci2u);
+    c->c_u2i.swap(cu2i);
+    c->n_i2u.swap(ni2u);
+    c->n_u2i.swap(nu2i);
+    {
+        // FNV-1a over the sizes and the internal connectivity
+        uint64_t hsh = 1469598103934665603ull;
+        auto mix = [&](uint64_t v) {
+            for (int b = 0; b < 8; ++b) {
+                hsh ^= (v >> (8 * b)) & 0xffu;
+                hsh *= 1099511628211ull;
+            }
+        };
+        mix((uint64_t)dim);
+        mix((uint64_t)n_nodes);
+        mix((uint64_t)n_cells);
+        mix((uint64_t)n_mesh);
+        for (int32_t q : c->c2n_host) mix((uint64_t)(uint32_t)q);
+        c->mesh_hash = hsh;
+    }
     c->cur = 0;
     c->prm = default_params(dim);
     c->have_mesh = true;
@@ -1476,7 +1619,7 @@ hl_status hl_mesh_upload(hl_ctx *c, int dim, int64_t n_nodes, const double *x0, 
     hl_status st = gather_mesh(dim, n_nodes, x0, n_cells, cells, nwall, normals, on_device, h);
     if (st != HL_OK) return st;
     std::vector<int64_t> no = {0, n_nodes}, co = {0, n_cells};
-    return upload_impl(c, dim, 1, no, co, h);
+    return upload_impl(c, dim, 1, no, co, h, true);
 }
 
 hl_status hl_mesh_upload_batch(hl_ctx *c, int dim, int n_meshes, const int64_t *node_offsets,
@@ -1501,7 +1644,7 @@ hl_status hl_mesh_upload_batch(hl_ctx *c, int dim, int n_meshes, const int64_t *
             if (h.cells[q] < 0 || g >= no[m + 1]) return HL_E_INVALID;
             h.cells[q] = (int32_t)g;
         }
-    return upload_impl(c, dim, n_meshes, no, co, h);
+    return upload_impl(c, dim, n_meshes, no, co, h, true);
 }
 
 hl_status hl_mesh_refine(hl_ctx *c, int levels) {
@@ -1520,10 +1663,7 @@ hl_status hl_mesh_refine(hl_ctx *c, int levels) {
         }
     }
     HostMesh h;
-    h.x = c->x0_host;
-    h.cells = c->c2n_host;
-    h.nw = c->nw_host;
-    h.nrm = c->nrm_host;
+    user_mesh(c, h);
     for (int l = 0; l < levels; ++l) {
         const int64_t nn = (int64_t)h.nw.size(), nc = (int64_t)h.cells.size() / nv;
         std::vector<double> xo;
@@ -1564,7 +1704,32 @@ hl_status hl_mesh_refine(hl_ctx *c, int levels) {
     }
     const int64_t nn = (int64_t)h.nw.size(), nc = (int64_t)h.cells.size() / nv;
     std::vector<int64_t> no = {0, nn}, cof = {0, nc};
-    return upload_impl(c, d, 1, no, cof, h);
+    // red refinement of a conforming mesh is conforming: no second check
+    return upload_impl(c, d, 1, no, cof, h, false);
+}
+
+hl_status hl_set_numbering(hl_ctx *c, int numbering) {
+    if (!c || (numbering != HL_NUMBERING_KEEP && numbering != HL_NUMBERING_SPATIAL)) return HL_E_INVALID;
+    c->numbering = numbering;
+    return HL_OK;
+}
+
+hl_status hl_mesh_check(int dim, int64_t n_nodes, const double *x0, int64_t n_cells, const int32_t *cells) {
+    if ((dim != 2 && dim != 3) || n_nodes < 0 || n_cells < 0) return HL_E_INVALID;
+    if ((n_nodes > 0 && !x0) || (n_cells > 0 && !cells)) return HL_E_INVALID;
+    if (n_cells * (dim + 1) >= (int64_t)INT32_MAX || n_nodes >= (int64_t)INT32_MAX) return HL_E_INVALID;
+    const int nv = dim + 1;
+    for (int64_t q = 0; q < n_cells * nv; ++q)
+        if (cells[q] < 0 || cells[q] >= n_nodes) return HL_E_INVALID;
+    for (int64_t i = 0; i < n_nodes * dim; ++i)
+        if (!std::isfinite(x0[i])) return HL_E_INVALID;
+    for (int64_t cc = 0; cc < n_cells; ++cc) {
+        double X[12];
+        for (int k = 0; k < nv; ++k)
+            for (int i = 0; i < dim; ++i) X[k * dim + i] = x0[(size_t)cells[cc * nv + k] * dim + i];
+        if (!(host_volume(dim, X) > 0.0)) return HL_E_DEGENERATE_CELL;
+    }
+    return hl::check_conforming(dim, x0, cells, 0, n_nodes, 0, n_cells);
 }
 
 hl_status hl_mesh_info(hl_ctx *c, int *dim, int64_t *n_nodes, int64_t *n_cells) {
@@ -1591,10 +1756,12 @@ hl_status hl_mesh_get(hl_ctx *c, double *x, int32_t *cells, uint8_t *nwall, doub
         return HL_OK;
     };
     hl_status st;
-    if ((st = put(x, c->x0_host.data(), sizeof(double) * c->x0_host.size())) != HL_OK) return st;
-    if ((st = put(cells, c->c2n_host.data(), sizeof(int32_t) * c->c2n_host.size())) != HL_OK) return st;
-    if ((st = put(nwall, c->nw_host.data(), c->nw_host.size())) != HL_OK) return st;
-    return put(normals, c->nrm_host.data(), sizeof(double) * c->nrm_host.size());
+    HostMesh h;
+    user_mesh(c, h);
+    if ((st = put(x, h.x.data(), sizeof(double) * h.x.size())) != HL_OK) return st;
+    if ((st = put(cells, h.cells.data(), sizeof(int32_t) * h.cells.size())) != HL_OK) return st;
+    if ((st = put(nwall, h.nw.data(), h.nw.size())) != HL_OK) return st;
+    return put(normals, h.nrm.data(), sizeof(double) * h.nrm.size());
 }
 
 hl_status hl_set_params(hl_ctx *c, const hl_params *p) {
@@ -1631,6 +1798,8 @@ hl_status hl_set_boundary_loads(hl_ctx *c, int64_t n, const int32_t *cell, const
         for (int q = 0; q < 6; ++q)
             if (!std::isfinite(hv[6 * l + q])) return HL_E_INVALID;
     }
+    if (c->permuted)
+        for (int64_t l = 0; l < n; ++l) hc[l] = c->c_u2i[hc[l]];  // the local face index is kept
     // entries grouped by node, each node's in the order of l
     const int64_t nn = c->nn;
     std::vector<int32_t> off(nn + 1, 0);
@@ -1698,6 +1867,8 @@ hl_status hl_set_contact(hl_ctx *c, int64_t n, const int32_t *nodes, const doubl
             if (nd[i] < 0 || nd[i] >= nn || seen[nd[i]]) return HL_E_INVALID;
             seen[nd[i]] = 1;
         }
+        if (c->permuted)
+            for (int64_t i = 0; i < n; ++i) nd[i] = c->n_u2i[nd[i]];
         double l = 0.0;
         for (int i = 0; i < d; ++i) {
             xT[i] = point[i];
@@ -1832,6 +2003,20 @@ hl_status hl_state_init(hl_ctx *c, const double *rho0, const double *mu, const d
     if ((st = to_host(v_node, nn * d, on_device, vn)) != HL_OK) return st;
     for (size_t i = 0; i < nc; ++i)
         if (!(r[i] > 0) || !(m_[i] >= 0) || !std::isfinite(l[i])) return HL_E_INVALID;
+    if (c->permuted) {
+        // the caller's numbering -> the internal one
+        auto perm_rows = [](std::vector<double> &a, const std::vector<int32_t> &i2u, int w) {
+            std::vector<double> o(a.size());
+            for (size_t i = 0; i < i2u.size(); ++i)
+                for (int k = 0; k < w; ++k) o[i * w + k] = a[(size_t)i2u[i] * w + k];
+            a.swap(o);
+        };
+        perm_rows(r, c->c_i2u, 1);
+        perm_rows(m_, c->c_i2u, 1);
+        perm_rows(l, c->c_i2u, 1);
+        perm_rows(vc, c->c_i2u, d);
+        perm_rows(vn, c->n_i2u, d);
+    }
     hl_params prm = p ? *p : default_params(d);
     if (!params_valid(prm)) return HL_E_INVALID;
 
@@ -1897,6 +2082,133 @@ hl_status hl_state_init(hl_ctx *c, const double *rho0, const double *mu, const d
     return hl_compute_dt(c, &dt0);
 }
 
+}  // extern "C"
+
+namespace {
+
+// State snapshot: this header, then the state (x, vhat [D][nn]; tau [nc];
+// v [D][nc]; e [nc]; B [nB][nc]), the material (mass, rho0, mu, K [nc]),
+// dt_cur and dt_next [n_mesh] as doubles in the internal numbering, the
+// cascade levels [nc] and the contact states [n_contact] as bytes.
+struct SnapHeader {
+    uint64_t magic;
+    uint64_t mesh_hash;
+    int32_t dim, n_mesh;
+    int64_t nn, nc, n_contact, bytes;
+    hl_params prm;
+};
+constexpr uint64_t kSnapMagic = 0x3170616e53676c48ull;
+
+size_t snap_doubles(const hl_ctx *c) {
+    const size_t d = c->dim, nn = c->nn, nc = c->nc, nB = d == 3 ? 6 : 3;
+    return 2 * d * nn + (2 + d + nB) * nc + 4 * nc + 2 * (size_t)c->n_mesh;
+}
+
+size_t snap_bytes(const hl_ctx *c) {
+    return sizeof(SnapHeader) + sizeof(double) * snap_doubles(c) + (size_t)c->nc + (size_t)c->ct.n;
+}
+
+// device arrays of a snapshot in blob order, with their lengths in doubles
+int snap_parts(hl_ctx *c, double **ptr, size_t *len) {
+    const size_t d = c->dim, nn = c->nn, nc = c->nc, nB = d == 3 ? 6 : 3;
+    const int b = c->cur;
+    double *p[12] = {c->x[b], c->vhat[b], c->tau[b], c->v[b], c->e[b], c->B[b],
+                     c->mass, c->rho0, c->mu, c->K, c->dt_cur, c->dt_next};
+    const size_t l[12] = {d * nn, d * nn, nc, d * nc, nc, nB * nc, nc, nc, nc, nc, (size_t)c->n_mesh,
+                          (size_t)c->n_mesh};
+    for (int k = 0; k < 12; ++k) {
+        ptr[k] = p[k];
+        len[k] = l[k];
+    }
+    return 12;
+}
+
+}  // namespace
+
+extern "C" {
+
+hl_status hl_state_save(hl_ctx *c, void *blob, int64_t *bytes) {
+    if (!c || !bytes) return HL_E_INVALID;
+    if (!c->have_state) return HL_E_STATE;
+    const int64_t need = (int64_t)snap_bytes(c);
+    if (!blob) {
+        *bytes = need;
+        return HL_OK;
+    }
+    if (*bytes < need) {
+        *bytes = need;
+        return HL_E_INVALID;
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    hipStream_t s = c->stream;
+    SnapHeader h{};
+    h.magic = kSnapMagic;
+    h.mesh_hash = c->mesh_hash;
+    h.dim = c->dim;
+    h.n_mesh = c->n_mesh;
+    h.nn = c->nn;
+    h.nc = c->nc;
+    h.n_contact = c->ct.n;
+    h.bytes = need;
+    h.prm = c->prm;
+    char *o = static_cast<char *>(blob);
+    std::memcpy(o, &h, sizeof h);
+    o += sizeof h;
+    double *ptr[12];
+    size_t len[12];
+    const int np = snap_parts(c, ptr, len);
+    for (int k = 0; k < np; ++k) {
+        if (len[k]) HIPCHK(hipMemcpyAsync(o, ptr[k], sizeof(double) * len[k], hipMemcpyDeviceToHost, s));
+        o += sizeof(double) * len[k];
+    }
+    if (c->nc) HIPCHK(hipMemcpyAsync(o, c->mask, (size_t)c->nc, hipMemcpyDeviceToHost, s));
+    o += c->nc;
+    HIPCHK(hipStreamSynchronize(s));
+    if (c->ct.n) std::memcpy(o, c->ct.state_h.data(), (size_t)c->ct.n);
+    *bytes = need;
+    return HL_OK;
+}
+
+hl_status hl_state_restore(hl_ctx *c, const void *blob, int64_t bytes) {
+    if (!c || !blob) return HL_E_INVALID;
+    if (!c->have_mesh) return HL_E_STATE;
+    if (bytes < (int64_t)sizeof(SnapHeader)) return HL_E_INVALID;
+    SnapHeader h;
+    std::memcpy(&h, blob, sizeof h);
+    if (h.magic != kSnapMagic || h.mesh_hash != c->mesh_hash || h.dim != c->dim || h.n_mesh != c->n_mesh ||
+        h.nn != c->nn || h.nc != c->nc || h.n_contact != c->ct.n || h.bytes != bytes ||
+        bytes != (int64_t)snap_bytes(c) || !params_valid(h.prm)) {
+        std::snprintf(g_last_error, sizeof g_last_error, "the snapshot does not belong to the held mesh");
+        return HL_E_INVALID;
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    hipStream_t s = c->stream;
+    c->cur = 0;
+    const char *o = static_cast<const char *>(blob) + sizeof h;
+    double *ptr[12];
+    size_t len[12];
+    const int np = snap_parts(c, ptr, len);
+    for (int k = 0; k < np; ++k) {
+        if (len[k]) HIPCHK(hipMemcpyAsync(ptr[k], o, sizeof(double) * len[k], hipMemcpyHostToDevice, s));
+        o += sizeof(double) * len[k];
+    }
+    if (c->nc) HIPCHK(hipMemcpyAsync(c->mask, o, (size_t)c->nc, hipMemcpyHostToDevice, s));
+    o += c->nc;
+    HIPCHK(hipStreamSynchronize(s));
+    if (c->ct.n) {
+        std::memcpy(c->ct.state_h.data(), o, (size_t)c->ct.n);
+        hl_status st = contact_apply(c);
+        if (st != HL_OK) return st;
+    }
+    // captured steps stay valid unless the parameters change (they hold
+    // them by value; the state goes to buffer 0, which has its own graph)
+    if (std::memcmp(&c->prm, &h.prm, sizeof(hl_params)) != 0) drop_graphs(c);
+    c->prm = h.prm;
+    c->have_state = true;
+    c->rec_valid = false;
+    return HL_OK;
+}
+
 hl_status hl_compute_dt(hl_ctx *c, double *dt_out) {
     if (!c) return HL_E_INVALID;
     if (!c->have_state) return HL_E_STATE;
@@ -1923,6 +2235,15 @@ static hl_status step_common(hl_ctx *c, double dt, const uint8_t *mask, int on_d
     if (!c->have_state) return HL_E_STATE;
     if (!std::isfinite(dt)) return HL_E_INVALID;
     if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
+    if (mask && c->permuted && c->nc) {
+        // the caller's cascade choice, gathered into the internal order
+        uint8_t *tmp = reinterpret_cast<uint8_t *>(c->scratch);
+        HIPCHK(hipMemcpyAsync(tmp, mask, (size_t)c->nc, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              c->stream));
+        hl::launch_gather_u8(c->nc, tmp, c->d_c_i2u, c->mask_in, c->stream);
+        mask = c->mask_in;
+        on_device = 1;
+    }
     hl_status st;
     if (c->ct.n > 0 && !mask && c->nc > 0)
         st = c->dim == 3 ? contact_step<3>(c, dt, info) : contact_step<2>(c, dt, info);
@@ -1979,21 +2300,28 @@ hl_status hl_query(hl_ctx *c, int field, void *out, int64_t count, int on_device
     hipStream_t s = c->stream;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (n == 0) return HL_OK;
+    // row i of the output is internal entity idx[i] (null: i)
+    const int32_t *idx = c->permuted ? (node ? c->d_n_u2i : c->d_c_u2i) : nullptr;
     if (u8) {
-        HIPCHK(hipMemcpyAsync(out, c->mask, (size_t)n, k, s));
+        if (idx) {
+            hl::launch_gather_u8(n, c->mask, idx, reinterpret_cast<uint8_t *>(c->scratch), s);
+            HIPCHK(hipMemcpyAsync(out, c->scratch, (size_t)n, k, s));
+        } else {
+            HIPCHK(hipMemcpyAsync(out, c->mask, (size_t)n, k, s));
+        }
     } else if (field == HL_T) {
         hl::StepArgs a = make_args(c, c->cur);
         if (c->dim == 3)
-            hl::launch_stress_query<3>(a, c->scratch, s);
+            hl::launch_stress_query<3>(a, idx, c->scratch, s);
         else
-            hl::launch_stress_query<2>(a, c->scratch, s);
+            hl::launch_stress_query<2>(a, idx, c->scratch, s);
         HIPCHK(hipMemcpyAsync(out, c->scratch, sizeof(double) * n * w, k, s));
     } else {
         double *src = field_ptr(c, field);
-        if (w == 1) {
+        if (w == 1 && !idx) {
             HIPCHK(hipMemcpyAsync(out, src, sizeof(double) * n, k, s));
         } else {
-            hl::launch_soa_to_aos(n, w, src, c->scratch, s);
+            hl::launch_soa_to_aos(n, w, src, c->scratch, s, idx);
             HIPCHK(hipMemcpyAsync(out, c->scratch, sizeof(double) * n * w, k, s));
         }
     }
@@ -2016,11 +2344,12 @@ hl_status hl_upload_field(hl_ctx *c, int field, const void *in, int64_t count, i
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     double *dst = field_ptr(c, field);
     c->rec_valid = false;
-    if (w == 1) {
+    const int32_t *idx = c->permuted ? (node ? c->d_n_u2i : c->d_c_u2i) : nullptr;
+    if (w == 1 && !idx) {
         HIPCHK(hipMemcpyAsync(dst, in, sizeof(double) * n, k, s));
     } else {
         HIPCHK(hipMemcpyAsync(c->scratch, in, sizeof(double) * n * w, k, s));
-        hl::launch_aos_to_soa(n, w, c->scratch, dst, s);
+        hl::launch_aos_to_soa(n, w, c->scratch, dst, s, idx);
     }
     HIPCHK(hipStreamSynchronize(s));
     return HL_OK;
@@ -2065,8 +2394,15 @@ hl_status hl_adjoint_run(hl_ctx *c, const double *dL_dx_final, double *dL_dmu, d
 hl_status hl_tape_get(hl_ctx *c, int step, uint8_t *mask, double *dt) {
     if (!c || step < 0 || step >= c->tape.nsteps) return HL_E_INVALID;
     if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
-    if (mask && c->nc)
-        HIPCHK(hipMemcpy(mask, c->tape.masks + (size_t)step * c->nc, (size_t)c->nc, hipMemcpyDeviceToHost));
+    if (mask && c->nc) {
+        if (c->permuted) {
+            std::vector<uint8_t> tmp((size_t)c->nc);
+            HIPCHK(hipMemcpy(tmp.data(), c->tape.masks + (size_t)step * c->nc, (size_t)c->nc, hipMemcpyDeviceToHost));
+            for (int64_t u = 0; u < c->nc; ++u) mask[u] = tmp[(size_t)c->c_u2i[u]];
+        } else {
+            HIPCHK(hipMemcpy(mask, c->tape.masks + (size_t)step * c->nc, (size_t)c->nc, hipMemcpyDeviceToHost));
+        }
+    }
     if (dt)
         HIPCHK(hipMemcpy(dt, c->tape.dts + (size_t)step * c->n_mesh, sizeof(double) * c->n_mesh,
                          hipMemcpyDeviceToHost));

@@ -56,7 +56,10 @@ struct StepArgs {
     const double *ld_val;
 };
 
-enum { CNT_F0 = 0, CNT_F1 = 1, CNT_NODES = 2, CNT_CELLS = 3, CNT_BAD = 4, CNT_N = 8 };
+// device counters of a step: flag counts of the two flag lists, nodes and
+// cells listed by the current MOOD pass, inadmissible first-order cells,
+// cell updates redone by the MOOD passes of the step
+enum { CNT_F0 = 0, CNT_F1 = 1, CNT_NODES = 2, CNT_CELLS = 3, CNT_BAD = 4, CNT_RECOMP = 5, CNT_N = 8 };
 
 // Corner records are stored corner-major within tiles of 256 cells: the
 // record of corner k of cell c is number ((c / 256) (D + 1) + k) 256 +
@@ -172,10 +175,16 @@ template <int D> void launch_predict(const StepArgs &a, const Sched &k, hipStrea
 template <int D> void launch_node_solve(const StepArgs &a, const Sched &k, hipStream_t s);
 template <int D> void launch_update(const StepArgs &a, const Sched &k, hipStream_t s);
 template <int D> void launch_acoustic(const StepArgs &a, hipStream_t s);
+// Diagnostics of the step just taken (a: the step's arguments, state n ->
+// candidate n+1): out[0..8] = mass, mom[3], sum m e, kinetic, elastic,
+// first-order and limited cell counts; out[9] = max relative GCL defect,
+// out[10] = max |sqrt(det B) - J|, out[11] = cells with that >= L_c^3.
+// part: [blocks][DIAG_N] partials.
+constexpr int DIAG_N = 12;
 template <int D>
-int64_t launch_diag(const StepArgs &a, const double *tau, const double *v, const double *e, const double *B,
-                    double *part, double *out, hipStream_t s);
-template <int D> void launch_stress_query(const StepArgs &a, double *out, hipStream_t s);
+int64_t launch_diag(const StepArgs &a, double *part, double *out, hipStream_t s);
+// stress query, AoS rows in the order idx (row i = cell idx[i]; null: i)
+template <int D> void launch_stress_query(const StepArgs &a, const int32_t *idx, double *out, hipStream_t s);
 // One sparse MOOD pass: flagged list `fb` in, newly flagged list written to
 // a.flist_out.  fixed_grid: launch shapes independent of the flag count
 // (for graph capture); kernels then read every count from device memory.
@@ -192,7 +201,12 @@ void launch_dt_reduce(int64_t nc, const double *dtc, const int32_t *cell_mesh, c
 void launch_dt_finalize(int n_mesh, const double *red, const double *dt, const hl_params &p, int first,
                         double *dt_next, double *parts, hipStream_t s);
 void launch_fill(double *p, int64_t n, double v, hipStream_t s);
-void launch_aos_to_soa(int64_t n, int w, const double *in, double *out, hipStream_t s);
+// AoS [n][w] rows <-> SoA [w][n] entities; row i is entity idx[i] (idx null:
+// entity i)
+void launch_aos_to_soa(int64_t n, int w, const double *in, double *out, hipStream_t s, const int32_t *idx = nullptr);
+// out row i = in row idx[i]
+void launch_gather_rows(int64_t n, int w, const double *in, const int32_t *idx, double *out, hipStream_t s);
+void launch_gather_u8(int64_t n, const uint8_t *in, const int32_t *idx, uint8_t *out, hipStream_t s);
 // up to six device-to-device copies of doubles in one launch
 struct CopyFields {
     const double *src[6];
@@ -200,6 +214,6 @@ struct CopyFields {
     int64_t n[6];
 };
 void launch_copy_fields(const CopyFields &f, hipStream_t s);
-void launch_soa_to_aos(int64_t n, int w, const double *in, double *out, hipStream_t s);
+void launch_soa_to_aos(int64_t n, int w, const double *in, double *out, hipStream_t s, const int32_t *idx = nullptr);
 
 }  // namespace hl

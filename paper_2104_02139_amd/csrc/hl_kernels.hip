@@ -1284,6 +1284,7 @@ __global__ __launch_bounds__(256) void k_update_list(StepArgs a) {
     const int64_t n = min((int64_t)a.counters[CNT_CELLS], a.nc);
     if (gtid() == 0) {
         a.counters[CNT_NODES] = 0u;
+        a.counters[CNT_RECOMP] += (unsigned)n;
         *a.stamp = *a.stamp + 1;
     }
     for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) update_cell<D, SG>(a, a.clist[i]);
@@ -1600,19 +1601,66 @@ __global__ __launch_bounds__(256) void k_acoustic(StepArgs a) {
     dtc[nc + c] = __builtin_huge_val();
 }
 
-// Diagnostics: per-block partial sums (fixed order), then one block adds
-// the partials in block order.  Sums: mass, mom[3], m e, kinetic, elastic,
-// n_p0.
-constexpr int NDIAG = 9;
+// Diagnostics: per-block partials (fixed order), then one block per
+// column combines the partials in block order.  Columns 0..8 and 11 are
+// sums (mass, mom[3], m e, kinetic, elastic, n_p0, n_limited, n_detB),
+// columns 9 and 10 maxima (GCL defect, det B defect).
+constexpr int NDIAG = DIAG_N;
+__device__ __forceinline__ bool diag_is_max(int s) { return s == 9 || s == 10; }
+
+// Involution monitors of cell c after the step (Section 3.5): the discrete
+// GCL V(x^{n+1}) - V(x^n) = dt sum_k Cbar_k . v*_k with Cbar the Simpson
+// average of the corner vectors at t^n, t^{n+1/2}, t^{n+1} (exact for the
+// straight node paths x^n + t v*), relative to V(x^n); and
+// |sqrt(det B^{n+1}) - J^{n+1}| (eq. test_detB_rho, J = rho0 tau) with the
+// in-sphere diameter L_c of t^{n+1}.
+template <int D>
+__device__ __forceinline__ void involution(const StepArgs &a, int64_t c, const double *__restrict__ x1,
+                                           const double b1[6], double tau1, double *gcl, double *dB,
+                                           double *Lc3) {
+    constexpr int NV = D + 1;
+    const int64_t nn = a.nn;
+    const double dt = mesh_dt(a.dt, a.cell_mesh, c);
+    double X0[NV][D], Xh[NV][D], X1[NV][D], vs[NV][D];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const int64_t p = a.c2n[c * NV + k];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            X0[k][i] = a.x[i * nn + p];
+            vs[k][i] = a.vstar[i * nn + p];
+            Xh[k][i] = X0[k][i] + 0.5 * dt * vs[k][i];
+            X1[k][i] = x1[i * nn + p];
+        }
+    }
+    Geo<D> g0, gh, g1;
+    geom<D>(X0, g0);
+    geom<D>(Xh, gh);
+    geom<D>(X1, g1);
+    double flux = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int i = 0; i < D; ++i) flux += (g0.C[k][i] + 4.0 * gh.C[k][i] + g1.C[k][i]) * (1.0 / 6.0) * vs[k][i];
+    *gcl = fabs(g1.V - g0.V - dt * flux) / g0.V;
+    *dB = fabs(sqrt(det6(b1)) - a.rho0[c] * tau1);
+    double S = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) S += g1.cn[k];
+    const double Lc = 2.0 * g1.V / S;
+    *Lc3 = Lc * Lc * Lc;
+}
 
 template <int D>
-__global__ __launch_bounds__(256) void k_diag(int64_t nc, const double *__restrict__ m, const double *__restrict__ tau,
-                                              const double *__restrict__ v, const double *__restrict__ e,
-                                              const double *__restrict__ B, const double *__restrict__ rho0,
-                                              const double *__restrict__ mu, const double *__restrict__ K,
-                                              const uint8_t *__restrict__ mask, double shear_a, int eos,
-                                              double *__restrict__ part) {
+__global__ __launch_bounds__(256) void k_diag(StepArgs a, double *__restrict__ part) {
     __shared__ double sh[NDIAG][256];
+    const int64_t nc = a.nc;
+    const double *__restrict__ m = a.mass, *__restrict__ tau = a.tau1, *__restrict__ v = a.v1,
+                                *__restrict__ e = a.e1, *__restrict__ B = a.B1, *__restrict__ rho0 = a.rho0,
+                                *__restrict__ mu = a.mu, *__restrict__ K = a.K;
+    const uint8_t *__restrict__ mask = a.mask;
+    const double shear_a = a.shear_a;
+    const int eos = a.eos;
     int64_t c = gtid();
     double q[NDIAG] = {};
     if (c < nc) {
@@ -1641,6 +1689,11 @@ __global__ __launch_bounds__(256) void k_diag(int64_t nc, const double *__restri
         q[6] = mc * psi;
         q[7] = mask[c] >= 2 ? 1.0 : 0.0;   // first order
         q[8] = mask[c] == 1 ? 1.0 : 0.0;   // limited slopes
+        double gcl, dB, Lc3;
+        involution<D>(a, c, a.x1, b, tau[c], &gcl, &dB, &Lc3);
+        q[9] = gcl;
+        q[10] = dB;
+        q[11] = dB >= Lc3 ? 1.0 : 0.0;
     }
 #pragma unroll
     for (int s = 0; s < NDIAG; ++s) sh[s][threadIdx.x] = q[s];
@@ -1648,7 +1701,9 @@ __global__ __launch_bounds__(256) void k_diag(int64_t nc, const double *__restri
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
 #pragma unroll
-            for (int s = 0; s < NDIAG; ++s) sh[s][threadIdx.x] += sh[s][threadIdx.x + w];
+            for (int s = 0; s < NDIAG; ++s)
+                sh[s][threadIdx.x] = diag_is_max(s) ? fmax(sh[s][threadIdx.x], sh[s][threadIdx.x + w])
+                                                    : sh[s][threadIdx.x] + sh[s][threadIdx.x + w];
         }
         __syncthreads();
     }
@@ -1663,40 +1718,65 @@ __global__ __launch_bounds__(256) void k_diag_finalize(int64_t nblocks, const do
                                                        double *__restrict__ out) {
     __shared__ double sh[256];
     const int s = blockIdx.x;
+    const bool mx = diag_is_max(s);
     double acc = 0.0;
-    for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) acc += part[b * NDIAG + s];
+    for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x)
+        acc = mx ? fmax(acc, part[b * NDIAG + s]) : acc + part[b * NDIAG + s];
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        if ((int)threadIdx.x < w)
+            sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], sh[threadIdx.x + w]) : sh[threadIdx.x] + sh[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) out[s] = sh[0];
 }
 
-// AoS [n][w] <-> SoA [w][n] copies for the ABI
-__global__ void k_aos_to_soa(int64_t n, int w, const double *__restrict__ in, double *__restrict__ out) {
+// AoS [n][w] (the caller's numbering) <-> SoA [w][n] (the internal one)
+// copies for the ABI; row i of the AoS side is entity idx[i] of the SoA
+// side (idx null: entity i).
+__global__ void k_aos_to_soa(int64_t n, int w, const double *__restrict__ in, const int32_t *__restrict__ idx,
+                             double *__restrict__ out) {
     int64_t i = gtid();
     if (i >= n) return;
-    for (int k = 0; k < w; ++k) out[k * n + i] = in[i * w + k];
+    const int64_t j = idx ? idx[i] : i;
+    for (int k = 0; k < w; ++k) out[k * n + j] = in[i * w + k];
 }
 
-__global__ void k_soa_to_aos(int64_t n, int w, const double *__restrict__ in, double *__restrict__ out) {
+__global__ void k_soa_to_aos(int64_t n, int w, const double *__restrict__ in, const int32_t *__restrict__ idx,
+                             double *__restrict__ out) {
     int64_t i = gtid();
     if (i >= n) return;
-    for (int k = 0; k < w; ++k) out[i * w + k] = in[k * n + i];
+    const int64_t j = idx ? idx[i] : i;
+    for (int k = 0; k < w; ++k) out[i * w + k] = in[k * n + j];
+}
+
+// out row i = in row idx[i] (AoS, w values per row)
+__global__ void k_gather_rows(int64_t n, int w, const double *__restrict__ in, const int32_t *__restrict__ idx,
+                              double *__restrict__ out) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    const int64_t j = idx[i];
+    for (int k = 0; k < w; ++k) out[i * w + k] = in[j * w + k];
+}
+
+__global__ void k_gather_u8(int64_t n, const uint8_t *__restrict__ in, const int32_t *__restrict__ idx,
+                            uint8_t *__restrict__ out) {
+    int64_t i = gtid();
+    if (i < n) out[i] = in[idx[i]];
 }
 
 // stress of the current state for queries: 3D (11,22,33,12,13,23),
-// 2D (11,22,12,33), AoS
+// 2D (11,22,12,33), AoS; row i is cell idx[i] (idx null: cell i)
 template <int D>
-__global__ void k_stress_query(StepArgs a, double *__restrict__ out) {
+__global__ void k_stress_query(StepArgs a, const int32_t *__restrict__ idx, double *__restrict__ out) {
     const int64_t nc = a.nc;
     const double *__restrict__ tau = a.tau, *__restrict__ rho0 = a.rho0, *__restrict__ mu = a.mu,
                                 *__restrict__ K = a.K;
     const double shear_a = a.shear_a;
-    int64_t c = gtid();
-    if (c >= nc) return;
+    const int64_t i = gtid();
+    if (i >= nc) return;
+    const int64_t c = idx ? idx[i] : i;
     double b[6], t[6];
     load_B6<D>(a.B, nc, c, b);
     if (a.eos) {
@@ -1709,12 +1789,12 @@ __global__ void k_stress_query(StepArgs a, double *__restrict__ out) {
     else
         stress6_family(rho0[c], mu[c], K[c], shear_a, tau[c], b, t);
     if (D == 3) {
-        for (int s = 0; s < 6; ++s) out[c * 6 + s] = t[s];
+        for (int s = 0; s < 6; ++s) out[i * 6 + s] = t[s];
     } else {
-        out[c * 4 + 0] = t[0];
-        out[c * 4 + 1] = t[1];
-        out[c * 4 + 2] = t[3];
-        out[c * 4 + 3] = t[2];
+        out[i * 4 + 0] = t[0];
+        out[i * 4 + 1] = t[1];
+        out[i * 4 + 2] = t[3];
+        out[i * 4 + 3] = t[2];
     }
 }
 
@@ -1840,9 +1920,17 @@ void launch_copy_fields(const CopyFields &f, hipStream_t s) {
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s) {
     if (n) k_fill_u8<<<std::min<unsigned>(nblk(n), 4096), 256, 0, s>>>(p, n, v);
 }
+// Start of a CFL reduction: per-mesh minima to +inf, the inadmissible
+// count to 0 (a reduction repeated after further MOOD passes counts afresh).
+__global__ void k_reduce_begin(double *__restrict__ red, int64_t n, unsigned *__restrict__ bad_count) {
+    const int64_t i = gtid();
+    if (i < n) red[i] = __builtin_huge_val();
+    if (i == 0) *bad_count = 0u;
+}
+
 void launch_dt_reduce(int64_t nc, const double *dtc, const int32_t *cell_mesh, const uint8_t *pstat, double *red,
                       double *part, const int64_t *mesh_cell_off, int n_mesh, unsigned *bad_count, hipStream_t s) {
-    k_fill<<<nblk(2 * n_mesh), 256, 0, s>>>(red, 2 * n_mesh, __builtin_huge_val());
+    k_reduce_begin<<<nblk(2 * n_mesh), 256, 0, s>>>(red, 2 * n_mesh, bad_count);
     if (nc) {
         const int64_t nb = (nc + 256 * DT_TILES - 1) / (256 * DT_TILES);
         k_dt_reduce<<<(unsigned)nb, 256, 0, s>>>(nc, dtc, cell_mesh, pstat, red, part, bad_count);
@@ -1858,26 +1946,30 @@ void launch_acoustic(const StepArgs &a, hipStream_t s) {
     if (a.nc) k_acoustic<D><<<nblk(a.nc), 256, 0, s>>>(a);
 }
 template <int D>
-int64_t launch_diag(const StepArgs &a, const double *tau, const double *v, const double *e, const double *B,
-                    double *part, double *out, hipStream_t s) {
+int64_t launch_diag(const StepArgs &a, double *part, double *out, hipStream_t s) {
     int64_t nb = nblk(a.nc);
-    if (a.nc)
-        k_diag<D><<<nb, 256, 0, s>>>(a.nc, a.mass, tau, v, e, B, a.rho0, a.mu, a.K, a.mask, a.shear_a, a.eos, part);
+    if (a.nc) k_diag<D><<<nb, 256, 0, s>>>(a, part);
     k_diag_finalize<<<NDIAG, 256, 0, s>>>(a.nc ? nb : 0, part, out);
     return nb;
 }
 void launch_fill(double *p, int64_t n, double v, hipStream_t s) {
     if (n) k_fill<<<nblk(n), 256, 0, s>>>(p, n, v);
 }
-void launch_aos_to_soa(int64_t n, int w, const double *in, double *out, hipStream_t s) {
-    if (n) k_aos_to_soa<<<nblk(n), 256, 0, s>>>(n, w, in, out);
+void launch_aos_to_soa(int64_t n, int w, const double *in, double *out, hipStream_t s, const int32_t *idx) {
+    if (n) k_aos_to_soa<<<nblk(n), 256, 0, s>>>(n, w, in, idx, out);
 }
-void launch_soa_to_aos(int64_t n, int w, const double *in, double *out, hipStream_t s) {
-    if (n) k_soa_to_aos<<<nblk(n), 256, 0, s>>>(n, w, in, out);
+void launch_soa_to_aos(int64_t n, int w, const double *in, double *out, hipStream_t s, const int32_t *idx) {
+    if (n) k_soa_to_aos<<<nblk(n), 256, 0, s>>>(n, w, in, idx, out);
+}
+void launch_gather_rows(int64_t n, int w, const double *in, const int32_t *idx, double *out, hipStream_t s) {
+    if (n) k_gather_rows<<<nblk(n), 256, 0, s>>>(n, w, in, idx, out);
+}
+void launch_gather_u8(int64_t n, const uint8_t *in, const int32_t *idx, uint8_t *out, hipStream_t s) {
+    if (n) k_gather_u8<<<nblk(n), 256, 0, s>>>(n, in, idx, out);
 }
 template <int D>
-void launch_stress_query(const StepArgs &a, double *out, hipStream_t s) {
-    if (a.nc) k_stress_query<D><<<nblk(a.nc), 256, 0, s>>>(a, out);
+void launch_stress_query(const StepArgs &a, const int32_t *idx, double *out, hipStream_t s) {
+    if (a.nc) k_stress_query<D><<<nblk(a.nc), 256, 0, s>>>(a, idx, out);
 }
 
 template void launch_centroids<2>(const StepArgs &, const Sched &, hipStream_t);
@@ -1898,11 +1990,9 @@ template void launch_mood_sparse<3>(const StepArgs &, const int32_t *, const uns
                                     unsigned *, int, hipStream_t);
 template void launch_acoustic<2>(const StepArgs &, hipStream_t);
 template void launch_acoustic<3>(const StepArgs &, hipStream_t);
-template int64_t launch_diag<2>(const StepArgs &, const double *, const double *, const double *, const double *,
-                                double *, double *, hipStream_t);
-template int64_t launch_diag<3>(const StepArgs &, const double *, const double *, const double *, const double *,
-                                double *, double *, hipStream_t);
-template void launch_stress_query<2>(const StepArgs &, double *, hipStream_t);
-template void launch_stress_query<3>(const StepArgs &, double *, hipStream_t);
+template int64_t launch_diag<2>(const StepArgs &, double *, double *, hipStream_t);
+template int64_t launch_diag<3>(const StepArgs &, double *, double *, hipStream_t);
+template void launch_stress_query<2>(const StepArgs &, const int32_t *, double *, hipStream_t);
+template void launch_stress_query<3>(const StepArgs &, const int32_t *, double *, hipStream_t);
 
 }  // namespace hl

@@ -27,7 +27,12 @@ EXPORTS = ["hl_create", "hl_destroy", "hl_mesh_upload", "hl_state_init", "hl_set
            "hl_last_error", "hl_mesh_upload_batch", "hl_step_batch", "hl_query_dt", "hl_use_graph",
            "hl_forward_record", "hl_forward_replay", "hl_adjoint_run", "hl_tape_get",
            "hl_set_schedule", "hl_get_schedule", "hl_autotune", "hl_set_boundary_loads",
-           "hl_set_contact", "hl_get_contact", "hl_mesh_refine", "hl_mesh_info", "hl_mesh_get"]
+           "hl_set_contact", "hl_get_contact", "hl_mesh_refine", "hl_mesh_info", "hl_mesh_get",
+           "hl_set_numbering", "hl_mesh_check", "hl_state_save", "hl_state_restore"]
+
+# internal numbering of uploaded meshes (hl_set_numbering)
+NUMBERING_KEEP, NUMBERING_SPATIAL = 0, 1
+HL_OK, HL_E_INVALID, HL_E_DEGENERATE_CELL, HL_E_NONCONFORMING = 0, -1, -2, -3
 
 # stages of the full-mesh part of a step (launch schedules)
 STAGES = ("pack", "node_agg", "predict", "node_solve", "update")
@@ -56,7 +61,8 @@ class StepInfo(C.Structure):
                 ("energy", C.c_double), ("kinetic", C.c_double), ("elastic", C.c_double),
                 ("n_p0", C.c_int64), ("n_flag_first", C.c_int64), ("mood_iters", C.c_int32),
                 ("status", C.c_int32), ("n_limited", C.c_int64), ("n_contact", C.c_int64),
-                ("trials", C.c_int32), ("clipped", C.c_int32)]
+                ("trials", C.c_int32), ("clipped", C.c_int32), ("n_recomputed", C.c_int64),
+                ("gcl_defect", C.c_double), ("detB_defect", C.c_double), ("n_detB", C.c_int64)]
 
     def as_dict(self):
         return dict(dt_used=self.dt_used, dt_next=self.dt_next, dt_acoustic=self.dt_acoustic,
@@ -64,7 +70,9 @@ class StepInfo(C.Structure):
                     energy=self.energy, kinetic=self.kinetic, elastic=self.elastic,
                     n_p0=self.n_p0, n_flag_first=self.n_flag_first,
                     mood_iters=self.mood_iters, status=self.status, n_limited=self.n_limited,
-                    n_contact=self.n_contact, trials=self.trials, clipped=self.clipped)
+                    n_contact=self.n_contact, trials=self.trials, clipped=self.clipped,
+                    n_recomputed=self.n_recomputed, gcl_defect=self.gcl_defect,
+                    detB_defect=self.detB_defect, n_detB=self.n_detB)
 
 
 class Schedule(C.Structure):
@@ -130,6 +138,10 @@ def load():
     L.hl_profile_enable.argtypes = [vp, C.c_int]
     L.hl_profile_reset.argtypes = [vp]
     L.hl_profile_get.argtypes = [vp, C.c_char_p, C.POINTER(dp), C.POINTER(i64)]
+    L.hl_set_numbering.argtypes = [vp, C.c_int]
+    L.hl_mesh_check.argtypes = [C.c_int, i64, vp, i64, vp]
+    L.hl_state_save.argtypes = [vp, vp, C.POINTER(i64)]
+    L.hl_state_restore.argtypes = [vp, vp, i64]
     for name in EXPORTS:
         if name not in ("hl_status_str", "hl_last_error"):
             getattr(L, name).restype = C.c_int
@@ -163,6 +175,16 @@ def _arg(a, dtype):
         return C.c_void_p(t.data_ptr()), t, 1 if t.is_cuda else 0
     arr = np.ascontiguousarray(a, dtype=dtype)
     return arr.ctypes.data_as(C.c_void_p), arr, 0
+
+
+def mesh_check(dim, x, cells):
+    """Host-side check of a simplicial mesh (hl_mesh_check): 0 if it is
+    valid and conforming, else the status code (HL_E_INVALID,
+    HL_E_DEGENERATE_CELL, HL_E_NONCONFORMING).  Needs no GPU."""
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    cc = np.ascontiguousarray(cells, dtype=np.int32)
+    return int(load().hl_mesh_check(int(dim), int(xx.shape[0]), xx.ctypes.data_as(C.c_void_p),
+                                    int(cc.shape[0]), cc.ctypes.data_as(C.c_void_p)))
 
 
 class Context:
@@ -200,6 +222,24 @@ class Context:
                "hl_mesh_upload")
         self._n_contact = 0
         self.dim, self.n_nodes, self.n_cells = int(dim), nn, nc
+
+    def set_numbering(self, numbering):
+        """Internal numbering of the next uploads: NUMBERING_SPATIAL (the
+        default; Hilbert order of the cells, nodes by first use) or
+        NUMBERING_KEEP.  Arrays at the interface keep the caller's order."""
+        _check(load().hl_set_numbering(self._h, int(numbering)), "hl_set_numbering")
+
+    def save_state(self):
+        """Snapshot of the held state (bytes)."""
+        n = C.c_int64()
+        _check(load().hl_state_save(self._h, None, C.byref(n)), "hl_state_save")
+        buf = C.create_string_buffer(n.value)
+        _check(load().hl_state_save(self._h, C.cast(buf, C.c_void_p), C.byref(n)), "hl_state_save")
+        return buf.raw
+
+    def restore_state(self, blob):
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        _check(load().hl_state_restore(self._h, C.cast(buf, C.c_void_p), len(blob)), "hl_state_restore")
 
     def refine(self, levels=1):
         """Conforming red refinement of the held mesh on the GPU; the state
@@ -396,6 +436,7 @@ class Context:
     # ----------------------------------------------------------- adjoint
     def forward_record(self, nsteps, ckpt_every=20):
         _check(load().hl_forward_record(self._h, int(nsteps), int(ckpt_every)), "hl_forward_record")
+        self.record_generation = getattr(self, "record_generation", 0) + 1
 
     def forward_replay(self):
         _check(load().hl_forward_replay(self._h), "hl_forward_replay")

@@ -33,9 +33,16 @@ def orc_params(w, detect=True, cascade=2):
     return O.default_params(w.c_cfl, detect=detect, cascade=cascade)
 
 
-def pair(w, detect=True, cascade=2):
-    """(gpu context, oracle problem) initialised from the same workload."""
-    ctx = H.from_workload(w, params=gpu_params(w, detect, cascade))
+def pair(w, detect=True, cascade=2, numbering=None):
+    """(gpu context, oracle problem) initialised from the same workload.
+    numbering: the library's internal numbering (None: its default)."""
+    if numbering is None:
+        ctx = H.from_workload(w, params=gpu_params(w, detect, cascade))
+    else:
+        ctx = H.Context(0)
+        ctx.set_numbering(numbering)
+        ctx.upload_mesh(w.dim, w.x, w.cells, w.nwall, w.normals)
+        ctx.init_state(w.rho0, w.mu, w.lam, w.v_cell, w.v_node, gpu_params(w, detect, cascade))
     prob = O.Problem(w, orc_params(w, detect, cascade))
     return ctx, prob
 

@@ -30,8 +30,14 @@ def _log(*a):
 
 @pytest.mark.parametrize("case", list(CASES))
 def test_one_step_parity_three_levels(case):
+    """In the caller's numbering, so that the nodes sum their corners in
+    the oracle's order: on the small 2D wave the nodal right-hand sides
+    cancel to a few 1e-3 of their terms, and the limiter's ratios (M - W)
+    / D of near-flat slopes carry that rounding, so another summation order
+    moves v* by up to 5e-13 of its size (the spatial numbering is compared
+    with the kept one in tests/test_gpu_numbering.py)."""
     w = CASES[case]()
-    ctx, prob = pair(w, cascade=3)
+    ctx, prob = pair(w, cascade=3, numbering=H.NUMBERING_KEEP)
     dt = prob.initial_dt()
     # a second step so that the state is no longer uniform
     info = ctx.step(dt)

@@ -37,6 +37,10 @@ def test_graph_equals_eager_single_mesh(passes):
         assert bad is None, (k, bad)
         assert ie["mood_iters"] == ig["mood_iters"] and ie["n_flag_first"] == ig["n_flag_first"]
         assert ie["dt_next"] == ig["dt_next"]
+        # the same return code and parachute status, also when the captured
+        # passes stop short of the fixpoint and the continuation runs
+        assert ie["rc"] == ig["rc"] and ie["status"] == ig["status"], k
+        assert ie["n_recomputed"] == ig["n_recomputed"], k
     # explicit dt through the graph as well
     eager.step(1e-9)
     graph.step(1e-9)

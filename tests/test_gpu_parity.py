@@ -16,7 +16,7 @@ import pytest
 from oracle import oracle as O
 from paper_2104_02139_amd import workloads as W
 
-from .parity_util import (FIELDS, err, fmt, max_err, oracle_state, pair, patch_around, submesh,
+from .parity_util import (FIELDS, err, fmt, max_err, node_cells, oracle_state, pair, patch_around, submesh,
                           compare_states)
 
 pytestmark = pytest.mark.gpu
@@ -83,6 +83,11 @@ def test_one_step_parity(case):
     # against the roundoff scale of its terms, sum m (K + mu) / rho0
     scale = float(np.sum(prob.m * (prob.K + prob.mu) / prob.rho0))
     assert abs(info["elastic"] - oi.elastic) <= 1e-13 * scale
+    # MOOD work and the involution monitors (eqs. GCL, test_detB_rho)
+    assert info["n_recomputed"] == oi.n_recomp
+    assert info["gcl_defect"] <= 1e-13 and oi.gcl_defect <= 1e-13
+    assert abs(info["detB_defect"] - oi.detB_defect) <= 1e-12
+    assert info["n_detB"] == oi.n_detB
 
 
 @pytest.mark.parametrize("case", ["rotating_cube_n8", "impact_bar_24x6x6", "plane_wave_2d_n40"])
@@ -196,6 +201,7 @@ def test_full_size_sampled_parity(case):
     ctx = H.from_workload(w)
     dt = ctx.compute_dt()
     st0 = ctx.state()
+    snap = ctx.save_state()
     info = ctx.step(0.0)
     _log(f"  gpu step done: mood {info['mood_iters']} p0 {info['n_p0']} dt {info['dt_used']:.3e}")
     mask = ctx.query("order")
@@ -204,34 +210,64 @@ def test_full_size_sampled_parity(case):
     for f in FIELDS:
         assert np.all(np.isfinite(st1[f])), f
     assert info["status"] == 0
-    # sampled cells: random ones plus flagged ones
+    # the unlimited candidate of the same step on the GPU (replay, all zero)
+    ctx.restore_state(snap)
+    ctx.step_replay(dt, np.zeros(w.n_cells, np.uint8))
+    cand = ctx.state()
+    # MOOD decisions at full size, taken by the oracle's detection (eqs.
+    # PAD, RDMP) on the GPU's states: (a) the flags of the first candidate
+    # are as many as the GPU counted and all ended at first order; (b) the
+    # final state is a fixpoint: no cell left at second order is troubled
+    full = O.Problem(w, O.default_params(w.c_cfl))
+    code0 = full.detect(oracle_state(cand), state=oracle_state(st0))
+    flags0 = np.nonzero(code0)[0]
+    _log(f"  first-candidate flags: oracle {flags0.size}, gpu {info['n_flag_first']}")
+    assert flags0.size == info["n_flag_first"]
+    assert np.all(mask[flags0] == 2)
+    code1 = full.detect(oracle_state(st1), state=oracle_state(st0), mask=mask)
+    assert not code1.any(), np.nonzero(code1)[0][:10]
+    del full
+    # sampled cells on two-ring patches: random cells, and flagged cells
+    # with every cell sharing a node with them
     rng = np.random.default_rng(11)
-    seeds = list(rng.choice(w.n_cells, size=6, replace=False))
+    groups = [[int(c)] for c in rng.choice(w.n_cells, size=10, replace=False)]
     flagged = np.nonzero(mask)[0]
+    starts, cell_of = node_cells(w.cells, w.n_nodes)
     if flagged.size:
-        seeds += list(rng.choice(flagged, size=min(4, flagged.size), replace=False))
+        for f in rng.choice(flagged, size=min(3, flagged.size), replace=False):
+            nb = sorted({int(j) for p in w.cells[f] for j in cell_of[starts[p]:starts[p + 1]]})
+            groups.append(nb)
     worst = {}
-    for s in seeds:
-        ids = patch_around(w.cells, w.n_nodes, [s], rings=2)
+    n_cmp = n_first = 0
+    for group in groups:
+        ids = patch_around(w.cells, w.n_nodes, group, rings=2)
         sub, nodes = submesh(w, ids)
         prob = O.Problem(sub, O.default_params(w.c_cfl))
         # identical input state restricted to the patch
         sst = O.State(st0["x"][nodes], st0["vhat"][nodes], st0["tau"][ids], st0["v"][ids],
                       st0["e"][ids], st0["B"][ids])
         o1, ovs, _, _ = prob.step(dt, mask=mask[ids], replay=True, state=sst)
-        loc = int(np.nonzero(ids == s)[0][0])
-        ln = np.searchsorted(nodes, w.cells[s])
-        pairs = {"tau": (st1["tau"][s], o1.tau[loc]), "v": (st1["v"][s], o1.v[loc]),
-                 "e": (st1["e"][s], o1.e[loc]), "B": (st1["B"][s], o1.B[loc]),
-                 "x": (st1["x"][w.cells[s]], o1.x[ln]), "vhat": (st1["vhat"][w.cells[s]], o1.vhat[ln]),
-                 "vstar": (vstar[w.cells[s]], ovs[ln])}
-        for k, (g, o) in pairs.items():
-            # scale by the field's magnitude over the whole mesh
-            full = st1[k] if k in st1 else vstar
-            scale = np.abs(full).max()
-            e = np.abs(np.asarray(g) - np.asarray(o)).max() / scale if scale > 0 else 0.0
-            worst[k] = max(worst.get(k, 0.0), e)
-    _log(f"  sampled errs {fmt(worst)}  ({time.time() - t0:.1f}s)")
+        # the oracle's own first candidate and its detection on the patch
+        oc, _, _, _ = prob.step(dt, mask=np.zeros(len(ids), np.uint8), replay=True, state=sst)
+        pcode = prob.detect(oc, state=sst)
+        for s in group:
+            loc = int(np.nonzero(ids == s)[0][0])
+            assert (pcode[loc] != 0) == (code0[s] != 0), s
+            n_first += int(code0[s] != 0)
+            ln = np.searchsorted(nodes, w.cells[s])
+            pairs = {"tau": (st1["tau"][s], o1.tau[loc]), "v": (st1["v"][s], o1.v[loc]),
+                     "e": (st1["e"][s], o1.e[loc]), "B": (st1["B"][s], o1.B[loc]),
+                     "x": (st1["x"][w.cells[s]], o1.x[ln]), "vhat": (st1["vhat"][w.cells[s]], o1.vhat[ln]),
+                     "vstar": (vstar[w.cells[s]], ovs[ln])}
+            for k, (g, o) in pairs.items():
+                # scale by the field's magnitude over the whole mesh
+                ref = st1[k] if k in st1 else vstar
+                scale = np.abs(ref).max()
+                e = np.abs(np.asarray(g) - np.asarray(o)).max() / scale if scale > 0 else 0.0
+                worst[k] = max(worst.get(k, 0.0), e)
+            n_cmp += 1
+    _log(f"  {n_cmp} sampled cells ({n_first} flagged first), errs {fmt(worst)}  ({time.time() - t0:.1f}s)")
+    assert n_cmp >= 20
     assert max(worst.values()) <= ONE_STEP, fmt(worst)
     # whole-mesh conservation of mass and total energy
     m = ctx.query("mass")
