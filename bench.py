@@ -27,7 +27,12 @@ if ROOT not in sys.path:
 
 METRIC = "FP64 cell-updates/s per Lagrangian step; adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector peak
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector peak: 256 CUs x 128 lanes x 2 flop (FMA) x 2.4 GHz
+# algorithmic FP64 work of one cell-update (hand count of the method's
+# arithmetic: geometry twice, least squares in node-aggregate form,
+# predictor with the chain rule, corner matrices, node solve, update with
+# the Crank-Nicolson solve, stress and detection), 3D and 2D
+ALG_FLOP_PER_CELL = {3: 4600.0, 2: 1700.0}
 PROFILED = ("pack", "node_agg", "predict", "node_solve", "update", "mood_sparse", "reduce")
 
 
@@ -42,9 +47,10 @@ def workloads():
 
 
 def kernel_bytes(dim, nc, nn):
-    """Compulsory HBM bytes of one launch of each kernel: every input the
-    kernel needs read once, every output written once (FP64 = 8 B, int32 =
-    4 B, flags 1 B).  Corner records count their useful doubles."""
+    """Bytes one launch of each stage kernel must move as built: every input
+    it reads once, every output once (FP64 = 8 B, int32 = 4 B, flags 1 B),
+    the staged design's intermediates (node aggregates, corner records,
+    gather records) included.  Reported beside the roofline, not in it."""
     d = dim
     nv = d + 1
     ncor = nv * nc
@@ -65,8 +71,10 @@ def kernel_bytes(dim, nc, nn):
 
 
 def step_alg_bytes(dim, nc, nn):
-    """Algorithmic bytes of a whole step: state in and out, constants,
-    connectivity, node data in and out, each once."""
+    """Algorithmic bytes of a whole step: cell state (tau, v, e, B) in and
+    out, the cell mass, the cell -> node and node -> corner connectivity,
+    node positions and carried velocities in and out, flags, each once
+    (about 235 B per cell-update in 3D on a Kuhn mesh, 177 B in 2D)."""
     d = dim
     nB = 6 if d == 3 else 3
     cell_state = 1 + d + 1 + nB
@@ -143,10 +151,21 @@ def read_valu(kernel, workload):
         return None
 
 
-def cpu_baseline(name, budget_s=25.0):
-    """The oracle as it stands (serial C, one thread) on a bounded sample of
-    the workload: the same mesh family at a reduced resolution, a few steps
-    from t = 0."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(name, budget_s=12.0):
+    """The oracle as it stands on a bounded sample of the workload (the same
+    mesh family at a reduced resolution, steps from t = 0): its serial
+    build on one core, and its OpenMP build (threads over output cells and
+    nodes, bitwise the serial results) on every core the process may use."""
     from oracle import oracle as O
     from paper_2104_02139_amd import workloads as W
     if name.startswith("impact_bar"):
@@ -158,19 +177,34 @@ def cpu_baseline(name, budget_s=25.0):
     else:
         w = W.plane_wave_2d(n=40)
         sample = "2D plane wave 40x40 (%d triangles), steps from t=0" % w.n_cells
-    prob = O.Problem(w)
-    dt = prob.initial_dt()
-    t0 = time.perf_counter()
-    steps = 0
-    while True:
-        _, _, _, info = prob.step(dt)
-        dt = info.dt_next
-        steps += 1
-        if time.perf_counter() - t0 > budget_s * 0.5 or steps >= 50:
-            break
-    el = time.perf_counter() - t0
-    return {"value": w.n_cells * steps / el, "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle", "sample": f"{sample}; {steps} steps in {el:.1f} s"}
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+    def run(threads):
+        O.use_threads(threads)
+        try:
+            prob = O.Problem(w)
+            dt = prob.initial_dt()
+            t0 = time.perf_counter()
+            steps = 0
+            while True:
+                _, _, _, info = prob.step(dt)
+                dt = info.dt_next
+                steps += 1
+                if time.perf_counter() - t0 > budget_s or steps >= 200:
+                    break
+            return steps, time.perf_counter() - t0
+        finally:
+            O.use_threads(False)
+
+    s1, e1 = run(False)
+    os.environ.setdefault("OMP_NUM_THREADS", str(ncores))
+    threads = int(os.environ["OMP_NUM_THREADS"])
+    sn, en = run(True)
+    return {"value": w.n_cells * sn / en, "unit": "cell-updates/s", "cores": threads,
+            "kind": "oracle", "sample": f"{sample}; OpenMP build, {threads} threads: {sn} steps in {en:.1f} s",
+            "one_core": {"value": w.n_cells * s1 / e1, "cores": 1,
+                         "sample": f"{sample}; serial build: {s1} steps in {e1:.1f} s"},
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 def batch_measure(steps=5, warmup=2, n_meshes=256, autotune=True):
@@ -374,6 +408,96 @@ def refined_measure(w, steps, warmup, graph):
     return out
 
 
+def permuted(w, seed):
+    """The workload with cells and nodes in a seeded random order, as a mesh
+    from a mesher may arrive."""
+    import copy
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    pc = rng.permutation(w.n_cells)
+    pn = rng.permutation(w.n_nodes)
+    new_of_old = np.argsort(pn)
+    g = copy.copy(w)
+    g.x = w.x[pn]
+    g.cells = new_of_old[w.cells[pc]].astype(np.int32)
+    g.nwall, g.normals, g.v_node = w.nwall[pn], w.normals[pn], w.v_node[pn]
+    g.rho0, g.mu, g.lam, g.v_cell = w.rho0[pc], w.mu[pc], w.lam[pc], w.v_cell[pc]
+    return g
+
+
+def timed_steps(ctx, n_cells, steps, warmup, graph, report_steps=True):
+    """warmup untimed steps, then `steps` timed steps as submitted in
+    production; the MOOD statistics of the timed steps come from replaying
+    them with reports after restoring the state they started from."""
+    import torch
+    ctx.use_graph(graph, 6)
+    for _ in range(warmup):
+        ctx.step(0.0, info=False)
+    stats = None
+    if report_steps:
+        blob = ctx.save_state()
+        p0, it, rec = [], [], []
+        for _ in range(steps):
+            inf = ctx.step(0.0, info=True)
+            p0.append(inf["n_p0"])
+            it.append(inf["mood_iters"])
+            rec.append(inf["n_recomputed"])
+        ctx.restore_state(blob)
+        stats = {"first_order_frac_mean": sum(p0) / len(p0) / n_cells,
+                 "first_order_frac_min": min(p0) / n_cells, "first_order_frac_max": max(p0) / n_cells,
+                 "mood_iters_mean": sum(it) / len(it), "recomputed_per_step_mean": sum(rec) / len(rec)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(0.0, info=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {"steps": steps, "ms_per_step": 1e3 * el / steps, "cell_updates_per_s": n_cells * steps / el}
+    if stats:
+        out.update(stats)
+    return out
+
+
+def workload_measure(name, w, steps, warmup, graph, numbering=None, prepare=None):
+    """A workload in a context of its own, stepped from t = 0 (after
+    `prepare(ctx)`, if given), timed like the headline."""
+    import torch
+    from paper_2104_02139_amd import hyperlag as H
+    ctx = H.Context(stream=torch.cuda.current_stream())
+    if numbering is not None:
+        ctx.set_numbering(numbering)
+    t0 = time.perf_counter()
+    ctx.upload_mesh(w.dim, w.x, w.cells, w.nwall, w.normals)
+    t_up = time.perf_counter() - t0
+    ctx.init_state(w.rho0, w.mu, w.lam, w.v_cell, w.v_node, H.default_params(w.dim, c_cfl=w.c_cfl))
+    if prepare:
+        prepare(ctx)
+    ctx.compute_dt()
+    out = {"variant": name, "n_cells": w.n_cells, "n_nodes": w.n_nodes, "upload_s": t_up}
+    out.update(timed_steps(ctx, w.n_cells, steps, warmup, graph))
+    ctx.close()
+    return out
+
+
+def impact_noise(w, amp=1.0, xmax=0.2, seed=0):
+    """Seeded velocity noise (amp m/s per component, normal) on the cells of
+    the impact region x < xmax, total energy raised by the kinetic energy
+    added: the relaxed DMP then flags several per cent of the cells per
+    step while the noise decays."""
+    import numpy as np
+    xc = w.x[w.cells].mean(axis=1)
+    sel = xc[:, 0] < xmax
+    rng = np.random.default_rng(seed)
+    v = w.v_cell.copy()
+    v[sel] += amp * rng.standard_normal((int(sel.sum()), w.dim))
+    e = 0.5 * np.sum(v * v, axis=1)
+
+    def prepare(ctx):
+        ctx.upload_field("v", v)
+        ctx.upload_field("e", e)
+    return prepare, float(sel.mean())
+
+
 def adjoint_measure(n=32, steps=200, every=20):
     """Shear-modulus identification cube (32^3 Kuhn cells, lognormal mu):
     time of the checkpointed forward record, of the same steps without
@@ -508,11 +632,17 @@ def main():
     total = {k: kern[k][0] * kern[k][1] for k in kern}
     dom = max(kb, key=lambda k: total.get(k, 0.0))
     avg_ms, launches = kern[dom]
-    achieved = kb[dom] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    step_bytes = step_alg_bytes(w.dim, w.n_cells, w.n_nodes)
+    # roofline of the dominant kernel on the algorithmic bytes of the step
+    # it is part of (state in and out, constants, connectivity and node data
+    # once), not on the intermediates the staged design adds
+    achieved = step_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     traffic = read_traffic(dom, name)
     flop = read_valu(dom, name)
-    step_bytes = step_alg_bytes(w.dim, w.n_cells, w.n_nodes)
     stage_traffic = read_stage_traffic(name)
+    step_flop = ALG_FLOP_PER_CELL[w.dim] * w.n_cells
+    hbm_frac = (step_bytes / (HBM_PEAK_GBS * 1e9)) / (ms_per_step * 1e-3)
+    fp64_frac = (step_flop / (FP64_PEAK_TFLOPS * 1e12)) / (ms_per_step * 1e-3)
 
     out = {
         "metric": METRIC,
@@ -528,12 +658,16 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": name, "dim": w.dim, "n_cells": w.n_cells, "n_nodes": w.n_nodes,
-                   "cascade": "P1->P0", "cfl": w.c_cfl, "launch": "eager" if args.eager else "hipGraph"},
+                   "cascade": "P1->P0", "cfl": w.c_cfl, "launch": "eager" if args.eager else "hipGraph",
+                   "numbering": "spatial (cells on a Hilbert curve, nodes by first use)"},
         "ms_per_step_profiled_eager": 1e3 * (t3 - t2) / args.steps,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "alg_bytes_per_launch": kb[dom],
+                     "traffic": traffic, "alg_bytes_per_launch": step_bytes,
+                     "alg_bytes_per_cell": step_bytes / w.n_cells,
                      "avg_launch_ms": avg_ms, "launches": launches},
+        # bytes each stage kernel moves as built (intermediates included)
+        "kernel_design_bytes_per_launch": kb,
         # the same launch against the FP64 vector peak, from the committed
         # VALU counter summary (null when taken on another kernel source)
         "fp64_valu": None if flop is None or avg_ms <= 0 else {
@@ -545,8 +679,9 @@ def main():
         # rocprofv3 HBM traffic of the four stage kernels (one launch each,
         # MOOD passes and the CFL reduction not included), null unless
         # taken on the current kernel source
-        "step_roofline": {"alg_bytes_per_step": step_bytes,
-                          "hbm_frac": (step_bytes / (HBM_PEAK_GBS * 1e9)) / (ms_per_step * 1e-3),
+        "step_roofline": {"alg_bytes_per_step": step_bytes, "alg_flop_per_step": step_flop,
+                          "hbm_frac": hbm_frac, "fp64_frac": fp64_frac,
+                          "classic_frac": max(hbm_frac, fp64_frac),
                           "measured_stage_bytes_per_step": None if stage_traffic is None
                           else sum(stage_traffic.values()),
                           "measured_hbm_frac": None if stage_traffic is None
@@ -576,6 +711,26 @@ def main():
                 variant_measure(ctx, jelly_material(w), args.steps, args.warmup, not args.eager,
                                 "stiffened gas (droplet material, 3 m/s)", eos=1, sg_gamma=2.2, sg_pinf=1e6),
             ]
+    if not args.no_variants and w.dim == 3 and name.startswith("impact_bar"):
+        print("[bench] numbering, MOOD-heavy and configuration variants", file=sys.stderr, flush=True)
+        ctx.close()
+        del ctx
+        out["variants"] += [
+            workload_measure("shuffled input (random cell and node order, renumbered by the library)",
+                             permuted(w, 1), args.steps, args.warmup, not args.eager),
+            workload_measure("caller's numbering kept (generator order)", w, args.steps, args.warmup,
+                             not args.eager, numbering=H.NUMBERING_KEEP),
+        ]
+        prep, frac = impact_noise(w)
+        v = workload_measure(f"MOOD-heavy: 1 m/s velocity noise on the impact region (x < 0.2, {frac:.3f} of the "
+                             "cells), timed from the second step", w, 10, 1, not args.eager, prepare=prep)
+        out["variants"].append(v)
+        out["configs"] = [
+            workload_measure("rotating cube 56^3 (1.05M tets)", workloads()["rotating_cube_1.05M"](),
+                             args.steps, args.warmup, not args.eager),
+            workload_measure("impact bar 240x60x60 (5.18M tets)", workloads()["impact_bar_5.2M"](),
+                             args.steps, args.warmup, not args.eager),
+        ]
     if not args.no_refined:
         print("[bench] the workload refined once on the GPU, stepped", file=sys.stderr, flush=True)
         out["refined_x8"] = refined_measure(w, args.steps, args.warmup, not args.eager)

@@ -10,6 +10,12 @@
  * the smoke check and the CPU-baseline leg of the benchmark may load it.
  * It shares no code, header, table or helper with the GPU path.
  *
+ * Built plain (serial) for the tests.  The loops over output cells and
+ * nodes carry OpenMP pragmas for the timed CPU baseline: every output is
+ * computed by one thread in the same order, sums over cells (the
+ * diagnostics) stay serial and the minima / maxima do not depend on the
+ * order, so the threaded build gives bitwise the serial results.
+ *
  * Every quantity is FP64.  Tensors are held as full 3x3 arrays; in 2D
  * (plane strain) the third row and column of L and G are zero, B33 == 1 and
  * the in-plane vectors carry a zero third component.  Loops run in the
@@ -712,6 +718,7 @@ static void cell_W(const orc_mesh *M, const double *tau, const double *v, const 
 static void lsq_gradients(const orc_mesh *M, const double *xc, const double *tau, const double *v,
                           const double *B, const double *e, double *grad) {
     int d = M->dim, nW = M->nW + 1, nv = M->nv;
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < M->nc; ++c) {
         double A[3][3] = {{0}};
         double b[11][3] = {{0}};
@@ -766,6 +773,7 @@ static void lsq_gradients(const orc_mesh *M, const double *xc, const double *tau
 static void bj_limit(const orc_mesh *M, const double *x, const double *xc, const double *tau,
                      const double *v, const double *B, const double *grad, double *glim) {
     int d = M->dim, nW = M->nW, nv = M->nv, st = M->nW + 1;
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < M->nc; ++c) {
         double Wc[11], Wk[11], lo[11], hi[11];
         cell_W(M, tau, v, B, NULL, c, Wc);
@@ -970,6 +978,7 @@ static void candidate(orc_work *w, const uint8_t *mask) {
     const orc_mesh *M = w->M;
     int d = M->dim, nv = M->nv;
     /* predictor at every corner */
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < M->nc; ++c) {
         orc_mat mat = mat_of(w, c);
         double Bc[3][3];
@@ -986,6 +995,7 @@ static void candidate(orc_work *w, const uint8_t *mask) {
         }
     }
     /* nodal solver (eq. nodal_solver^n, readings R14, R15, R22) */
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < M->nn; ++p) {
         double Mp[3][3] = {{0}}, r[3] = {0, 0, 0};
         for (int64_t q = M->n2c_off[p]; q < M->n2c_off[p + 1]; ++q) {
@@ -1092,6 +1102,7 @@ static void candidate(orc_work *w, const uint8_t *mask) {
         }
     }
     /* cell update (eqs. tau_c^n .. subforce^n; readings R12, R15) */
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < M->nc; ++c) {
         const orc_geo *g = &w->geo[c];
         double F[3] = {0, 0, 0}, W = 0.0;
@@ -1187,6 +1198,7 @@ static int troubled(const orc_work *w, const orc_params *prm, int64_t c) {
  * over {c} and its reconstruction stencil, the cells sharing a node with c. */
 static void rdmp_bounds(const orc_mesh *M, const double *tau, double *rmin, double *rmax) {
     int nv = M->nv;
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < M->nc; ++c) {
         double lo = 1.0 / tau[c], hi = lo;
         for (int k = 0; k < nv; ++k) {
@@ -1216,6 +1228,9 @@ static void involutions(const orc_mesh *M, const double *rho0, const double *x, 
     double *xh = (double *)malloc(sizeof(double) * (size_t)(M->nn * d + 1));
     for (int64_t p = 0; p < M->nn; ++p)
         for (int i = 0; i < d; ++i) xh[p * d + i] = x[p * d + i] + 0.5 * dt * vstar3[p * 3 + i];
+    double gmax = 0.0, bmax = 0.0;
+    int64_t ndet = 0;
+#pragma omp parallel for schedule(static) reduction(max : gmax, bmax) reduction(+ : ndet)
     for (int64_t c = 0; c < M->nc; ++c) {
         double X0[4][3], Xh[4][3], X1[4][3];
         orc_geo g0, gh, g1;
@@ -1232,13 +1247,16 @@ static void involutions(const orc_mesh *M, const double *rho0, const double *x, 
                 flux += (g0.C[k][i] + 4.0 * gh.C[k][i] + g1.C[k][i]) / 6.0 * vstar3[p * 3 + i];
         }
         double gcl = fabs(g1.V - g0.V - dt * flux) / g0.V;
-        if (gcl > info->gcl_defect) info->gcl_defect = gcl;
+        if (gcl > gmax) gmax = gcl;
         double Bc[3][3];
         unpack_B(d, B1 + c * M->nB, Bc);
         double dB = fabs(sqrt(det33(Bc)) - rho0[c] * tau1[c]);
-        if (dB > info->detB_defect) info->detB_defect = dB;
-        if (dB >= g1.Lc * g1.Lc * g1.Lc) info->n_detB++;
+        if (dB > bmax) bmax = dB;
+        if (dB >= g1.Lc * g1.Lc * g1.Lc) ndet++;
     }
+    info->gcl_defect = gmax;
+    info->detB_defect = bmax;
+    info->n_detB = ndet;
     free(xh);
 }
 
@@ -1272,6 +1290,7 @@ static void time_step(const orc_mesh *M, const double *rho0, const double *mu, c
                       const orc_params *prm, orc_info *info) {
     int d = M->dim;
     double ac = INFINITY, vol = INFINITY;
+#pragma omp parallel for schedule(static) reduction(min : ac, vol)
     for (int64_t c = 0; c < M->nc; ++c) {
         double X[4][3];
         orc_geo g;
@@ -1352,6 +1371,7 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
     double *V0 = (double *)malloc(sizeof(double) * (size_t)(M->nc + 1));
     uint8_t *flag = (uint8_t *)calloc((size_t)M->nc + 1, 1);
 
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < M->nc; ++c) {
         double X[4][3];
         cell_nodes(M, x, c, X);
@@ -1371,6 +1391,7 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
         ++iters;
         if (replay || !prm->detect) break;
         int64_t nflag = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nflag)
         for (int64_t c = 0; c < M->nc; ++c) {
             flag[c] = 0;
             if (mask[c] < 2 && troubled(&w, prm, c)) {
@@ -1388,6 +1409,7 @@ int orc_step(const orc_mesh *M, const double *rho0, const double *mu, const doub
         for (int64_t c = 0; c < M->nc; ++c)
             if (flag[c])
                 for (int k = 0; k < nv; ++k) touch[M->c2n[c * nv + k]] = 1;
+#pragma omp parallel for schedule(static) reduction(+ : recomp)
         for (int64_t c = 0; c < M->nc; ++c) {
             int hit = 0;
             for (int k = 0; k < nv; ++k) hit |= touch[M->c2n[c * nv + k]];

@@ -20,18 +20,38 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hl_oracle.c")
 LIB = os.path.join(HERE, "libhl_oracle.so")
+# the same source threaded over output cells and nodes (OpenMP), for the
+# timed CPU baseline only; bitwise the serial results
+LIB_OMP = os.path.join(HERE, "libhl_oracle_omp.so")
 
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
-          "-Wall", "-Wno-unused-function"]
+          "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas", "-Wno-maybe-uninitialized"]
+CFLAGS_OMP = ["-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
+              "-Wall", "-Wno-unused-function", "-Wno-maybe-uninitialized"]
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C, no FMA contraction)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, LIB)
+    """Compile the oracle with gcc (plain C, no FMA contraction): the serial
+    library and its OpenMP build."""
+    for lib_path, flags in ((LIB, CFLAGS), (LIB_OMP, CFLAGS_OMP)):
+        if force or not os.path.exists(lib_path) or os.path.getmtime(lib_path) < os.path.getmtime(SRC):
+            tmp = lib_path + ".tmp"
+            subprocess.check_call(["gcc", *flags, SRC, "-o", tmp, "-lm"])
+            os.replace(tmp, lib_path)
     return LIB
+
+
+_variant = "serial"
+
+
+def use_threads(on: bool) -> None:
+    """Select the OpenMP build (True) or the serial one (False) for the
+    libraries loaded from now on; call before the first oracle call."""
+    global _variant, _lib
+    want = "omp" if on else "serial"
+    if want != _variant:
+        _variant = want
+        _lib = None
 
 
 class Params(C.Structure):
@@ -80,9 +100,10 @@ _U8 = C.POINTER(C.c_uint8)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        path = LIB_OMP if _variant == "omp" else LIB
+        if not os.path.exists(path):
             build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(path)
         L.orc_mesh_new.restype = C.c_void_p
         L.orc_mesh_new.argtypes = [C.c_int, C.c_int64, C.c_int64, _I32, _U8, _P]
         L.orc_mesh_free.argtypes = [C.c_void_p]
