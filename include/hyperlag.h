@@ -287,6 +287,27 @@ hl_status hl_set_boundary_loads(hl_ctx *ctx, int64_t n, const int32_t *cell, con
  * at the first step).  It also becomes the dt used by hl_step(ctx, 0). */
 hl_status hl_compute_dt(hl_ctx *ctx, double *dt_out);
 
+/* Allocation-free acoustic time step, for callers that cannot allocate
+ * device memory (work under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  The value of hl_compute_dt, C_CFL min_c L_c / a_c with
+ * the neo-Hookean sound speed at J = rho0 tau (K = lambda + 2 mu / 3), for a
+ * state held in the caller's device memory, with no context:
+ *   x [n_nodes][dim], cells [n_cells][dim+1] (int32), rho0, mu, lam, tau
+ *   [n_cells]: device pointers, read only; dt_out: one double of device
+ *   memory, written.
+ * The work is enqueued on hip_stream (NULL: the default stream) of device
+ * `device` and the call returns without waiting: dt_out holds the result
+ * once the stream has run it.  Partial minima go to a workspace of 512 KiB
+ * that the library holds in static device memory on each GPU it runs on
+ * (until the process ends): one per 2048 cells, so n_cells <= 134,217,728,
+ * else HL_E_INVALID.  Calls that overlap on one GPU share that workspace and
+ * race; serialise them (one stream, or events).  A node id out of range
+ * gives dt_out = NaN (the arrays are not read on the host).  n_cells = 0
+ * gives +inf.  The call allocates nothing. */
+hl_status hl_acoustic_dt_noalloc(int device, void *hip_stream, int dim, int64_t n_nodes, const double *x,
+                                 int64_t n_cells, const int32_t *cells, const double *rho0, const double *mu,
+                                 const double *lam, const double *tau, double c_cfl, double *dt_out);
+
 /* One ADER-MOOD step (Section 3.7): unlimited second-order candidate,
  * detection, first-order recompute of troubled cells until no new cell is
  * flagged, then the CFL reduction for the next dt.  dt > 0 is used as is;

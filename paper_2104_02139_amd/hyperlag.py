@@ -28,7 +28,8 @@ EXPORTS = ["hl_create", "hl_destroy", "hl_mesh_upload", "hl_state_init", "hl_set
            "hl_forward_record", "hl_forward_replay", "hl_adjoint_run", "hl_tape_get",
            "hl_set_schedule", "hl_get_schedule", "hl_autotune", "hl_set_boundary_loads",
            "hl_set_contact", "hl_get_contact", "hl_mesh_refine", "hl_mesh_info", "hl_mesh_get",
-           "hl_set_numbering", "hl_mesh_check", "hl_state_save", "hl_state_restore"]
+           "hl_set_numbering", "hl_mesh_check", "hl_state_save", "hl_state_restore",
+           "hl_acoustic_dt_noalloc"]
 
 # internal numbering of uploaded meshes (hl_set_numbering)
 NUMBERING_KEEP, NUMBERING_SPATIAL = 0, 1
@@ -142,6 +143,7 @@ def load():
     L.hl_mesh_check.argtypes = [C.c_int, i64, vp, i64, vp]
     L.hl_state_save.argtypes = [vp, vp, C.POINTER(i64)]
     L.hl_state_restore.argtypes = [vp, vp, i64]
+    L.hl_acoustic_dt_noalloc.argtypes = [C.c_int, vp, C.c_int, i64, vp, i64, vp, vp, vp, vp, vp, dp, vp]
     for name in EXPORTS:
         if name not in ("hl_status_str", "hl_last_error"):
             getattr(L, name).restype = C.c_int
@@ -185,6 +187,26 @@ def mesh_check(dim, x, cells):
     cc = np.ascontiguousarray(cells, dtype=np.int32)
     return int(load().hl_mesh_check(int(dim), int(xx.shape[0]), xx.ctypes.data_as(C.c_void_p),
                                     int(cc.shape[0]), cc.ctypes.data_as(C.c_void_p)))
+
+
+def acoustic_dt_noalloc(x, cells, rho0, mu, lam, tau, c_cfl, out, device=0, stream=None):
+    """hl_acoustic_dt_noalloc on CUDA tensors (no context, nothing
+    allocated by the library): enqueues C_CFL min L_c / a_c into the
+    one-element float64 tensor ``out``."""
+    def p(t, dtype):
+        return _arg(t, dtype)
+    args = [p(a, np.float64) for a in (x, rho0, mu, lam, tau)]
+    pc = p(cells, np.int32)
+    po = p(out, np.float64)
+    if not all(a[2] for a in args + [pc, po]):
+        raise ValueError("hl_acoustic_dt_noalloc takes device arrays")
+    handle = None if stream is None else C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream")
+                                                    else int(stream))
+    dim = int(x.shape[1])
+    _check(load().hl_acoustic_dt_noalloc(int(device), handle, dim, int(x.shape[0]), args[0][0], int(cells.shape[0]),
+                                         pc[0], args[1][0], args[2][0], args[3][0], args[4][0], float(c_cfl),
+                                         po[0]), "hl_acoustic_dt_noalloc")
+    return out
 
 
 class Context:
