@@ -342,6 +342,33 @@ hl_status hl_step_replay(hl_ctx *ctx, double dt, const uint8_t *mask, int on_dev
  * max_mood_passes: 0..64. */
 hl_status hl_use_graph(hl_ctx *ctx, int on, int max_mood_passes);
 
+/* ---- Groups: a 2D and a 3D context stepped together --------------------
+ * Batching across dimensions (a family of triangle and tetrahedron meshes,
+ * each dimension held as a batch in its own context): hl_group_step runs
+ * every stage, MOOD pass and CFL reduction of the two contexts as ONE
+ * kernel launch, the launch's blocks split between them, so the family
+ * costs the launches of one context.  Each context takes one step with its
+ * per-mesh dt held on the device (as hl_step(ctx, 0, ..) or
+ * hl_step_batch(ctx, NULL, ..)), with results bitwise equal to stepping the
+ * two contexts one after the other.
+ * The group borrows the contexts: destroy it before them.  Both contexts
+ * need a state and cells, one device and one stream, the neo-Hookean law
+ * with the two-level cascade (hl_params.shear_a = -1, eos = 0, cascade 2),
+ * the same `detect`, no boundary loads or contact, and, for each stage
+ * where both have work, one block size in their schedules (the defaults
+ * agree); otherwise HL_E_INVALID with the reason in hl_last_error(). */
+typedef struct hl_group hl_group;
+hl_status hl_group_create(hl_group **out, hl_ctx *ctx_2d, hl_ctx *ctx_3d);
+hl_status hl_group_destroy(hl_group *group);
+/* The group's step as a captured hipGraph per pair of buffer parities,
+ * with `max_mood_passes` (0..64) paired passes; flags left after them are
+ * finished eagerly (as hl_use_graph).  Captured graphs are rebuilt when a
+ * context drops its own (new mesh, state, parameters or schedules). */
+hl_status hl_group_use_graph(hl_group *group, int on, int max_mood_passes);
+/* One step of both contexts; either info may be NULL.  Returns
+ * HL_WARN_PARACHUTE_INADMISSIBLE (steps applied) as hl_step does. */
+hl_status hl_group_step(hl_group *group, hl_step_info *info_2d_or_null, hl_step_info *info_3d_or_null);
+
 /* Rigid-plane contact, a boundary condition that changes type during the
  * run (Section 3.8, "Boundary condition treatments"; single mesh only).
  * The plane passes through point[dim] with normal[dim] pointing from the
@@ -398,10 +425,11 @@ typedef struct {
     int32_t reserved;
 } hl_schedule;
 
-/* Set / get the schedule of stage `stage` (HL_STAGE_*).  The default is
- * {256, 256, 0} for the cell stages and {32, 256, 0} for the node stages
- * (8 lanes per node: one pass of 32 nodes per block).  Setting one drops
- * captured graphs. */
+/* Set / get the schedule of stage `stage` (HL_STAGE_*).  The defaults are
+ * {256, 256, 0} for pack and update, {64, 64, 0} for predict, {64, 256, 0}
+ * for the node aggregates and {32, 256, 0} for the node solve (8 lanes per
+ * node: one pass of 64 or 32 nodes per block).  Setting one drops captured
+ * graphs. */
 hl_status hl_set_schedule(hl_ctx *ctx, int stage, const hl_schedule *sched);
 hl_status hl_get_schedule(hl_ctx *ctx, int stage, hl_schedule *sched);
 

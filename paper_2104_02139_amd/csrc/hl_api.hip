@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <new>
 #include <numeric>
 #include <string>
 #include <utility>
@@ -88,6 +89,7 @@ struct hl_ctx {
     unsigned *pass_log = nullptr;   // input flag count of each pass (graph mode)
     int64_t max_deg = 0;
     // captured step, one per buffer parity
+    uint64_t gen = 0;     // advanced whenever captured graphs are dropped (groups re-capture then)
     bool graph_on = false;
     int graph_passes = 6;
     hipStream_t cap_stream = nullptr;
@@ -112,11 +114,13 @@ struct hl_ctx {
     Prof prof;
     // stage schedules and their work lists (device memory in allocs)
     int n_cu = 0;
-    // default schedules: a cell stage one 256-cell item per block; a node
-    // stage (AGG_G lanes per node) one pass of 32 nodes per block, which
-    // keeps each XCD's nodes in flight, and the cell records they share, in
-    // its L2
-    StageCfg cfg[HL_STAGE_COUNT] = {{256, 256, 0}, {32, 256, 0}, {256, 256, 0}, {32, 256, 0}, {256, 256, 0}};
+    // default schedules (the autotuner's choice on the 8.1M-tet bar): pack
+    // and update one 256-cell item per block; predict one 64-cell item per
+    // 64-thread block (its corner records staged in 18 KB of LDS, many
+    // blocks per CU); the node stages (AGG_G lanes per node) one pass of 64
+    // (aggregates) or 32 (solve) nodes per 256-thread block, which keeps
+    // each XCD's nodes in flight, and the cell records they share, in its L2
+    StageCfg cfg[HL_STAGE_COUNT] = {{256, 256, 0}, {64, 256, 0}, {64, 64, 0}, {32, 256, 0}, {256, 256, 0}};
     hl::Sched sk[HL_STAGE_COUNT] = {};
     bool sched_ready = false;
     std::map<std::pair<int, int>, DevList> wlists;  // (entity kind, tile) -> list
@@ -201,6 +205,7 @@ bool params_valid(const hl_params &p) {
 }
 
 void drop_graphs(hl_ctx *c) {
+    ++c->gen;
     for (int b = 0; b < 2; ++b) {
         if (c->gexec[b]) (void)hipGraphExecDestroy(c->gexec[b]);
         for (int f = 0; f < 2; ++f) {
@@ -2475,6 +2480,298 @@ hl_status hl_profile_get(hl_ctx *c, const char *name, double *avg_ms, int64_t *l
         }
     }
     return HL_E_INVALID;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ groups
+// A 2D and a 3D context stepped together: every stage, MOOD pass and CFL
+// reduction of the two runs as one paired launch (hl::launch_*_pair), so a
+// family of meshes of both dimensions costs the launches of one context.
+struct hl_group {
+    hl_ctx *c[2] = {nullptr, nullptr};  // the 2D context, the 3D context
+    bool graph_on = false;
+    int graph_passes = 6;
+    hipStream_t cap_stream = nullptr;
+    // captured step per (buffer parity of c[0], of c[1]), with the
+    // contexts' generations it was captured at
+    hipGraph_t graph[2][2] = {};
+    hipGraphExec_t gexec[2][2] = {};
+    uint64_t gen[2][2][2] = {};
+};
+
+namespace {
+
+void group_drop_graphs(hl_group *g) {
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            if (g->gexec[i][j]) (void)hipGraphExecDestroy(g->gexec[i][j]);
+            if (g->graph[i][j]) (void)hipGraphDestroy(g->graph[i][j]);
+            g->gexec[i][j] = nullptr;
+            g->graph[i][j] = nullptr;
+        }
+}
+
+// The configurations the paired kernels cover, and one launch shape per
+// stage where both contexts have work.
+hl_status group_check(hl_group *g) {
+    const char *why = nullptr;
+    for (int i = 0; i < 2 && !why; ++i) {
+        const hl_ctx *c = g->c[i];
+        if (!c->have_state)
+            return HL_E_STATE;
+        else if (c->nc == 0)
+            why = "a grouped context holds no cells";
+        else if (c->prm.shear_a != -1.0 || c->prm.eos != 0 || c->prm.cascade == 3)
+            why = "grouped contexts run the neo-Hookean law with the two-level cascade";
+        else if (c->ld.n > 0 || c->ct.n > 0)
+            why = "grouped contexts take no boundary loads or contact";
+    }
+    if (!why && g->c[0]->prm.detect != g->c[1]->prm.detect) why = "grouped contexts differ in detection";
+    if (!why && (g->c[0]->device != g->c[1]->device || g->c[0]->stream != g->c[1]->stream))
+        why = "grouped contexts use one device and one stream";
+    if (!why)
+        for (int st = 0; st < HL_STAGE_COUNT; ++st)
+            if (g->c[0]->sk[st].w.n_items && g->c[1]->sk[st].w.n_items &&
+                g->c[0]->sk[st].block != g->c[1]->sk[st].block)
+                why = "grouped contexts need one block size per stage";
+    if (why) {
+        std::snprintf(g_last_error, sizeof g_last_error, "%s", why);
+        return HL_E_INVALID;
+    }
+    return HL_OK;
+}
+
+hl::PairBook pair_book(hl_ctx *c) {
+    hl::PairBook b{};
+    b.counters = c->counters;
+    b.dt_cur = c->dt_cur;
+    b.dt_next = c->dt_next;
+    b.n_mesh = c->n_mesh;
+    b.copy_dt = 1;
+    b.mask = c->mask;
+    b.nc = c->nc;
+    b.dtc = c->dtc;
+    b.cell_mesh = c->cell_mesh;
+    b.pstat = c->pstat;
+    b.red = c->dt_red;
+    b.part = c->dt_part;
+    b.parts = c->dt_parts;
+    b.mesh_cell_off = c->mesh_cell_off;
+    b.bad_count = c->counters + hl::CNT_BAD;
+    b.c_cfl = c->prm.c_cfl;
+    b.c_v = c->prm.c_v;
+    b.c_i = c->prm.c_i;
+    return b;
+}
+
+// the step's first part (enqueue_first of both contexts, clearing the masks)
+void group_first(hl_group *g, hl::StepArgs a[2], hipStream_t s) {
+    hl_ctx *c0 = g->c[0], *c1 = g->c[1];
+    hl::launch_step_begin_pair(pair_book(c0), pair_book(c1), s);
+    for (int i = 0; i < 2; ++i) {
+        a[i].flist_out = g->c[i]->flist[0];
+        a[i].fcount_out = g->c[i]->counters + hl::CNT_F0;
+    }
+    hl::launch_node_agg_pair(a[0], c0->sk[HL_STAGE_NODE_AGG], a[1], c1->sk[HL_STAGE_NODE_AGG], s);
+    hl::launch_predict_pair(a[0], c0->sk[HL_STAGE_PREDICT], a[1], c1->sk[HL_STAGE_PREDICT], s);
+    hl::launch_node_solve_pair(a[0], c0->sk[HL_STAGE_NODE_SOLVE], a[1], c1->sk[HL_STAGE_NODE_SOLVE], s);
+    hl::launch_update_pair(a[0], c0->sk[HL_STAGE_UPDATE], a[1], c1->sk[HL_STAGE_UPDATE], s);
+}
+
+// one MOOD pass of both contexts reading flag list fb (a context with no
+// flagged cell runs an empty pass: its lists and stamp move on, nothing else)
+void group_pass(hl_group *g, hl::StepArgs a[2], int fb, int log_index, const int64_t nflag[2], bool fixed,
+                hipStream_t s) {
+    hl::PairPass p[2];
+    for (int i = 0; i < 2; ++i) {
+        hl_ctx *c = g->c[i];
+        a[i].flist_out = c->flist[1 - fb];
+        a[i].fcount_out = c->counters + hl::CNT_F0 + (1 - fb);
+        p[i] = hl::PairPass{c->flist[fb], c->counters + hl::CNT_F0 + fb, nflag[i], c->max_deg,
+                            log_index >= 0 ? c->pass_log : nullptr};
+    }
+    hl::launch_mood_sparse_pair(a[0], p[0], a[1], p[1], fixed, log_index >= 0 ? log_index : 0, s);
+}
+
+hl_status group_read_counters(hl_group *g, hipStream_t s) {
+    for (int i = 0; i < 2; ++i)
+        HIPCHK(hipMemcpyAsync(g->c[i]->counters_host, g->c[i]->counters, hl::CNT_N * sizeof(unsigned),
+                              hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HL_OK;
+}
+
+hl_status group_capture(hl_group *g, int s0, int s1) {
+    if (!g->cap_stream) HIPCHK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = g->cap_stream;
+    hl::StepArgs a[2] = {make_args(g->c[0], s0), make_args(g->c[1], s1)};
+    const int64_t zero[2] = {0, 0};
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    group_first(g, a, cs);
+    for (int p = 0; p < g->graph_passes; ++p) group_pass(g, a, p & 1, p, zero, true, cs);
+    hl::launch_dt_reduce_pair(pair_book(g->c[0]), pair_book(g->c[1]), cs);
+    hipGraph_t gr = nullptr;
+    HIPCHK(hipStreamEndCapture(cs, &gr));
+    g->graph[s0][s1] = gr;
+    HIPCHK(hipGraphInstantiate(&g->gexec[s0][s1], gr, nullptr, nullptr, 0));
+    g->gen[s0][s1][0] = g->c[0]->gen;
+    g->gen[s0][s1][1] = g->c[1]->gen;
+    return HL_OK;
+}
+
+hl_status group_step(hl_group *g, hl_step_info *info0, hl_step_info *info1) {
+    hl_ctx *c[2] = {g->c[0], g->c[1]};
+    hl_status st;
+    for (int i = 0; i < 2; ++i)
+        if ((st = ensure_scheds(c[i])) != HL_OK) return st;
+    if ((st = group_check(g)) != HL_OK) return st;
+    if (hipSetDevice(c[0]->device) != hipSuccess) return HL_E_HIP;
+    hipStream_t s = c[0]->stream;
+    const int src[2] = {c[0]->cur, c[1]->cur};
+    hl::StepArgs a[2] = {make_args(c[0], src[0]), make_args(c[1], src[1])};
+    for (int i = 0; i < 2; ++i) {
+        if (c[i]->stamp_host > INT32_MAX - 4096) {
+            HIPCHK(hipMemsetAsync(c[i]->nstamp, 0, sizeof(int32_t) * c[i]->nn, s));
+            HIPCHK(hipMemsetAsync(c[i]->cstamp, 0, sizeof(int32_t) * c[i]->nc, s));
+            HIPCHK(hipMemsetAsync(c[i]->stamp_dev, 0, sizeof(int32_t), s));
+            c[i]->stamp_host = 0;
+        }
+        if (!c[i]->rec_valid) {
+            if (i == 0)
+                hl::launch_centroids<2>(a[0], c[0]->sk[HL_STAGE_PACK], s);
+            else
+                hl::launch_centroids<3>(a[1], c[1]->sk[HL_STAGE_PACK], s);
+            c[i]->rec_valid = true;
+        }
+    }
+    const bool detect = a[0].detect != 0;
+    int64_t nflag[2] = {0, 0}, first[2] = {0, 0};
+    int iters[2] = {1, 1};
+    int fb = 0;
+    auto more = [&]() { return detect && (nflag[0] > 0 || nflag[1] > 0); };
+    auto eager_passes = [&]() -> hl_status {
+        while (more()) {
+            group_pass(g, a, fb, -1, nflag, false, s);
+            for (int i = 0; i < 2; ++i) {
+                c[i]->stamp_host++;
+                iters[i] += nflag[i] > 0;
+            }
+            hl_status r = group_read_counters(g, s);
+            if (r != HL_OK) return r;
+            fb = 1 - fb;
+            for (int i = 0; i < 2; ++i) nflag[i] = c[i]->counters_host[hl::CNT_F0 + fb];
+        }
+        return HL_OK;
+    };
+    if (g->graph_on) {
+        hipGraphExec_t &ge = g->gexec[src[0]][src[1]];
+        if (ge && (g->gen[src[0]][src[1]][0] != c[0]->gen || g->gen[src[0]][src[1]][1] != c[1]->gen)) {
+            (void)hipGraphExecDestroy(ge);
+            (void)hipGraphDestroy(g->graph[src[0]][src[1]]);
+            ge = nullptr;
+            g->graph[src[0]][src[1]] = nullptr;
+        }
+        if (!ge && (st = group_capture(g, src[0], src[1])) != HL_OK) return st;
+        HIPCHK(hipGraphLaunch(ge, s));
+        const int np = std::min(g->graph_passes, 64);
+        unsigned log[2][64];
+        for (int i = 0; i < 2; ++i) {
+            c[i]->stamp_host += g->graph_passes;
+            if (np) HIPCHK(hipMemcpyAsync(log[i], c[i]->pass_log, sizeof(unsigned) * np, hipMemcpyDeviceToHost, s));
+        }
+        if ((st = group_read_counters(g, s)) != HL_OK) return st;
+        fb = g->graph_passes & 1;
+        for (int i = 0; i < 2; ++i) {
+            nflag[i] = c[i]->counters_host[hl::CNT_F0 + fb];
+            first[i] = np ? log[i][0] : nflag[i];
+            for (int p = 0; p < np; ++p) iters[i] += log[i][p] > 0;
+        }
+        if (more()) {
+            // the captured passes did not reach the fixpoint: further passes
+            // eagerly, then the reduction again
+            if ((st = eager_passes()) != HL_OK) return st;
+            hl::launch_dt_reduce_pair(pair_book(c[0]), pair_book(c[1]), s);
+            if ((st = group_read_counters(g, s)) != HL_OK) return st;
+        }
+    } else {
+        group_first(g, a, s);
+        if ((st = group_read_counters(g, s)) != HL_OK) return st;
+        for (int i = 0; i < 2; ++i) first[i] = nflag[i] = c[i]->counters_host[hl::CNT_F0];
+        if ((st = eager_passes()) != HL_OK) return st;
+        hl::launch_dt_reduce_pair(pair_book(c[0]), pair_book(c[1]), s);
+        if ((st = group_read_counters(g, s)) != HL_OK) return st;
+    }
+    hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return hip_fail(le, "kernel launch", __LINE__);
+    bool inadm = false;
+    hl_step_info *info[2] = {info0, info1};
+    for (int i = 0; i < 2; ++i) {
+        c[i]->last_first = first[i];
+        c[i]->last_iters = iters[i];
+        c[i]->last_inadm = c[i]->counters_host[hl::CNT_BAD];
+        c[i]->last_recomp = c[i]->counters_host[hl::CNT_RECOMP];
+        inadm = inadm || c[i]->last_inadm;
+        c[i]->cur = 1 - src[i];
+        if (info[i]) {
+            st = i == 0 ? fill_info<2>(c[0], src[0], info[0]) : fill_info<3>(c[1], src[1], info[1]);
+            if (st != HL_OK) return st;
+        }
+    }
+    return inadm ? HL_WARN_PARACHUTE_INADMISSIBLE : HL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hl_status hl_group_create(hl_group **out, hl_ctx *ctx_2d, hl_ctx *ctx_3d) {
+    g_last_error[0] = '\0';
+    if (!out) return HL_E_INVALID;
+    *out = nullptr;
+    if (!ctx_2d || !ctx_3d || ctx_2d == ctx_3d) return HL_E_INVALID;
+    if (!ctx_2d->have_mesh || !ctx_3d->have_mesh) return HL_E_STATE;
+    if (ctx_2d->dim != 2 || ctx_3d->dim != 3) return HL_E_INVALID;
+    hl_group *g = new (std::nothrow) hl_group;
+    if (!g) return HL_E_OOM;
+    g->c[0] = ctx_2d;
+    g->c[1] = ctx_3d;
+    *out = g;
+    return HL_OK;
+}
+
+hl_status hl_group_destroy(hl_group *g) {
+    if (!g) return HL_OK;
+    if (g->c[0]) (void)hipSetDevice(g->c[0]->device);
+    group_drop_graphs(g);
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+    delete g;
+    return HL_OK;
+}
+
+hl_status hl_group_use_graph(hl_group *g, int on, int max_mood_passes) {
+    if (!g || max_mood_passes < 0 || max_mood_passes > 64) return HL_E_INVALID;
+    if (g->graph_passes != max_mood_passes || !on) group_drop_graphs(g);
+    g->graph_on = on != 0;
+    g->graph_passes = max_mood_passes;
+    return HL_OK;
+}
+
+hl_status hl_group_step(hl_group *g, hl_step_info *info_2d, hl_step_info *info_3d) {
+    g_last_error[0] = '\0';
+    if (!g) return HL_E_INVALID;
+    hl_status st = group_step(g, info_2d, info_3d);
+    if (st != HL_OK && st != HL_WARN_PARACHUTE_INADMISSIBLE) {
+        // a failed step leaves no half-captured graph behind
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (g->cap_stream && hipStreamIsCapturing(g->cap_stream, &cs) == hipSuccess &&
+            cs != hipStreamCaptureStatusNone) {
+            hipGraph_t tmp = nullptr;
+            (void)hipStreamEndCapture(g->cap_stream, &tmp);
+            if (tmp) (void)hipGraphDestroy(tmp);
+        }
+    }
+    return st;
 }
 
 }  // extern "C"

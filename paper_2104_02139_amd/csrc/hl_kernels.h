@@ -195,6 +195,46 @@ void launch_mood_sparse(const StepArgs &a, const int32_t *flist, const unsigned 
                         int64_t max_deg, bool fixed_grid, unsigned *log, int log_idx, hipStream_t s);
 void launch_step_begin(unsigned *counters, double *dt_cur, const double *dt_next, int n_mesh, int copy_dt,
                        hipStream_t s);
+
+// Paired launches: the stage of a 2D context (a2, k2) and of a 3D context
+// (a3, k3) as one kernel launch, each part as its own launch would run it.
+// Both contexts run the base configuration (neo-Hookean law, two-level
+// cascade, no boundary loads) and, where both have work, one block size.
+void launch_node_agg_pair(const StepArgs &a2, const Sched &k2, const StepArgs &a3, const Sched &k3, hipStream_t s);
+void launch_predict_pair(const StepArgs &a2, const Sched &k2, const StepArgs &a3, const Sched &k3, hipStream_t s);
+void launch_node_solve_pair(const StepArgs &a2, const Sched &k2, const StepArgs &a3, const Sched &k3,
+                            hipStream_t s);
+void launch_update_pair(const StepArgs &a2, const Sched &k2, const StepArgs &a3, const Sched &k3, hipStream_t s);
+// one sparse MOOD pass of each part (see launch_mood_sparse)
+struct PairPass {
+    const int32_t *flist;
+    const unsigned *fcount;
+    int64_t nflag, max_deg;
+    unsigned *log;   // may be null
+};
+void launch_mood_sparse_pair(const StepArgs &a2, const PairPass &p2, const StepArgs &a3, const PairPass &p3,
+                             bool fixed_grid, int log_idx, hipStream_t s);
+// per-context buffers of the step's start (counters, dt, cascade levels)
+// and of the CFL reduction
+struct PairBook {
+    unsigned *counters;
+    double *dt_cur, *dt_next;
+    int n_mesh;
+    int copy_dt;
+    uint8_t *mask;
+    int64_t nc;
+    const double *dtc;
+    const int32_t *cell_mesh;
+    const uint8_t *pstat;
+    double *red, *part, *parts;
+    const int64_t *mesh_cell_off;
+    unsigned *bad_count;
+    double c_cfl, c_v, c_i;
+};
+// step start: counters cleared, dt_cur = dt_next if copy_dt, mask = 0
+void launch_step_begin_pair(const PairBook &b2, const PairBook &b3, hipStream_t s);
+// the CFL reduction of launch_dt_reduce + launch_dt_finalize (first = 0)
+void launch_dt_reduce_pair(const PairBook &b2, const PairBook &b3, hipStream_t s);
 void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 void launch_dt_reduce(int64_t nc, const double *dtc, const int32_t *cell_mesh, const uint8_t *pstat, double *red,
                       double *part, const int64_t *mesh_cell_off, int n_mesh, unsigned *bad_count, hipStream_t s);

@@ -27,6 +27,17 @@ __device__ __forceinline__ int64_t gtid() {
     return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 }
 
+// Block coordinates of a launch, or of one part of a launch that runs the
+// stages of two contexts together (k_pair): the block's number within its
+// part and the part's block count.  Parts start at a multiple of 8 blocks,
+// so id & 7 still names the block's XCD.
+struct Blk {
+    int64_t id, n;
+    __device__ __forceinline__ int64_t tid() const { return id * blockDim.x + threadIdx.x; }
+    __device__ __forceinline__ int64_t stride() const { return n * blockDim.x; }
+};
+__device__ __forceinline__ Blk grid_blk() { return Blk{(int64_t)blockIdx.x, (int64_t)gridDim.x}; }
+
 // Streamed stores: data that the next kernels read only after gigabytes of
 // other traffic (corner records, gather records, the new cell state) are
 // written with the nontemporal hint, so they do not push reused data (node
@@ -83,12 +94,12 @@ __device__ __forceinline__ void wave_append(int32_t *__restrict__ list, unsigned
 
 // Walk the items of a work list (see WorkList); f(entity) for each entity.
 template <class F>
-__device__ __forceinline__ void walk_items(const WorkList &w, F f) {
-    const int64_t nslot = gridDim.x >> 3;
+__device__ __forceinline__ void walk_items(const WorkList &w, const Blk b, F f) {
+    const int64_t nslot = b.n >> 3;
     const int64_t per = (w.n_items + 7) >> 3;
-    const int64_t i0 = (int64_t)(blockIdx.x & 7u) * per;
+    const int64_t i0 = (b.id & 7) * per;
     const int64_t i1 = i0 + per < w.n_items ? i0 + per : w.n_items;
-    for (int64_t i = i0 + (blockIdx.x >> 3); i < i1; i += nslot) {
+    for (int64_t i = i0 + (b.id >> 3); i < i1; i += nslot) {
         const int64_t s0 = w.start[i];
         const int n = w.len[i];
         for (int j = threadIdx.x; j < n; j += blockDim.x) f(s0 + j);
@@ -99,20 +110,20 @@ __device__ __forceinline__ void walk_items(const WorkList &w, F f) {
 // than a block: the same XCD grouping without a loop around the body, which
 // keeps the body's register allocation as low as a plain launch's.
 template <class F>
-__device__ __forceinline__ void one_item(const WorkList &w, F f) {
+__device__ __forceinline__ void one_item(const WorkList &w, const Blk b, F f) {
     const int64_t per = (w.n_items + 7) >> 3;
-    const int64_t slot = blockIdx.x >> 3;
-    const int64_t i = (int64_t)(blockIdx.x & 7u) * per + slot;
+    const int64_t slot = b.id >> 3;
+    const int64_t i = (b.id & 7) * per + slot;
     if (slot >= per || i >= w.n_items) return;
     if ((int)threadIdx.x < w.len[i]) f(w.start[i] + threadIdx.x);
 }
 
 template <bool LOOP, class F>
-__device__ __forceinline__ void for_items(const WorkList &w, F f) {
+__device__ __forceinline__ void for_items(const WorkList &w, const Blk b, F f) {
     if (LOOP)
-        walk_items(w, f);
+        walk_items(w, b, f);
     else
-        one_item(w, f);
+        one_item(w, b, f);
 }
 
 __device__ __forceinline__ double mesh_dt(const double *dtm, const int32_t *mesh_id, int64_t i) {
@@ -156,7 +167,7 @@ __device__ __forceinline__ void pack_cell(const StepArgs &a, const int64_t c) {
 
 template <int D, bool LOOP>
 __global__ __launch_bounds__(256) void k_pack(StepArgs a, WorkList w) {
-    for_items<LOOP>(w, [&](int64_t c) { pack_cell<D>(a, c); });
+    for_items<LOOP>(w, grid_blk(), [&](int64_t c) { pack_cell<D>(a, c); });
 }
 
 // ------------------------------------------------ node aggregates (R8)
@@ -280,37 +291,49 @@ __device__ __forceinline__ void node_agg_group(const StepArgs &a, const int64_t 
     }
 }
 
+// LDS of the aggregate stage: one record of NA + 1 doubles per node group
+template <int D>
+constexpr int agg_lds_doubles() {
+    return (256 / AGG_G) * (Dims<D>::NA + 1);
+}
+
 template <int D, bool LOOP>
-__global__ __launch_bounds__(256) void k_node_agg(StepArgs a, WorkList w) {
+__device__ __forceinline__ void node_agg_body(const StepArgs &a, const WorkList &w, const Blk bk, double *sh_all) {
     using Dm = Dims<D>;
-    __shared__ double sh[256 / AGG_G][Dm::NA + 1];
     const int l = threadIdx.x & (AGG_G - 1);
     const int g = threadIdx.x / AGG_G;
     const int per_pass = blockDim.x / AGG_G;
     const int64_t nn = a.nn;
+    double *sh = sh_all + g * (Dm::NA + 1);
     // items as in walk_items; every thread of the block runs the same passes
-    const int64_t nslot = gridDim.x >> 3;
+    const int64_t nslot = bk.n >> 3;
     const int64_t per = (w.n_items + 7) >> 3;
-    const int64_t i0 = (int64_t)(blockIdx.x & 7u) * per;
+    const int64_t i0 = (bk.id & 7) * per;
     const int64_t i1 = i0 + per < w.n_items ? i0 + per : w.n_items;
-    for (int64_t it = i0 + (blockIdx.x >> 3); it < i1; it += nslot) {
+    for (int64_t it = i0 + (bk.id >> 3); it < i1; it += nslot) {
         const int64_t s0 = w.start[it];
         const int len = w.len[it];
         for (int base = 0; base < len; base += per_pass) {
             const bool act = base + g < len;
             const int64_t p = s0 + base + g;
-            if (act) node_agg_group<D>(a, p, l, sh[g]);
+            if (act) node_agg_group<D>(a, p, l, sh);
             __syncthreads();
             if (act) {
                 double2 *b = reinterpret_cast<double2 *>(a.agg) + p;
                 const int np = (a.limited ? Dm::NA : (a.eos ? Dm::NA_SG : Dm::NA_BASE)) / 2;
                 for (int j = l; j < np; j += AGG_G)
-                    b[(int64_t)j * nn] = make_double2(sh[g][2 * j], sh[g][2 * j + 1]);
+                    b[(int64_t)j * nn] = make_double2(sh[2 * j], sh[2 * j + 1]);
             }
             __syncthreads();
         }
         if (!LOOP) break;
     }
+}
+
+template <int D, bool LOOP>
+__global__ __launch_bounds__(256) void k_node_agg(StepArgs a, WorkList w) {
+    __shared__ double sh[agg_lds_doubles<D>()];
+    node_agg_body<D, LOOP>(a, w, grid_blk(), sh);
 }
 
 // ---------------------------------------------------------- helpers
@@ -671,8 +694,12 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c,
 }
 
 template <int D, bool LOOP, bool LIM, bool FAM, bool SG>
+__device__ __forceinline__ void predict_body(const StepArgs &a, const WorkList &w, const Blk b) {
+    for_items<LOOP>(w, b, [&](int64_t c) { predict_cell<D, LIM, FAM, SG>(a, c); });
+}
+template <int D, bool LOOP, bool LIM, bool FAM, bool SG>
 __global__ __launch_bounds__(256) void k_predict(StepArgs a, WorkList w) {
-    for_items<LOOP>(w, [&](int64_t c) { predict_cell<D, LIM, FAM, SG>(a, c); });
+    predict_body<D, LOOP, LIM, FAM, SG>(a, w, grid_blk());
 }
 
 // One block per item (the one_item mapping), corner records staged in LDS
@@ -681,14 +708,13 @@ __global__ __launch_bounds__(256) void k_predict(StepArgs a, WorkList w) {
 // store covers 512 consecutive bytes instead of 64 records 72 bytes apart.
 // Same values as k_predict.
 template <int D, bool LIM, bool FAM, bool SG>
-__global__ __launch_bounds__(256) void k_predict_staged(StepArgs a, WorkList w) {
+__device__ __forceinline__ void predict_staged_body(const StepArgs &a, const WorkList &w, const Blk b, double *cs) {
     using Dm = Dims<D>;
     constexpr int NV = D + 1, RW = Dm::CW;
     static_assert(Dm::CW == Dm::NMS + D, "corner records hold M_cp and r_cp only");
-    extern __shared__ double cs[];
     const int64_t per = (w.n_items + 7) >> 3;
-    const int64_t slot = blockIdx.x >> 3;
-    const int64_t it = (int64_t)(blockIdx.x & 7u) * per + slot;
+    const int64_t slot = b.id >> 3;
+    const int64_t it = (b.id & 7) * per + slot;
     if (slot >= per || it >= w.n_items) return;  // the whole block
     const int64_t s0 = w.start[it];
     const int len = w.len[it];
@@ -706,6 +732,20 @@ __global__ __launch_bounds__(256) void k_predict_staged(StepArgs a, WorkList w) 
             store_stream(&a.corner[corner_slot<D>(s0 + ci, k) * RW + j], cs[k * bs * RW + r]);
         }
 }
+template <int D, bool LIM, bool FAM, bool SG>
+__global__ __launch_bounds__(256) void k_predict_staged(StepArgs a, WorkList w) {
+    extern __shared__ double cs[];
+    predict_staged_body<D, LIM, FAM, SG>(a, w, grid_blk(), cs);
+}
+
+// x^{n+1} = x^n + dt v* (reading R13) and vhat^{n+1} = 2 v* - vhat^n (R9),
+// as one fused multiply-add and one exact doubling.  The node solve stores
+// both; the cell update recomputes vhat^{n+1} from the vhat^n and v* it
+// gathers anyway (one node vector fewer, the same bits).  Recomputing
+// x^{n+1} too raised the update from 166 to 182 VGPRs (3 to 2 waves per
+// SIMD), so it gathers x^{n+1}.
+__device__ __forceinline__ double next_position(double x, double dt, double vs) { return __fma_rn(dt, vs, x); }
+__device__ __forceinline__ double next_vhat(double vs, double vh) { return 2.0 * vs - vh; }
 
 // ---------------------------------------------------------- node solve
 // M_p v*_p = sum_c (M_cp v*_cp - T*_cp C_cp) (eq. nodal_solver^n, readings
@@ -963,26 +1003,30 @@ __device__ __forceinline__ void node_solve_finish(const StepArgs &a, const int64
     for (int i = 0; i < D; ++i) {
         if (comp >= 0 && comp != i) continue;
         a.vstar[i * nn + p] = vs[i];
-        a.x1[i * nn + p] = a.x[i * nn + p] + dt * vs[i];
-        a.vhat1[i * nn + p] = 2.0 * vs[i] - a.vhat[i * nn + p];
+        a.x1[i * nn + p] = next_position(a.x[i * nn + p], dt, vs[i]);
+        a.vhat1[i * nn + p] = next_vhat(vs[i], a.vhat[i * nn + p]);
     }
 }
 
 template <int D, bool LOOP, bool LD>
-__global__ __launch_bounds__(256) void k_node_solve(StepArgs a, WorkList w) {
+__device__ __forceinline__ void node_solve_body(const StepArgs &a, const WorkList &w, const Blk b) {
     const int l = threadIdx.x & (AGG_G - 1);
     const int g = threadIdx.x / AGG_G;
     const int per_pass = blockDim.x / AGG_G;
-    const int64_t nslot = gridDim.x >> 3;
+    const int64_t nslot = b.n >> 3;
     const int64_t per = (w.n_items + 7) >> 3;
-    const int64_t i0 = (int64_t)(blockIdx.x & 7u) * per;
+    const int64_t i0 = (b.id & 7) * per;
     const int64_t i1 = i0 + per < w.n_items ? i0 + per : w.n_items;
-    for (int64_t it = i0 + (blockIdx.x >> 3); it < i1; it += nslot) {
+    for (int64_t it = i0 + (b.id >> 3); it < i1; it += nslot) {
         const int64_t s0 = w.start[it];
         const int len = w.len[it];
         for (int base = g; base < len; base += per_pass) node_solve_group<D, LD>(a, s0 + base, l);
         if (!LOOP) break;
     }
+}
+template <int D, bool LOOP, bool LD>
+__global__ __launch_bounds__(256) void k_node_solve(StepArgs a, WorkList w) {
+    node_solve_body<D, LOOP, LD>(a, w, grid_blk());
 }
 
 
@@ -1122,7 +1166,7 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const double w0 = u0[i * nn + p];
-                const double w1 = p1 ? a.vhat1[i * nn + p] : 0.0;
+                const double w1 = p1 ? next_vhat(a.vstar[i * nn + p], w0) : 0.0;
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
                     L0[i][j] += w0 * g0.C[k][j];
@@ -1234,8 +1278,12 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
 }
 
 template <int D, bool LOOP, bool SG>
+__device__ __forceinline__ void update_body(const StepArgs &a, const WorkList &w, const Blk b) {
+    for_items<LOOP>(w, b, [&](int64_t c) { update_cell<D, SG>(a, c); });
+}
+template <int D, bool LOOP, bool SG>
 __global__ __launch_bounds__(256) void k_update(StepArgs a, WorkList w) {
-    for_items<LOOP>(w, [&](int64_t c) { update_cell<D, SG>(a, c); });
+    update_body<D, LOOP, SG>(a, w, grid_blk());
 }
 
 // LDS stride of a staged gather record: 18 doubles in 3D, so that the
@@ -1249,13 +1297,12 @@ constexpr int staged_gr() {
 // staged_gr doubles): the item's records are one contiguous run, copied
 // out after a barrier in 16-byte chunks in address order.
 template <int D, bool SG>
-__global__ __launch_bounds__(256) void k_update_staged(StepArgs a, WorkList w) {
+__device__ __forceinline__ void update_staged_body(const StepArgs &a, const WorkList &w, const Blk b, double *cs) {
     using Dm = Dims<D>;
     constexpr int LS = staged_gr<D>(), NPR = Dm::GR / 2;
-    extern __shared__ double cs[];
     const int64_t per = (w.n_items + 7) >> 3;
-    const int64_t slot = blockIdx.x >> 3;
-    const int64_t it = (int64_t)(blockIdx.x & 7u) * per + slot;
+    const int64_t slot = b.id >> 3;
+    const int64_t it = (b.id & 7) * per + slot;
     if (slot >= per || it >= w.n_items) return;  // the whole block
     const int64_t s0 = w.start[it];
     const int len = w.len[it];
@@ -1267,6 +1314,11 @@ __global__ __launch_bounds__(256) void k_update_staged(StepArgs a, WorkList w) {
         const int ci = q / NPR, j = q - ci * NPR;
         store_stream(&out[q], src[ci * (LS / 2) + j]);
     }
+}
+template <int D, bool SG>
+__global__ __launch_bounds__(256) void k_update_staged(StepArgs a, WorkList w) {
+    extern __shared__ double cs[];
+    update_staged_body<D, SG>(a, w, grid_blk(), cs);
 }
 
 // The cells of a MOOD pass's list, strided over the grid.  (A loop-free
@@ -1280,14 +1332,18 @@ __global__ __launch_bounds__(256) void k_update_staged(StepArgs a, WorkList w) {
 // thread of k_update_list clears the node list and advances the stamp for
 // the next pass.  k_step_begin clears every count before the first pass.
 template <int D, bool SG>
-__global__ __launch_bounds__(256) void k_update_list(StepArgs a) {
+__device__ __forceinline__ void update_list_body(const StepArgs &a, const Blk b) {
     const int64_t n = min((int64_t)a.counters[CNT_CELLS], a.nc);
-    if (gtid() == 0) {
+    if (b.tid() == 0) {
         a.counters[CNT_NODES] = 0u;
         a.counters[CNT_RECOMP] += (unsigned)n;
         *a.stamp = *a.stamp + 1;
     }
-    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) update_cell<D, SG>(a, a.clist[i]);
+    for (int64_t i = b.tid(); i < n; i += b.stride()) update_cell<D, SG>(a, a.clist[i]);
+}
+template <int D, bool SG>
+__global__ __launch_bounds__(256) void k_update_list(StepArgs a) {
+    update_list_body<D, SG>(a, grid_blk());
 }
 
 // ------------------------------------------------------ MOOD bookkeeping
@@ -1298,18 +1354,18 @@ __global__ __launch_bounds__(256) void k_update_list(StepArgs a) {
 // corner records are recomputed at that level, and its nodes are listed
 // once.  log (may be null): log[log_idx] = the input count.
 template <int D, bool LIM, bool FAM, bool SG>
-__global__ __launch_bounds__(256) void k_pass_cells(StepArgs a, const int32_t *__restrict__ list,
-                                                    const unsigned *__restrict__ count, unsigned *__restrict__ log,
-                                                    int log_idx) {
+__device__ __forceinline__ void pass_cells_body(const StepArgs &a, const int32_t *__restrict__ list,
+                                                const unsigned *__restrict__ count, unsigned *__restrict__ log,
+                                                int log_idx, const Blk b) {
     const int64_t n = min((int64_t)*count, a.nc);
     const int32_t st = *a.stamp + 1;
-    if (gtid() == 0) {
+    if (b.tid() == 0) {
         *a.fcount_out = 0u;
         a.counters[CNT_CELLS] = 0u;
         if (log) log[log_idx] = (unsigned)n;
     }
     uint8_t *mask = const_cast<uint8_t *>(a.mask);
-    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = b.tid(); i < n; i += b.stride()) {
         const int32_t c = list[i];
         mask[c] = (a.cascade == 3 && mask[c] == 0) ? 1 : 2;
         predict_cell<D, LIM, FAM, SG>(a, c);
@@ -1321,19 +1377,24 @@ __global__ __launch_bounds__(256) void k_pass_cells(StepArgs a, const int32_t *_
             wave_append(a.nlist, &a.counters[CNT_NODES], fresh[k], a.c2n[(int64_t)c * (D + 1) + k], (unsigned)a.nn);
     }
 }
+template <int D, bool LIM, bool FAM, bool SG>
+__global__ __launch_bounds__(256) void k_pass_cells(StepArgs a, const int32_t *__restrict__ list,
+                                                    const unsigned *__restrict__ count, unsigned *__restrict__ log,
+                                                    int log_idx) {
+    pass_cells_body<D, LIM, FAM, SG>(a, list, count, log, log_idx, grid_blk());
+}
 
 // Second: every listed node is solved again by a group of AGG_G lanes (the
 // cooperative gather of the full node solve, same sums), and the group
 // lists the cells around it once.
 template <int D, bool LD>
-__global__ __launch_bounds__(256) void k_pass_nodes(StepArgs a) {
-    __shared__ unsigned sh[5];
+__device__ __forceinline__ void pass_nodes_body(const StepArgs &a, const Blk bk, unsigned *sh) {
     const int64_t n = min((int64_t)a.counters[CNT_NODES], a.nn);
     const int32_t st = *a.stamp + 1;
     const int l = threadIdx.x & (AGG_G - 1);
     const int per_block = blockDim.x / AGG_G;
     // block-uniform loops (block_append synchronises the block)
-    for (int64_t b0 = (int64_t)blockIdx.x * per_block; b0 < n; b0 += (int64_t)gridDim.x * per_block) {
+    for (int64_t b0 = bk.id * per_block; b0 < n; b0 += bk.n * per_block) {
         const int64_t i = b0 + threadIdx.x / AGG_G;
         int32_t q0 = 0, q1 = 0;
         if (i < n) {
@@ -1353,14 +1414,24 @@ __global__ __launch_bounds__(256) void k_pass_nodes(StepArgs a) {
         }
     }
 }
+template <int D, bool LD>
+__global__ __launch_bounds__(256) void k_pass_nodes(StepArgs a) {
+    __shared__ unsigned sh[5];
+    pass_nodes_body<D, LD>(a, grid_blk(), sh);
+}
 
 // Start of a step: clear the counters, take the device-side dt.
-__global__ void k_step_begin(unsigned *__restrict__ counters, double *__restrict__ dt_cur,
-                             const double *__restrict__ dt_next, int n_mesh, int copy_dt) {
-    const int64_t i = gtid();
+__device__ __forceinline__ void step_begin_body(unsigned *__restrict__ counters, double *__restrict__ dt_cur,
+                                                const double *__restrict__ dt_next, int n_mesh, int copy_dt,
+                                                const Blk b) {
+    const int64_t i = b.tid();
     if (i < CNT_N) counters[i] = 0u;
     if (copy_dt)
-        for (int64_t m = i; m < n_mesh; m += (int64_t)gridDim.x * blockDim.x) dt_cur[m] = dt_next[m];
+        for (int64_t m = i; m < n_mesh; m += b.stride()) dt_cur[m] = dt_next[m];
+}
+__global__ void k_step_begin(unsigned *__restrict__ counters, double *__restrict__ dt_cur,
+                             const double *__restrict__ dt_next, int n_mesh, int copy_dt) {
+    step_begin_body(counters, dt_cur, dt_next, n_mesh, copy_dt, grid_blk());
 }
 
 // blockIdx.y picks the field; blocks stride over its elements
@@ -1373,9 +1444,10 @@ __global__ __launch_bounds__(256) void k_copy_fields(CopyFields f) {
         dst[i] = src[i];
 }
 
-__global__ void k_fill_u8(uint8_t *__restrict__ p, int64_t n, uint8_t v) {
-    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+__device__ __forceinline__ void fill_u8_body(uint8_t *__restrict__ p, int64_t n, uint8_t v, const Blk b) {
+    for (int64_t i = b.tid(); i < n; i += b.stride()) p[i] = v;
 }
+__global__ void k_fill_u8(uint8_t *__restrict__ p, int64_t n, uint8_t v) { fill_u8_body(p, n, v, grid_blk()); }
 
 // -------------------------------------------------------- reductions
 // Per-mesh minimum of non-negative doubles through their ordered bit
@@ -1399,12 +1471,13 @@ __device__ __forceinline__ double wave_min(double v) {
 // is +inf.  The minimum runs on the ordered bit patterns of non-negative
 // doubles: order independent, hence deterministic.
 constexpr int DT_TILES = 8;
-__global__ __launch_bounds__(256) void k_dt_reduce(int64_t nc, const double *__restrict__ dtc,
-                                                   const int32_t *__restrict__ cell_mesh,
-                                                   const uint8_t *__restrict__ pstat,
-                                                   double *__restrict__ red /* [n_mesh][2] */,
-                                                   double *__restrict__ part /* [nblocks][2] */,
-                                                   unsigned *__restrict__ bad_count) {
+__device__ __forceinline__ void dt_reduce_body(int64_t nc, const double *__restrict__ dtc,
+                                               const int32_t *__restrict__ cell_mesh,
+                                               const uint8_t *__restrict__ pstat,
+                                               double *__restrict__ red /* [n_mesh][2] */,
+                                               double *__restrict__ part /* [nblocks][2] */,
+                                               unsigned *__restrict__ bad_count, const Blk bk) {
+    const int64_t bid = bk.id;
     __shared__ double sa[DT_TILES][4], sv[DT_TILES][4];
     __shared__ int sbad[DT_TILES][4];
     __shared__ int smesh[DT_TILES];
@@ -1413,7 +1486,7 @@ __global__ __launch_bounds__(256) void k_dt_reduce(int64_t nc, const double *__r
     int bad[DT_TILES];
 #pragma unroll
     for (int g = 0; g < DT_TILES; ++g) {
-        const int64_t c = ((int64_t)blockIdx.x * DT_TILES + g) * 256 + threadIdx.x;
+        const int64_t c = (bid * DT_TILES + g) * 256 + threadIdx.x;
         ac[g] = vol[g] = __builtin_huge_val();
         bad[g] = 0;
         if (c < nc) {
@@ -1422,7 +1495,7 @@ __global__ __launch_bounds__(256) void k_dt_reduce(int64_t nc, const double *__r
             bad[g] = pstat[c];
         }
     }
-    const int64_t cb0 = (int64_t)blockIdx.x * DT_TILES * 256;
+    const int64_t cb0 = bid * DT_TILES * 256;
     const int64_t cb1 = min(cb0 + DT_TILES * 256, nc) - 1;
     if (!cell_mesh || cell_mesh[cb0] == cell_mesh[cb1]) {
         // the block lies in one mesh: one minimum over all its cells
@@ -1443,8 +1516,8 @@ __global__ __launch_bounds__(256) void k_dt_reduce(int64_t nc, const double *__r
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            part[2 * blockIdx.x] = fmin(fmin(sa[0][0], sa[0][1]), fmin(sa[0][2], sa[0][3]));
-            part[2 * blockIdx.x + 1] = fmin(fmin(sv[0][0], sv[0][1]), fmin(sv[0][2], sv[0][3]));
+            part[2 * bid] = fmin(fmin(sa[0][0], sa[0][1]), fmin(sa[0][2], sa[0][3]));
+            part[2 * bid + 1] = fmin(fmin(sv[0][0], sv[0][1]), fmin(sv[0][2], sv[0][3]));
             const int nb = sbad[0][0] + sbad[0][1] + sbad[0][2] + sbad[0][3];
             if (nb) atomicAdd(bad_count, (unsigned)nb);
         }
@@ -1452,7 +1525,7 @@ __global__ __launch_bounds__(256) void k_dt_reduce(int64_t nc, const double *__r
     }
 #pragma unroll
     for (int g = 0; g < DT_TILES; ++g) {
-        const int64_t first = ((int64_t)blockIdx.x * DT_TILES + g) * 256;
+        const int64_t first = (bid * DT_TILES + g) * 256;
         const int64_t c = first + threadIdx.x;
         double a = ac[g], v = vol[g];
         if (!(a >= 0.0)) a = __builtin_huge_val();
@@ -1507,18 +1580,25 @@ __global__ __launch_bounds__(256) void k_dt_reduce(int64_t nc, const double *__r
             atomic_min_pos(&red[2 * cur], am);
             atomic_min_pos(&red[2 * cur + 1], vm);
         }
-        part[2 * blockIdx.x] = __builtin_huge_val();
-        part[2 * blockIdx.x + 1] = __builtin_huge_val();
+        part[2 * bid] = __builtin_huge_val();
+        part[2 * bid + 1] = __builtin_huge_val();
         if (nb) atomicAdd(bad_count, (unsigned)nb);
     }
+}
+__global__ __launch_bounds__(256) void k_dt_reduce(int64_t nc, const double *__restrict__ dtc,
+                                                   const int32_t *__restrict__ cell_mesh,
+                                                   const uint8_t *__restrict__ pstat, double *__restrict__ red,
+                                                   double *__restrict__ part, unsigned *__restrict__ bad_count) {
+    dt_reduce_body(nc, dtc, cell_mesh, pstat, red, part, bad_count, grid_blk());
 }
 
 // Stage 2: one block per mesh reduces the partials of the stage-1 blocks
 // that hold its cells (blocks shared with another mesh left +inf).
-__global__ __launch_bounds__(256) void k_dt_reduce2(int n_mesh, const int64_t *__restrict__ mesh_cell_off,
-                                                    const double *__restrict__ part, double *__restrict__ red) {
+__device__ __forceinline__ void dt_reduce2_body(int n_mesh, const int64_t *__restrict__ mesh_cell_off,
+                                                const double *__restrict__ part, double *__restrict__ red,
+                                                const Blk b) {
     __shared__ double sa[4], sv[4];
-    const int m = blockIdx.x;
+    const int64_t m = b.id;
     if (m >= n_mesh) return;
     const int64_t c0 = mesh_cell_off[m], c1 = mesh_cell_off[m + 1];
     double ac = __builtin_huge_val(), vol = __builtin_huge_val();
@@ -1544,6 +1624,10 @@ __global__ __launch_bounds__(256) void k_dt_reduce2(int n_mesh, const int64_t *_
         atomic_min_pos(&red[2 * m + 1], fmin(fmin(sv[0], sv[1]), fmin(sv[2], sv[3])));
     }
 }
+__global__ __launch_bounds__(256) void k_dt_reduce2(int n_mesh, const int64_t *__restrict__ mesh_cell_off,
+                                                    const double *__restrict__ part, double *__restrict__ red) {
+    dt_reduce2_body(n_mesh, mesh_cell_off, part, red, grid_blk());
+}
 
 __global__ void k_fill(double *p, int64_t n, double v) {
     int64_t i = gtid();
@@ -1551,10 +1635,11 @@ __global__ void k_fill(double *p, int64_t n, double v) {
 }
 
 // dt_next = min(C_CFL min L/a, C_v dt min V1/|dV|, (1 + C_i) dt)
-__global__ void k_dt_finalize(int n_mesh, const double *__restrict__ red, const double *__restrict__ dt,
-                              double c_cfl, double c_v, double c_i, int first, double *__restrict__ dt_next,
-                              double *__restrict__ parts /* [n_mesh][2]: acoustic, volume */) {
-    int m = gtid();
+__device__ __forceinline__ void dt_finalize_body(int n_mesh, const double *__restrict__ red,
+                                                 const double *__restrict__ dt, double c_cfl, double c_v, double c_i,
+                                                 int first, double *__restrict__ dt_next,
+                                                 double *__restrict__ parts /* [n_mesh][2] */, const Blk b) {
+    const int64_t m = b.tid();
     if (m >= n_mesh) return;
     double ac = c_cfl * red[2 * m];
     double vol = c_v * dt[m] * red[2 * m + 1];
@@ -1563,6 +1648,11 @@ __global__ void k_dt_finalize(int n_mesh, const double *__restrict__ red, const 
     dt_next[m] = d;
     parts[2 * m] = ac;
     parts[2 * m + 1] = first ? __builtin_huge_val() : vol;
+}
+__global__ void k_dt_finalize(int n_mesh, const double *__restrict__ red, const double *__restrict__ dt,
+                              double c_cfl, double c_v, double c_i, int first, double *__restrict__ dt_next,
+                              double *__restrict__ parts /* [n_mesh][2]: acoustic, volume */) {
+    dt_finalize_body(n_mesh, red, dt, c_cfl, c_v, c_i, first, dt_next, parts, grid_blk());
 }
 
 // acoustic bound of the current state (initial time step)
@@ -1922,10 +2012,14 @@ void launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s) {
 }
 // Start of a CFL reduction: per-mesh minima to +inf, the inadmissible
 // count to 0 (a reduction repeated after further MOOD passes counts afresh).
-__global__ void k_reduce_begin(double *__restrict__ red, int64_t n, unsigned *__restrict__ bad_count) {
-    const int64_t i = gtid();
+__device__ __forceinline__ void reduce_begin_body(double *__restrict__ red, int64_t n, unsigned *__restrict__ bad_count,
+                                                  const Blk b) {
+    const int64_t i = b.tid();
     if (i < n) red[i] = __builtin_huge_val();
     if (i == 0) *bad_count = 0u;
+}
+__global__ void k_reduce_begin(double *__restrict__ red, int64_t n, unsigned *__restrict__ bad_count) {
+    reduce_begin_body(red, n, bad_count, grid_blk());
 }
 
 void launch_dt_reduce(int64_t nc, const double *dtc, const int32_t *cell_mesh, const uint8_t *pstat, double *red,
@@ -1970,6 +2064,194 @@ void launch_gather_u8(int64_t n, const uint8_t *in, const int32_t *idx, uint8_t 
 template <int D>
 void launch_stress_query(const StepArgs &a, const int32_t *idx, double *out, hipStream_t s) {
     if (a.nc) k_stress_query<D><<<nblk(a.nc), 256, 0, s>>>(a, idx, out);
+}
+
+// ------------------------------------------------- paired launches
+// The stages of a 2D and a 3D context in one launch (hl_group_step): blocks
+// [0, g0) run the first part, the rest the second, each on its own arguments
+// and work list exactly as its own launch would.  Every body is the one the
+// single-context kernels run, so the results are bitwise theirs.  Parts run
+// the base configuration: neo-Hookean law, two-level cascade, no boundary
+// loads (the host checks this).
+template <class F0, class F1>
+__global__ __launch_bounds__(256) void k_pair(F0 f0, int64_t g0, F1 f1) {
+    extern __shared__ double dyn[];
+    if ((int64_t)blockIdx.x < g0)
+        f0(Blk{(int64_t)blockIdx.x, g0}, dyn);
+    else
+        f1(Blk{(int64_t)blockIdx.x - g0, (int64_t)gridDim.x - g0}, dyn);
+}
+
+namespace {
+template <int D, bool LOOP>
+struct FNodeAgg {
+    StepArgs a;
+    WorkList w;
+    __device__ void operator()(Blk b, double *sh) const { node_agg_body<D, LOOP>(a, w, b, sh); }
+};
+template <int D, bool LOOP>
+struct FPredict {
+    StepArgs a;
+    WorkList w;
+    __device__ void operator()(Blk b, double *sh) const {
+        if (LOOP)
+            predict_body<D, true, false, false, false>(a, w, b);
+        else
+            predict_staged_body<D, false, false, false>(a, w, b, sh);
+    }
+};
+template <int D, bool LOOP>
+struct FNodeSolve {
+    StepArgs a;
+    WorkList w;
+    __device__ void operator()(Blk b, double *) const { node_solve_body<D, LOOP, false>(a, w, b); }
+};
+template <int D, bool LOOP>
+struct FUpdate {
+    StepArgs a;
+    WorkList w;
+    __device__ void operator()(Blk b, double *sh) const {
+        if (LOOP)
+            update_body<D, true, false>(a, w, b);
+        else
+            update_staged_body<D, false>(a, w, b, sh);
+    }
+};
+template <int D>
+struct FPassCells {
+    StepArgs a;
+    const int32_t *list;
+    const unsigned *count;
+    unsigned *log;
+    int log_idx;
+    __device__ void operator()(Blk b, double *) const {
+        pass_cells_body<D, false, false, false>(a, list, count, log, log_idx, b);
+    }
+};
+template <int D>
+struct FPassNodes {
+    StepArgs a;
+    __device__ void operator()(Blk b, double *sh) const {
+        pass_nodes_body<D, false>(a, b, reinterpret_cast<unsigned *>(sh));
+    }
+};
+template <int D>
+struct FUpdateList {
+    StepArgs a;
+    __device__ void operator()(Blk b, double *) const { update_list_body<D, false>(a, b); }
+};
+// start of a step: counters, device dt, and the cascade levels to 0
+struct FBegin {
+    PairBook k;
+    __device__ void operator()(Blk b, double *) const {
+        step_begin_body(k.counters, k.dt_cur, k.dt_next, k.n_mesh, k.copy_dt, b);
+        fill_u8_body(k.mask, k.nc, 0, b);
+    }
+};
+struct FReduceBegin {
+    PairBook k;
+    __device__ void operator()(Blk b, double *) const { reduce_begin_body(k.red, 2 * k.n_mesh, k.bad_count, b); }
+};
+struct FDtReduce {
+    PairBook k;
+    __device__ void operator()(Blk b, double *) const {
+        dt_reduce_body(k.nc, k.dtc, k.cell_mesh, k.pstat, k.red, k.part, k.bad_count, b);
+    }
+};
+struct FDtReduce2 {
+    PairBook k;
+    __device__ void operator()(Blk b, double *) const { dt_reduce2_body(k.n_mesh, k.mesh_cell_off, k.part, k.red, b); }
+};
+struct FDtFinalize {
+    PairBook k;
+    __device__ void operator()(Blk b, double *) const {
+        dt_finalize_body(k.n_mesh, k.red, k.dt_cur, k.c_cfl, k.c_v, k.c_i, 0, k.dt_next, k.parts, b);
+    }
+};
+
+unsigned round8(int64_t n) { return (unsigned)((n + 7) & ~(int64_t)7); }
+
+// one paired launch: part grids g0, g1 (either may be 0), one block size
+template <class F0, class F1>
+void pair_launch(const F0 &f0, unsigned g0, const F1 &f1, unsigned g1, unsigned block, size_t lds, hipStream_t s) {
+    if (g0 + g1 == 0) return;
+    k_pair<F0, F1><<<g0 + g1, block, lds, s>>>(f0, (int64_t)g0, f1);
+}
+
+// a cell or node stage whose body is F<D, LOOP> on each part's schedule
+template <template <int, bool> class F>
+void pair_stage(const StepArgs &a2, const Sched &k2, const StepArgs &a3, const Sched &k3, size_t lds,
+                hipStream_t s) {
+    const unsigned g2 = k2.w.n_items ? k2.grid : 0, g3 = k3.w.n_items ? k3.grid : 0;
+    const unsigned block = g2 ? k2.block : k3.block;
+    if (k2.loop) {
+        if (k3.loop)
+            pair_launch(F<2, true>{a2, k2.w}, g2, F<3, true>{a3, k3.w}, g3, block, lds, s);
+        else
+            pair_launch(F<2, true>{a2, k2.w}, g2, F<3, false>{a3, k3.w}, g3, block, lds, s);
+    } else {
+        if (k3.loop)
+            pair_launch(F<2, false>{a2, k2.w}, g2, F<3, true>{a3, k3.w}, g3, block, lds, s);
+        else
+            pair_launch(F<2, false>{a2, k2.w}, g2, F<3, false>{a3, k3.w}, g3, block, lds, s);
+    }
+}
+}  // namespace
+
+void launch_node_agg_pair(const StepArgs &a2, const Sched &k2, const StepArgs &a3, const Sched &k3, hipStream_t s) {
+    const size_t lds = sizeof(double) * (size_t)std::max(agg_lds_doubles<2>(), agg_lds_doubles<3>());
+    pair_stage<FNodeAgg>(a2, k2, a3, k3, lds, s);
+}
+void launch_predict_pair(const StepArgs &a2, const Sched &k2, const StepArgs &a3, const Sched &k3, hipStream_t s) {
+    const size_t lds = sizeof(double) * (size_t)std::max(k2.block, k3.block) * std::max(3 * Dims<2>::CW, 4 * Dims<3>::CW);
+    pair_stage<FPredict>(a2, k2, a3, k3, lds, s);
+}
+void launch_node_solve_pair(const StepArgs &a2, const Sched &k2, const StepArgs &a3, const Sched &k3,
+                            hipStream_t s) {
+    pair_stage<FNodeSolve>(a2, k2, a3, k3, 0, s);
+}
+void launch_update_pair(const StepArgs &a2, const Sched &k2, const StepArgs &a3, const Sched &k3, hipStream_t s) {
+    const size_t lds = sizeof(double) * (size_t)std::max(k2.block, k3.block) * std::max(staged_gr<2>(), staged_gr<3>());
+    pair_stage<FUpdate>(a2, k2, a3, k3, lds, s);
+}
+void launch_mood_sparse_pair(const StepArgs &a2, const PairPass &p2, const StepArgs &a3, const PairPass &p3,
+                             bool fixed_grid, int log_idx, hipStream_t s) {
+    // the grids of launch_mood_sparse, per part
+    const int64_t gmax = fixed_grid ? 1024 : 16384;
+    auto grid = [gmax](int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, gmax)); };
+    auto shape = [&](const StepArgs &a, const PairPass &p, int d, unsigned g[3]) {
+        const int64_t nflag = fixed_grid ? std::min<int64_t>(a.nc, 256 * 1024) : p.nflag;
+        const int64_t nnodes = std::min<int64_t>(a.nn, (d + 1) * nflag);
+        const int64_t ncells = std::min<int64_t>(a.nc, nnodes * p.max_deg);
+        g[0] = round8(grid(nflag));
+        g[1] = round8(grid(AGG_G * nnodes));
+        g[2] = round8(grid(ncells));
+    };
+    unsigned g2[3], g3[3];
+    shape(a2, p2, 2, g2);
+    shape(a3, p3, 3, g3);
+    pair_launch(FPassCells<2>{a2, p2.flist, p2.fcount, p2.log, log_idx}, g2[0],
+                FPassCells<3>{a3, p3.flist, p3.fcount, p3.log, log_idx}, g3[0], 256, 0, s);
+    pair_launch(FPassNodes<2>{a2}, g2[1], FPassNodes<3>{a3}, g3[1], 256, sizeof(double) * 4, s);
+    pair_launch(FUpdateList<2>{a2}, g2[2], FUpdateList<3>{a3}, g3[2], 256, 0, s);
+}
+void launch_step_begin_pair(const PairBook &b2, const PairBook &b3, hipStream_t s) {
+    auto g = [](const PairBook &b) {
+        return round8(std::min<int64_t>(std::max<int64_t>(nblk(std::max<int64_t>(b.nc, b.n_mesh)), 1), 4096));
+    };
+    pair_launch(FBegin{b2}, g(b2), FBegin{b3}, g(b3), 256, 0, s);
+}
+void launch_dt_reduce_pair(const PairBook &b2, const PairBook &b3, hipStream_t s) {
+    auto gb = [](const PairBook &b) { return round8(nblk(2 * b.n_mesh)); };
+    pair_launch(FReduceBegin{b2}, gb(b2), FReduceBegin{b3}, gb(b3), 256, 0, s);
+    // exact grids: a block past the cells would read past them (the
+    // reduction does not use the XCD grouping)
+    auto gr = [](const PairBook &b) { return (unsigned)((b.nc + 256 * DT_TILES - 1) / (256 * DT_TILES)); };
+    pair_launch(FDtReduce{b2}, gr(b2), FDtReduce{b3}, gr(b3), 256, 0, s);
+    auto g2 = [](const PairBook &b) { return b.nc ? (unsigned)b.n_mesh : 0u; };
+    pair_launch(FDtReduce2{b2}, g2(b2), FDtReduce2{b3}, g2(b3), 256, 0, s);
+    auto gf = [](const PairBook &b) { return round8(nblk(b.n_mesh)); };
+    pair_launch(FDtFinalize{b2}, gf(b2), FDtFinalize{b3}, gf(b3), 256, 0, s);
 }
 
 template void launch_centroids<2>(const StepArgs &, const Sched &, hipStream_t);

@@ -29,7 +29,8 @@ EXPORTS = ["hl_create", "hl_destroy", "hl_mesh_upload", "hl_state_init", "hl_set
            "hl_set_schedule", "hl_get_schedule", "hl_autotune", "hl_set_boundary_loads",
            "hl_set_contact", "hl_get_contact", "hl_mesh_refine", "hl_mesh_info", "hl_mesh_get",
            "hl_set_numbering", "hl_mesh_check", "hl_state_save", "hl_state_restore",
-           "hl_acoustic_dt_noalloc"]
+           "hl_acoustic_dt_noalloc", "hl_group_create", "hl_group_destroy", "hl_group_use_graph",
+           "hl_group_step"]
 
 # internal numbering of uploaded meshes (hl_set_numbering)
 NUMBERING_KEEP, NUMBERING_SPATIAL = 0, 1
@@ -144,6 +145,10 @@ def load():
     L.hl_state_save.argtypes = [vp, vp, C.POINTER(i64)]
     L.hl_state_restore.argtypes = [vp, vp, i64]
     L.hl_acoustic_dt_noalloc.argtypes = [C.c_int, vp, C.c_int, i64, vp, i64, vp, vp, vp, vp, vp, dp, vp]
+    L.hl_group_create.argtypes = [C.POINTER(vp), vp, vp]
+    L.hl_group_destroy.argtypes = [vp]
+    L.hl_group_use_graph.argtypes = [vp, C.c_int, C.c_int]
+    L.hl_group_step.argtypes = [vp, vp, vp]
     for name in EXPORTS:
         if name not in ("hl_status_str", "hl_last_error"):
             getattr(L, name).restype = C.c_int
@@ -154,8 +159,10 @@ def load():
 def _check(rc, what):
     if rc < 0:
         msg = load().hl_status_str(rc).decode()
-        if rc == -5:
-            msg += ": " + load().hl_last_error().decode()
+        detail = load().hl_last_error().decode()
+        # HIP errors carry their detail; so does an invalid group
+        if rc == -5 or (rc == -1 and what.startswith("hl_group") and detail):
+            msg += ": " + detail
         raise HyperLagError(f"{what} failed: {msg} ({rc})")
     return rc
 
@@ -507,6 +514,43 @@ class Context:
         _check(load().hl_profile_get(self._h, name.encode(), C.byref(ms), C.byref(n)),
                "hl_profile_get")
         return ms.value, n.value
+
+
+class Group:
+    """A 2D and a 3D context stepped together (hl_group_*): each stage, MOOD
+    pass and CFL reduction of the two is one kernel launch.  Holds
+    references to both contexts, so they outlive it."""
+
+    def __init__(self, ctx_2d, ctx_3d):
+        self._h = C.c_void_p()
+        self.contexts = (ctx_2d, ctx_3d)
+        _check(load().hl_group_create(C.byref(self._h), ctx_2d._h, ctx_3d._h), "hl_group_create")
+
+    def close(self):
+        if self._h:
+            load().hl_group_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def use_graph(self, on=True, max_mood_passes=6):
+        _check(load().hl_group_use_graph(self._h, 1 if on else 0, int(max_mood_passes)), "hl_group_use_graph")
+
+    def step(self, info=True):
+        """One step of both contexts on their device-held dt; returns the
+        two step reports (2D, 3D)."""
+        i2 = StepInfo() if info else None
+        i3 = StepInfo() if info else None
+        rc = _check(load().hl_group_step(self._h, C.byref(i2) if info else None, C.byref(i3) if info else None),
+                    "hl_group_step")
+        out = (i2.as_dict() if info else {}, i3.as_dict() if info else {})
+        for o in out:
+            o["rc"] = rc
+        return out
 
 
 def from_workloads(ws, device=0, stream=None, params=None):

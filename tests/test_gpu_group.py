@@ -1,0 +1,106 @@
+"""Groups (hl_group_*): a 2D batch context and a 3D batch context stepped
+together, every stage, MOOD pass and CFL reduction of the two as one kernel
+launch.  Each context's steps must equal, bitwise, the same context stepped
+alone (and hence the oracle, through the batch and single-mesh parity
+tests), eagerly and as a captured graph, also when one context has flagged
+cells and the other none, and after a context changes its parameters."""
+import numpy as np
+import pytest
+
+from paper_2104_02139_amd import hyperlag as H
+from paper_2104_02139_amd import workloads as W
+
+from .parity_util import FIELDS
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("dt_used", "dt_next", "mood_iters", "n_p0", "n_flag_first", "n_recomputed", "energy", "mass", "n_detB")
+
+
+def _family(dim):
+    if dim == 3:
+        ws = [W.impact_bar_3d(nx=10, ny=3, graded=False, seed=2), W.rotating_cube_3d(n=3, seed=1),
+              W.rotating_cube_3d(n=5, seed=3)]
+        ws[2].mu = ws[2].mu * 1.7
+    else:
+        ws = [W.plane_wave_2d(n=6, amp=0.02, seed=5), W.plane_wave_2d(n=17, seed=6),
+              W.swinging_plate_2d(n=5, seed=7)]
+        ws[1].rho0 = ws[1].rho0 * 2.0
+    return ws
+
+
+def _pair():
+    return H.from_workloads(_family(2)), H.from_workloads(_family(3))
+
+
+def _same(a, b, tag):
+    sa, sb = a.state(), b.state()
+    for f in FIELDS:
+        assert np.array_equal(sa[f], sb[f]), (tag, f)
+    assert np.array_equal(a.query("order"), b.query("order")), tag
+    assert np.array_equal(a.next_dt(), b.next_dt()), tag
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_group_equals_contexts_stepped_alone(graph):
+    g2, g3 = _pair()
+    r2, r3 = _pair()
+    for c in (g2, g3, r2, r3):
+        c.compute_dt()
+    grp = H.Group(g2, g3)
+    grp.use_graph(graph, 2)   # few captured passes: the eager finish runs too
+    moods = [0, 0]
+    for k in range(10):
+        i2, i3 = grp.step()
+        j2 = r2.step_batch(None)
+        j3 = r3.step_batch(None)
+        for key in KEYS:
+            assert i2[key] == j2[key], (k, "2D", key)
+            assert i3[key] == j3[key], (k, "3D", key)
+        moods[0] += i2["n_p0"]
+        moods[1] += i3["n_p0"]
+    print(f"[group] first-order cells over the steps: 2D {moods[0]}, 3D {moods[1]}", flush=True)
+    assert moods[1] > 0, "the 3D family should exercise MOOD"
+    _same(g2, r2, "2D")
+    _same(g3, r3, "3D")
+
+
+def test_group_recaptures_after_a_parameter_change():
+    g2, g3 = _pair()
+    r2, r3 = _pair()
+    for c in (g2, g3, r2, r3):
+        c.compute_dt()
+    grp = H.Group(g2, g3)
+    grp.use_graph(True, 6)
+    for _ in range(3):
+        grp.step(info=False)
+        r2.step_batch(None, info=False)
+        r3.step_batch(None, info=False)
+    for c in (g3, r3):
+        c.set_params(H.default_params(3, c_cfl=0.2))
+    for _ in range(3):
+        grp.step(info=False)
+        r2.step_batch(None, info=False)
+        r3.step_batch(None, info=False)
+    _same(g2, r2, "2D")
+    _same(g3, r3, "3D")
+
+
+def test_group_rejects_what_it_does_not_pair():
+    g2, g3 = _pair()
+    with pytest.raises(H.HyperLagError):
+        H.Group(g3, g2)       # dimensions swapped
+    with pytest.raises(H.HyperLagError):
+        H.Group(g3, g3)
+    grp = H.Group(g2, g3)
+    g3.set_params(H.default_params(3, cascade=3))
+    with pytest.raises(H.HyperLagError, match="cascade"):
+        grp.step()
+    g3.set_params(H.default_params(3))
+    g3.set_schedule("update", tile=128, block=128)
+    with pytest.raises(H.HyperLagError, match="block size"):
+        grp.step()
+    g3.set_schedule("update", tile=256, block=256)
+    g2.compute_dt()
+    g3.compute_dt()
+    grp.step()

@@ -56,10 +56,13 @@ def _family():
 
 def test_default_schedules():
     ctx = H.from_workload(_bar())
+    want = {"pack": dict(tile=256, block=256, blocks_per_cu=0),
+            "node_agg": dict(tile=64, block=256, blocks_per_cu=0),
+            "predict": dict(tile=64, block=64, blocks_per_cu=0),
+            "node_solve": dict(tile=32, block=256, blocks_per_cu=0),
+            "update": dict(tile=256, block=256, blocks_per_cu=0)}
     for stage in H.STAGES:
-        want = (dict(tile=32, block=256, blocks_per_cu=0) if stage in ("node_agg", "node_solve")
-                else dict(tile=256, block=256, blocks_per_cu=0))
-        assert ctx.get_schedule(stage) == want, stage
+        assert ctx.get_schedule(stage) == want[stage], stage
 
 
 @pytest.mark.parametrize("sched", range(len(SCHEDULES)))
