@@ -2498,6 +2498,11 @@ struct hl_group {
     hipGraph_t graph[2][2] = {};
     hipGraphExec_t gexec[2][2] = {};
     uint64_t gen[2][2][2] = {};
+    // continuation: CONT_PASSES more paired passes, per buffer parities and
+    // parity of the input flag lists
+    hipGraph_t cgraph[2][2][2] = {};
+    hipGraphExec_t cexec[2][2][2] = {};
+    uint64_t cgen[2][2][2][2] = {};
 };
 
 namespace {
@@ -2509,6 +2514,12 @@ void group_drop_graphs(hl_group *g) {
             if (g->graph[i][j]) (void)hipGraphDestroy(g->graph[i][j]);
             g->gexec[i][j] = nullptr;
             g->graph[i][j] = nullptr;
+            for (int f = 0; f < 2; ++f) {
+                if (g->cexec[i][j][f]) (void)hipGraphExecDestroy(g->cexec[i][j][f]);
+                if (g->cgraph[i][j][f]) (void)hipGraphDestroy(g->cgraph[i][j][f]);
+                g->cexec[i][j][f] = nullptr;
+                g->cgraph[i][j][f] = nullptr;
+            }
         }
 }
 
@@ -2620,6 +2631,23 @@ hl_status group_capture(hl_group *g, int s0, int s1) {
     return HL_OK;
 }
 
+// CONT_PASSES paired passes from input list parity fb, captured
+hl_status group_capture_cont(hl_group *g, int s0, int s1, int fb) {
+    if (!g->cap_stream) HIPCHK(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = g->cap_stream;
+    hl::StepArgs a[2] = {make_args(g->c[0], s0), make_args(g->c[1], s1)};
+    const int64_t zero[2] = {0, 0};
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int p = 0; p < CONT_PASSES; ++p) group_pass(g, a, fb ^ (p & 1), 64 + p, zero, true, cs);
+    hipGraph_t gr = nullptr;
+    HIPCHK(hipStreamEndCapture(cs, &gr));
+    g->cgraph[s0][s1][fb] = gr;
+    HIPCHK(hipGraphInstantiate(&g->cexec[s0][s1][fb], gr, nullptr, nullptr, 0));
+    g->cgen[s0][s1][fb][0] = g->c[0]->gen;
+    g->cgen[s0][s1][fb][1] = g->c[1]->gen;
+    return HL_OK;
+}
+
 hl_status group_step(hl_group *g, hl_step_info *info0, hl_step_info *info1) {
     hl_ctx *c[2] = {g->c[0], g->c[1]};
     hl_status st;
@@ -2688,9 +2716,31 @@ hl_status group_step(hl_group *g, hl_step_info *info0, hl_step_info *info1) {
             for (int p = 0; p < np; ++p) iters[i] += log[i][p] > 0;
         }
         if (more()) {
-            // the captured passes did not reach the fixpoint: further passes
-            // eagerly, then the reduction again
-            if ((st = eager_passes()) != HL_OK) return st;
+            // the captured passes did not reach the fixpoint: captured blocks
+            // of CONT_PASSES paired passes (a pass with no input exits at
+            // once) until no cell is flagged, then the reduction again
+            while (more()) {
+                hipGraphExec_t &ce = g->cexec[src[0]][src[1]][fb];
+                const uint64_t *cg = g->cgen[src[0]][src[1]][fb];
+                if (ce && (cg[0] != c[0]->gen || cg[1] != c[1]->gen)) {
+                    (void)hipGraphExecDestroy(ce);
+                    (void)hipGraphDestroy(g->cgraph[src[0]][src[1]][fb]);
+                    ce = nullptr;
+                    g->cgraph[src[0]][src[1]][fb] = nullptr;
+                }
+                if (!ce && (st = group_capture_cont(g, src[0], src[1], fb)) != HL_OK) return st;
+                HIPCHK(hipGraphLaunch(ce, s));
+                unsigned clog[2][CONT_PASSES];
+                for (int i = 0; i < 2; ++i) {
+                    c[i]->stamp_host += CONT_PASSES;
+                    HIPCHK(hipMemcpyAsync(clog[i], c[i]->pass_log + 64, sizeof clog[i], hipMemcpyDeviceToHost, s));
+                }
+                if ((st = group_read_counters(g, s)) != HL_OK) return st;
+                for (int i = 0; i < 2; ++i) {
+                    for (int p = 0; p < CONT_PASSES; ++p) iters[i] += clog[i][p] > 0;
+                    nflag[i] = c[i]->counters_host[hl::CNT_F0 + fb];
+                }
+            }
             hl::launch_dt_reduce_pair(pair_book(c[0]), pair_book(c[1]), s);
             if ((st = group_read_counters(g, s)) != HL_OK) return st;
         }

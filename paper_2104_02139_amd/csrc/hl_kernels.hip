@@ -739,11 +739,9 @@ __global__ __launch_bounds__(256) void k_predict_staged(StepArgs a, WorkList w) 
 }
 
 // x^{n+1} = x^n + dt v* (reading R13) and vhat^{n+1} = 2 v* - vhat^n (R9),
-// as one fused multiply-add and one exact doubling.  The node solve stores
-// both; the cell update recomputes vhat^{n+1} from the vhat^n and v* it
-// gathers anyway (one node vector fewer, the same bits).  Recomputing
-// x^{n+1} too raised the update from 166 to 182 VGPRs (3 to 2 waves per
-// SIMD), so it gathers x^{n+1}.
+// as one fused multiply-add and one exact doubling.  (The cell update
+// gathers vhat^{n+1}: recomputing it there from v* and vhat^n gave the same
+// bits but took the update from 1.14 to 1.23 ms on the 8.1M-tet bar.)
 __device__ __forceinline__ double next_position(double x, double dt, double vs) { return __fma_rn(dt, vs, x); }
 __device__ __forceinline__ double next_vhat(double vs, double vh) { return 2.0 * vs - vh; }
 
@@ -1166,7 +1164,7 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const double w0 = u0[i * nn + p];
-                const double w1 = p1 ? next_vhat(a.vstar[i * nn + p], w0) : 0.0;
+                const double w1 = p1 ? a.vhat1[i * nn + p] : 0.0;
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
                     L0[i][j] += w0 * g0.C[k][j];
