@@ -159,6 +159,12 @@ struct hl_ctx {
         double *cadj = nullptr, *nadj = nullptr, *cell = nullptr, *agg = nullptr, *xadj = nullptr;
         double *mu_bar = nullptr, *out = nullptr;
         double *dtn = nullptr;  // dt_next after the last recorded step [n_mesh]
+        // forward intermediates of the steps of one segment (node
+        // aggregates, corner records, v*), inter_sz doubles per step, kept
+        // by the segment's replay for its reverse steps; null when they do
+        // not fit the budget (the reverse steps then recompute them)
+        double *inter = nullptr;
+        size_t inter_sz = 0;
         std::vector<void *> mem;
     } tape;
 };
@@ -229,6 +235,8 @@ void free_tape(hl_ctx *c) {
     c->tape.lam[0] = c->tape.lam[1] = nullptr;
     c->tape.cadj = c->tape.nadj = c->tape.cell = c->tape.agg = c->tape.xadj = c->tape.mu_bar = c->tape.out = nullptr;
     c->tape.dtn = nullptr;
+    c->tape.inter = nullptr;
+    c->tape.inter_sz = 0;
 }
 
 void free_loads(hl_ctx *c) {
@@ -686,7 +694,9 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
         HIPCHK(hipMemcpyAsync(c->mask, replay_mask, (size_t)c->nc,
                               mask_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         a.detect = 0;
-        a.limited = 2;  // the given levels may include the limited one
+        // a caller's levels may include the limited one; the adjoint's
+        // replays (quick) repeat recorded two-level choices (levels 0 and 2)
+        a.limited = quick && c->prm.cascade != 3 ? 0 : 2;
     }
     {
         hl_status st = ensure_scheds(c);
@@ -1029,6 +1039,43 @@ hl::AdjArgs adj_args(hl_ctx *c, int in) {
     return j;
 }
 
+// node aggregates the step writes (no limiter bounds, no gas sums: the
+// adjoint runs neither)
+template <int D>
+constexpr size_t kAggBase = hl::Dims<D>::NA_BASE;
+
+// Save (to_tape) or point at the forward intermediates of step n of the
+// current segment (slot k): the node aggregates, corner records and v*.
+template <int D>
+hl_status save_inter(hl_ctx *c, int k) {
+    auto &t = c->tape;
+    const size_t nn = c->nn, nc = c->nc;
+    const size_t na = kAggBase<D> * nn, ncr = (nc + 255) / 256 * 256 * (D + 1) * hl::Dims<D>::CW;
+    double *dst = t.inter + (size_t)k * t.inter_sz;
+    hl::CopyFields f{};
+    f.src[0] = c->agg;
+    f.dst[0] = dst;
+    f.n[0] = (int64_t)na;
+    f.src[1] = c->corner;
+    f.dst[1] = dst + na;
+    f.n[1] = (int64_t)ncr;
+    f.src[2] = c->vstar;
+    f.dst[2] = dst + na + ncr;
+    f.n[2] = (int64_t)(D * nn);
+    hl::launch_copy_fields(f, c->stream);
+    return HL_OK;
+}
+template <int D>
+void inter_args(hl_ctx *c, int k, hl::StepArgs &a) {
+    auto &t = c->tape;
+    const size_t nn = c->nn, nc = c->nc;
+    const size_t na = kAggBase<D> * nn, ncr = (nc + 255) / 256 * 256 * (D + 1) * hl::Dims<D>::CW;
+    double *src = t.inter + (size_t)k * t.inter_sz;
+    a.agg = src;
+    a.corner = src + na;
+    a.vstar = src + na + ncr;
+}
+
 template <int D>
 hl_status forward_record(hl_ctx *c, int nsteps, int every) {
     free_tape(c);
@@ -1053,6 +1100,19 @@ hl_status forward_record(hl_ctx *c, int nsteps, int every) {
     if ((st = talloc(c, &t.mu_bar, nc)) != HL_OK) return st;
     if ((st = talloc(c, &t.out, std::max(nn, nc) * 3)) != HL_OK) return st;
     if ((st = talloc(c, &t.dtn, (size_t)c->n_mesh)) != HL_OK) return st;
+    {
+        // the segment's forward intermediates, if they fit 8 GiB
+        t.inter_sz = kAggBase<D> * nn + (nc + 255) / 256 * 256 * (D + 1) * hl::Dims<D>::CW + D * nn;
+        const size_t n_inter = t.inter_sz * (size_t)every;
+        void *q = nullptr;
+        if (sizeof(double) * n_inter <= (size_t(8) << 30) && hipMalloc(&q, sizeof(double) * n_inter) == hipSuccess) {
+            t.mem.push_back(q);
+            t.inter = static_cast<double *>(q);
+        } else {
+            (void)hipGetLastError();  // a refused allocation is not an error here
+            t.inter = nullptr;
+        }
+    }
     for (int n = 0; n < nsteps; ++n) {
         if (n % every == 0) {
             if ((st = copy_state(c, c->cur, t.ckpt + (size_t)(n / every) * t.state_sz, true)) != HL_OK) return st;
@@ -1108,12 +1168,42 @@ hl_status adjoint_run(hl_ctx *c, const double *dLdx, double *dLdmu, double *dLdv
         c->rec_valid = false;
         for (int n = s0; n < s1; ++n) {
             if ((st = copy_state(c, c->cur, t.seg + (size_t)(n - s0) * t.state_sz, true)) != HL_OK) return st;
-            if (n + 1 < s1 && (st = replay_recorded<D>(c, n)) != HL_OK) return st;
+            // with room for them, the replay also runs the segment's last
+            // step and keeps every step's intermediates
+            if (t.inter || n + 1 < s1) {
+                if ((st = replay_recorded<D>(c, n)) != HL_OK) return st;
+                if (t.inter && (st = save_inter<D>(c, n - s0)) != HL_OK) return st;
+            }
         }
         for (int n = s1 - 1; n >= s0; --n) {
             if ((st = copy_state(c, 0, t.seg + (size_t)(n - s0) * t.state_sz, false)) != HL_OK) return st;
-            recompute_step<D>(c, n);
-            hl::launch_adjoint_step<D>(make_args(c, 0), adj_args(c, in), s);
+            hl::StepArgs a;
+            if (t.inter) {
+                // the step's dt, cascade levels and intermediates from the
+                // replay; x^{n+1} and vhat^{n+1} from the next state held
+                HIPCHK(hipMemcpyAsync(c->dt_cur, t.dts + (size_t)n * c->n_mesh, sizeof(double) * c->n_mesh,
+                                      hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(c->mask, t.masks + (size_t)n * c->nc, (size_t)c->nc, hipMemcpyDeviceToDevice,
+                                      s));
+                a = make_args(c, 0);
+                inter_args<D>(c, n - s0, a);
+                const double *next = n + 1 < s1 ? t.seg + (size_t)(n + 1 - s0) * t.state_sz
+                                                : t.ckpt + (size_t)(seg + 1) * t.state_sz;
+                // the candidate of step n is state n + 1, laid out as in
+                // copy_state: x, vhat, tau, v, e, B
+                const size_t nn = c->nn, nc = c->nc;
+                double *nx = const_cast<double *>(next);
+                a.x1 = nx;
+                a.vhat1 = nx + D * nn;
+                a.tau1 = nx + 2 * D * nn;
+                a.v1 = nx + 2 * D * nn + nc;
+                a.e1 = nx + 2 * D * nn + (1 + D) * nc;
+                a.B1 = nx + 2 * D * nn + (2 + D) * nc;
+            } else {
+                recompute_step<D>(c, n);
+                a = make_args(c, 0);
+            }
+            hl::launch_adjoint_step<D>(a, adj_args(c, in), s);
             in = 1 - in;
         }
     }
