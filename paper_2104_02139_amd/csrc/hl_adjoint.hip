@@ -288,12 +288,26 @@ __global__ __launch_bounds__(256) void k_adj_node1(StepArgs a, AdjArgs j) {
 }
 
 // ------------------------------------------------------------------ A3
+// The reverse corner loop's accumulators (W0bar, gradbar) live in LDS, a
+// column per thread: in registers, next to the forward values, they made
+// the kernel spill.
+constexpr int ADJ_PB = 128;   // threads per block of k_adj_predict
+
 template <int D>
-__global__ __launch_bounds__(256) void k_adj_predict(StepArgs a, AdjArgs j) {
+__global__ __launch_bounds__(ADJ_PB) void k_adj_predict(StepArgs a, AdjArgs j) {
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
     constexpr int NMS = Dm::NMS;
     constexpr int NW = Dm::NW;
+    constexpr int NACC = Dims<D>::NW * (D + 1) + 2 * (D + 1) * D;
+    __shared__ double acc_lds[ADJ_PB * NACC];
+    double *acc = acc_lds + threadIdx.x;
+    auto W0b = [&](int w) -> double & { return acc[w * ADJ_PB]; };
+    auto gradb = [&](int w, int q) -> double & { return acc[(Dims<D>::NW + w * D + q) * ADJ_PB]; };
+    auto Cb = [&](int k, int q) -> double & { return acc[(Dims<D>::NW * (D + 1) + k * D + q) * ADJ_PB]; };
+    auto Xb = [&](int k, int q) -> double & {
+        return acc[(Dims<D>::NW * (D + 1) + (D + 1) * D + k * D + q) * ADJ_PB];
+    };
     const int64_t c = tid();
     if (c >= a.nc) return;
     const int64_t nc = a.nc, nn = a.nn;
@@ -434,7 +448,8 @@ __global__ __launch_bounds__(256) void k_adj_predict(StepArgs a, AdjArgs j) {
             for (int q = i; q < D; ++q) S[midx<D>(i, q)] += g.C[jj][i] * g.C[jj][q] / g.cn[jj];
 
     // ---- reverse over the corners
-    double W0b[NW] = {}, gradb[NW][D] = {}, Cb[NV][D] = {}, Xb[NV][D] = {}, xcb[D] = {};
+    for (int e = 0; e < NACC; ++e) acc[e * ADJ_PB] = 0.0;
+    double xcb[D] = {};
     double mub = 0.0, Kb = 0.0;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -489,7 +504,7 @@ __global__ __launch_bounds__(256) void k_adj_predict(StepArgs a, AdjArgs j) {
             double s = 0.0;
 #pragma unroll
             for (int i = 0; i < D; ++i) s += rb[i] * T[sidx(i, q)];
-            Cb[k][q] -= s;
+            Cb(k, q) -= s;
         }
         // M = z N
         double zb = 0.0, Nb[NMS];
@@ -502,7 +517,12 @@ __global__ __launch_bounds__(256) void k_adj_predict(StepArgs a, AdjArgs j) {
 #pragma unroll
         for (int jj = 0; jj < NV; ++jj) {
             if (jj == k) continue;
-            outer_norm_vjp<D>(g.C[jj], Nb, Cb[jj]);
+            double cbj[D];
+#pragma unroll
+            for (int q = 0; q < D; ++q) cbj[q] = Cb(jj, q);
+            outer_norm_vjp<D>(g.C[jj], Nb, cbj);
+#pragma unroll
+            for (int q = 0; q < D; ++q) Cb(jj, q) = cbj[q];
         }
         double taub = 0.0, bkb[6] = {0, 0, 0, 0, 0, 0};
         impedance_vjp(rho0, mu, K, Wk[0], zb, taub, mub, Kb);
@@ -514,17 +534,17 @@ __global__ __launch_bounds__(256) void k_adj_predict(StepArgs a, AdjArgs j) {
 #pragma unroll
         for (int q = 0; q < Dm::NB; ++q) Wkb[1 + D + q] = bkb[slot<D>(q)];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) W0b[w] += Wkb[w];
+        for (int w = 0; w < NW; ++w) W0b(w) += Wkb[w];
         if (p1) {
 #pragma unroll
             for (int q = 0; q < D; ++q) {
                 double s = 0.0;
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
-                    gradb[w][q] += Wkb[w] * dl[k][q];
+                    gradb(w, q) += Wkb[w] * dl[k][q];
                     s += grad[w][q] * Wkb[w];
                 }
-                Xb[k][q] += s;
+                Xb(k, q) += s;
                 xcb[q] -= s;
             }
         }
@@ -533,7 +553,7 @@ __global__ __launch_bounds__(256) void k_adj_predict(StepArgs a, AdjArgs j) {
     // ---- half step W0 = Wc + h dW/dt and the least-squares solve
     double Wcb[NW];
 #pragma unroll
-    for (int w = 0; w < NW; ++w) Wcb[w] = W0b[w];
+    for (int w = 0; w < NW; ++w) Wcb[w] = W0b(w);
     double bbar[NW][D] = {}, Ahat[NMS] = {};
     if (p1) {
         double trG = 0.0;
@@ -541,15 +561,15 @@ __global__ __launch_bounds__(256) void k_adj_predict(StepArgs a, AdjArgs j) {
         for (int i = 0; i < D; ++i) trG += G[i][i];
         double Gb[D][D] = {};
         // tau: W0[0] = tau + h tau tr G
-        Wcb[0] += W0b[0] * h * trG;
+        Wcb[0] += W0b(0) * h * trG;
 #pragma unroll
-        for (int i = 0; i < D; ++i) Gb[i][i] += W0b[0] * h * tau;
+        for (int i = 0; i < D; ++i) Gb[i][i] += W0b(0) * h * tau;
         // v: W0[1+i] = v_i + h tau divT_i
         double dvb[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            Wcb[0] += W0b[1 + i] * h * divT[i];
-            dvb[i] = W0b[1 + i] * h * tau;
+            Wcb[0] += W0b(1 + i) * h * divT[i];
+            dvb[i] = W0b(1 + i) * h * tau;
         }
         double taub = 0.0, bb6[6] = {0, 0, 0, 0, 0, 0}, gtb[D] = {}, gBb[6][D] = {};
         divT_vjp<D>(rho0, mu, K, tau, b, gt, gB, dvb, taub, bb6, gtb, gBb, mub, Kb);
@@ -567,10 +587,10 @@ __global__ __launch_bounds__(256) void k_adj_predict(StepArgs a, AdjArgs j) {
         for (int s = 0; s < N; ++s) {
             double t = 0.0;
 #pragma unroll
-            for (int r = 0; r < N; ++r) t += h * MG[r][s] * W0b[1 + D + r];
+            for (int r = 0; r < N; ++r) t += h * MG[r][s] * W0b(1 + D + r);
             bb6[slot<D>(s)] += t;
 #pragma unroll
-            for (int r = 0; r < N; ++r) MGb[r][s] = h * W0b[1 + D + r] * b[slot<D>(s)];
+            for (int r = 0; r < N; ++r) MGb[r][s] = h * W0b(1 + D + r) * b[slot<D>(s)];
         }
         lie_matrix_T<D>(MGb, Gb);
 #pragma unroll
@@ -578,14 +598,14 @@ __global__ __launch_bounds__(256) void k_adj_predict(StepArgs a, AdjArgs j) {
         // gradients
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            gradb[0][i] += gtb[i];
+            gradb(0, i) += gtb[i];
 #pragma unroll
-            for (int q = 0; q < D; ++q) gradb[1 + i][q] += Gb[i][q];
+            for (int q = 0; q < D; ++q) gradb(1 + i, q) += Gb[i][q];
         }
 #pragma unroll
         for (int qq = 0; qq < Dm::NB; ++qq)
 #pragma unroll
-            for (int q = 0; q < D; ++q) gradb[1 + D + qq][q] += gBb[slot<D>(qq)][q];
+            for (int q = 0; q < D; ++q) gradb(1 + D + qq, q) += gBb[slot<D>(qq)][q];
         if (ok) {
             // g = A^{-1} b  ->  bbar = A^{-1} gbar, Abar = -sum_w bbar_w g_w^T
             double Ab[D][D] = {};
@@ -595,7 +615,7 @@ __global__ __launch_bounds__(256) void k_adj_predict(StepArgs a, AdjArgs j) {
                 for (int i = 0; i < D; ++i) {
                     double s = 0.0;
 #pragma unroll
-                    for (int q = 0; q < D; ++q) s += inv[midx<D>(i, q)] * gradb[w][q];
+                    for (int q = 0; q < D; ++q) s += inv[midx<D>(i, q)] * gradb(w, q);
                     bbar[w][i] = s;
                 }
 #pragma unroll
@@ -612,12 +632,17 @@ __global__ __launch_bounds__(256) void k_adj_predict(StepArgs a, AdjArgs j) {
 
     // ---- geometry of the corner vectors and the centroid
     double Xg[NV][D] = {};
-    geom_vjp<D>(X, Cb, 0.0, Xg);
+    double Cbl[NV][D];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int q = 0; q < D; ++q) Cbl[k][q] = Cb(k, q);
+    geom_vjp<D>(X, Cbl, 0.0, Xg);
     double *xo = j.xadj + c * NV * D;
 #pragma unroll
     for (int k = 0; k < NV; ++k)
 #pragma unroll
-        for (int i = 0; i < D; ++i) xo[k * D + i] = Xb[k][i] + Xg[k][i] + xcb[i] * (1.0 / NV);
+        for (int i = 0; i < D; ++i) xo[k * D + i] = Xb(k, i) + Xg[k][i] + xcb[i] * (1.0 / NV);
     double *cl = j.cell + c * AdjArgs::CL;
 #pragma unroll
     for (int w = 0; w < NW; ++w)
@@ -842,7 +867,7 @@ template <int D>
 void launch_adjoint_step(const StepArgs &a, const AdjArgs &j, hipStream_t s) {
     if (a.nc) k_adj_update<D><<<nb(a.nc), 256, 0, s>>>(a, j);
     if (a.nn) k_adj_node1<D><<<nb(AG * a.nn), 256, 0, s>>>(a, j);
-    if (a.nc) k_adj_predict<D><<<nb(a.nc), 256, 0, s>>>(a, j);
+    if (a.nc) k_adj_predict<D><<<(unsigned)((a.nc + ADJ_PB - 1) / ADJ_PB), ADJ_PB, 0, s>>>(a, j);
     if (a.nn) k_adj_agg<D><<<nb(AG * a.nn), 256, 0, s>>>(a, j);
     if (a.nc) k_adj_lsq<D><<<nb(a.nc), 256, 0, s>>>(a, j);
     if (a.nn) k_adj_node2<D><<<nb(AG * a.nn), 256, 0, s>>>(a, j);
