@@ -469,7 +469,10 @@ hl_status hl_forward_replay(hl_ctx *ctx);
  *   dL_dmu      [n_cells]       gradient w.r.t. the per-cell shear modulus
  *   dL_dvcell   [n_cells][dim]  gradient w.r.t. the initial cell velocity
  *   dL_dvnode   [n_nodes][dim]  gradient w.r.t. the initial node velocity
- * The context is left at the final forward state. */
+ * The context is left at the final forward state.  HL_E_STATE without a
+ * recorded run; HL_E_INVALID (with hl_last_error set) when the parameters
+ * were changed after the recording to ones hl_forward_record refuses
+ * (cascade 3, shear_a != -1, eos != 0). */
 hl_status hl_adjoint_run(hl_ctx *ctx, const double *dL_dx_final, double *dL_dmu, double *dL_dvcell,
                          double *dL_dvnode, int on_device);
 

@@ -669,10 +669,17 @@ hl_status capture_cont(hl_ctx *c, int src, int fb) {
 // enqueued without waiting for its counters.
 template <int D>
 hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on_device, hl_step_info *info,
-                   bool quick = false) {
+                   bool quick = false, bool reduce = true, double *const *inter = nullptr) {
     hipStream_t s = c->stream;
     const int src = c->cur;
     hl::StepArgs a = make_args(c, src);
+    if (quick && inter) {
+        // the adjoint's replay writes the step's node aggregates, corner
+        // records and v* straight into its tape slot
+        a.agg = inter[0];
+        a.corner = inter[1];
+        a.vstar = inter[2];
+    }
     if (c->nc == 0) {
         // nothing moves: copy the node state through
         HIPCHK(hipMemcpyAsync(c->x[1 - src], c->x[src], sizeof(double) * c->nn * D, hipMemcpyDeviceToDevice, s));
@@ -758,7 +765,8 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
     } else if (quick && replay_mask && !info) {
         if (dt > 0.0) hl::launch_fill(c->dt_cur, c->n_mesh, dt, s);
         enqueue_first<D>(c, a, !(dt > 0.0), false, s);
-        enqueue_reduce(c, s);
+        // the next dt: not wanted when the caller sets it from a record
+        if (reduce) enqueue_reduce(c, s);
         c->last_first = 0;
         c->last_iters = 1;
         c->last_inadm = 0;
@@ -989,13 +997,15 @@ hl_status copy_state(hl_ctx *c, int buf, double *dst, bool to_snapshot) {
     return HL_OK;
 }
 
-// one step with the recorded dt and cascade choice of step n
+// one step with the recorded dt and cascade choice of step n; with reduce
+// false the step leaves no next dt (the caller takes it from the record)
 template <int D>
-hl_status replay_recorded(hl_ctx *c, int n) {
+hl_status replay_recorded(hl_ctx *c, int n, bool reduce, double *const *inter = nullptr) {
     hipStream_t s = c->stream;
     HIPCHK(hipMemcpyAsync(c->dt_next, c->tape.dts + (size_t)n * c->n_mesh, sizeof(double) * c->n_mesh,
                           hipMemcpyDeviceToDevice, s));
-    return run_step<D>(c, 0.0, c->tape.masks + (size_t)n * c->nc, 1, nullptr, true) < 0 ? HL_E_HIP : HL_OK;
+    return run_step<D>(c, 0.0, c->tape.masks + (size_t)n * c->nc, 1, nullptr, true, reduce, inter) < 0 ? HL_E_HIP
+                                                                                                      : HL_OK;
 }
 
 // forward intermediates of step n for the reverse sweep: state n in buffer 0
@@ -1044,36 +1054,18 @@ hl::AdjArgs adj_args(hl_ctx *c, int in) {
 template <int D>
 constexpr size_t kAggBase = hl::Dims<D>::NA_BASE;
 
-// Save (to_tape) or point at the forward intermediates of step n of the
-// current segment (slot k): the node aggregates, corner records and v*.
+// The forward intermediates of step n of the current segment (tape slot
+// k): node aggregates [kAggBase][nn] (the pairs a step without limiter
+// bounds or gas sums writes), corner records in whole 256-cell tiles, v*.
 template <int D>
-hl_status save_inter(hl_ctx *c, int k) {
-    auto &t = c->tape;
-    const size_t nn = c->nn, nc = c->nc;
-    const size_t na = kAggBase<D> * nn, ncr = (nc + 255) / 256 * 256 * (D + 1) * hl::Dims<D>::CW;
-    double *dst = t.inter + (size_t)k * t.inter_sz;
-    hl::CopyFields f{};
-    f.src[0] = c->agg;
-    f.dst[0] = dst;
-    f.n[0] = (int64_t)na;
-    f.src[1] = c->corner;
-    f.dst[1] = dst + na;
-    f.n[1] = (int64_t)ncr;
-    f.src[2] = c->vstar;
-    f.dst[2] = dst + na + ncr;
-    f.n[2] = (int64_t)(D * nn);
-    hl::launch_copy_fields(f, c->stream);
-    return HL_OK;
-}
-template <int D>
-void inter_args(hl_ctx *c, int k, hl::StepArgs &a) {
+void inter_slot(hl_ctx *c, int k, double *p[3]) {
     auto &t = c->tape;
     const size_t nn = c->nn, nc = c->nc;
     const size_t na = kAggBase<D> * nn, ncr = (nc + 255) / 256 * 256 * (D + 1) * hl::Dims<D>::CW;
     double *src = t.inter + (size_t)k * t.inter_sz;
-    a.agg = src;
-    a.corner = src + na;
-    a.vstar = src + na + ncr;
+    p[0] = src;
+    p[1] = src + na;
+    p[2] = src + na + ncr;
 }
 
 template <int D>
@@ -1132,7 +1124,9 @@ hl_status forward_record(hl_ctx *c, int nsteps, int every) {
 template <int D>
 hl_status forward_replay(hl_ctx *c) {
     for (int n = 0; n < c->tape.nsteps; ++n) {
-        hl_status st = replay_recorded<D>(c, n);
+        // each replayed step takes its dt from the record: only the last
+        // one computes the next dt (that of the replayed state)
+        hl_status st = replay_recorded<D>(c, n, n + 1 == c->tape.nsteps);
         if (st != HL_OK) return st;
     }
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1169,29 +1163,40 @@ hl_status adjoint_run(hl_ctx *c, const double *dLdx, double *dLdmu, double *dLdv
         for (int n = s0; n < s1; ++n) {
             if ((st = copy_state(c, c->cur, t.seg + (size_t)(n - s0) * t.state_sz, true)) != HL_OK) return st;
             // with room for them, the replay also runs the segment's last
-            // step and keeps every step's intermediates
-            if (t.inter || n + 1 < s1) {
-                if ((st = replay_recorded<D>(c, n)) != HL_OK) return st;
-                if (t.inter && (st = save_inter<D>(c, n - s0)) != HL_OK) return st;
+            // step and writes every step's intermediates to the tape
+            if (t.inter) {
+                double *slot[3];
+                inter_slot<D>(c, n - s0, slot);
+                if ((st = replay_recorded<D>(c, n, false, slot)) != HL_OK) return st;
+            } else if (n + 1 < s1) {
+                if ((st = replay_recorded<D>(c, n, false)) != HL_OK) return st;
             }
         }
         for (int n = s1 - 1; n >= s0; --n) {
-            if ((st = copy_state(c, 0, t.seg + (size_t)(n - s0) * t.state_sz, false)) != HL_OK) return st;
             hl::StepArgs a;
             if (t.inter) {
-                // the step's dt, cascade levels and intermediates from the
-                // replay; x^{n+1} and vhat^{n+1} from the next state held
-                HIPCHK(hipMemcpyAsync(c->dt_cur, t.dts + (size_t)n * c->n_mesh, sizeof(double) * c->n_mesh,
-                                      hipMemcpyDeviceToDevice, s));
-                HIPCHK(hipMemcpyAsync(c->mask, t.masks + (size_t)n * c->nc, (size_t)c->nc, hipMemcpyDeviceToDevice,
-                                      s));
+                // the step's dt and cascade levels read from the record,
+                // its intermediates from the replay, state n and the
+                // candidate (state n + 1) from the held snapshots
                 a = make_args(c, 0);
-                inter_args<D>(c, n - s0, a);
+                a.dt = t.dts + (size_t)n * c->n_mesh;
+                a.mask = t.masks + (size_t)n * c->nc;
+                double *slot[3];
+                inter_slot<D>(c, n - s0, slot);
+                a.agg = slot[0];
+                a.corner = slot[1];
+                a.vstar = slot[2];
+                double *cx = t.seg + (size_t)(n - s0) * t.state_sz;
+                a.x = cx;
+                a.vhat = cx + D * nn;
+                a.tau = cx + 2 * D * nn;
+                a.v = cx + 2 * D * nn + nc;
+                a.e = cx + 2 * D * nn + (1 + D) * nc;
+                a.B = cx + 2 * D * nn + (2 + D) * nc;
                 const double *next = n + 1 < s1 ? t.seg + (size_t)(n + 1 - s0) * t.state_sz
                                                 : t.ckpt + (size_t)(seg + 1) * t.state_sz;
                 // the candidate of step n is state n + 1, laid out as in
                 // copy_state: x, vhat, tau, v, e, B
-                const size_t nn = c->nn, nc = c->nc;
                 double *nx = const_cast<double *>(next);
                 a.x1 = nx;
                 a.vhat1 = nx + D * nn;
@@ -1200,6 +1205,7 @@ hl_status adjoint_run(hl_ctx *c, const double *dLdx, double *dLdmu, double *dLdv
                 a.e1 = nx + 2 * D * nn + (1 + D) * nc;
                 a.B1 = nx + 2 * D * nn + (2 + D) * nc;
             } else {
+                if ((st = copy_state(c, 0, t.seg + (size_t)(n - s0) * t.state_sz, false)) != HL_OK) return st;
                 recompute_step<D>(c, n);
                 a = make_args(c, 0);
             }
@@ -1235,6 +1241,9 @@ hl_status adjoint_run(hl_ctx *c, const double *dLdx, double *dLdmu, double *dLdv
     hl_status st = copy_state(c, 0, t.ckpt + (size_t)(t.nckpt - 1) * t.state_sz, false);
     if (st != HL_OK) return st;
     HIPCHK(hipMemcpyAsync(c->dt_next, t.dtn, sizeof(double) * c->n_mesh, hipMemcpyDeviceToDevice, s));
+    if (t.nsteps > 0)
+        HIPCHK(hipMemcpyAsync(c->dt_cur, t.dts + (size_t)(t.nsteps - 1) * c->n_mesh, sizeof(double) * c->n_mesh,
+                              hipMemcpyDeviceToDevice, s));
     if (nc)
         HIPCHK(hipMemcpyAsync(c->mask, t.masks + (size_t)(t.nsteps - 1) * nc, nc, hipMemcpyDeviceToDevice, s));
     c->rec_valid = false;
@@ -2451,6 +2460,7 @@ hl_status hl_upload_field(hl_ctx *c, int field, const void *in, int64_t count, i
 }
 
 hl_status hl_forward_record(hl_ctx *c, int nsteps, int ckpt_every) {
+    g_last_error[0] = '\0';
     if (!c || nsteps < 1 || ckpt_every < 1) return HL_E_INVALID;
     if (!c->have_state) return HL_E_STATE;
     if (c->prm.cascade == 3 || c->prm.shear_a != -1.0 || c->prm.eos != 0 || c->ld.n > 0 || c->ct.n > 0) {
@@ -2479,8 +2489,18 @@ hl_status hl_forward_replay(hl_ctx *c) {
 
 hl_status hl_adjoint_run(hl_ctx *c, const double *dL_dx_final, double *dL_dmu, double *dL_dvcell,
                          double *dL_dvnode, int on_device) {
+    g_last_error[0] = '\0';
     if (!c || !dL_dx_final || !dL_dmu || !dL_dvcell || !dL_dvnode) return HL_E_INVALID;
     if (!c->have_state || c->tape.nsteps == 0) return HL_E_STATE;
+    if (c->prm.cascade == 3 || c->prm.shear_a != -1.0 || c->prm.eos != 0) {
+        // parameters changed since the recording to ones the adjoint does
+        // not cover (the replays would also write aggregates the tape has
+        // no room for)
+        std::snprintf(g_last_error, sizeof g_last_error,
+                      "the adjoint covers the two-level cascade and the neo-Hookean law (cascade 2, shear_a -1, "
+                      "eos 0); the parameters were changed after the recording");
+        return HL_E_INVALID;
+    }
     if (hipSetDevice(c->device) != hipSuccess) return HL_E_HIP;
     return c->dim == 3 ? adjoint_run<3>(c, dL_dx_final, dL_dmu, dL_dvcell, dL_dvnode, on_device)
                        : adjoint_run<2>(c, dL_dx_final, dL_dmu, dL_dvcell, dL_dvnode, on_device);

@@ -160,8 +160,10 @@ def _check(rc, what):
     if rc < 0:
         msg = load().hl_status_str(rc).decode()
         detail = load().hl_last_error().decode()
-        # HIP errors carry their detail; so does an invalid group
-        if rc == -5 or (rc == -1 and what.startswith("hl_group") and detail):
+        # HIP errors carry their detail; so do an invalid group and an
+        # adjoint request the recorded run does not support
+        if rc == -5 or (rc == -1 and detail and (what.startswith("hl_group") or
+                                                 what in ("hl_forward_record", "hl_adjoint_run"))):
             msg += ": " + detail
         raise HyperLagError(f"{what} failed: {msg} ({rc})")
     return rc

@@ -274,6 +274,39 @@ def test_adjoint_leaves_the_final_state_and_next_dt():
         assert np.array_equal(v, b.state()[f]), f
 
 
+def test_replay_leaves_the_recorded_next_dt():
+    """hl_forward_replay from the recorded initial state repeats the run:
+    its final state and next dt equal those of the recording (only the
+    last replayed step computes a next dt)."""
+    w = W.impact_bar_3d(nx=8, ny=2, graded=False)
+    a = H.from_workload(w)
+    b = H.from_workload(w)
+    a.forward_record(6, 2)
+    b.forward_record(6, 2)
+    a.init_state(w.rho0, w.mu, w.lam, w.v_cell, w.v_node, a.params)
+    a.forward_replay()
+    assert np.array_equal(a.next_dt(), b.next_dt())
+    for f, v in a.state().items():
+        assert np.array_equal(v, b.state()[f]), f
+
+
+def test_adjoint_refuses_parameters_it_does_not_cover():
+    """Parameters changed after the recording to a cascade or law the
+    adjoint does not cover: hl_adjoint_run returns an error, and runs again
+    once they are set back."""
+    w = W.impact_bar_3d(nx=8, ny=2, graded=False)
+    a = H.from_workload(w)
+    a.forward_record(4, 2)
+    g = np.ones((w.n_nodes, 3))
+    for kw in ({"cascade": 3}, {"eos": 1}):
+        a.set_params(H.default_params(3, c_cfl=w.c_cfl, **kw))
+        with pytest.raises(H.HyperLagError, match="adjoint covers"):
+            a.adjoint_run(g)
+    a.set_params(H.default_params(3, c_cfl=w.c_cfl))
+    gmu, _, _ = a.adjoint_run(g)
+    assert np.all(np.isfinite(gmu))
+
+
 def test_autograd_function_identification_step():
     """torch.autograd through the library: L = sum |x(T) - x_target|^2 with
     x_target from another shear-modulus field; the gradient from backward
