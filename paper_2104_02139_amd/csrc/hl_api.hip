@@ -102,7 +102,7 @@ struct hl_ctx {
     int64_t *mesh_cell_off = nullptr;
     double *dt_part = nullptr;
     unsigned *counters = nullptr;
-    unsigned *counters_host = nullptr;
+    unsigned *counters_host = nullptr;  // pinned: CNT_N counters, then 128 pass-log entries
     double *dt_cur = nullptr, *dt_next = nullptr, *dt_red = nullptr, *dt_parts = nullptr;
     double *diag_part = nullptr, *diag_out = nullptr;
     double *scratch = nullptr;
@@ -727,7 +727,8 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
         }
         HIPCHK(hipGraphLaunch(c->gexec[src], s));
         c->stamp_host += c->graph_passes;
-        unsigned log[64];
+        // pass log and counters land in pinned memory: one wait for both
+        unsigned *log = c->counters_host + hl::CNT_N;
         const int np = std::min(c->graph_passes, 64);
         if (np) HIPCHK(hipMemcpyAsync(log, c->pass_log, sizeof(unsigned) * np, hipMemcpyDeviceToHost, s));
         hl_status st = read_counters(c, s);
@@ -752,8 +753,9 @@ hl_status run_step(hl_ctx *c, double dt, const uint8_t *replay_mask, int mask_on
                 if (!c->gcont[src][fb] && (st = capture_cont<D>(c, src, fb)) != HL_OK) return st;
                 HIPCHK(hipGraphLaunch(c->gcont[src][fb], s));
                 c->stamp_host += CONT_PASSES;
-                unsigned clog[CONT_PASSES];
-                HIPCHK(hipMemcpyAsync(clog, c->pass_log + 64, sizeof clog, hipMemcpyDeviceToHost, s));
+                unsigned *clog = c->counters_host + hl::CNT_N + 64;
+                HIPCHK(hipMemcpyAsync(clog, c->pass_log + 64, sizeof(unsigned) * CONT_PASSES, hipMemcpyDeviceToHost,
+                                      s));
                 if ((st = read_counters(c, s)) != HL_OK) return st;
                 for (int p = 0; p < CONT_PASSES; ++p) iters += clog[p] > 0;
                 pass += CONT_PASSES;
@@ -1634,7 +1636,8 @@ hl_status upload_impl(hl_ctx *c, int dim, int n_mesh, const std::vector<int64_t>
         A_(c->d_n_u2i, nn);
     }
 #undef A_
-    if (hipHostMalloc((void **)&c->counters_host, hl::CNT_N * sizeof(unsigned), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->counters_host, (hl::CNT_N + 128) * sizeof(unsigned), hipHostMallocDefault) !=
+        hipSuccess) {
         free_all(c);
         return HL_E_OOM;
     }
@@ -2813,7 +2816,7 @@ hl_status group_step(hl_group *g, hl_step_info *info0, hl_step_info *info1) {
         if (!ge && (st = group_capture(g, src[0], src[1])) != HL_OK) return st;
         HIPCHK(hipGraphLaunch(ge, s));
         const int np = std::min(g->graph_passes, 64);
-        unsigned log[2][64];
+        unsigned *log[2] = {c[0]->counters_host + hl::CNT_N, c[1]->counters_host + hl::CNT_N};  // pinned
         for (int i = 0; i < 2; ++i) {
             c[i]->stamp_host += g->graph_passes;
             if (np) HIPCHK(hipMemcpyAsync(log[i], c[i]->pass_log, sizeof(unsigned) * np, hipMemcpyDeviceToHost, s));
@@ -2840,10 +2843,11 @@ hl_status group_step(hl_group *g, hl_step_info *info0, hl_step_info *info1) {
                 }
                 if (!ce && (st = group_capture_cont(g, src[0], src[1], fb)) != HL_OK) return st;
                 HIPCHK(hipGraphLaunch(ce, s));
-                unsigned clog[2][CONT_PASSES];
+                unsigned *clog[2] = {c[0]->counters_host + hl::CNT_N + 64, c[1]->counters_host + hl::CNT_N + 64};
                 for (int i = 0; i < 2; ++i) {
                     c[i]->stamp_host += CONT_PASSES;
-                    HIPCHK(hipMemcpyAsync(clog[i], c[i]->pass_log + 64, sizeof clog[i], hipMemcpyDeviceToHost, s));
+                    HIPCHK(hipMemcpyAsync(clog[i], c[i]->pass_log + 64, sizeof(unsigned) * CONT_PASSES,
+                                          hipMemcpyDeviceToHost, s));
                 }
                 if ((st = group_read_counters(g, s)) != HL_OK) return st;
                 for (int i = 0; i < 2; ++i) {
