@@ -702,6 +702,12 @@ def main():
         "schedules": schedules,
         "kernel_source_sha1": kernel_source_hash(),
     }
+    # what two plain kernels reach on this device (streaming copy, FP64
+    # FMA), for reading the vendor-peak fractions above
+    copy_gbs, fma_tf = H.measure_peaks(0, stream)
+    out["device_peaks"] = {"copy_GBps": copy_gbs, "fp64_fma_TFLOPs": fma_tf,
+                           "vendor_hbm_GBps": HBM_PEAK_GBS, "vendor_fp64_TFLOPs": FP64_PEAK_TFLOPS,
+                           "roofline_achieved_over_copy": achieved / copy_gbs if copy_gbs > 0 else None}
     if not args.no_variants:
         print("[bench] scheme variants on the same workload", file=sys.stderr, flush=True)
         out["variants"] = [

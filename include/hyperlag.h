@@ -500,6 +500,21 @@ const char *hl_status_str(hl_status s);
  * where, and the runtime's message), or "" if none failed. */
 const char *hl_last_error(void);
 
+/* What the device reaches with two plain kernels, against which the step
+ * kernels' vendor-peak rooflines can be read (not part of the method):
+ *   copy_gbs     streaming copy of copy_bytes (>= 1 MiB, a multiple of 16)
+ *                between two buffers the call allocates and frees: bytes
+ *                read + written per second / 1e9, over 10 launches, the
+ *                best of four launch shapes;
+ *   fp64_tflops  independent FP64 fused multiply-adds (8 chains of 4096 per
+ *                lane, 1 M lanes): 2 flop per FMA, per second / 1e12, over
+ *                5 launches.
+ * Runs on hip_stream (NULL: the default stream) of `device` and waits for
+ * it.  HL_E_INVALID for bad sizes or null outputs, HL_E_OOM when the
+ * buffers cannot be allocated. */
+hl_status hl_measure_peaks(int device, void *hip_stream, int64_t copy_bytes, double *copy_gbs,
+                           double *fp64_tflops);
+
 #ifdef __cplusplus
 }
 #endif

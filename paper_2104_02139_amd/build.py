@@ -17,7 +17,7 @@ SELFTEST_LIB = os.path.join(PKG, "libhl_selftest.so")
 SELFTEST_SRC = os.path.join(CSRC, "hl_selftest.hip")
 SOURCES = [os.path.join(CSRC, "hl_kernels.hip"), os.path.join(CSRC, "hl_adjoint.hip"),
            os.path.join(CSRC, "hl_refine.hip"), os.path.join(CSRC, "hl_mesh.hip"), os.path.join(CSRC, "hl_noalloc.hip"),
-           os.path.join(CSRC, "hl_api.hip")]
+           os.path.join(CSRC, "hl_peaks.hip"), os.path.join(CSRC, "hl_api.hip")]
 ARCH = os.environ.get("HL_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -30,7 +30,7 @@ EXPORTS = ["hl_create", "hl_destroy", "hl_mesh_upload", "hl_state_init", "hl_set
            "hl_set_contact", "hl_get_contact", "hl_mesh_refine", "hl_mesh_info", "hl_mesh_get",
            "hl_set_numbering", "hl_mesh_check", "hl_state_save", "hl_state_restore",
            "hl_acoustic_dt_noalloc", "hl_group_create", "hl_group_destroy", "hl_group_use_graph",
-           "hl_group_step"]
+           "hl_group_step", "hl_measure_peaks"]
 
 # internal numbering of uploaded meshes (hl_set_numbering)
 NUMBERING_KEEP, NUMBERING_SPATIAL = 0, 1
@@ -149,6 +149,7 @@ def load():
     L.hl_group_destroy.argtypes = [vp]
     L.hl_group_use_graph.argtypes = [vp, C.c_int, C.c_int]
     L.hl_group_step.argtypes = [vp, vp, vp]
+    L.hl_measure_peaks.argtypes = [C.c_int, vp, i64, C.POINTER(dp), C.POINTER(dp)]
     for name in EXPORTS:
         if name not in ("hl_status_str", "hl_last_error"):
             getattr(L, name).restype = C.c_int
@@ -216,6 +217,17 @@ def acoustic_dt_noalloc(x, cells, rho0, mu, lam, tau, c_cfl, out, device=0, stre
                                          pc[0], args[1][0], args[2][0], args[3][0], args[4][0], float(c_cfl),
                                          po[0]), "hl_acoustic_dt_noalloc")
     return out
+
+
+def measure_peaks(device=0, stream=None, copy_bytes=1 << 30):
+    """hl_measure_peaks: (copy GB/s, FP64 FMA TFLOP/s) of two plain kernels
+    on the device."""
+    handle = None if stream is None else C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream")
+                                                    else int(stream))
+    gbs, tf = C.c_double(), C.c_double()
+    _check(load().hl_measure_peaks(int(device), handle, int(copy_bytes), C.byref(gbs), C.byref(tf)),
+           "hl_measure_peaks")
+    return gbs.value, tf.value
 
 
 class Context:
