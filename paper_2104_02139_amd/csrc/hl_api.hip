@@ -1602,7 +1602,9 @@ hl_status upload_impl(hl_ctx *c, int dim, int n_mesh, const std::vector<int64_t>
     A_(c->vstar, nn * dim);
     A_(c->xc, ncl * (dim == 3 ? hl::Dims<3>::GR : hl::Dims<2>::GR));
     A_(c->agg, nn * NA);
-    A_(c->corner, (ncl + 255) / 256 * 256 * nv * CW);  // whole 256-cell tiles
+    // whole 256-cell tiles, and two doubles of pad: the node gathers read
+    // each record in 16-byte pairs, the last one reaching one double past it
+    A_(c->corner, (ncl + 255) / 256 * 256 * nv * CW + 2);
     A_(c->dtc, 2 * ncl);
     A_(c->mask, ncl);
     A_(c->pstat, ncl);

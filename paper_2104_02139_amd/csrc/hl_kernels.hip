@@ -788,40 +788,42 @@ __device__ __forceinline__ bool node_gather(const StepArgs &a, const int64_t p, 
 }
 
 // Cooperative corner gather (as for the node aggregates): lane l of a group
-// of AGG_G sums value l of the node's corner records in CSR order (lane
-// 0 also value AGG_G of the 9-value 3D record), so a wave-wide load brings
-// whole records; the sums then meet in every lane of the group, which all
-// run the solve.  Lane i < D writes component i.
+// of AGG_G sums values 2l and 2l + 1 of the node's corner records in CSR
+// order, each read with one 16-byte load, so a wave-wide load brings whole
+// records (the last pair's second value lies past the record: the next
+// record's first, or the two doubles of pad after the corner array); the
+// sums then meet in every lane of the group, which all run the solve.
+// Lane i < D writes component i.
 template <int D, bool LD>
 __device__ __forceinline__ void node_solve_group(const StepArgs &a, const int64_t p, const int l) {
     using Dm = Dims<D>;
-    constexpr int CW = Dm::CW;  // values per corner record
-    static_assert(CW < 2 * AGG_G, "a lane sums at most two values of a record");
-    const bool has = l < CW, has2 = l + AGG_G < CW;
-    double S = 0.0, S2 = 0.0;
+    constexpr int CW = Dm::CW;           // values per corner record
+    constexpr int NPAIR = (CW + 1) / 2;  // 16-byte loads per record
+    static_assert(NPAIR <= AGG_G, "a lane sums one pair of a record");
+    const bool has = l < NPAIR;
+    double Sa = 0.0, Sb = 0.0;
     const int32_t q0 = a.n2c_off[p], q1 = a.n2c_off[p + 1];
     for (int32_t qb = q0; qb < q1; qb += AGG_G) {
         const int32_t ql = qb + l;
         const int kl = ql < q1 ? a.n2c[ql] : 0;
-        double t[AGG_G], t2[AGG_G];
+        double2 t[AGG_G];
 #pragma unroll
         for (int m = 0; m < AGG_G; ++m) {
             const int km = __shfl(kl, m, AGG_G);
             const double *rec = a.corner + corner_slot_of<D>(km) * CW;
             const bool in = qb + m < q1;
-            t[m] = (has && in) ? rec[l] : 0.0;
-            t2[m] = (has2 && in) ? rec[l + AGG_G] : 0.0;
+            t[m] = (has && in) ? *reinterpret_cast<const double2 *>(rec + 2 * l) : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int m = 0; m < AGG_G; ++m) {
             if (qb + m >= q1) break;
-            S += t[m];
-            S2 += t2[m];
+            Sa += t[m].x;
+            Sb += t[m].y;
         }
     }
     double v[CW];
 #pragma unroll
-    for (int j = 0; j < CW; ++j) v[j] = j < AGG_G ? __shfl(S, j, AGG_G) : __shfl(S2, j - AGG_G, AGG_G);
+    for (int j = 0; j < CW; ++j) v[j] = __shfl((j & 1) ? Sb : Sa, j >> 1, AGG_G);
     double M[Dm::NMS], r[D];
 #pragma unroll
     for (int s = 0; s < Dm::NMS; ++s) M[s] = v[s];
