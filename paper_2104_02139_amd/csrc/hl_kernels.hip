@@ -723,14 +723,25 @@ __device__ __forceinline__ void predict_staged_body(const StepArgs &a, const Wor
         predict_cell<D, LIM, FAM, SG, true>(a, s0 + threadIdx.x, cs + threadIdx.x * RW, bs * RW);
     __syncthreads();
     // the item's records of corner k are one run within a tile (two runs
-    // if the item crosses a tile boundary)
+    // if the item crosses a tile boundary); a single run that starts on a
+    // 16-byte boundary and holds an even number of values goes out in
+    // 16-byte stores
     const int tot = len * RW;
+    const bool one_run = (int)(s0 & 255) + len <= 256 && (tot & 1) == 0;
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
-        for (int r = threadIdx.x; r < tot; r += bs) {
-            const int ci = r / RW, j = r - ci * RW;
-            store_stream(&a.corner[corner_slot<D>(s0 + ci, k) * RW + j], cs[k * bs * RW + r]);
+    for (int k = 0; k < NV; ++k) {
+        double *run = a.corner + corner_slot<D>(s0, k) * RW;
+        if (one_run && ((reinterpret_cast<uintptr_t>(run) | reinterpret_cast<uintptr_t>(cs + k * bs * RW)) & 15) == 0) {
+            const double2 *src = reinterpret_cast<const double2 *>(cs + k * bs * RW);
+            double2 *dst = reinterpret_cast<double2 *>(run);
+            for (int r = threadIdx.x; r < tot / 2; r += bs) store_stream(&dst[r], src[r]);
+        } else {
+            for (int r = threadIdx.x; r < tot; r += bs) {
+                const int ci = r / RW, j = r - ci * RW;
+                store_stream(&a.corner[corner_slot<D>(s0 + ci, k) * RW + j], cs[k * bs * RW + r]);
+            }
         }
+    }
 }
 template <int D, bool LIM, bool FAM, bool SG>
 __global__ __launch_bounds__(256) void k_predict_staged(StepArgs a, WorkList w) {
