@@ -391,6 +391,15 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c,
 #pragma unroll
         for (int i = 0; i < D; ++i) X[k][i] = a.x[i * nn + p];
     }
+    if (STAGE) {
+        // the node positions wait in this thread's record slots (filled
+        // with the records only after the assembly loop) for that loop to
+        // read them back: LDS reads instead of gathers from x
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+#pragma unroll
+            for (int i = 0; i < D; ++i) lrec[k * lstride + i] = X[k][i];
+    }
     Geo<D> g;
     geom<D>(X, g);
     double xc[D];
@@ -447,7 +456,7 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c,
             const int64_t p = a.c2n[c * NV + k];
             double u[D];
 #pragma unroll
-            for (int i = 0; i < D; ++i) u[i] = xc[i] - a.x[i * nn + p];
+            for (int i = 0; i < D; ++i) u[i] = xc[i] - (STAGE ? lrec[k * lstride + i] : a.x[i * nn + p]);
             const AggRef ag(a.agg, nn, p);
             const double n = ag[0];
             visits += n - 1.0;
