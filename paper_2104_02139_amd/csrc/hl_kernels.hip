@@ -759,9 +759,9 @@ __global__ __launch_bounds__(256) void k_predict_staged(StepArgs a, WorkList w) 
 }
 
 // x^{n+1} = x^n + dt v* (reading R13) and vhat^{n+1} = 2 v* - vhat^n (R9),
-// as one fused multiply-add and one exact doubling.  (The cell update
-// gathers vhat^{n+1}: recomputing it there from v* and vhat^n gave the same
-// bits but took the update from 1.14 to 1.23 ms on the 8.1M-tet bar.)
+// as one fused multiply-add and one exact doubling.  The staged cell update
+// applies the same two functions to the v* it gathers for its forces, which
+// gives the node solve's bits without gathering x^{n+1} and vhat^{n+1}.
 __device__ __forceinline__ double next_position(double x, double dt, double vs) { return __fma_rn(dt, vs, x); }
 __device__ __forceinline__ double next_vhat(double vs, double vh) { return 2.0 * vs - vh; }
 
@@ -1120,6 +1120,13 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
         double vs[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) vs[i] = a.vstar[i * nn + p];
+        if (STAGE) {
+            // kept in this thread's record slots (the gather record is
+            // written there only at the end): x^{n+1} and vhat^{n+1} follow
+            // from them below instead of being gathered
+#pragma unroll
+            for (int i = 0; i < D; ++i) lrec[k * D + i] = vs[i];
+        }
         const double *rec = a.corner + corner_slot<D>(c, k) * Dm::CW;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
@@ -1151,7 +1158,9 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 X0[k][i] = a.x[i * nn + p];
-                X1[k][i] = a.x1[i * nn + p];
+                // the node solve's own x^n + dt v* (the node's mesh is the
+                // cell's, so dt is the same value)
+                X1[k][i] = STAGE ? next_position(X0[k][i], dt, lrec[k * D + i]) : a.x1[i * nn + p];
             }
         }
         Geo<D> g0, g1;
@@ -1185,8 +1194,9 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
             const int64_t p = a.c2n[c * NV + k];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                const double w0 = u0[i * nn + p];
-                const double w1 = p1 ? a.vhat1[i * nn + p] : 0.0;
+                const double vsk = STAGE ? lrec[k * D + i] : 0.0;
+                const double w0 = (STAGE && !p1) ? vsk : u0[i * nn + p];
+                const double w1 = p1 ? (STAGE ? next_vhat(vsk, w0) : a.vhat1[i * nn + p]) : 0.0;
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
                     L0[i][j] += w0 * g0.C[k][j];
@@ -1335,8 +1345,11 @@ __device__ __forceinline__ void update_staged_body(const StepArgs &a, const Work
         store_stream(&out[q], src[ci * (LS / 2) + j]);
     }
 }
+// Three waves per SIMD: the kernel needs 178 VGPRs (two waves) unless
+// capped; the cap costs a 12-byte spill and is faster on the 8.1M-tet bar
+// (1.077 against 1.165 ms).
 template <int D, bool SG>
-__global__ __launch_bounds__(256) void k_update_staged(StepArgs a, WorkList w) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_update_staged(StepArgs a, WorkList w) {
     extern __shared__ double cs[];
     update_staged_body<D, SG>(a, w, grid_blk(), cs);
 }
