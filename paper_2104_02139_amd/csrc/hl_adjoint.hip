@@ -86,13 +86,14 @@ __device__ __forceinline__ void sym_outer_acc(const double yb[D], const double x
 }  // namespace
 
 // ------------------------------------------------------------------ A1
+// Cell c's part: the corner records rec (returned for the caller to store)
+// and the cell record's W adjoint (stored here).
 template <int D>
-__global__ __launch_bounds__(256) void k_adj_update(StepArgs a, AdjArgs j) {
+__device__ __forceinline__ void adj_update_cell(const StepArgs &a, const AdjArgs &j, const int64_t c,
+                                                double (&rec)[D + 1][AdjArgs::CA]) {
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
     constexpr int NMS = Dm::NMS;
-    const int64_t c = tid();
-    if (c >= a.nc) return;
     const int64_t nc = a.nc, nn = a.nn;
     const double m = a.mass[c];
     const double dt = dtof(a.dt, a.cell_mesh, c);
@@ -113,7 +114,6 @@ __global__ __launch_bounds__(256) void k_adj_update(StepArgs a, AdjArgs j) {
     double fb[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) fb[i] = dt / m * j.lv_in[i * nc + c];
-    double rec[NV][AdjArgs::CA];
 #pragma unroll
     for (int k = 0; k < NV; ++k)
 #pragma unroll
@@ -216,9 +216,6 @@ __global__ __launch_bounds__(256) void k_adj_update(StepArgs a, AdjArgs j) {
             rec[k][AdjArgs::O_X0 + i] = X0b[k][i];
             rec[k][AdjArgs::O_X1 + i] = X1b[k][i];
         }
-        double *o = j.cadj + (c * NV + k) * AdjArgs::CA;
-#pragma unroll
-        for (int q = 0; q < AdjArgs::CA; ++q) o[q] = rec[k][q];
     }
     // cell partial adjoint of W = (tau, v, B): v1 = v + ..., B via the update
     double *cw = j.cell + c * AdjArgs::CL + AdjArgs::O_WB;
@@ -227,6 +224,37 @@ __global__ __launch_bounds__(256) void k_adj_update(StepArgs a, AdjArgs j) {
     for (int i = 0; i < D; ++i) cw[1 + i] = j.lv_in[i * nc + c];
 #pragma unroll
     for (int q = 0; q < Dm::NB; ++q) cw[1 + D + q] = bb[slot<D>(q)];
+}
+
+// The block's corner records go out corner by corner through LDS: a
+// thread that wrote its own 192-byte record made every wave store touch
+// one cache line per lane; copied out in address order, 16 bytes per lane,
+// a wave store covers about five whole records.
+constexpr int ADJ_UB = 256;
+template <int D>
+__global__ __launch_bounds__(ADJ_UB) void k_adj_update(StepArgs a, AdjArgs j) {
+    constexpr int NV = D + 1, CA = AdjArgs::CA, CP = CA / 2;
+    static_assert(CA % 2 == 0, "corner adjoint records hold value pairs");
+    __shared__ double2 st[ADJ_UB * CP];
+    const int64_t c0 = (int64_t)blockIdx.x * ADJ_UB, c = c0 + threadIdx.x;
+    const bool live = c < a.nc;
+    double rec[NV][CA];
+    if (live) adj_update_cell<D>(a, j, c, rec);
+    const int ncell = (int)min((int64_t)ADJ_UB, a.nc - c0);
+    double2 *dst = reinterpret_cast<double2 *>(j.cadj);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        __syncthreads();  // the previous corner's copy-out has read st
+        if (live) {
+#pragma unroll
+            for (int q = 0; q < CP; ++q) st[threadIdx.x * CP + q] = make_double2(rec[k][2 * q], rec[k][2 * q + 1]);
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < ncell * CP; r += ADJ_UB) {
+            const int ci = r / CP, q = r - ci * CP;
+            dst[((c0 + ci) * NV + k) * CP + q] = st[r];
+        }
+    }
 }
 
 // ------------------------------------------------------------------ A2
@@ -865,7 +893,7 @@ static inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 template <int D>
 void launch_adjoint_step(const StepArgs &a, const AdjArgs &j, hipStream_t s) {
-    if (a.nc) k_adj_update<D><<<nb(a.nc), 256, 0, s>>>(a, j);
+    if (a.nc) k_adj_update<D><<<(unsigned)((a.nc + ADJ_UB - 1) / ADJ_UB), ADJ_UB, 0, s>>>(a, j);
     if (a.nn) k_adj_node1<D><<<nb(AG * a.nn), 256, 0, s>>>(a, j);
     if (a.nc) k_adj_predict<D><<<(unsigned)((a.nc + ADJ_PB - 1) / ADJ_PB), ADJ_PB, 0, s>>>(a, j);
     if (a.nn) k_adj_agg<D><<<nb(AG * a.nn), 256, 0, s>>>(a, j);
