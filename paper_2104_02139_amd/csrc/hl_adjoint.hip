@@ -322,13 +322,21 @@ __global__ __launch_bounds__(256) void k_adj_node1(StepArgs a, AdjArgs j) {
 constexpr int ADJ_PB = 128;   // threads per block of k_adj_predict
 
 template <int D>
-__global__ __launch_bounds__(ADJ_PB) void k_adj_predict(StepArgs a, AdjArgs j) {
+constexpr int adj_pred_nacc() {
+    return Dims<D>::NW * (D + 1) + 2 * (D + 1) * D;
+}
+
+// Cell c's part: the accumulators live in the block's LDS (acc_lds,
+// ADJ_PB-strided), the cell's xadj values and its cell record are returned
+// for the caller to store, mu_bar is updated here.
+template <int D>
+__device__ __forceinline__ void adj_predict_cell(const StepArgs &a, const AdjArgs &j, const int64_t c,
+                                                 double *acc_lds, double (&xo)[(D + 1) * D],
+                                                 double (&cl)[AdjArgs::CL]) {
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
     constexpr int NMS = Dm::NMS;
     constexpr int NW = Dm::NW;
-    constexpr int NACC = Dims<D>::NW * (D + 1) + 2 * (D + 1) * D;
-    __shared__ double acc_lds[ADJ_PB * NACC];
     double *acc = acc_lds + threadIdx.x;
     auto W0b = [&](int w) -> double & { return acc[w * ADJ_PB]; };
     auto gradb = [&](int w, int q) -> double & { return acc[(Dims<D>::NW + w * D + q) * ADJ_PB]; };
@@ -336,8 +344,6 @@ __global__ __launch_bounds__(ADJ_PB) void k_adj_predict(StepArgs a, AdjArgs j) {
     auto Xb = [&](int k, int q) -> double & {
         return acc[(Dims<D>::NW * (D + 1) + (D + 1) * D + k * D + q) * ADJ_PB];
     };
-    const int64_t c = tid();
-    if (c >= a.nc) return;
     const int64_t nc = a.nc, nn = a.nn;
     int64_t nid[NV];
     double X[NV][D];
@@ -476,7 +482,7 @@ __global__ __launch_bounds__(ADJ_PB) void k_adj_predict(StepArgs a, AdjArgs j) {
             for (int q = i; q < D; ++q) S[midx<D>(i, q)] += g.C[jj][i] * g.C[jj][q] / g.cn[jj];
 
     // ---- reverse over the corners
-    for (int e = 0; e < NACC; ++e) acc[e * ADJ_PB] = 0.0;
+    for (int e = 0; e < adj_pred_nacc<D>(); ++e) acc[e * ADJ_PB] = 0.0;
     double xcb[D] = {};
     double mub = 0.0, Kb = 0.0;
 #pragma unroll
@@ -666,12 +672,13 @@ __global__ __launch_bounds__(ADJ_PB) void k_adj_predict(StepArgs a, AdjArgs j) {
 #pragma unroll
         for (int q = 0; q < D; ++q) Cbl[k][q] = Cb(k, q);
     geom_vjp<D>(X, Cbl, 0.0, Xg);
-    double *xo = j.xadj + c * NV * D;
 #pragma unroll
     for (int k = 0; k < NV; ++k)
 #pragma unroll
         for (int i = 0; i < D; ++i) xo[k * D + i] = Xb(k, i) + Xg[k][i] + xcb[i] * (1.0 / NV);
-    double *cl = j.cell + c * AdjArgs::CL;
+    const double *clg = j.cell + c * AdjArgs::CL;
+#pragma unroll
+    for (int q = 0; q < AdjArgs::CL; ++q) cl[q] = 0.0;
 #pragma unroll
     for (int w = 0; w < NW; ++w)
 #pragma unroll
@@ -679,9 +686,43 @@ __global__ __launch_bounds__(ADJ_PB) void k_adj_predict(StepArgs a, AdjArgs j) {
 #pragma unroll
     for (int s = 0; s < NMS; ++s) cl[AdjArgs::O_AH + s] = Ahat[s];
 #pragma unroll
-    for (int w = 0; w < NW; ++w) cl[AdjArgs::O_WB + w] += Wcb[w];
+    for (int w = 0; w < NW; ++w) cl[AdjArgs::O_WB + w] = clg[AdjArgs::O_WB + w] + Wcb[w];
     // K = lambda + 2 mu / 3
     j.mu_bar[c] += mub + (2.0 / 3.0) * Kb;
+}
+
+// The block's cell records and xadj values go out through LDS (the
+// accumulators' space, free once every thread is done) in address order,
+// 16 bytes per lane, instead of one 368-byte record per lane.
+template <int D>
+__global__ __launch_bounds__(ADJ_PB) void k_adj_predict(StepArgs a, AdjArgs j) {
+    constexpr int NACC = adj_pred_nacc<D>();
+    constexpr int CL = AdjArgs::CL, XA = (D + 1) * D;
+    constexpr int NST = NACC > CL ? NACC : CL;
+    static_assert(CL % 2 == 0 && XA % 2 == 0, "records hold value pairs");
+    __shared__ double acc_lds[ADJ_PB * NST];
+    const int64_t c0 = (int64_t)blockIdx.x * ADJ_PB, c = c0 + threadIdx.x;
+    const bool live = c < a.nc;
+    double xo[XA], cl[CL];
+    if (live) adj_predict_cell<D>(a, j, c, acc_lds, xo, cl);
+    const int ncell = (int)min((int64_t)ADJ_PB, a.nc - c0);
+    double2 *st = reinterpret_cast<double2 *>(acc_lds);
+    __syncthreads();  // every thread is done with its accumulators
+    if (live) {
+#pragma unroll
+        for (int q = 0; q < CL / 2; ++q) st[threadIdx.x * (CL / 2) + q] = make_double2(cl[2 * q], cl[2 * q + 1]);
+    }
+    __syncthreads();
+    double2 *dcl = reinterpret_cast<double2 *>(j.cell) + c0 * (CL / 2);
+    for (int r = threadIdx.x; r < ncell * (CL / 2); r += ADJ_PB) dcl[r] = st[r];
+    __syncthreads();
+    if (live) {
+#pragma unroll
+        for (int q = 0; q < XA / 2; ++q) st[threadIdx.x * (XA / 2) + q] = make_double2(xo[2 * q], xo[2 * q + 1]);
+    }
+    __syncthreads();
+    double2 *dx = reinterpret_cast<double2 *>(j.xadj) + c0 * (XA / 2);
+    for (int r = threadIdx.x; r < ncell * (XA / 2); r += ADJ_PB) dx[r] = st[r];
 }
 
 // ------------------------------------------------------------------ A4
