@@ -1103,8 +1103,14 @@ __global__ __launch_bounds__(256) void k_contact_eval(StepArgs a, ContactArgs k)
 // the admissibility test, its sound speed in the time-step bound.
 // STAGE: the gather record goes to LDS at lrec (16-byte aligned) for the
 // block to copy out (k_update_staged).
-template <int D, bool SG, bool STAGE = false>
-__device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, double *lrec = nullptr) {
+// STAGE: the gather record goes to LDS at lrec for the block to copy out.
+// VS: the v* gathered for the forces waits in the thread's LDS slots vsl
+// (NV * D doubles) and gives x^{n+1} and vhat^{n+1} with the node solve's
+// own formulas instead of further gathers (the same bits).
+template <int D, bool SG, bool STAGE = false, bool VS = STAGE>
+__device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, double *lrec = nullptr,
+                                            double *vsl = nullptr) {
+    if (STAGE && VS) vsl = lrec;
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
     const int64_t nc = a.nc, nn = a.nn;
@@ -1120,12 +1126,11 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
         double vs[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) vs[i] = a.vstar[i * nn + p];
-        if (STAGE) {
-            // kept in this thread's record slots (the gather record is
-            // written there only at the end): x^{n+1} and vhat^{n+1} follow
-            // from them below instead of being gathered
+        if (VS) {
+            // kept in this thread's LDS slots (for the staged kernel its
+            // record slots: the gather record goes there only at the end)
 #pragma unroll
-            for (int i = 0; i < D; ++i) lrec[k * D + i] = vs[i];
+            for (int i = 0; i < D; ++i) vsl[k * D + i] = vs[i];
         }
         const double *rec = a.corner + corner_slot<D>(c, k) * Dm::CW;
 #pragma unroll
@@ -1160,7 +1165,7 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
                 X0[k][i] = a.x[i * nn + p];
                 // the node solve's own x^n + dt v* (the node's mesh is the
                 // cell's, so dt is the same value)
-                X1[k][i] = STAGE ? next_position(X0[k][i], dt, lrec[k * D + i]) : a.x1[i * nn + p];
+                X1[k][i] = VS ? next_position(X0[k][i], dt, vsl[k * D + i]) : a.x1[i * nn + p];
             }
         }
         Geo<D> g0, g1;
@@ -1194,9 +1199,9 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
             const int64_t p = a.c2n[c * NV + k];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                const double vsk = STAGE ? lrec[k * D + i] : 0.0;
-                const double w0 = (STAGE && !p1) ? vsk : u0[i * nn + p];
-                const double w1 = p1 ? (STAGE ? next_vhat(vsk, w0) : a.vhat1[i * nn + p]) : 0.0;
+                const double vsk = VS ? vsl[k * D + i] : 0.0;
+                const double w0 = (VS && !p1) ? vsk : u0[i * nn + p];
+                const double w1 = p1 ? (VS ? next_vhat(vsk, w0) : a.vhat1[i * nn + p]) : 0.0;
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
                     L0[i][j] += w0 * g0.C[k][j];
@@ -1365,18 +1370,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // thread of k_update_list clears the node list and advances the stamp for
 // the next pass.  k_step_begin clears every count before the first pass.
 template <int D, bool SG>
-__device__ __forceinline__ void update_list_body(const StepArgs &a, const Blk b) {
+__device__ __forceinline__ void update_list_body(const StepArgs &a, const Blk b, double *sh) {
     const int64_t n = min((int64_t)a.counters[CNT_CELLS], a.nc);
     if (b.tid() == 0) {
         a.counters[CNT_NODES] = 0u;
         a.counters[CNT_RECOMP] += (unsigned)n;
         *a.stamp = *a.stamp + 1;
     }
-    for (int64_t i = b.tid(); i < n; i += b.stride()) update_cell<D, SG>(a, a.clist[i]);
+    double *vsl = sh + threadIdx.x * (D + 1) * D;
+    for (int64_t i = b.tid(); i < n; i += b.stride()) update_cell<D, SG, false, true>(a, a.clist[i], nullptr, vsl);
 }
 template <int D, bool SG>
 __global__ __launch_bounds__(256) void k_update_list(StepArgs a) {
-    update_list_body<D, SG>(a, grid_blk());
+    __shared__ double sh[256 * (D + 1) * D];
+    update_list_body<D, SG>(a, grid_blk(), sh);
 }
 
 // ------------------------------------------------------ MOOD bookkeeping
@@ -2171,7 +2178,7 @@ struct FPassNodes {
 template <int D>
 struct FUpdateList {
     StepArgs a;
-    __device__ void operator()(Blk b, double *) const { update_list_body<D, false>(a, b); }
+    __device__ void operator()(Blk b, double *sh) const { update_list_body<D, false>(a, b, sh); }
 };
 // start of a step: counters, device dt, and the cascade levels to 0
 struct FBegin {
@@ -2266,7 +2273,7 @@ void launch_mood_sparse_pair(const StepArgs &a2, const PairPass &p2, const StepA
     pair_launch(FPassCells<2>{a2, p2.flist, p2.fcount, p2.log, log_idx}, g2[0],
                 FPassCells<3>{a3, p3.flist, p3.fcount, p3.log, log_idx}, g3[0], 256, 0, s);
     pair_launch(FPassNodes<2>{a2}, g2[1], FPassNodes<3>{a3}, g3[1], 256, sizeof(double) * 4, s);
-    pair_launch(FUpdateList<2>{a2}, g2[2], FUpdateList<3>{a3}, g3[2], 256, 0, s);
+    pair_launch(FUpdateList<2>{a2}, g2[2], FUpdateList<3>{a3}, g3[2], 256, sizeof(double) * 256 * 4 * 3, s);
 }
 void launch_step_begin_pair(const PairBook &b2, const PairBook &b3, hipStream_t s) {
     auto g = [](const PairBook &b) {
