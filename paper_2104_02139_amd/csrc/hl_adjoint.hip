@@ -784,12 +784,15 @@ __global__ __launch_bounds__(256) void k_adj_agg(StepArgs a, AdjArgs j) {
         for (int i = 0; i < D; ++i) S[OAY + i] += Ay[i];
     }
     group_sum(S);
-    // same record order as before: SB, SYB, SBW, SA, SAY; lane l writes
-    // the values l, l + AG, ...
-    double *o = j.agg + p * AdjArgs::NAA;
+    // same record order as before: SB, SYB, SBW, SA, SAY, stored as pairs
+    // of values interleaved over the nodes like the forward aggregates
+    // (pair i of node p at i nn + p), so that the cells' gathers of them
+    // bring a few cache lines per wave instead of one per lane; lane l
+    // writes the values l, l + AG, ...
+    double *o = j.agg;
 #pragma unroll
     for (int t = 0; t < NS; ++t)
-        if ((t & (AG - 1)) == l) o[t] = S[t];
+        if ((t & (AG - 1)) == l) o[((int64_t)(t >> 1) * nn + p) * 2 + (t & 1)] = S[t];
 }
 
 // ------------------------------------------------------------------ A5
@@ -838,7 +841,7 @@ __global__ __launch_bounds__(256) void k_adj_lsq(StepArgs a, AdjArgs j) {
         double y[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) y[i] = xc[i] - X[k][i];
-        const double *ad = j.agg + p * AdjArgs::NAA;
+        const AggRef ad(j.agg, a.nn, p);
         const AggRef fg(a.agg, a.nn, p);
         const double n = fg[0];
         // as a neighbour of the cells around p
