@@ -426,10 +426,15 @@ typedef struct {
 } hl_schedule;
 
 /* Set / get the schedule of stage `stage` (HL_STAGE_*).  The defaults are
- * {256, 256, 0} for pack and update, {64, 64, 0} for predict, {64, 256, 0}
- * for the node aggregates and {32, 256, 0} for the node solve (8 lanes per
- * node: one pass of 64 or 32 nodes per block).  Setting one drops captured
- * graphs. */
+ * {256, 256, 0} for pack and update, {64, 256, 0} for the node aggregates
+ * and {32, 256, 0} for the node solve (8 lanes per node: one pass of 64 or
+ * 32 nodes per block).  The predictor's default follows the meshes: {T, T,
+ * 0} with T the largest of 256, 128, 64 that still gives at least 8 items
+ * per compute unit (counted over both contexts of a group).  With one item
+ * per block (blocks_per_cu 0, tile <= block) the predictor's items are cut
+ * further where their cells use more distinct nodes than the block's LDS
+ * holds (at most 189 in 3D, 255 in 2D, with 256 threads).  Setting one drops
+ * captured graphs. */
 hl_status hl_set_schedule(hl_ctx *ctx, int stage, const hl_schedule *sched);
 hl_status hl_get_schedule(hl_ctx *ctx, int stage, hl_schedule *sched);
 

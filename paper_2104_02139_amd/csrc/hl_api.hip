@@ -12,6 +12,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -46,6 +47,10 @@ struct DevList {
     int64_t *start = nullptr;
     int32_t *len = nullptr;
     int64_t n = 0;
+    // node tiles of the items (predictor lists only; see hl::WorkList)
+    int32_t *tn_off = nullptr, *tn = nullptr;
+    uint32_t *tloc = nullptr;
+    int tn_max = 0;
 };
 
 }  // namespace
@@ -114,16 +119,21 @@ struct hl_ctx {
     Prof prof;
     // stage schedules and their work lists (device memory in allocs)
     int n_cu = 0;
-    // default schedules (the autotuner's choice on the 8.1M-tet bar): pack
-    // and update one 256-cell item per block; predict one 64-cell item per
-    // 64-thread block (its corner records staged in 18 KB of LDS, many
-    // blocks per CU); the node stages (AGG_G lanes per node) one pass of 64
-    // (aggregates) or 32 (solve) nodes per 256-thread block, which keeps
+    // default schedules (the autotuner's choice on the 8.1M-tet bar): pack,
+    // predict and update one 256-cell item per block (the predictor's node
+    // tile, about 130 nodes of the bar, and then its corner records in the
+    // same 80 KB of LDS); the node stages (AGG_G lanes per node) one pass of
+    // 64 (aggregates) or 32 (solve) nodes per 256-thread block, which keeps
     // each XCD's nodes in flight, and the cell records they share, in its L2
-    StageCfg cfg[HL_STAGE_COUNT] = {{256, 256, 0}, {64, 256, 0}, {64, 64, 0}, {32, 256, 0}, {256, 256, 0}};
+    // A predictor schedule the caller has not set follows the mesh
+    // (predict_default): 256-cell items while they still give 8 blocks per
+    // CU, else 128 or 64 (a small mesh would leave CUs idle).
+    StageCfg cfg[HL_STAGE_COUNT] = {{256, 256, 0}, {64, 256, 0}, {256, 256, 0}, {32, 256, 0}, {256, 256, 0}};
+    bool cfg_set[HL_STAGE_COUNT] = {};  // set by hl_set_schedule or hl_autotune
     hl::Sched sk[HL_STAGE_COUNT] = {};
     bool sched_ready = false;
-    std::map<std::pair<int, int>, DevList> wlists;  // (entity kind, tile) -> list
+    // (entity kind, tile, most nodes per node tile or 0) -> list
+    std::map<std::tuple<int, int, int>, DevList> wlists;
     // boundary loads grouped by node (own allocations, freed with the mesh)
     struct {
         int64_t n = 0;  // loads set by the caller
@@ -315,8 +325,13 @@ hl_status dalloc(hl_ctx *c, T **p, size_t n) {
 // while after a refinement the edge midpoints (numbered after the old
 // nodes) are interleaved with the old nodes around them, so the cells
 // both gather are fetched once.
-hl_status work_list(hl_ctx *c, int kind, int tile, DevList *out) {
-    const auto key = std::make_pair(kind, tile);
+//
+// With tile_nodes > 0 (cell lists of the one-item predictor) every item also
+// gets its node tile: its cells' distinct nodes, ascending, and for each
+// cell the places of its nodes in that list.  An item with more than
+// tile_nodes distinct nodes is cut in halves until each part fits.
+hl_status work_list(hl_ctx *c, int kind, int tile, int tile_nodes, DevList *out) {
+    const auto key = std::make_tuple(kind, tile, tile_nodes);
     auto it = c->wlists.find(key);
     if (it != c->wlists.end()) {
         *out = it->second;
@@ -350,6 +365,48 @@ hl_status work_list(hl_ctx *c, int kind, int tile, DevList *out) {
             ln.push_back((int32_t)std::min<int64_t>(tile, off[m + 1] - t.second));
         }
     }
+    std::vector<int32_t> tn_off, tn;
+    std::vector<uint32_t> tloc;
+    if (tile_nodes > 0 && kind == 0) {
+        const int nv = c->dim + 1;
+        std::vector<int64_t> st2;
+        std::vector<int32_t> ln2;
+        std::vector<int32_t> u;
+        tn_off.push_back(0);
+        tloc.assign((size_t)c->nc, 0u);
+        // items still to place, last first
+        std::vector<std::pair<int64_t, int32_t>> todo;
+        for (size_t i = 0; i < st.size(); ++i) {
+            todo.assign(1, {st[i], ln[i]});
+            while (!todo.empty()) {
+                const auto [s0, n0] = todo.back();
+                todo.pop_back();
+                u.assign(c->c2n_host.begin() + s0 * nv, c->c2n_host.begin() + (s0 + n0) * nv);
+                std::sort(u.begin(), u.end());
+                u.erase(std::unique(u.begin(), u.end()), u.end());
+                if ((int)u.size() > tile_nodes) {
+                    todo.push_back({s0 + n0 / 2, n0 - n0 / 2});
+                    todo.push_back({s0, n0 / 2});
+                    continue;
+                }
+                if ((int64_t)tn.size() + (int64_t)u.size() > INT32_MAX) return HL_E_INVALID;
+                for (int64_t cc = s0; cc < s0 + n0; ++cc) {
+                    uint32_t w = 0;
+                    for (int k = 0; k < nv; ++k) {
+                        const int32_t p = c->c2n_host[(size_t)(cc * nv + k)];
+                        w |= (uint32_t)(std::lower_bound(u.begin(), u.end(), p) - u.begin()) << (8 * k);
+                    }
+                    tloc[(size_t)cc] = w;
+                }
+                tn.insert(tn.end(), u.begin(), u.end());
+                tn_off.push_back((int32_t)tn.size());
+                st2.push_back(s0);
+                ln2.push_back(n0);
+            }
+        }
+        st.swap(st2);
+        ln.swap(ln2);
+    }
     DevList d;
     d.n = (int64_t)st.size();
     hl_status r;
@@ -359,6 +416,16 @@ hl_status work_list(hl_ctx *c, int kind, int tile, DevList *out) {
         HIPCHK(hipMemcpy(d.start, st.data(), sizeof(int64_t) * st.size(), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(d.len, ln.data(), sizeof(int32_t) * ln.size(), hipMemcpyHostToDevice));
     }
+    if (!tn_off.empty()) {
+        if ((r = dalloc(c, &d.tn_off, tn_off.size())) != HL_OK) return r;
+        if ((r = dalloc(c, &d.tn, tn.size())) != HL_OK) return r;
+        if ((r = dalloc(c, &d.tloc, tloc.size())) != HL_OK) return r;
+        HIPCHK(hipMemcpy(d.tn_off, tn_off.data(), sizeof(int32_t) * tn_off.size(), hipMemcpyHostToDevice));
+        if (!tn.empty()) HIPCHK(hipMemcpy(d.tn, tn.data(), sizeof(int32_t) * tn.size(), hipMemcpyHostToDevice));
+        if (!tloc.empty())
+            HIPCHK(hipMemcpy(d.tloc, tloc.data(), sizeof(uint32_t) * tloc.size(), hipMemcpyHostToDevice));
+        d.tn_max = tile_nodes;
+    }
     c->wlists.emplace(key, d);
     *out = d;
     return HL_OK;
@@ -366,11 +433,20 @@ hl_status work_list(hl_ctx *c, int kind, int tile, DevList *out) {
 
 hl_status build_sched(hl_ctx *c, int stage, const StageCfg &g, hl::Sched *k) {
     DevList d;
-    hl_status r = work_list(c, kStageKind[stage], g.tile, &d);
+    // the one-item predictor reads node values from node tiles
+    const bool one_item = g.blocks_per_cu == 0 && g.tile <= g.block;
+    const int tn = stage == HL_STAGE_PREDICT && one_item
+                       ? (c->dim == 3 ? hl::tile_max_nodes<3>(g.block) : hl::tile_max_nodes<2>(g.block))
+                       : 0;
+    hl_status r = work_list(c, kStageKind[stage], g.tile, tn, &d);
     if (r != HL_OK) return r;
     k->w.start = d.start;
     k->w.len = d.len;
     k->w.n_items = d.n;
+    k->w.tn_off = d.tn_off;
+    k->w.tn = d.tn;
+    k->w.tloc = d.tloc;
+    k->w.tn_max = d.tn_max;
     int64_t grid = (d.n + 7) / 8 * 8;
     if (g.blocks_per_cu > 0) grid = std::min<int64_t>(grid, ((int64_t)g.blocks_per_cu * c->n_cu + 7) / 8 * 8);
     k->grid = (unsigned)std::max<int64_t>(8, grid);
@@ -380,7 +456,36 @@ hl_status build_sched(hl_ctx *c, int stage, const StageCfg &g, hl::Sched *k) {
 }
 
 // Device work lists are built before any launch that may be captured.
-hl_status ensure_scheds(hl_ctx *c) {
+// The predictor's default schedule for the uploaded meshes (and those of
+// `peer`, the other context of a group, whose launches are shared): one
+// item of T cells per T-thread block with T the largest of 256, 128, 64
+// whose items number at least 8 per CU (node tiles of 256 cells hold about
+// 130 nodes against about 48 for 64 cells, but a launch of few large blocks
+// leaves CUs idle at its end).
+StageCfg predict_default(const hl_ctx *c, const hl_ctx *peer = nullptr) {
+    for (int t : {256, 128}) {
+        int64_t items = 0;
+        for (const hl_ctx *x : {c, peer})
+            if (x)
+                for (size_t m = 0; m + 1 < x->cell_off_host.size(); ++m)
+                    items += (x->cell_off_host[m + 1] - x->cell_off_host[m] + t - 1) / t;
+        if (items >= 8 * (int64_t)c->n_cu) return StageCfg{t, t, 0};
+    }
+    return StageCfg{64, 64, 0};
+}
+
+hl_status ensure_scheds(hl_ctx *c, const hl_ctx *peer = nullptr) {
+    if (!c->cfg_set[HL_STAGE_PREDICT]) {
+        const StageCfg want = predict_default(c, peer);
+        StageCfg &have = c->cfg[HL_STAGE_PREDICT];
+        if (want.tile != have.tile || want.block != have.block || want.blocks_per_cu != have.blocks_per_cu) {
+            have = want;
+            if (c->sched_ready) {
+                c->sched_ready = false;
+                drop_graphs(c);
+            }
+        }
+    }
     if (c->sched_ready) return HL_OK;
     for (int st = 0; st < HL_STAGE_COUNT; ++st) {
         hl_status r = build_sched(c, st, c->cfg[st], &c->sk[st]);
@@ -1325,6 +1430,7 @@ hl_status autotune(hl_ctx *c, int reps, double *best_ms) {
         st = sweep(stage, &keep, &best);
         if (st != HL_OK) break;
         c->cfg[stage] = keep;
+        c->cfg_set[stage] = true;
         if (best_ms) best_ms[stage] = best < 1e300 ? best / reps : 0.0;
     }
     (void)hipEventDestroy(e0);
@@ -2545,6 +2651,7 @@ hl_status hl_set_schedule(hl_ctx *c, int stage, const hl_schedule *sch) {
     g.blocks_per_cu = sch->blocks_per_cu;
     if (!cfg_valid(g)) return HL_E_INVALID;
     c->cfg[stage] = g;
+    c->cfg_set[stage] = true;
     c->sched_ready = false;
     drop_graphs(c);
     return HL_OK;
@@ -2552,9 +2659,10 @@ hl_status hl_set_schedule(hl_ctx *c, int stage, const hl_schedule *sch) {
 
 hl_status hl_get_schedule(hl_ctx *c, int stage, hl_schedule *sch) {
     if (!c || !sch || stage < 0 || stage >= HL_STAGE_COUNT) return HL_E_INVALID;
-    sch->tile = c->cfg[stage].tile;
-    sch->block = c->cfg[stage].block;
-    sch->blocks_per_cu = c->cfg[stage].blocks_per_cu;
+    const StageCfg g = stage == HL_STAGE_PREDICT && !c->cfg_set[stage] ? predict_default(c) : c->cfg[stage];
+    sch->tile = g.tile;
+    sch->block = g.block;
+    sch->blocks_per_cu = g.blocks_per_cu;
     sch->reserved = 0;
     return HL_OK;
 }
@@ -2767,7 +2875,7 @@ hl_status group_step(hl_group *g, hl_step_info *info0, hl_step_info *info1) {
     hl_ctx *c[2] = {g->c[0], g->c[1]};
     hl_status st;
     for (int i = 0; i < 2; ++i)
-        if ((st = ensure_scheds(c[i])) != HL_OK) return st;
+        if ((st = ensure_scheds(c[i], c[1 - i])) != HL_OK) return st;
     if ((st = group_check(g)) != HL_OK) return st;
     if (hipSetDevice(c[0]->device) != hipSuccess) return HL_E_HIP;
     hipStream_t s = c[0]->stream;

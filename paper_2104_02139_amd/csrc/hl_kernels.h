@@ -7,6 +7,7 @@
 
 #include <vector>
 
+#include "hl_device.h"
 #include "hyperlag.h"
 
 namespace hl {
@@ -129,11 +130,35 @@ void launch_adj_project(int64_t nn, const uint8_t *nallow, const double *allow, 
 // list in order (block slot s takes items s, s + nslot, ...), so the items one
 // L2 serves are neighbours in the mesh.  With fewer blocks than items the
 // blocks are persistent.
+//
+// Node tiles (cell items of the predictor, one item per block; all null
+// otherwise): item i uses the distinct nodes tn[tn_off[i] .. tn_off[i+1]),
+// ascending, at most tn_max of them; tloc[c] gives the places in that list
+// of cell c's nodes, 8 bits per corner, corner k in bits 8k .. 8k+7.
 struct WorkList {
     const int64_t *start;  // first entity of each item
     const int32_t *len;    // entities in each item
     int64_t n_items;
+    const int32_t *tn_off, *tn;
+    const uint32_t *tloc;
+    int tn_max;
 };
+
+// Pairs of doubles per node in a node tile held in LDS: the aggregate values
+// the least-squares sums read (count, sum y, sum y y^T, sum W, sum y W^T),
+// then the node position (padded to a whole pair).
+template <int D>
+__host__ __device__ constexpr int tile_pairs() {
+    return (Dims<D>::O_RMM + 1) / 2 + (D + 1) / 2;
+}
+// the most nodes a node tile may hold with blocks of `block` threads:
+// 20 KB of LDS per 64 threads, so that two waves per SIMD still fit, and
+// no more than an 8-bit place can name
+template <int D>
+__host__ __device__ constexpr int tile_max_nodes(int block) {
+    return (block / 64) * 20480 / (16 * tile_pairs<D>()) < 255 ? (block / 64) * 20480 / (16 * tile_pairs<D>())
+                                                                 : 255;
+}
 struct Sched {
     WorkList w;
     unsigned grid, block;  // grid: multiple of 8; block: multiple of 64, <= 256

@@ -378,20 +378,43 @@ __device__ __forceinline__ constexpr int bslot(int s) {
 // d eps/dt = tau T : grad v and carries it through div T.
 // STAGE: the corner records go to LDS, record k at lrec + k * lstride (NMS +
 // D values), for the block to copy out (k_predict_staged).
-template <int D, bool LIM, bool FAM, bool SG, bool STAGE = false>
+// TILE (with STAGE): the node positions and aggregates come from the block's
+// node tile in LDS (tile_pairs<D>() pairs per node at ta, the node of corner
+// k at place (loc >> 8k) & 255), which the record stage then overwrites:
+// every thread of the block calls this, and the block meets at a barrier
+// once the tile is read.
+template <int D>
+struct TileRef {   // one node of a node tile, read like AggRef
+    const double2 *b;
+    __device__ __forceinline__ TileRef(const double2 *ta, int l) : b(ta + l * tile_pairs<D>()) {}
+    __device__ __forceinline__ double operator[](int j) const {
+        const double2 t = b[j >> 1];
+        return (j & 1) ? t.y : t.x;
+    }
+    __device__ __forceinline__ double pos(int i) const { return (*this)[2 * ((Dims<D>::O_RMM + 1) / 2) + i]; }
+};
+template <int D, bool LIM, bool FAM, bool SG, bool STAGE = false, bool TILE = false>
 __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c, double *lrec = nullptr,
-                                             const int lstride = 0) {
+                                             const int lstride = 0, const double2 *ta = nullptr,
+                                             const uint32_t loc = 0) {
+    static_assert((STAGE || !TILE) && !(TILE && SG), "node tiles: staged records, base aggregates");
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
     const int64_t nc = a.nc, nn = a.nn;
     double X[NV][D];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        const int64_t p = a.c2n[c * NV + k];
+        if (TILE) {
+            const TileRef<D> tr(ta, (loc >> (8 * k)) & 255);
 #pragma unroll
-        for (int i = 0; i < D; ++i) X[k][i] = a.x[i * nn + p];
+            for (int i = 0; i < D; ++i) X[k][i] = tr.pos(i);
+        } else {
+            const int64_t p = a.c2n[c * NV + k];
+#pragma unroll
+            for (int i = 0; i < D; ++i) X[k][i] = a.x[i * nn + p];
+        }
     }
-    if (STAGE) {
+    if (STAGE && !TILE) {
         // the node positions wait in this thread's record slots (filled
         // with the records only after the assembly loop) for that loop to
         // read them back: LDS reads instead of gathers from x
@@ -445,43 +468,65 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c,
     }
     double eps_mid = eps0;
 
+    // ---- least-squares normal equations from the node aggregates (R8)
+    double A[Dm::NMS] = {};
+    double rhs[Dm::NW][D] = {};
+    double rhs_e[D] = {};
+    double visits = 0.0;  // neighbour visits: sum over nodes of (n - 1)
+    // the sums of one node's aggregates (ag: AggRef or TileRef) with u =
+    // the centroid minus the node's position
+    auto add_node = [&](const auto &ag, const double (&u)[D]) {
+        const double n = ag[0];
+        visits += n - 1.0;
+        double Sy[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) Sy[i] = ag[Dm::O_SY + i];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = i; j < D; ++j)
+                A[midx<D>(i, j)] += ag[Dm::O_SYY + midx<D>(i, j)] - u[i] * Sy[j] - Sy[i] * u[j] + n * u[i] * u[j];
+#pragma unroll
+        for (int w = 0; w < Dm::NW; ++w) {
+            const double sw = ag[Dm::O_SW + w];
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                rhs[w][j] += ag[Dm::O_SYW + w * D + j] - u[j] * sw - Sy[j] * W0[w] + n * u[j] * W0[w];
+        }
+        if (SG) {
+            const double se = ag[Dm::O_SE];
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                rhs_e[j] += ag[Dm::O_SYE + j] - u[j] * se - Sy[j] * eps0 + n * u[j] * eps0;
+        }
+    };
     if (p1) {
-        // ---- least-squares normal equations from the node aggregates (R8)
-        double A[Dm::NMS] = {};
-        double rhs[Dm::NW][D] = {};
-        double rhs_e[D] = {};
-        double visits = 0.0;  // neighbour visits: sum over nodes of (n - 1)
 #pragma unroll 1
         for (int k = 0; k < NV; ++k) {
-            const int64_t p = a.c2n[c * NV + k];
             double u[D];
+            if (TILE) {
+                const TileRef<D> tr(ta, (loc >> (8 * k)) & 255);
 #pragma unroll
-            for (int i = 0; i < D; ++i) u[i] = xc[i] - (STAGE ? lrec[k * lstride + i] : a.x[i * nn + p]);
-            const AggRef ag(a.agg, nn, p);
-            const double n = ag[0];
-            visits += n - 1.0;
-            double Sy[D];
+                for (int i = 0; i < D; ++i) u[i] = xc[i] - tr.pos(i);
+                add_node(tr, u);
+            } else {
+                const int64_t p = a.c2n[c * NV + k];
 #pragma unroll
-            for (int i = 0; i < D; ++i) Sy[i] = ag[Dm::O_SY + i];
-#pragma unroll
-            for (int i = 0; i < D; ++i)
-#pragma unroll
-                for (int j = i; j < D; ++j)
-                    A[midx<D>(i, j)] += ag[Dm::O_SYY + midx<D>(i, j)] - u[i] * Sy[j] - Sy[i] * u[j] + n * u[i] * u[j];
-#pragma unroll
-            for (int w = 0; w < Dm::NW; ++w) {
-                const double sw = ag[Dm::O_SW + w];
-#pragma unroll
-                for (int j = 0; j < D; ++j)
-                    rhs[w][j] += ag[Dm::O_SYW + w * D + j] - u[j] * sw - Sy[j] * W0[w] + n * u[j] * W0[w];
-            }
-            if (SG) {
-                const double se = ag[Dm::O_SE];
-#pragma unroll
-                for (int j = 0; j < D; ++j)
-                    rhs_e[j] += ag[Dm::O_SYE + j] - u[j] * se - Sy[j] * eps0 + n * u[j] * eps0;
+                for (int i = 0; i < D; ++i) u[i] = xc[i] - (STAGE ? lrec[k * lstride + i] : a.x[i * nn + p]);
+                add_node(AggRef(a.agg, nn, p), u);
             }
         }
+    }
+    // the node tile has been read: its LDS becomes the block's record stage.
+    // The other variants meet a no-op wave barrier here instead, so that
+    // every variant keeps the sums and the solve apart in the same way and
+    // the compiler forms the same fused multiply-adds (bitwise the same
+    // records whatever the schedule)
+    if (TILE)
+        __syncthreads();
+    else
+        __builtin_amdgcn_wave_barrier();
+    if (p1) {
         double inv[Dm::NMS];
         double det, tr = 0.0;
         if (D == 3)
@@ -715,8 +760,13 @@ __global__ __launch_bounds__(256) void k_predict(StepArgs a, WorkList w) {
 // ([corner][cell][NMS + D], dynamic, NV * blockDim * (NMS + D) doubles):
 // after a barrier the block copies them out in address order, so each wave
 // store covers 512 consecutive bytes instead of 64 records 72 bytes apart.
-// Same values as k_predict.
-template <int D, bool LIM, bool FAM, bool SG>
+// TILE: the block first loads its item's node tile into the same LDS (the
+// aggregate pairs its cells' least-squares sums read and the positions of
+// each of the item's distinct nodes, tile_pairs<D>() pairs per node), so
+// that a node's values are fetched once per item instead of once per corner
+// that uses it; threads past the item's end repeat its last cell and keep
+// the records to themselves.  Same values as k_predict.
+template <int D, bool LIM, bool FAM, bool SG, bool TILE = false>
 __device__ __forceinline__ void predict_staged_body(const StepArgs &a, const WorkList &w, const Blk b, double *cs) {
     using Dm = Dims<D>;
     constexpr int NV = D + 1, RW = Dm::CW;
@@ -728,8 +778,35 @@ __device__ __forceinline__ void predict_staged_body(const StepArgs &a, const Wor
     const int64_t s0 = w.start[it];
     const int len = w.len[it];
     const int bs = blockDim.x;
-    if ((int)threadIdx.x < len)
+    if constexpr (TILE) {
+        constexpr int NP = (Dm::O_RMM + 1) / 2, NT = tile_pairs<D>();
+        const int o0 = w.tn_off[it], cnt = w.tn_off[it + 1] - o0;
+        double2 *ta = reinterpret_cast<double2 *>(cs);
+        const double2 *ag2 = reinterpret_cast<const double2 *>(a.agg);
+        const int64_t nn = a.nn;
+        const int64_t c = s0 + min((int)threadIdx.x, len - 1);
+        const uint32_t loc = w.tloc[c];
+        // one node per thread, all of its loads in flight together;
+        // consecutive threads on consecutive nodes of each aggregate plane
+        for (int u = threadIdx.x; u < cnt; u += bs) {
+            const int64_t p = w.tn[o0 + u];
+            double2 v[NT];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) v[j] = ag2[(int64_t)j * nn + p];
+#pragma unroll
+            for (int j = NP; j < NT; ++j) {
+                const int i0 = 2 * (j - NP);
+                v[j].x = a.x[i0 * nn + p];
+                v[j].y = i0 + 1 < D ? a.x[(i0 + 1) * nn + p] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < NT; ++j) ta[u * NT + j] = v[j];
+        }
+        __syncthreads();
+        predict_cell<D, LIM, FAM, SG, true, true>(a, c, cs + threadIdx.x * RW, bs * RW, ta, loc);
+    } else if ((int)threadIdx.x < len) {
         predict_cell<D, LIM, FAM, SG, true>(a, s0 + threadIdx.x, cs + threadIdx.x * RW, bs * RW);
+    }
     __syncthreads();
     // the item's records of corner k are one run within a tile (two runs
     // if the item crosses a tile boundary); a single run that starts on a
@@ -752,10 +829,10 @@ __device__ __forceinline__ void predict_staged_body(const StepArgs &a, const Wor
         }
     }
 }
-template <int D, bool LIM, bool FAM, bool SG>
+template <int D, bool LIM, bool FAM, bool SG, bool TILE = false>
 __global__ __launch_bounds__(256) void k_predict_staged(StepArgs a, WorkList w) {
     extern __shared__ double cs[];
-    predict_staged_body<D, LIM, FAM, SG>(a, w, grid_blk(), cs);
+    predict_staged_body<D, LIM, FAM, SG, TILE>(a, w, grid_blk(), cs);
 }
 
 // x^{n+1} = x^n + dt v* (reading R13) and vhat^{n+1} = 2 v* - vhat^n (R9),
@@ -1947,6 +2024,14 @@ void launch_node_agg(const StepArgs &a, const Sched &k, hipStream_t s) {
     else
         k_node_agg<D, false><<<k.grid, k.block, 0, s>>>(a, k.w);
 }
+// LDS of a staged predictor launch: its record stage, or its node tiles if
+// they are larger (the two share the memory)
+template <int D>
+size_t predict_lds_bytes(const Sched &k) {
+    const size_t rec = sizeof(double) * (size_t)(D + 1) * k.block * (Dims<D>::NMS + D);
+    const size_t tile = k.w.tn_off ? sizeof(double2) * (size_t)k.w.tn_max * tile_pairs<D>() : 0;
+    return std::max(rec, tile);
+}
 template <int D>
 void launch_predict(const StepArgs &a, const Sched &k, hipStream_t s) {
     if (!k.w.n_items) return;
@@ -1965,10 +2050,14 @@ void launch_predict(const StepArgs &a, const Sched &k, hipStream_t s) {
             lim ? HL_PREDICT_LAUNCH(true, true, false) : HL_PREDICT_LAUNCH(true, false, false);
     } else {
         // one block per item: corner records staged through LDS (not for the
-        // shear family, whose staged body no longer fits two waves per SIMD)
-        const size_t lds = sizeof(double) * (size_t)(D + 1) * k.block * (Dims<D>::NMS + D);
+        // shear family, whose staged body no longer fits two waves per SIMD),
+        // node values from the item's node tile when the list has them
+        const size_t lds = predict_lds_bytes<D>(k);
         if (fam)
             lim ? HL_PREDICT_LAUNCH(false, true, true) : HL_PREDICT_LAUNCH(false, false, true);
+        else if (k.w.tn_off)
+            lim ? k_predict_staged<D, true, false, false, true><<<k.grid, k.block, lds, s>>>(a, k.w)
+                : k_predict_staged<D, false, false, false, true><<<k.grid, k.block, lds, s>>>(a, k.w);
         else if (lim)
             k_predict_staged<D, true, false, false><<<k.grid, k.block, lds, s>>>(a, k.w);
         else
@@ -2134,10 +2223,11 @@ struct FPredict {
     StepArgs a;
     WorkList w;
     __device__ void operator()(Blk b, double *sh) const {
+        // one-item predictor lists of a group always carry node tiles
         if (LOOP)
             predict_body<D, true, false, false, false>(a, w, b);
         else
-            predict_staged_body<D, false, false, false>(a, w, b, sh);
+            predict_staged_body<D, false, false, false, true>(a, w, b, sh);
     }
 };
 template <int D, bool LOOP>
@@ -2243,7 +2333,7 @@ void launch_node_agg_pair(const StepArgs &a2, const Sched &k2, const StepArgs &a
     pair_stage<FNodeAgg>(a2, k2, a3, k3, lds, s);
 }
 void launch_predict_pair(const StepArgs &a2, const Sched &k2, const StepArgs &a3, const Sched &k3, hipStream_t s) {
-    const size_t lds = sizeof(double) * (size_t)std::max(k2.block, k3.block) * std::max(3 * Dims<2>::CW, 4 * Dims<3>::CW);
+    const size_t lds = std::max(predict_lds_bytes<2>(k2), predict_lds_bytes<3>(k3));
     pair_stage<FPredict>(a2, k2, a3, k3, lds, s);
 }
 void launch_node_solve_pair(const StepArgs &a2, const Sched &k2, const StepArgs &a3, const Sched &k3,

@@ -54,15 +54,32 @@ def _family():
     return ws
 
 
+def _predict_default(cells_per_mesh, n_cu):
+    """The predictor's default: T-cell items on T-thread blocks, T the
+    largest of 256, 128, 64 that gives at least 8 items per CU."""
+    for t in (256, 128):
+        if sum(-(-n // t) for n in cells_per_mesh) >= 8 * n_cu:
+            return dict(tile=t, block=t, blocks_per_cu=0)
+    return dict(tile=64, block=64, blocks_per_cu=0)
+
+
 def test_default_schedules():
-    ctx = H.from_workload(_bar())
+    import torch
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    w = _bar()
+    ctx = H.from_workload(w)
     want = {"pack": dict(tile=256, block=256, blocks_per_cu=0),
             "node_agg": dict(tile=64, block=256, blocks_per_cu=0),
-            "predict": dict(tile=64, block=64, blocks_per_cu=0),
+            "predict": _predict_default([w.n_cells], n_cu),
             "node_solve": dict(tile=32, block=256, blocks_per_cu=0),
             "update": dict(tile=256, block=256, blocks_per_cu=0)}
     for stage in H.STAGES:
         assert ctx.get_schedule(stage) == want[stage], stage
+    assert want["predict"]["tile"] == 64   # 2400 cells: few items
+    # a mesh with 8 items of 256 cells per CU takes 256-cell items
+    big = W.rotating_cube_3d(n=48, seed=1)
+    assert big.n_cells >= 8 * 256 * n_cu, (big.n_cells, n_cu)
+    assert H.from_workload(big).get_schedule("predict") == dict(tile=256, block=256, blocks_per_cu=0)
 
 
 @pytest.mark.parametrize("sched", range(len(SCHEDULES)))
@@ -119,3 +136,35 @@ def test_invalid_schedules_rejected():
             ctx.set_schedule("predict", **bad)
     with pytest.raises(ValueError):
         ctx.set_schedule("no_such_stage")
+
+
+def _scattered(w, seed):
+    """The workload's cells in a random order and held in that order
+    (NUMBERING_KEEP): each 256-cell item then uses far more distinct nodes
+    than a node tile of the one-item predictor holds (189 in 3D, 255 in 2D),
+    so its items are cut until each part fits."""
+    rng = np.random.default_rng(seed)
+    pc = rng.permutation(w.n_cells)
+    ctx = H.Context(0)
+    ctx.set_numbering(H.NUMBERING_KEEP)
+    cells = np.ascontiguousarray(w.cells[pc], dtype=np.int32)
+    ctx.upload_mesh(w.dim, w.x, cells, w.nwall, w.normals)
+    ctx.init_state(w.rho0[pc], w.mu[pc], w.lam[pc], w.v_cell[pc], w.v_node,
+                   H.default_params(w.dim, c_cfl=w.c_cfl))
+    return ctx, cells
+
+
+@pytest.mark.parametrize("make", [lambda: W.impact_bar_3d(nx=16, ny=4, graded=True, seed=11),
+                                  lambda: W.plane_wave_2d(n=24, amp=0.05, seed=2)])
+def test_predict_items_cut_to_fit_node_tiles(make):
+    w = make()
+    tiled, cells = _scattered(w, 5)
+    first = len(np.unique(cells[:256]))
+    assert first > (189 if w.dim == 3 else 255), first
+    plain, _ = _scattered(w, 5)
+    # the persistent predictor walks its items with no node tiles
+    plain.set_schedule("predict", tile=512, block=128, blocks_per_cu=2)
+    tiled.set_schedule("predict", tile=256, block=256)
+    print(f"[schedule] node tiles on a scattered {w.dim}D mesh of {w.n_cells} cells "
+          f"({first} nodes in the first 256 cells)", flush=True)
+    _same(_run(plain, 8, False), _run(tiled, 8, False))
