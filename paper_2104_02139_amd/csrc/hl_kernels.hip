@@ -393,10 +393,28 @@ struct TileRef {   // one node of a node tile, read like AggRef
     }
     __device__ __forceinline__ double pos(int i) const { return (*this)[2 * ((Dims<D>::O_RMM + 1) / 2) + i]; }
 };
+// A cell's own inputs to the predictor, loaded by the tiled block before
+// its node tile so that the two loads' latencies overlap.
+template <int D>
+struct PredIn {
+    double tau, b[6], v[D], rho0, mu, K, dt;
+    int level;
+    __device__ __forceinline__ void load(const StepArgs &a, int64_t c) {
+        tau = a.tau[c];
+        load_B6<D>(a.B, a.nc, c, b);
+#pragma unroll
+        for (int i = 0; i < D; ++i) v[i] = a.v[i * a.nc + c];
+        rho0 = a.rho0[c];
+        mu = a.mu[c];
+        K = a.K[c];
+        dt = mesh_dt(a.dt, a.cell_mesh, c);
+        level = a.mask[c];
+    }
+};
 template <int D, bool LIM, bool FAM, bool SG, bool STAGE = false, bool TILE = false>
 __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c, double *lrec = nullptr,
                                              const int lstride = 0, const double2 *ta = nullptr,
-                                             const uint32_t loc = 0) {
+                                             const uint32_t loc = 0, const PredIn<D> *pin = nullptr) {
     static_assert((STAGE || !TILE) && !(TILE && SG), "node tiles: staged records, base aggregates");
     using Dm = Dims<D>;
     constexpr int NV = D + 1;
@@ -439,18 +457,24 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c,
 #pragma unroll
         for (int i = 0; i < D; ++i) X[k][i] -= xc[i];
 
-    const double tau = a.tau[c];
+    PredIn<D> q;
+    if (TILE)
+        q = *pin;
+    else
+        q.load(a, c);
+    const double tau = q.tau;
     double b[6];
-    load_B6<D>(a.B, nc, c, b);
-    const double rho0 = a.rho0[c], mu = a.mu[c], K = a.K[c];
-    const int level = a.mask[c];   // cascade level: 0 unlimited, 1 limited, 2 first order
+#pragma unroll
+    for (int s6 = 0; s6 < 6; ++s6) b[s6] = q.b[s6];
+    const double rho0 = q.rho0, mu = q.mu, K = q.K;
+    const int level = q.level;   // cascade level: 0 unlimited, 1 limited, 2 first order
     const bool p1 = level < 2;
 
     // W0 = W_c + (dt/2) dW/dt at the centroid; corner value W0 + grad W . delta
     double W0[Dm::NW];
     W0[0] = tau;
 #pragma unroll
-    for (int i = 0; i < D; ++i) W0[1 + i] = a.v[i * nc + c];
+    for (int i = 0; i < D; ++i) W0[1 + i] = q.v[i];
 #pragma unroll
     for (int q = 0; q < Dm::NB; ++q) W0[1 + D + q] = b[bslot<D>(q)];
     double grad[Dm::NW][D];
@@ -601,7 +625,7 @@ __device__ __forceinline__ void predict_cell(const StepArgs &a, const int64_t c,
         double trG = 0.0;
 #pragma unroll
         for (int i = 0; i < D; ++i) trG += G[i][i];
-        const double h = 0.5 * mesh_dt(a.dt, a.cell_mesh, c);
+        const double h = 0.5 * q.dt;
         const double B3[3][3] = {{b[0], b[3], b[4]}, {b[3], b[1], b[5]}, {b[4], b[5], b[2]}};
         // dB/dt = G B + B G^T, stored components only
 #pragma unroll
@@ -786,6 +810,8 @@ __device__ __forceinline__ void predict_staged_body(const StepArgs &a, const Wor
         const int64_t nn = a.nn;
         const int64_t c = s0 + min((int)threadIdx.x, len - 1);
         const uint32_t loc = w.tloc[c];
+        PredIn<D> pin;
+        pin.load(a, c);
         // one node per thread, all of its loads in flight together;
         // consecutive threads on consecutive nodes of each aggregate plane
         for (int u = threadIdx.x; u < cnt; u += bs) {
@@ -803,7 +829,7 @@ __device__ __forceinline__ void predict_staged_body(const StepArgs &a, const Wor
             for (int j = 0; j < NT; ++j) ta[u * NT + j] = v[j];
         }
         __syncthreads();
-        predict_cell<D, LIM, FAM, SG, true, true>(a, c, cs + threadIdx.x * RW, bs * RW, ta, loc);
+        predict_cell<D, LIM, FAM, SG, true, true>(a, c, cs + threadIdx.x * RW, bs * RW, ta, loc, &pin);
     } else if ((int)threadIdx.x < len) {
         predict_cell<D, LIM, FAM, SG, true>(a, s0 + threadIdx.x, cs + threadIdx.x * RW, bs * RW);
     }
