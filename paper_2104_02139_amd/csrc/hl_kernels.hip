@@ -1206,7 +1206,6 @@ __global__ __launch_bounds__(256) void k_contact_eval(StepArgs a, ContactArgs k)
 // the admissibility test, its sound speed in the time-step bound.
 // STAGE: the gather record goes to LDS at lrec (16-byte aligned) for the
 // block to copy out (k_update_staged).
-// STAGE: the gather record goes to LDS at lrec for the block to copy out.
 // VS: the v* gathered for the forces waits in the thread's LDS slots vsl
 // (NV * D doubles) and gives x^{n+1} and vhat^{n+1} with the node solve's
 // own formulas instead of further gathers (the same bits).
@@ -1220,6 +1219,12 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
     const double m = a.mass[c];
     const double dt = mesh_dt(a.dt, a.cell_mesh, c);
     const double dtm = dt / m;
+    // the cell's own values, loaded ahead of the force loop's gathers
+    double v0[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) v0[i] = a.v[i * nc + c];
+    const double e0 = a.e[c];
+    const int lev = a.mask[c];
 
     // ---- subcell forces and the compatible momentum / energy update
     double F[D] = {}, Wk = 0.0;
@@ -1248,14 +1253,14 @@ __device__ __forceinline__ void update_cell(const StepArgs &a, const int64_t c, 
     double v1[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        v1[i] = a.v[i * nc + c] + dtm * F[i];
+        v1[i] = v0[i] + dtm * F[i];
         store_stream(&a.v1[i * nc + c], v1[i]);
     }
-    const double e1 = a.e[c] + dtm * Wk;
+    const double e1 = e0 + dtm * Wk;
     store_stream(&a.e1[c], e1);
 
     // ---- geometry at t^n and t^{n+1}; velocity gradients
-    const bool p1 = a.mask[c] < 2;   // unlimited or limited second order
+    const bool p1 = lev < 2;   // unlimited or limited second order
     double L0[D][D], L1[D][D];
     double tau1, Lc, xc1[D];
     {
