@@ -104,3 +104,29 @@ def test_group_rejects_what_it_does_not_pair():
     g2.compute_dt()
     g3.compute_dt()
     grp.step()
+
+
+def test_group_predictor_default_counts_both_contexts():
+    """The predictor's default item size follows the meshes; in a group it
+    counts both contexts' cells, so that the paired launch has one block
+    size: a small 2D context (64-cell items alone) with a 3D context large
+    enough for 256-cell items steps as a group, bitwise as the two stepped
+    alone."""
+    small = _family(2)
+    big = [W.rotating_cube_3d(n=48, seed=1)]
+    g2, g3 = H.from_workloads(small), H.from_workloads(big)
+    r2, r3 = H.from_workloads(small), H.from_workloads(big)
+    assert g2.get_schedule("predict")["tile"] == 64
+    assert g3.get_schedule("predict")["tile"] == 256
+    for c in (g2, g3, r2, r3):
+        c.compute_dt()
+    grp = H.Group(g2, g3)
+    for k in range(3):
+        i2, i3 = grp.step()
+        j2 = r2.step_batch(None)
+        j3 = r3.step_batch(None)
+        for key in KEYS:
+            assert i2[key] == j2[key], (k, "2D", key)
+            assert i3[key] == j3[key], (k, "3D", key)
+    _same(g2, r2, "2D")
+    _same(g3, r3, "3D")
